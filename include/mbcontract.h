@@ -1,0 +1,265 @@
+/*
+ * mbcontract.h -- C ABI of the MI355X (gfx950) implementation of the
+ * recursive multibaryon contraction method of Guenther, Toth and Varnhorst,
+ * "A recursive approach to determine correlation functions in multibaryon
+ * systems" (arXiv:1301.4895).
+ *
+ * Three calls carry the method:
+ *   mb_build_term_list      the per-nucleus, configuration-independent part
+ *                           (Sec. 3-5, 7): L by the recursion of eq. recr_L,
+ *                           the required components of every stage and the
+ *                           operation lists Lambda, built once on the host.
+ *   mb_make_blocks          the baryon blocks f_P, f_N of Sec. 2 (with the
+ *                           several-source form of Sec. 6) from quark
+ *                           propagators in device memory, antisymmetrised in
+ *                           their same-flavour quark indices (Sec. 4).
+ *   mb_contract_correlator  the recursion F_-^(n+1) = F_-^(n) . f (eq. recr_F)
+ *                           over the operation lists and the final contraction
+ *                           with L (eq. C_final, eq. C_final_moresource).
+ *
+ * Conventions (0-based).  Quark index xi = N_s*(3*spin + colour) + source;
+ * with nonrelativistic operators only spins 0, 1 enter (Sec. 7), so xi runs
+ * over 3*D*N_s values with D = 4 (relativistic) or 2.  Baryon index
+ * psi (sink) or chi (source) = N_s*alpha + s, D*N_s values; at the sink s
+ * selects the sink function.  Within a correlator the baryons are ordered
+ * protons first, each species in ascending index, identically at sink and
+ * source; the result is C(delta set; alpha set) of eq. C_final with the
+ * normalisation that makes it equal the Wick contraction of Sec. 2 (no
+ * overall Grassmann sign).
+ *
+ * Ownership.  A term list is an opaque host object owned by the caller
+ * (free it with mb_term_list_free).  Every device buffer -- propagators, sink
+ * weights, exponents, blocks, correlators, workspaces and the device image of
+ * the term list -- is allocated and owned by the caller; the library never
+ * allocates device memory.  Device calls are asynchronous on the given HIP
+ * stream (NULL = default stream); device faults surface at the caller's next
+ * synchronisation.
+ *
+ * Errors.  Every call returns MB_OK (0) or a negative MB_E* code; arguments
+ * are validated on the host before anything is launched, and nothing is
+ * launched when a call fails.  mb_last_error() gives a message for the last
+ * failure of the calling thread.
+ */
+#ifndef MBCONTRACT_H
+#define MBCONTRACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MB_OK 0
+#define MB_EINVAL (-1)        /* malformed argument                          */
+#define MB_EPAULI (-2)        /* more baryons/quarks than indices (Sec. 6)    */
+#define MB_EUNSUPPORTED (-3)  /* outside what this build supports             */
+#define MB_ENOWORKSPACE (-4)  /* buffer smaller than the queried size         */
+#define MB_EHIP (-5)          /* a HIP runtime call failed                    */
+#define MB_ENOMEM (-6)        /* host allocation failed                       */
+
+#define MB_PATH_AUTO 0         /* more numerous species first, neutrons on a tie (Sec. 7) */
+#define MB_PATH_PROTONS_FIRST 1
+#define MB_PATH_NEUTRONS_FIRST 2
+
+#define MB_C64 0               /* complex float (re, im)   */
+#define MB_C128 1              /* complex double (re, im)  */
+
+#define MB_FP64 0              /* blocks, products and sums in double            */
+#define MB_MIXED 1             /* float products and block partial sums; double
+                                  site reduction and final signed sum            */
+
+/* A nucleus of n_P protons and n_N neutrons (Sec. 7).
+ *   rel    1: Gamma_1 = 1, Gamma_2 = C gamma_5; 0: the nonrelativistic
+ *          Gamma_1 = P_nr, Gamma_2 = C gamma_5 P_nr (Dirac representation).
+ *   n_src  number of orthogonal quark sources N_s (Sec. 6), 1 or 2.
+ *   path   order of the recursion (MB_PATH_*); all baryons of the first
+ *          species are added before any of the second.                       */
+typedef struct {
+    int n_P, n_N;
+    int rel;
+    int n_src;
+    int path;
+} mb_nucleus;
+
+/* Which components of C(delta set; alpha set) are wanted (Sec. 5, Sec. 8).
+ *   all_components != 0: every sink set over the D*N_s baryon indices and,
+ *          with one source, every source set; with two sources the source
+ *          sets that put min(n, D) baryons of a species on source 0 and the
+ *          rest on source 1 (the convention of Tables 1-3).  The other
+ *          fields are ignored.
+ *   otherwise: sink_P, sink_N are bit masks of the sink baryon indices; the
+ *          output rows are every n_P-subset of sink_P times every
+ *          n_N-subset of sink_N.  alpha[2*i], alpha[2*i+1] are the proton
+ *          and neutron source index sets (bit masks, popcounts n_P and n_N)
+ *          of output column i, 0 <= i < n_alpha.  A single spin component
+ *          (Sec. 8) has sink_P = alpha[0], sink_N = alpha[1], n_alpha = 1.  */
+typedef struct {
+    int all_components;
+    uint32_t sink_P, sink_N;
+    int n_alpha;
+    const uint32_t *alpha;
+} mb_spin_request;
+
+typedef struct mb_term_list mb_term_list;
+
+/* Builds the term list of a nucleus and spin request (Sec. 3-5, 7): the
+ * antisymmetrised G of each baryon type, L on sorted index sets by
+ * L^(n+1) = L^(n) . G (eq. recr_L) restricted to the requested source sets,
+ * the final required components (requested sink sets times every index set
+ * with a nonzero L), the required components of every earlier stage and the
+ * operation list of every step, in the factorised form
+ *     (quark split of the output) x (baryon-index split of the output),
+ * which is the split of eq. antis_product_2 with its sign.  Host only,
+ * deterministic, independent of any gauge configuration.
+ * Returns MB_EPAULI when a species has more baryons than baryon indices or a
+ * flavour more quarks than quark indices, MB_EUNSUPPORTED beyond 16 baryons
+ * or 24 quark indices, MB_EINVAL for malformed requests.  On success *out
+ * owns the list.                                                           */
+int mb_build_term_list(const mb_nucleus *nuc, const mb_spin_request *req,
+                       mb_term_list **out);
+
+/* Same as mb_build_term_list but builds only the required-component sets
+ * and counts (the memory-saving mode of Sec. 3): no operation tables, no
+ * device image.  mb_term_list_counts works on the result.                  */
+int mb_build_term_list_counts_only(const mb_nucleus *nuc, const mb_spin_request *req,
+                                   mb_term_list **out);
+
+void mb_term_list_free(mb_term_list *tl);
+
+#define MB_MAX_STAGES 16
+
+/* Sizes of a term list.  Stage s (0-based) holds the components with the
+ * first s+1 baryons of the path; step s (s >= 1) forms stage s from stage
+ * s-1 and the block of baryon path[s].
+ *   n_lambda        total operations (one complex multiply-add each; the
+ *                   count the paper's tables report)
+ *   n_lambda_step   operations of step s (entry 0 is 0)
+ *   n_req           |required components| of stage s
+ *   n_quark         distinct (u set, d set) parts of stage s
+ *   n_spin          distinct (proton set, neutron set) parts of stage s
+ *   n_L             nonzero entries of L over all requested source sets
+ *   n_U             distinct quark parts with a nonzero L (final stage)
+ *   n_delta, n_alpha  output rows / columns
+ *   n_psi, n_xi     D*N_s and 3*D*N_s
+ *   device_bytes    size of the device image (0 in counts-only mode)      */
+typedef struct {
+    int n_stages;
+    int path[MB_MAX_STAGES];
+    int64_t n_lambda;
+    int64_t n_lambda_step[MB_MAX_STAGES];
+    int64_t n_req[MB_MAX_STAGES];
+    int64_t n_quark[MB_MAX_STAGES];
+    int32_t n_spin[MB_MAX_STAGES];
+    int64_t n_L;
+    int64_t n_U;
+    int32_t n_delta, n_alpha;
+    int32_t n_psi, n_xi;
+    int64_t device_bytes;
+} mb_counts;
+
+int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
+
+/* Export of the term list for inspection and tests (host memory).  If buf is
+ * NULL, *bytes receives the size; otherwise *bytes must be at least that
+ * size.  `stage` selects the stage where relevant.
+ *   MB_EXPORT_QUARK  uint32 [n_quark][2]: (u mask, d mask), ascending in
+ *                    (u, d); the order of the stage's quark parts
+ *   MB_EXPORT_SPIN   uint32 [n_spin][2]: (proton mask, neutron mask) in the
+ *                    stage's order (proton rank major)
+ *   MB_EXPORT_QSPLIT uint32 [n_quark][S][2] for stage >= 1: per output quark
+ *                    part, per split: (quark part index in stage-1,
+ *                    block quark index | sign bit 31 set for -1)
+ *   MB_EXPORT_SSPLIT int32 [n_spin][k][3] for stage >= 1: per output spin
+ *                    part, per split: (spin part index in stage-1, baryon
+ *                    index psi of the added baryon, sign +1/-1)
+ *   MB_EXPORT_COEF   int64 [n_alpha+1] row starts, then int64 [n_L] final
+ *                    quark part indices, then int64 [n_L] values of L on
+ *                    sorted sets (the coefficient c of the final sum)
+ *   MB_EXPORT_DELTA  uint32 [n_delta][2] sink sets, MB_EXPORT_ALPHA uint32
+ *                    [n_alpha][2] source sets (proton mask, neutron mask)
+ * The block quark index of a proton split with u pair (a<b) and d index c is
+ * (b*(b-1)/2 + a)*n_xi + c; of a neutron split with u index c and d pair
+ * (a<b) it is c*(n_xi*(n_xi-1)/2) + b*(b-1)/2 + a.                          */
+#define MB_EXPORT_QUARK 1
+#define MB_EXPORT_SPIN 2
+#define MB_EXPORT_QSPLIT 3
+#define MB_EXPORT_SSPLIT 4
+#define MB_EXPORT_COEF 5
+#define MB_EXPORT_DELTA 6
+#define MB_EXPORT_ALPHA 7
+int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
+                        size_t *bytes);
+
+/* Copies the operation tables to device memory `dev` (caller-owned, at least
+ * counts.device_bytes, 256-byte aligned) and binds the term list to it; the
+ * buffer must stay alive while the term list is used on the device.  A term
+ * list may be bound to one buffer at a time (a later call rebinds it).
+ * Synchronous with respect to the host copy (the host tables may be freed
+ * with the term list afterwards).                                          */
+int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream);
+
+/* One batch of independent (problem, timeslice) units ("lanes").
+ *   batch      B, number of lanes
+ *   V          sink sites per timeslice
+ *   in_dtype   MB_C64 or MB_C128, element type of the propagators
+ *   precision  MB_FP64 or MB_MIXED
+ *   prop_u, prop_d  device, [B][V][n_src][12][12] complex of in_dtype:
+ *              element [b][x][s][row][col] = S(x)[(spin,colour) row at the
+ *              sink; source spin-colour col of source s]; prop_d may equal
+ *              prop_u (isospin limit: one diquark, one block serves both
+ *              species).
+ *   sink_w     device, complex double [n_src][V]: sink function s' at site
+ *              x (Sec. 2, 6); NULL means s(x) = 1 for every sink function.
+ *   scale_exp  device, int32 [B]: the propagators of lane b are read
+ *              multiplied by 2^scale_exp[b] (exact); NULL means 0.          */
+typedef struct {
+    int64_t batch;
+    int64_t V;
+    int in_dtype;
+    int precision;
+    const void *prop_u;
+    const void *prop_d;
+    const double *sink_w;
+    const int32_t *scale_exp;
+} mb_problem;
+
+/* Device buffer sizes for one batch:
+ *   blocks_bytes     output of mb_make_blocks / input of the contraction
+ *   blocks_ws_bytes  workspace of mb_make_blocks (site-chunk partial sums)
+ *   contract_ws_bytes workspace of mb_contract_correlator (two stages of F) */
+int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
+                       size_t *blocks_bytes, size_t *blocks_ws_bytes,
+                       size_t *contract_ws_bytes);
+
+/* Baryon blocks (Sec. 2; Sec. 6 with one sink function per source index)
+ *   f_B(psi; xi1, xi2, xi3) = sum_x s_{s'(psi)}(x) eps_abc
+ *        (Gamma_1)_{alpha(psi) beta} (Gamma_2)_{gamma delta}
+ *        S_q1[(beta,a), xi1] S_q2[(gamma,b), xi2] S_q3[(delta,c), xi3]
+ * for the proton (u,u,d) and neutron (d,u,d), antisymmetrised without
+ * normalisation in the two same-flavour slots (Sec. 4), for every lane.
+ * The sum over sites runs in double precision in both precision modes.
+ * Output layout (precision MB_FP64: complex double, MB_MIXED: complex float):
+ * proton block [psi][block quark index][lane] followed by the neutron block,
+ * lanes padded to a multiple of 64.                                        */
+int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
+                   size_t blocks_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* Correlators from blocks: the recursion of eq. recr_F over the operation
+ * lists, then C(delta; alpha) = sum_z F_-(delta; z) L(alpha; z) / (n_P! n_N!)
+ * (eq. C_final with the sum over sorted index sets), the final sum in double.
+ *   corr_out  device, complex double [B][n_delta][n_alpha]
+ *   exp_out   device, int32 [B] or NULL: 3*A*scale_exp[b], so that the
+ *             correlator of the unscaled propagators is corr_out * 2^-exp_out
+ * The term list must be uploaded.                                           */
+int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p,
+                           const void *blocks, size_t blocks_bytes, double *corr_out,
+                           int32_t *exp_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBCONTRACT_H */

@@ -1,0 +1,186 @@
+"""ctypes binding of libmbcontract (include/mbcontract.h).
+
+Argument marshalling only: every step of the method runs in the library (host
+term-list builder, HIP kernels).  PyTorch tensors provide device memory and
+streams.  There is no fallback: a missing library raises at import of the
+first call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmbcontract.so")
+
+MB_OK, MB_EINVAL, MB_EPAULI, MB_EUNSUPPORTED, MB_ENOWORKSPACE, MB_EHIP, MB_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST = 0, 1, 2
+MB_C64, MB_C128 = 0, 1
+MB_FP64, MB_MIXED = 0, 1
+MB_MAX_STAGES = 16
+(MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
+ MB_EXPORT_DELTA, MB_EXPORT_ALPHA) = range(1, 8)
+
+EXPORTED_SYMBOLS = [
+    "mb_build_term_list", "mb_build_term_list_counts_only", "mb_term_list_free",
+    "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
+    "mb_make_blocks", "mb_contract_correlator", "mb_last_error",
+]
+
+
+class MBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmbcontract error {code}: {msg}")
+        self.code = code
+
+
+class mb_nucleus(C.Structure):
+    _fields_ = [("n_P", C.c_int), ("n_N", C.c_int), ("rel", C.c_int), ("n_src", C.c_int),
+                ("path", C.c_int)]
+
+
+class mb_spin_request(C.Structure):
+    _fields_ = [("all_components", C.c_int), ("sink_P", C.c_uint32), ("sink_N", C.c_uint32),
+                ("n_alpha", C.c_int), ("alpha", C.POINTER(C.c_uint32))]
+
+
+class mb_counts(C.Structure):
+    _fields_ = [("n_stages", C.c_int), ("path", C.c_int * MB_MAX_STAGES), ("n_lambda", C.c_int64),
+                ("n_lambda_step", C.c_int64 * MB_MAX_STAGES), ("n_req", C.c_int64 * MB_MAX_STAGES),
+                ("n_quark", C.c_int64 * MB_MAX_STAGES), ("n_spin", C.c_int32 * MB_MAX_STAGES),
+                ("n_L", C.c_int64), ("n_U", C.c_int64), ("n_delta", C.c_int32),
+                ("n_alpha", C.c_int32), ("n_psi", C.c_int32), ("n_xi", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+
+class mb_problem(C.Structure):
+    _fields_ = [("batch", C.c_int64), ("V", C.c_int64), ("in_dtype", C.c_int),
+                ("precision", C.c_int), ("prop_u", C.c_void_p), ("prop_d", C.c_void_p),
+                ("sink_w", C.c_void_p), ("scale_exp", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.mb_build_term_list.argtypes = [C.POINTER(mb_nucleus), C.POINTER(mb_spin_request), C.POINTER(P)]
+        L.mb_build_term_list_counts_only.argtypes = L.mb_build_term_list.argtypes
+        L.mb_term_list_free.argtypes = [P]
+        L.mb_term_list_free.restype = None
+        L.mb_term_list_counts.argtypes = [P, C.POINTER(mb_counts)]
+        L.mb_term_list_export.argtypes = [P, C.c_int, C.c_int, P, C.POINTER(C.c_size_t)]
+        L.mb_term_list_upload.argtypes = [P, P, C.c_size_t, P]
+        L.mb_workspace_query.argtypes = [P, C.POINTER(mb_problem), C.POINTER(C.c_size_t),
+                                         C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.mb_make_blocks.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, C.c_size_t, P]
+        L.mb_contract_correlator.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, P, P,
+                                             C.c_size_t, P]
+        L.mb_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MB_OK:
+        raise MBError(rc, lib().mb_last_error().decode())
+
+
+class TermList:
+    """Owner of an mb_term_list handle."""
+
+    def __init__(self, n_P, n_N, rel, n_src=1, *, all_components=False, sink_P=0, sink_N=0,
+                 alphas=(), path=MB_PATH_AUTO, counts_only=False):
+        nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path)
+        arr = np.ascontiguousarray(np.asarray(alphas, np.uint32).reshape(-1))
+        self._alpha_keep = arr
+        req = mb_spin_request(int(all_components), sink_P, sink_N, len(arr) // 2,
+                              arr.ctypes.data_as(C.POINTER(C.c_uint32)) if len(arr) else None)
+        h = C.c_void_p()
+        fn = lib().mb_build_term_list_counts_only if counts_only else lib().mb_build_term_list
+        _check(fn(C.byref(nuc), C.byref(req), C.byref(h)))
+        self.h = h
+        self.nucleus = dict(n_P=n_P, n_N=n_N, rel=bool(rel), n_src=n_src)
+        self._dev = None
+
+    @classmethod
+    def spin_state(cls, n_P, n_N, rel, n_src, spins, **kw):
+        """Single spin component (Sec. 8): indices listed protons first."""
+        pm = sum(1 << s for s in spins[:n_P])
+        nm = sum(1 << s for s in spins[n_P:n_P + n_N])
+        return cls(n_P, n_N, rel, n_src, sink_P=pm, sink_N=nm, alphas=[(pm, nm)], **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mb_term_list_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def counts(self):
+        c = mb_counts()
+        _check(lib().mb_term_list_counts(self.h, C.byref(c)))
+        n = c.n_stages
+        return dict(n_stages=n, path=list(c.path[:n]), n_lambda=c.n_lambda,
+                    n_lambda_step=list(c.n_lambda_step[:n]), n_req=list(c.n_req[:n]),
+                    n_quark=list(c.n_quark[:n]), n_spin=list(c.n_spin[:n]), n_L=c.n_L, n_U=c.n_U,
+                    n_delta=c.n_delta, n_alpha=c.n_alpha, n_psi=c.n_psi, n_xi=c.n_xi,
+                    device_bytes=c.device_bytes)
+
+    def export(self, what, stage=0, dtype=np.uint32):
+        n = C.c_size_t(0)
+        _check(lib().mb_term_list_export(self.h, what, stage, None, C.byref(n)))
+        buf = np.zeros(max(n.value, 1), np.uint8)
+        _check(lib().mb_term_list_export(self.h, what, stage, buf.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return buf[:n.value].view(dtype)
+
+    def upload(self, torch_device="cuda"):
+        """Allocates the device image (a torch tensor) and uploads the tables."""
+        import torch
+        nbytes = self.counts()["device_bytes"]
+        dev = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch_device)
+        ptr = dev.data_ptr()
+        off = (-ptr) % 256
+        stream = torch.cuda.current_stream().cuda_stream
+        _check(lib().mb_term_list_upload(self.h, C.c_void_p(ptr + off), nbytes, C.c_void_p(stream)))
+        self._dev = dev
+        return self
+
+
+def problem(batch, V, props_u, props_d, precision, sink_w=None, scale_exp=None):
+    """mb_problem for torch device tensors (props complex64 / complex128)."""
+    import torch
+    in_dtype = MB_C128 if props_u.dtype == torch.complex128 else MB_C64
+    return mb_problem(batch, V, in_dtype, precision, props_u.data_ptr(), props_d.data_ptr(),
+                      sink_w.data_ptr() if sink_w is not None else None,
+                      scale_exp.data_ptr() if scale_exp is not None else None)
+
+
+def workspace_query(tl: TermList, p: mb_problem):
+    a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    _check(lib().mb_workspace_query(tl.h, C.byref(p), C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def make_blocks(tl: TermList, p: mb_problem, blocks, ws, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().mb_make_blocks(tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()), blocks.numel() * blocks.element_size(),
+                                C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))
+
+
+def contract_correlator(tl: TermList, p: mb_problem, blocks, corr, exp_out, ws, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().mb_contract_correlator(
+        tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()), blocks.numel() * blocks.element_size(),
+        C.c_void_p(corr.data_ptr()), C.c_void_p(exp_out.data_ptr()) if exp_out is not None else None,
+        C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))

@@ -1,0 +1,73 @@
+"""Builds libmbcontract.so (HIP, gfx950) in-tree, and synth/libsynth.so."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libmbcontract.so")
+SYNTH_LIB = os.path.join(ROOT, "synth", "libsynth.so")
+BUILD_DIR = os.path.join(ROOT, "_build")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "--offload-arch=gfx950"
+# packed FP32 instructions stay off; hipcc forms none by itself with this
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("build failed: " + " ".join(cmd))
+    return r
+
+
+def _compile(src, obj, kind):
+    if kind == "host":   # plain C++ (no HIP): the host compiler
+        cmd = ["g++"] + COMMON + ["-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, ARCH] + COMMON + (DEVICE_FLAGS if kind == "hip" else []) + ["-c", src, "-o", obj]
+    _run(cmd)
+
+
+def build_library(verbose: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for name, kind in [("termlist.cpp", "host"), ("capi.cpp", "hipapi"), ("blocks.hip", "hip"),
+                       ("contract.hip", "hip")]:
+        obj = os.path.join(BUILD_DIR, name + ".o")
+        _compile(os.path.join(CSRC, name), obj, kind)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+def build_synth(verbose: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    obj = os.path.join(BUILD_DIR, "synth.hip.o")
+    _run([HIPCC, ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off"] + DEVICE_FLAGS +
+         ["-c", os.path.join(ROOT, "synth", "synth.hip"), "-o", obj])
+    tmp = SYNTH_LIB + ".tmp"
+    _run([HIPCC, ARCH, "-shared", "-fPIC", "-o", tmp, obj])
+    os.replace(tmp, SYNTH_LIB)
+    if verbose:
+        print("built", SYNTH_LIB)
+    return SYNTH_LIB
+
+
+def build_all(verbose: bool = False):
+    build_library(verbose)
+    build_synth(verbose)
+
+
+if __name__ == "__main__":
+    build_all(verbose=True)

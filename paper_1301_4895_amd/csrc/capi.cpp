@@ -1,0 +1,266 @@
+// C ABI of libmbcontract: device image of the term list, workspace sizes and
+// the two device calls (blocks, contraction).  Arguments are validated on the
+// host before anything is launched.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace mb;
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+#define HIP_CHECK(expr)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) return fail(MB_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t lanes_padded(int64_t B) { return (B + 63) / 64 * 64; }
+
+// Blocks are multiplied by 2^-norm_exp (exact) so that products of many
+// blocks stay well inside float range; the final sum undoes it.
+int block_norm_exp(int64_t V) {
+  int e = 0;
+  while ((int64_t(1) << (2 * (e + 1))) <= V) e++;
+  return e;
+}
+
+int nchunks_for(int64_t B, int64_t V) {
+  int64_t want = std::max<int64_t>(1, (4096 + B - 1) / B);
+  int64_t maxc = std::max<int64_t>(1, (V + 63) / 64);
+  return int(std::min(want, maxc));
+}
+
+int check_problem(const mb_term_list *tl, const mb_problem *p) {
+  if (!tl || !p) return fail(MB_EINVAL, "null argument");
+  if (p->batch < 1 || p->V < 1) return fail(MB_EINVAL, "batch and V must be positive");
+  if (p->batch > (int64_t(1) << 26)) return fail(MB_EUNSUPPORTED, "batch too large");
+  if (p->in_dtype != MB_C64 && p->in_dtype != MB_C128) return fail(MB_EINVAL, "bad in_dtype");
+  if (p->precision != MB_FP64 && p->precision != MB_MIXED) return fail(MB_EINVAL, "bad precision");
+  if (tl->counts_only) return fail(MB_EINVAL, "counts-only term list");
+  if (tl->nxi > 12) return fail(MB_EUNSUPPORTED, "blocks support at most 12 quark indices");
+  return MB_OK;
+}
+
+size_t elem_bytes(const mb_problem *p) { return p->precision == MB_MIXED ? 8 : 16; }
+
+size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+  const int64_t nyq = int64_t(tl->nxi) * (tl->nxi - 1) / 2 * tl->nxi;
+  return size_t(2 * tl->npsi * nyq) * size_t(lanes_padded(p->batch)) * elem_bytes(p);
+}
+
+size_t blocks_ws_of(const mb_term_list *tl, const mb_problem *p) {
+  const bool sym = p->prop_u == p->prop_d;
+  const int npair = sym ? tl->nxi * (tl->nxi + 1) / 2 : tl->nxi * tl->nxi;
+  const size_t per = size_t(nchunks_for(p->batch, p->V)) * tl->npsi * tl->nxi * npair * 16;
+  return al256(per * size_t(p->batch)) * (sym ? 1 : 2);
+}
+
+void stage_buffer_sizes(const mb_term_list *tl, const mb_problem *p, size_t *even, size_t *odd) {
+  size_t e = 0, o = 0;
+  for (int s = 0; s < tl->nstages; s++) {
+    size_t n = size_t(tl->st[s].nreq()) * size_t(lanes_padded(p->batch)) * elem_bytes(p);
+    if (s % 2 == 0) e = std::max(e, n);
+    else o = std::max(o, n);
+  }
+  *even = al256(e);
+  *odd = al256(o);
+}
+
+void psi_positions(uint32_t base, int *out) {
+  int k = 0;
+  for (int i = 0; i < 32 && k < 8; i++)
+    if (base >> i & 1) out[k++] = i;
+  for (; k < 8; k++) out[k] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream) {
+  if (!tl || !dev) return fail(MB_EINVAL, "null argument");
+  if (tl->counts_only) return fail(MB_EINVAL, "counts-only term list has no device image");
+  const size_t need = tl->image_bytes();
+  if (bytes < need) return fail(MB_ENOWORKSPACE, "device buffer smaller than device_bytes");
+  if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(MB_EINVAL, "device buffer not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(dev);
+  size_t o = 0;
+  tl->off_qsplit.assign(tl->nstages, 0);
+  for (int st = 1; st < tl->nstages; st++) {
+    tl->off_qsplit[st] = o;
+    const auto &v = tl->st[st].qsplit;
+    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    o += al256(v.size() * 4);
+  }
+  tl->off_first = o;
+  {
+    const auto &v = tl->st[0].first;
+    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    o += al256(v.size() * 4);
+  }
+  tl->off_crow = o;
+  HIP_CHECK(hipMemcpyAsync(base + o, tl->crow.data(), tl->crow.size() * 8, hipMemcpyHostToDevice, s));
+  o += al256(tl->crow.size() * 8);
+  tl->off_ccol = o;
+  std::vector<int32_t> col(tl->ccol.begin(), tl->ccol.end());
+  std::vector<double> val(tl->cval.begin(), tl->cval.end());
+  if (!col.empty()) HIP_CHECK(hipMemcpyAsync(base + o, col.data(), col.size() * 4, hipMemcpyHostToDevice, s));
+  o += al256(col.size() * 4);
+  tl->off_cval = o;
+  if (!val.empty()) HIP_CHECK(hipMemcpyAsync(base + o, val.data(), val.size() * 8, hipMemcpyHostToDevice, s));
+  o += al256(val.size() * 8);
+  HIP_CHECK(hipStreamSynchronize(s));
+  tl->dev = dev;
+  tl->dev_bytes = bytes;
+  return MB_OK;
+}
+
+int mb_workspace_query(const mb_term_list *tl, const mb_problem *p, size_t *blocks_bytes,
+                       size_t *blocks_ws_bytes, size_t *contract_ws_bytes) {
+  int rc = check_problem(tl, p);
+  if (rc) return rc;
+  if (blocks_bytes) *blocks_bytes = blocks_bytes_of(tl, p);
+  if (blocks_ws_bytes) *blocks_ws_bytes = blocks_ws_of(tl, p);
+  if (contract_ws_bytes) {
+    size_t e, o;
+    stage_buffer_sizes(tl, p, &e, &o);
+    *contract_ws_bytes = e + o;
+  }
+  return MB_OK;
+}
+
+int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks, size_t blocks_bytes,
+                   void *ws, size_t ws_bytes, void *stream) {
+  int rc = check_problem(tl, p);
+  if (rc) return rc;
+  if (!p->prop_u || !p->prop_d || !blocks || !ws) return fail(MB_EINVAL, "null device buffer");
+  if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
+  if (ws_bytes < blocks_ws_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool sym = p->prop_u == p->prop_d;
+  const bool mixed = p->precision == MB_MIXED;
+  BlocksArgs a{};
+  a.prop_u = p->prop_u;
+  a.prop_d = p->prop_d;
+  a.sink_w = p->sink_w;
+  a.scale_exp = p->scale_exp;
+  a.B = p->batch;
+  a.V = p->V;
+  a.nsrc = tl->nsrc;
+  a.D = tl->D;
+  a.nchunk = nchunks_for(p->batch, p->V);
+  a.sites_per_chunk = (p->V + a.nchunk - 1) / a.nchunk;
+  a.in_c128 = p->in_dtype == MB_C128;
+  const size_t half = blocks_ws_of(tl, p) / (sym ? 1 : 2);
+  double *partP = static_cast<double *>(ws);
+  double *partN = sym ? partP : reinterpret_cast<double *>(static_cast<char *>(ws) + half);
+  a.prop_q1 = p->prop_u;
+  a.partial = partP;
+  HIP_CHECK(launch_blocks_partial(a, mixed, sym, s));
+  if (!sym) {
+    a.prop_q1 = p->prop_d;
+    a.partial = partN;
+    HIP_CHECK(launch_blocks_partial(a, mixed, sym, s));
+  }
+  FinishArgs f{};
+  f.partP = partP;
+  f.partN = partN;
+  f.blocks = blocks;
+  f.B = p->batch;
+  f.Bp = lanes_padded(p->batch);
+  f.nsrc = tl->nsrc;
+  f.D = tl->D;
+  f.nchunk = a.nchunk;
+  f.sym = sym;
+  f.norm_exp = block_norm_exp(p->V);
+  HIP_CHECK(launch_blocks_finish(f, mixed, s));
+  return MB_OK;
+}
+
+int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p, const void *blocks,
+                           size_t blocks_bytes, double *corr_out, int32_t *exp_out, void *ws,
+                           size_t ws_bytes, void *stream) {
+  int rc = check_problem(tl, p);
+  if (rc) return rc;
+  if (!tl->dev) return fail(MB_EINVAL, "term list not uploaded");
+  if (!blocks || !corr_out || !ws) return fail(MB_EINVAL, "null device buffer");
+  if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
+  size_t ev, od;
+  stage_buffer_sizes(tl, p, &ev, &od);
+  if (ws_bytes < ev + od) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool mixed = p->precision == MB_MIXED;
+  const int64_t Bp = lanes_padded(p->batch);
+  const int nxi = tl->nxi;
+  const int nyq = nxi * (nxi - 1) / 2 * nxi;
+  const size_t eb = elem_bytes(p);
+  const char *blk = static_cast<const char *>(blocks);
+  const void *fblk[2] = {blk, blk + size_t(tl->npsi) * nyq * Bp * eb};  // proton, neutron
+  char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
+  const char *img = static_cast<const char *>(tl->dev);
+
+  // stage 0: the first baryon's block restricted to the required components
+  {
+    const Stage &S0 = tl->st[0];
+    Stage0Args a{};
+    a.fblk = fblk[S0.type];
+    a.Fout = buf[0];
+    a.first = reinterpret_cast<const uint32_t *>(img + tl->off_first);
+    a.nq = int64_t(S0.quark.size());
+    a.Bp = Bp;
+    a.nyq = nyq;
+    a.ns = int(S0.nspin());
+    psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+    if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
+  }
+  for (int st = 1; st < tl->nstages; st++) {
+    const Stage &S = tl->st[st], &Pv = tl->st[st - 1];
+    StageArgs a{};
+    a.Fin = buf[(st - 1) % 2];
+    a.Fout = buf[st % 2];
+    a.fblk = fblk[S.type];
+    a.qsplit = reinterpret_cast<const uint32_t *>(img + tl->off_qsplit[st]);
+    a.nq_out = int64_t(S.quark.size());
+    a.Bp = Bp;
+    a.Sq = S.Sq;
+    a.nyq = nyq;
+    a.act_is_P = S.type == PROTON;
+    a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
+    a.K = S.type == PROTON ? Pv.kP : Pv.kN;
+    a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
+    psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+    if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
+    if (a.nq_out > 0) HIP_CHECK(launch_stage(a, mixed, s));
+  }
+  {
+    const Stage &SN = tl->st[tl->nstages - 1];
+    FinalArgs a{};
+    a.F = buf[(tl->nstages - 1) % 2];
+    a.crow = reinterpret_cast<const int64_t *>(img + tl->off_crow);
+    a.ccol = reinterpret_cast<const int32_t *>(img + tl->off_ccol);
+    a.cval = reinterpret_cast<const double *>(img + tl->off_cval);
+    a.corr = corr_out;
+    a.exp_out = exp_out;
+    a.scale_exp = p->scale_exp;
+    a.B = p->batch;
+    a.Bp = Bp;
+    a.n_delta = int(SN.nspin());
+    a.n_alpha = int(tl->alphas.size());
+    a.A = tl->A;
+    a.norm = std::ldexp(1.0, tl->A * block_norm_exp(p->V)) /
+             (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
+    HIP_CHECK(launch_final(a, mixed, s));
+  }
+  return MB_OK;
+}
+
+}  // extern "C"

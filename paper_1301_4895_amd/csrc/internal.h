@@ -1,0 +1,73 @@
+// Internal structures of libmbcontract shared by the host builder, the C ABI
+// and the kernel launchers.  Not part of the public interface.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mbcontract.h"
+
+namespace mb {
+
+// Quark part of a component: (u index set, d index set) as bit masks,
+// packed as (u << 32) | d so that sorting the packed value sorts by (u, d).
+inline uint64_t qkey(uint32_t u, uint32_t d) { return (uint64_t(u) << 32) | d; }
+inline uint32_t qkey_u(uint64_t k) { return uint32_t(k >> 32); }
+inline uint32_t qkey_d(uint64_t k) { return uint32_t(k); }
+
+enum { PROTON = 0, NEUTRON = 1 };
+
+// One stage of the recursion: the components holding the first s+1 baryons
+// of the path.  Required components are (spin part) x (quark part); the spin
+// parts are every kP-subset of the sink proton base set times every
+// kN-subset of the neutron base set, ordered (proton rank, neutron rank)
+// with subsets ranked by mask value.
+struct Stage {
+  int type = 0;                  // species of the baryon added to reach this stage
+  int kP = 0, kN = 0, ku = 0, kd = 0;
+  int nPsets = 0, nNsets = 0;    // C(|SP|, kP), C(|SN|, kN)
+  std::vector<uint64_t> quark;   // sorted quark parts
+  int Sq = 0;                    // quark splits per output quark part (s >= 1)
+  std::vector<uint32_t> qsplit;  // [nq][Sq][2]: x index, y block index | sign<<31
+  std::vector<uint32_t> first;   // stage 0: block quark index of every quark part
+  int64_t n_lambda = 0;
+  int64_t nspin() const { return int64_t(nPsets) * nNsets; }
+  int64_t nreq() const { return nspin() * int64_t(quark.size()); }
+};
+
+}  // namespace mb
+
+struct mb_term_list {
+  mb_nucleus nuc{};
+  int D = 0, nsrc = 0, npsi = 0, nxi = 0, A = 0;
+  int nstages = 0;
+  int path[MB_MAX_STAGES] = {};
+  uint32_t SP = 0, SN = 0;                      // sink base sets
+  std::vector<std::array<uint32_t, 2>> alphas;   // requested source sets
+  std::vector<mb::Stage> st;
+  // final coefficients c_alpha(q) = L(alpha; q) on sorted sets, CSR over alpha
+  std::vector<int64_t> crow, ccol, cval;
+  int64_t nL = 0, nU = 0;
+  bool counts_only = false;
+  // device image
+  void *dev = nullptr;
+  size_t dev_bytes = 0;
+  std::vector<size_t> off_qsplit;  // per stage (s >= 1)
+  size_t off_first = 0, off_crow = 0, off_ccol = 0, off_cval = 0;
+  size_t image_bytes() const;
+};
+
+namespace mb {
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int binom(int n, int k);
+int factorial(int n);
+// rank of a k-subset (mask over positions 0..m-1) among the k-subsets of
+// 0..m-1 ordered by mask value
+int subset_rank(uint32_t posmask, int m);
+// the positions of the bits of `sub` within base set `base`, as a mask
+uint32_t to_positions(uint32_t sub, uint32_t base);
+uint32_t from_positions(uint32_t pos, uint32_t base);
+}  // namespace mb

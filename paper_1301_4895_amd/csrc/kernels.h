@@ -1,0 +1,77 @@
+// Kernel launchers of libmbcontract (implemented in blocks.hip, contract.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mb {
+
+// Site-chunk partial sums of the full block f_{q1}(psi; xi1, (xi2, xi3)) for
+// every lane.  partial layout: [lane][chunk][psi][xi1][pair] complex double,
+// pair = xi3*(xi3+1)/2 + xi2 (xi2 <= xi3) when sym, else xi2*nxi + xi3.
+struct BlocksArgs {
+  const void *prop_q1;   // flavour in slot 1 (u for the proton, d for the neutron)
+  const void *prop_u;    // slot 2
+  const void *prop_d;    // slot 3
+  const double *sink_w;  // [nsrc][V] complex or null
+  const int32_t *scale_exp;  // [B] or null
+  double *partial;
+  int64_t B, V;
+  int nsrc, D, nchunk, in_c128;
+  int64_t sites_per_chunk;
+};
+hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipStream_t s);
+
+// Sums the chunks in double, antisymmetrises the same-flavour slots and
+// writes the block arrays [psi][block quark index][Bp] (float2 or double2),
+// multiplied by 2^-norm_exp.  partN may equal partP (isospin limit).
+struct FinishArgs {
+  const double *partP, *partN;
+  void *blocks;
+  int64_t B, Bp;
+  int nsrc, D, nchunk, sym, norm_exp;
+};
+hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s);
+
+// Stage 0: F0[q][sigma][b] = f_T0[psi(sigma)][first[q]][b].
+struct Stage0Args {
+  const void *fblk;
+  void *Fout;
+  const uint32_t *first;
+  int64_t nq, Bp;
+  int nyq, ns;
+  int psi_of_pos[8];
+};
+hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s);
+
+// One recursion step F^(s) = F^(s-1) . f_T over the factorised operation list.
+struct StageArgs {
+  const void *Fin;
+  void *Fout;
+  const void *fblk;          // block of the added species, [npsi][nyq][Bp]
+  const uint32_t *qsplit;    // [nq_out][Sq][2]
+  int64_t nq_out, Bp;
+  int Sq, nyq, npass;
+  int act_is_P;              // 1: added species is the proton
+  int M, K;                  // active base-set size, active input subset size
+  int psi_of_pos[8];
+};
+hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);
+
+// Final signed sum C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b].
+struct FinalArgs {
+  const void *F;
+  const int64_t *crow;
+  const int32_t *ccol;
+  const double *cval;
+  double *corr;
+  int32_t *exp_out;
+  const int32_t *scale_exp;
+  int64_t B, Bp;
+  int n_delta, n_alpha, A;
+  double norm;
+};
+hipError_t launch_final(const FinalArgs &a, bool mixed, hipStream_t s);
+
+}  // namespace mb

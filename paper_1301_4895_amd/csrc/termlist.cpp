@@ -1,0 +1,624 @@
+// Term list of the recursive multibaryon method (host side, integer exact).
+//
+// Builds, once per nucleus and spin request (Sec. 3-5, 7):
+//   * G of each nucleon type antisymmetrised in its same-flavour slots;
+//   * L on sorted index sets by L^(n+1) = L^(n) . G (eq. recr_L), with the
+//     antisymmetric product of eq. antis_product_2 over the proton-spin,
+//     neutron-spin, u and d index groups;
+//   * the final required components (requested sink sets times every quark
+//     index set with a nonzero L for a requested source set), and backwards
+//     the required components of every stage (Sec. 3, pruning);
+//   * the operation list of every step in factorised form: the split of a
+//     component into (previous component, block component) is a split of
+//     its quark part times a split of its baryon-index part, and the sign of
+//     eq. antis_product_2 is the product of the per-group signs.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace mb {
+
+static thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+int fail(int code, const std::string &m) {
+  g_err = m;
+  return code;
+}
+
+int binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long long r = 1;
+  for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+  return int(r);
+}
+
+int factorial(int n) {
+  int r = 1;
+  for (int i = 2; i <= n; i++) r *= i;
+  return r;
+}
+
+int subset_rank(uint32_t pos, int m) {
+  int rem = __builtin_popcount(pos), r = 0;
+  for (int i = m - 1; i >= 0; i--)
+    if (pos >> i & 1) {
+      r += binom(i, rem);
+      rem--;
+    }
+  return r;
+}
+
+uint32_t to_positions(uint32_t sub, uint32_t base) {
+  uint32_t out = 0;
+  int p = 0;
+  for (int i = 0; i < 32; i++)
+    if (base >> i & 1) {
+      if (sub >> i & 1) out |= 1u << p;
+      p++;
+    }
+  return out;
+}
+
+uint32_t from_positions(uint32_t pos, uint32_t base) {
+  uint32_t out = 0;
+  int p = 0;
+  for (int i = 0; i < 32; i++)
+    if (base >> i & 1) {
+      if (pos >> p & 1) out |= 1u << i;
+      p++;
+    }
+  return out;
+}
+
+// (-1)^(number of pairs i in x, j in y with i > j): the sign of the
+// permutation that sorts the indices of x followed by those of y.
+static inline int split_sign(uint32_t x, uint32_t y) {
+  int s = 0;
+  for (uint32_t t = y; t; t &= t - 1) {
+    int j = __builtin_ctz(t);
+    s += j >= 31 ? 0 : __builtin_popcount(x >> (j + 1));
+  }
+  return (s & 1) ? -1 : 1;
+}
+
+static inline uint32_t pair_rank(int a, int b) { return uint32_t(b * (b - 1) / 2 + a); }
+
+// Block quark index of a block component (see mbcontract.h).
+static inline uint32_t block_qidx(int type, uint32_t yu, uint32_t yd, int nxi) {
+  if (type == PROTON) {
+    int a = __builtin_ctz(yu), b = 31 - __builtin_clz(yu), c = __builtin_ctz(yd);
+    return pair_rank(a, b) * uint32_t(nxi) + uint32_t(c);
+  }
+  int c = __builtin_ctz(yu), a = __builtin_ctz(yd), b = 31 - __builtin_clz(yd);
+  return uint32_t(c) * uint32_t(nxi * (nxi - 1) / 2) + pair_rank(a, b);
+}
+
+// ---------------------------------------------------------------------------
+// Gamma matrices restricted to the active spins (Sec. 7).  On the spins that
+// enter (all four relativistically, the upper two nonrelativistically in the
+// Dirac representation) Gamma_1 is the identity in both cases and Gamma_2 is
+// C gamma_5 = [[0,-1,0,0],[1,0,0,0],[0,0,0,-1],[0,0,1,0]] (C = i g^2 g^0).
+static int cg5(int a, int b) {
+  if ((a == 0 && b == 1) || (a == 2 && b == 3)) return -1;
+  if ((a == 1 && b == 0) || (a == 3 && b == 2)) return 1;
+  return 0;
+}
+
+static int levi(int a, int b, int c) {
+  if (a == b || b == c || a == c) return 0;
+  return ((b - a + 3) % 3 == 1) ? 1 : -1;
+}
+
+struct GEnt {
+  int chi;
+  uint32_t u, d;
+  int64_t c;
+};
+
+// G-tilde(chi; xi1, xi2, xi3) of eq. def_g / eq. G_tilde over active indices.
+static int g_value(int chi, int x1, int x2, int x3, int nsrc) {
+  int s = chi % nsrc, alpha = chi / nsrc;
+  if (x1 % nsrc != s || x2 % nsrc != s || x3 % nsrc != s) return 0;
+  int k1 = x1 / nsrc, k2 = x2 / nsrc, k3 = x3 / nsrc;
+  if (k1 / 3 != alpha) return 0;
+  return cg5(k2 / 3, k3 / 3) * levi(k1 % 3, k2 % 3, k3 % 3);
+}
+
+// Nonzero entries of G antisymmetrised (without normalisation) in the two
+// same-flavour slots: proton slots (u,u,d), neutron slots (d,u,d).
+static std::vector<GEnt> g_antisym(int type, int nsrc, int npsi, int nxi, uint32_t allowed) {
+  std::vector<GEnt> out;
+  for (int chi = 0; chi < npsi; chi++) {
+    if (!(allowed >> chi & 1)) continue;
+    for (int a = 0; a < nxi; a++)
+      for (int b = a + 1; b < nxi; b++)
+        for (int c = 0; c < nxi; c++) {
+          int v;
+          if (type == PROTON)
+            v = g_value(chi, a, b, c, nsrc) - g_value(chi, b, a, c, nsrc);
+          else
+            v = g_value(chi, a, c, b, nsrc) - g_value(chi, b, c, a, nsrc);
+          if (!v) continue;
+          GEnt e;
+          e.chi = chi;
+          e.c = v;
+          if (type == PROTON) {
+            e.u = (1u << a) | (1u << b);
+            e.d = 1u << c;
+          } else {
+            e.u = 1u << c;
+            e.d = (1u << a) | (1u << b);
+          }
+          out.push_back(e);
+        }
+  }
+  return out;
+}
+
+// Component key for L: proton set (8 bits), neutron set (8), u (24), d (24).
+static inline uint64_t lkey(uint32_t p, uint32_t n, uint32_t u, uint32_t d) {
+  return (uint64_t(p) << 56) | (uint64_t(n) << 48) | (uint64_t(u) << 24) | uint64_t(d);
+}
+
+// Open-addressing set of uint64 keys (insert only), for the required sets.
+struct KeySet {
+  std::vector<uint64_t> slot;
+  std::vector<uint8_t> used;
+  size_t n = 0, mask = 0;
+  explicit KeySet(size_t cap = 1024) { reset(cap); }
+  void reset(size_t cap) {
+    size_t c = 64;
+    while (c < 2 * cap) c <<= 1;
+    slot.assign(c, 0);
+    used.assign(c, 0);
+    mask = c - 1;
+    n = 0;
+  }
+  static inline uint64_t mix(uint64_t h) {
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
+    return h;
+  }
+  void insert(uint64_t k) {
+    if (2 * (n + 1) > slot.size()) grow();
+    size_t i = mix(k) & mask;
+    while (used[i]) {
+      if (slot[i] == k) return;
+      i = (i + 1) & mask;
+    }
+    used[i] = 1;
+    slot[i] = k;
+    n++;
+  }
+  void grow() {
+    std::vector<uint64_t> s2;
+    s2.reserve(n);
+    for (size_t i = 0; i < slot.size(); i++)
+      if (used[i]) s2.push_back(slot[i]);
+    reset(2 * slot.size());
+    for (uint64_t k : s2) insert(k);
+  }
+  std::vector<uint64_t> sorted() const {
+    std::vector<uint64_t> v;
+    v.reserve(n);
+    for (size_t i = 0; i < slot.size(); i++)
+      if (used[i]) v.push_back(slot[i]);
+    std::sort(v.begin(), v.end());
+    return v;
+  }
+};
+
+// Enumerates the quark splits of quark part (u, d) for the added species:
+// proton: u pair (colex order of pairs) x d single; neutron: u single x d
+// pair.  f(yu, yd) is called for every split in this canonical order.
+template <class F>
+static inline void for_quark_splits(int type, uint32_t u, uint32_t d, F &&f) {
+  if (type == PROTON) {
+    for (uint32_t tb = u; tb; tb &= tb - 1) {
+      int b = __builtin_ctz(tb);
+      for (uint32_t ta = u & ((1u << b) - 1); ta; ta &= ta - 1) {
+        int a = __builtin_ctz(ta);
+        for (uint32_t tc = d; tc; tc &= tc - 1) f((1u << a) | (1u << b), tc & (~tc + 1));
+      }
+    }
+  } else {
+    for (uint32_t tc = u; tc; tc &= tc - 1)
+      for (uint32_t tb = d; tb; tb &= tb - 1) {
+        int b = __builtin_ctz(tb);
+        for (uint32_t ta = d & ((1u << b) - 1); ta; ta &= ta - 1) {
+          int a = __builtin_ctz(ta);
+          f(tc & (~tc + 1), (1u << a) | (1u << b));
+        }
+      }
+  }
+}
+
+static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_only,
+                 mb_term_list **out) {
+  if (!nuc || !req || !out) return fail(MB_EINVAL, "null argument");
+  *out = nullptr;
+  const int nP = nuc->n_P, nN = nuc->n_N;
+  if (nP < 0 || nN < 0 || nP + nN < 1) return fail(MB_EINVAL, "need at least one baryon");
+  if (nP + nN > MB_MAX_STAGES) return fail(MB_EUNSUPPORTED, "more than 16 baryons");
+  if (nuc->rel != 0 && nuc->rel != 1) return fail(MB_EINVAL, "rel must be 0 or 1");
+  if (nuc->n_src != 1 && nuc->n_src != 2) return fail(MB_EUNSUPPORTED, "n_src must be 1 or 2");
+  if (nuc->path < 0 || nuc->path > 2) return fail(MB_EINVAL, "bad path");
+  const int D = nuc->rel ? 4 : 2, nsrc = nuc->n_src;
+  const int npsi = D * nsrc, nxi = 3 * D * nsrc;
+  const int nu = 2 * nP + nN, nd = nP + 2 * nN;
+  if (nP > npsi || nN > npsi)
+    return fail(MB_EPAULI, "more baryons of one species than baryon indices");
+  if (nu > nxi || nd > nxi) return fail(MB_EPAULI, "more quarks of one flavour than quark indices");
+
+  mb_term_list *tl = new (std::nothrow) mb_term_list();
+  if (!tl) return fail(MB_ENOMEM, "out of host memory");
+  std::unique_ptr<mb_term_list> guard(tl);
+  tl->nuc = *nuc;
+  tl->D = D;
+  tl->nsrc = nsrc;
+  tl->npsi = npsi;
+  tl->nxi = nxi;
+  tl->A = nP + nN;
+  tl->counts_only = counts_only;
+  const int A = tl->A;
+
+  // path (Sec. 7)
+  int first = nuc->path == MB_PATH_PROTONS_FIRST ? PROTON
+              : nuc->path == MB_PATH_NEUTRONS_FIRST ? NEUTRON
+              : (nN >= nP ? NEUTRON : PROTON);
+  if (first == PROTON && nP == 0) first = NEUTRON;
+  if (first == NEUTRON && nN == 0) first = PROTON;
+  {
+    int nf = first == PROTON ? nP : nN;
+    for (int i = 0; i < A; i++) tl->path[i] = i < nf ? first : 1 - first;
+    tl->nstages = A;
+  }
+
+  // spin request
+  const uint32_t all = (1u << npsi) - 1;
+  if (req->all_components) {
+    tl->SP = nP ? all : 0;
+    tl->SN = nN ? all : 0;
+    auto src_sets = [&](int n) {
+      std::vector<uint32_t> v;
+      if (nsrc == 1) {
+        for (uint32_t m = 0; m <= all; m++)
+          if (__builtin_popcount(m) == n) v.push_back(m);
+      } else {
+        int n0 = std::min(n, D), n1 = n - n0;
+        for (uint32_t m0 = 0; m0 < (1u << D); m0++) {
+          if (__builtin_popcount(m0) != n0) continue;
+          for (uint32_t m1 = 0; m1 < (1u << D); m1++) {
+            if (__builtin_popcount(m1) != n1) continue;
+            uint32_t m = 0;
+            for (int a = 0; a < D; a++) {
+              if (m0 >> a & 1) m |= 1u << (nsrc * a + 0);
+              if (m1 >> a & 1) m |= 1u << (nsrc * a + 1);
+            }
+            v.push_back(m);
+          }
+        }
+        std::sort(v.begin(), v.end());
+      }
+      return v;
+    };
+    for (uint32_t p : src_sets(nP))
+      for (uint32_t n : src_sets(nN)) tl->alphas.push_back({p, n});
+  } else {
+    if ((req->sink_P & ~all) || (req->sink_N & ~all))
+      return fail(MB_EINVAL, "sink set has indices beyond D*N_s");
+    if (__builtin_popcount(req->sink_P) < nP || __builtin_popcount(req->sink_N) < nN)
+      return fail(MB_EINVAL, "sink base set smaller than the number of baryons");
+    if (req->n_alpha < 1 || !req->alpha) return fail(MB_EINVAL, "no source sets");
+    tl->SP = req->sink_P;
+    tl->SN = req->sink_N;
+    for (int i = 0; i < req->n_alpha; i++) {
+      uint32_t p = req->alpha[2 * i], n = req->alpha[2 * i + 1];
+      if ((p & ~all) || (n & ~all) || __builtin_popcount(p) != nP || __builtin_popcount(n) != nN)
+        return fail(MB_EINVAL, "source set with wrong indices or size");
+      tl->alphas.push_back({p, n});
+    }
+  }
+  if (nP == 0) tl->SP = 0;
+  if (nN == 0) tl->SN = 0;
+
+  // ---- L by the recursion L^(n+1) = L^(n) . G (eq. recr_L)
+  uint32_t allowP = 0, allowN = 0;
+  for (auto &a : tl->alphas) {
+    allowP |= a[0];
+    allowN |= a[1];
+  }
+  const std::vector<GEnt> gP = g_antisym(PROTON, nsrc, npsi, nxi, allowP);
+  const std::vector<GEnt> gN = g_antisym(NEUTRON, nsrc, npsi, nxi, allowN);
+  auto wanted_spins = [&](uint32_t p, uint32_t n) {
+    for (auto &a : tl->alphas)
+      if (!(p & ~a[0]) && !(n & ~a[1])) return true;
+    return false;
+  };
+  std::unordered_map<uint64_t, int64_t> L, L2;
+  for (const GEnt &g : (tl->path[0] == PROTON ? gP : gN)) {
+    uint32_t p = tl->path[0] == PROTON ? (1u << g.chi) : 0, n = tl->path[0] == PROTON ? 0 : (1u << g.chi);
+    L[lkey(p, n, g.u, g.d)] += g.c;
+  }
+  for (int s = 1; s < A; s++) {
+    const int T = tl->path[s];
+    const std::vector<GEnt> &G = T == PROTON ? gP : gN;
+    L2.clear();
+    L2.reserve(L.size() * 8);
+    for (auto &kv : L) {
+      uint64_t k = kv.first;
+      uint32_t p = uint32_t(k >> 56), n = uint32_t(k >> 48) & 0xff, u = uint32_t(k >> 24) & 0xffffff,
+               d = uint32_t(k) & 0xffffff;
+      for (const GEnt &g : G) {
+        uint32_t sb = 1u << g.chi;
+        uint32_t xs = T == PROTON ? p : n;
+        if ((xs & sb) || (u & g.u) || (d & g.d)) continue;
+        uint32_t p2 = T == PROTON ? (p | sb) : p, n2 = T == PROTON ? n : (n | sb);
+        if (!wanted_spins(p2, n2)) continue;
+        int sg = split_sign(xs, sb) * split_sign(u, g.u) * split_sign(d, g.d);
+        L2[lkey(p2, n2, u | g.u, d | g.d)] += sg * kv.second * g.c;
+      }
+    }
+    L.clear();
+    for (auto &kv : L2)
+      if (kv.second != 0) L.insert(kv);
+  }
+
+  // c_alpha(q) = L^(N)(alpha; q) / (n_P! n_N!): the recursion antisymmetrises
+  // the baryon indices too, which multiplies L on sorted sets by n_P! n_N!.
+  const int64_t norm = int64_t(factorial(nP)) * factorial(nN);
+  std::vector<std::vector<std::pair<uint64_t, int64_t>>> per_alpha(tl->alphas.size());
+  {
+    std::unordered_map<uint64_t, int> aidx;
+    for (size_t i = 0; i < tl->alphas.size(); i++)
+      aidx[(uint64_t(tl->alphas[i][0]) << 32) | tl->alphas[i][1]] = int(i);
+    for (auto &kv : L) {
+      uint64_t k = kv.first;
+      uint32_t p = uint32_t(k >> 56), n = uint32_t(k >> 48) & 0xff, u = uint32_t(k >> 24) & 0xffffff,
+               d = uint32_t(k) & 0xffffff;
+      auto it = aidx.find((uint64_t(p) << 32) | n);
+      if (it == aidx.end()) continue;
+      if (kv.second % norm != 0) return fail(MB_EINVAL, "internal: L not divisible by n_P! n_N!");
+      per_alpha[it->second].push_back({qkey(u, d), kv.second / norm});
+    }
+  }
+  std::vector<uint64_t> U;
+  for (auto &v : per_alpha) {
+    std::sort(v.begin(), v.end());
+    for (auto &e : v) U.push_back(e.first);
+  }
+  std::sort(U.begin(), U.end());
+  U.erase(std::unique(U.begin(), U.end()), U.end());
+  tl->nU = int64_t(U.size());
+  tl->crow.assign(1, 0);
+  for (auto &v : per_alpha) {
+    for (auto &e : v) {
+      tl->ccol.push_back(std::lower_bound(U.begin(), U.end(), e.first) - U.begin());
+      tl->cval.push_back(e.second);
+    }
+    tl->crow.push_back(int64_t(tl->ccol.size()));
+  }
+  tl->nL = int64_t(tl->ccol.size());
+
+  // ---- stages
+  tl->st.resize(A);
+  {
+    int kp = 0, kn = 0;
+    for (int s = 0; s < A; s++) {
+      Stage &S = tl->st[s];
+      S.type = tl->path[s];
+      (S.type == PROTON ? kp : kn)++;
+      S.kP = kp;
+      S.kN = kn;
+      S.ku = 2 * kp + kn;
+      S.kd = kp + 2 * kn;
+      S.nPsets = binom(__builtin_popcount(tl->SP), kp);
+      S.nNsets = binom(__builtin_popcount(tl->SN), kn);
+    }
+  }
+  tl->st[A - 1].quark = U;
+  for (int s = A - 1; s >= 1; s--) {
+    Stage &S = tl->st[s], &P = tl->st[s - 1];
+    const int T = S.type;
+    KeySet X(S.quark.size() * 4 + 16);
+    for (uint64_t q : S.quark) {
+      uint32_t u = qkey_u(q), d = qkey_d(q);
+      for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(u & ~yu, d & ~yd)); });
+    }
+    P.quark = X.sorted();
+    S.Sq = T == PROTON ? binom(S.ku, 2) * S.kd : S.ku * binom(S.kd, 2);
+    const int kT = T == PROTON ? S.kP : S.kN;
+    S.n_lambda = S.nreq() * kT * S.Sq;
+    if (!counts_only) {
+      try {
+        S.qsplit.resize(S.quark.size() * size_t(S.Sq) * 2);
+      } catch (...) {
+        return fail(MB_ENOMEM, "out of host memory for the operation tables");
+      }
+      size_t o = 0;
+      for (uint64_t q : S.quark) {
+        uint32_t u = qkey_u(q), d = qkey_d(q);
+        for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) {
+          uint32_t xu = u & ~yu, xd = d & ~yd;
+          uint64_t xk = qkey(xu, xd);
+          uint32_t xi = uint32_t(std::lower_bound(P.quark.begin(), P.quark.end(), xk) - P.quark.begin());
+          int sg = split_sign(xu, yu) * split_sign(xd, yd);
+          S.qsplit[o++] = xi;
+          S.qsplit[o++] = block_qidx(T, yu, yd, nxi) | (sg < 0 ? 0x80000000u : 0u);
+        });
+      }
+    }
+  }
+  {
+    Stage &S0 = tl->st[0];
+    if (!counts_only) {
+      S0.first.resize(S0.quark.size());
+      for (size_t i = 0; i < S0.quark.size(); i++)
+        S0.first[i] = block_qidx(S0.type, qkey_u(S0.quark[i]), qkey_d(S0.quark[i]), nxi);
+    }
+  }
+  *out = guard.release();
+  set_error("");
+  return MB_OK;
+}
+
+}  // namespace mb
+
+size_t mb_term_list::image_bytes() const {
+  if (counts_only) return 0;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t o = 0;
+  for (int s = 1; s < nstages; s++) o += al(st[s].qsplit.size() * 4);
+  o += al(st[0].first.size() * 4);
+  o += al(crow.size() * 8) + al(ccol.size() * 4) + al(cval.size() * 8);
+  return o + 256;
+}
+
+using namespace mb;
+
+extern "C" {
+
+int mb_build_term_list(const mb_nucleus *nuc, const mb_spin_request *req, mb_term_list **out) {
+  try {
+    return build(nuc, req, false, out);
+  } catch (const std::bad_alloc &) {
+    return fail(MB_ENOMEM, "out of host memory");
+  }
+}
+
+int mb_build_term_list_counts_only(const mb_nucleus *nuc, const mb_spin_request *req,
+                                   mb_term_list **out) {
+  try {
+    return build(nuc, req, true, out);
+  } catch (const std::bad_alloc &) {
+    return fail(MB_ENOMEM, "out of host memory");
+  }
+}
+
+void mb_term_list_free(mb_term_list *tl) { delete tl; }
+
+int mb_term_list_counts(const mb_term_list *tl, mb_counts *c) {
+  if (!tl || !c) return fail(MB_EINVAL, "null argument");
+  std::memset(c, 0, sizeof *c);
+  c->n_stages = tl->nstages;
+  for (int s = 0; s < tl->nstages; s++) {
+    const Stage &S = tl->st[s];
+    c->path[s] = tl->path[s];
+    c->n_lambda_step[s] = S.n_lambda;
+    c->n_lambda += S.n_lambda;
+    c->n_req[s] = S.nreq();
+    c->n_quark[s] = int64_t(S.quark.size());
+    c->n_spin[s] = int32_t(S.nspin());
+  }
+  c->n_L = tl->nL;
+  c->n_U = tl->nU;
+  c->n_delta = int32_t(tl->st[tl->nstages - 1].nspin());
+  c->n_alpha = int32_t(tl->alphas.size());
+  c->n_psi = tl->npsi;
+  c->n_xi = tl->nxi;
+  c->device_bytes = int64_t(tl->image_bytes());
+  return MB_OK;
+}
+
+int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, size_t *bytes) {
+  if (!tl || !bytes) return fail(MB_EINVAL, "null argument");
+  if (stage < 0 || stage >= tl->nstages) return fail(MB_EINVAL, "bad stage");
+  const Stage &S = tl->st[stage];
+  std::vector<uint8_t> tmp;
+  auto put = [&](const void *p, size_t n) {
+    size_t o = tmp.size();
+    tmp.resize(o + n);
+    if (n) std::memcpy(tmp.data() + o, p, n);
+  };
+  switch (what) {
+    case MB_EXPORT_QUARK:
+      for (uint64_t q : S.quark) {
+        uint32_t v[2] = {qkey_u(q), qkey_d(q)};
+        put(v, 8);
+      }
+      break;
+    case MB_EXPORT_SPIN: {
+      int mP = __builtin_popcount(tl->SP), mN = __builtin_popcount(tl->SN);
+      std::vector<uint32_t> ps, ns;
+      for (uint32_t m = 0; m < (1u << mP); m++)
+        if (__builtin_popcount(m) == S.kP) ps.push_back(from_positions(m, tl->SP));
+      for (uint32_t m = 0; m < (1u << mN); m++)
+        if (__builtin_popcount(m) == S.kN) ns.push_back(from_positions(m, tl->SN));
+      for (uint32_t p : ps)
+        for (uint32_t n : ns) {
+          uint32_t v[2] = {p, n};
+          put(v, 8);
+        }
+      break;
+    }
+    case MB_EXPORT_QSPLIT:
+      if (stage < 1 || tl->counts_only) return fail(MB_EINVAL, "no split table for this stage");
+      put(S.qsplit.data(), S.qsplit.size() * 4);
+      break;
+    case MB_EXPORT_SSPLIT: {
+      if (stage < 1) return fail(MB_EINVAL, "no split table for stage 0");
+      const Stage &Pv = tl->st[stage - 1];
+      const int T = S.type;
+      int mP = __builtin_popcount(tl->SP), mN = __builtin_popcount(tl->SN);
+      for (int rp = 0; rp < S.nPsets; rp++)
+        for (int rn = 0; rn < S.nNsets; rn++) {
+          // unrank
+          uint32_t pp = 0, np = 0;
+          int c = 0;
+          for (uint32_t m = 0; m < (1u << mP); m++)
+            if (__builtin_popcount(m) == S.kP && c++ == rp) pp = m;
+          c = 0;
+          for (uint32_t m = 0; m < (1u << mN); m++)
+            if (__builtin_popcount(m) == S.kN && c++ == rn) np = m;
+          uint32_t act = T == PROTON ? pp : np, base = T == PROTON ? tl->SP : tl->SN;
+          for (uint32_t t = act; t; t &= t - 1) {
+            uint32_t bit = t & (~t + 1);
+            uint32_t rest = act & ~bit;
+            int32_t sg = split_sign(rest, bit);
+            int32_t psi = __builtin_ctz(from_positions(bit, base));
+            int32_t idx = T == PROTON ? subset_rank(rest, mP) * Pv.nNsets + rn
+                                      : rp * Pv.nNsets + subset_rank(rest, mN);
+            int32_t v[3] = {idx, psi, sg};
+            put(v, 12);
+          }
+        }
+      break;
+    }
+    case MB_EXPORT_COEF:
+      put(tl->crow.data(), tl->crow.size() * 8);
+      put(tl->ccol.data(), tl->ccol.size() * 8);
+      put(tl->cval.data(), tl->cval.size() * 8);
+      break;
+    case MB_EXPORT_DELTA: {
+      size_t n = 0;
+      mb_term_list_export(tl, MB_EXPORT_SPIN, tl->nstages - 1, nullptr, &n);
+      tmp.resize(n);
+      mb_term_list_export(tl, MB_EXPORT_SPIN, tl->nstages - 1, tmp.data(), &n);
+      break;
+    }
+    case MB_EXPORT_ALPHA:
+      for (auto &a : tl->alphas) put(a.data(), 8);
+      break;
+    default:
+      return fail(MB_EINVAL, "unknown export item");
+  }
+  if (!buf) {
+    *bytes = tmp.size();
+    return MB_OK;
+  }
+  if (*bytes < tmp.size()) return fail(MB_ENOWORKSPACE, "export buffer too small");
+  std::memcpy(buf, tmp.data(), tmp.size());
+  *bytes = tmp.size();
+  return MB_OK;
+}
+
+const char *mb_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

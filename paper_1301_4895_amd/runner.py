@@ -1,0 +1,53 @@
+"""Device buffers (PyTorch) around the library's two device calls."""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+class Runner:
+    """Blocks + contraction for one batch of lanes with fixed shapes.
+
+    props_u / props_d: complex64 or complex128 device tensors
+    [batch][V][n_src][12][12]; sink_w: complex128 [n_src][V] or None;
+    scale_exp: int32 [batch] or None.  Buffers are allocated once here;
+    ``run`` only launches."""
+
+    def __init__(self, tl: B.TermList, props_u, props_d, precision, sink_w=None, scale_exp=None):
+        self.tl = tl
+        if tl._dev is None:
+            tl.upload(props_u.device)
+        self.batch, self.V = props_u.shape[0], props_u.shape[1]
+        self.keep = (props_u, props_d, sink_w, scale_exp)
+        self.p = B.problem(self.batch, self.V, props_u, props_d, precision,
+                           None if sink_w is None else torch.view_as_real(sink_w), scale_exp)
+        nb, nbw, ncw = B.workspace_query(tl, self.p)
+        dev = props_u.device
+        self.blocks = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.bws = torch.empty(max(nbw, 1), dtype=torch.uint8, device=dev)
+        self.cws = torch.empty(max(ncw, 1), dtype=torch.uint8, device=dev)
+        c = tl.counts()
+        self.corr = torch.empty((self.batch, c["n_delta"], c["n_alpha"]), dtype=torch.complex128,
+                                device=dev)
+        self.exp = torch.empty(self.batch, dtype=torch.int32, device=dev)
+
+    def set_props(self, props_u, props_d, scale_exp=None):
+        """Points the problem at other propagators of the same shape."""
+        sink_w = self.keep[2]
+        self.keep = (props_u, props_d, sink_w, scale_exp if scale_exp is not None else self.keep[3])
+        self.p.prop_u = props_u.data_ptr()
+        self.p.prop_d = props_d.data_ptr()
+        if scale_exp is not None:
+            self.p.scale_exp = scale_exp.data_ptr()
+
+    def run_blocks(self, stream=None):
+        B.make_blocks(self.tl, self.p, self.blocks, self.bws, stream)
+
+    def run_contract(self, stream=None):
+        B.contract_correlator(self.tl, self.p, self.blocks, self.corr, self.exp, self.cws, stream)
+
+    def run(self, stream=None):
+        self.run_blocks(stream)
+        self.run_contract(stream)
+        return self.corr, self.exp

@@ -1,0 +1,251 @@
+"""The library's host term list against the oracle (bit-exact) and the paper.
+
+CPU only: builds term lists through the C ABI and compares
+  * L on sorted sets (integer coefficients) per source set,
+  * the required components of every stage,
+  * every operation (output, previous component, block component, sign),
+    expanded from the library's factorised tables,
+with the oracle's direct enumeration; and the operation counts with every
+row of Tables 1-6.
+"""
+import math
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1301_4895_amd import binding as B
+from tests.paper_tables import row_id, rows
+
+
+def lib_termlist(rel, nsrc, nP, nN, spins=None, counts_only=False):
+    if spins is None:
+        return B.TermList(nP, nN, rel, nsrc, all_components=True, counts_only=counts_only)
+    return B.TermList.spin_state(nP, nN, rel, nsrc, spins, counts_only=counts_only)
+
+
+def oracle_request(rel, nsrc, nP, nN, spins):
+    D = 4 if rel else 2
+    if spins is None:
+        return O.all_components_request(nP, nN, D, nsrc)
+    return O.spin_state_request(nP, nN, spins)
+
+
+def _pairs(n):
+    return [(a, b) for b in range(n) for a in range(b)]  # colex: rank b(b-1)/2 + a
+
+
+def expand_ops(tl, stage):
+    """Full operations of a step from the factorised export:
+    (z spin, z quark, x spin, x quark, y spin, y quark, sign) as masks."""
+    c = tl.counts()
+    nxi = c["n_xi"]
+    pr = _pairs(nxi)
+    npair = len(pr)
+    Q = tl.export(B.MB_EXPORT_QUARK, stage).reshape(-1, 2)
+    S = tl.export(B.MB_EXPORT_SPIN, stage).reshape(-1, 2)
+    Qp = tl.export(B.MB_EXPORT_QUARK, stage - 1).reshape(-1, 2)
+    Sp = tl.export(B.MB_EXPORT_SPIN, stage - 1).reshape(-1, 2)
+    qs = tl.export(B.MB_EXPORT_QSPLIT, stage).reshape(len(Q), -1, 2)
+    ss = tl.export(B.MB_EXPORT_SSPLIT, stage, np.int32).reshape(len(S), -1, 3)
+    added = c["path"][stage]
+    yidx = (qs[:, :, 1] & 0x7FFFFFFF).astype(np.int64)
+    qsign = np.where(qs[:, :, 1] >> 31, -1, 1)
+    if added == 0:
+        pair = yidx // nxi
+        yu = np.array([(1 << a) | (1 << b) for a, b in pr], np.int64)[pair]
+        yd = (1 << (yidx % nxi)).astype(np.int64)
+    else:
+        pair = yidx % npair
+        yu = (1 << (yidx // npair)).astype(np.int64)
+        yd = np.array([(1 << a) | (1 << b) for a, b in pr], np.int64)[pair]
+    out = []
+    nq, sq = qs.shape[:2]
+    ns, k = ss.shape[:2]
+    # broadcast over (output quark, quark split, output spin, spin split)
+    zq = np.broadcast_to(np.arange(nq)[:, None, None, None], (nq, sq, ns, k))
+    zs = np.broadcast_to(np.arange(ns)[None, None, :, None], (nq, sq, ns, k))
+    xq = np.broadcast_to(qs[:, :, 0][:, :, None, None], (nq, sq, ns, k))
+    xs = np.broadcast_to(ss[:, :, 0][None, None, :, :], (nq, sq, ns, k))
+    ypsi = np.broadcast_to(ss[:, :, 1][None, None, :, :], (nq, sq, ns, k))
+    sgn = qsign[:, :, None, None] * ss[:, :, 2][None, None, :, :]
+    yum = np.broadcast_to(yu[:, :, None, None], (nq, sq, ns, k))
+    ydm = np.broadcast_to(yd[:, :, None, None], (nq, sq, ns, k))
+    ysp = (1 << ypsi.astype(np.int64))
+    out = dict(
+        z=(S[zs.ravel()], Q[zq.ravel()]),
+        x=(Sp[xs.ravel()], Qp[xq.ravel()]),
+        y=(ysp.ravel(), yum.ravel(), ydm.ravel()),
+        sign=np.broadcast_to(sgn, (nq, sq, ns, k)).ravel())
+    return out
+
+
+def _key(sp, q):
+    return ((sp[:, 0].astype(np.uint64) << np.uint64(56)) | (sp[:, 1].astype(np.uint64) << np.uint64(48)) |
+            (q[:, 0].astype(np.uint64) << np.uint64(24)) | q[:, 1].astype(np.uint64))
+
+
+CASES = [
+    (False, 1, 1, 1, None), (False, 1, 0, 2, None), (False, 1, 1, 2, None), (False, 1, 2, 2, None),
+    (False, 1, 2, 1, None), (False, 1, 2, 2, (0, 1, 0, 1)), (False, 1, 1, 2, (1, 0, 1)),
+    (True, 1, 1, 1, None), (True, 1, 0, 2, (0, 1)), (True, 1, 1, 1, (1, 0)), (True, 1, 1, 2, (0, 0, 1)),
+    (True, 1, 0, 3, (0, 1, 3)), (True, 1, 1, 0, None), (False, 1, 0, 1, None),
+    (False, 2, 1, 1, None), (False, 2, 1, 2, None), (False, 2, 2, 2, (0, 2, 0, 2)),
+    (False, 2, 0, 3, (0, 2, 3)), (False, 2, 1, 2, (2, 0, 2)), (False, 2, 2, 2, None),
+]
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins", CASES)
+def test_term_list_bit_exact_against_oracle(rel, nsrc, nP, nN, spins):
+    tl = lib_termlist(rel, nsrc, nP, nN, spins)
+    c = tl.counts()
+    ref = O.term_list(rel, nsrc, nP, nN, oracle_request(rel, nsrc, nP, nN, spins), with_ops=True)
+    assert c["path"] == ref["path"]
+    # L on sorted sets, per source set (the coefficients of the final sum)
+    alphas = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+    assert sorted(map(tuple, alphas.tolist())) == sorted(ref["L"].keys())
+    coef = tl.export(B.MB_EXPORT_COEF, dtype=np.int64)
+    na = len(alphas)
+    row = coef[:na + 1]
+    col = coef[na + 1:na + 1 + row[-1]]
+    val = coef[na + 1 + row[-1]:]
+    Qf = tl.export(B.MB_EXPORT_QUARK, c["n_stages"] - 1).reshape(-1, 2)
+    for i, a in enumerate(map(tuple, alphas.tolist())):
+        got = {(int(Qf[q, 0]), int(Qf[q, 1])): int(v) for q, v in zip(col[row[i]:row[i + 1]], val[row[i]:row[i + 1]])}
+        assert got == ref["L"][a]
+    assert c["n_U"] == len(ref["U"])
+    # required components of every stage
+    for s in range(c["n_stages"]):
+        S = tl.export(B.MB_EXPORT_SPIN, s).reshape(-1, 2)
+        Q = tl.export(B.MB_EXPORT_QUARK, s).reshape(-1, 2)
+        lib_keys = np.sort(_key(np.repeat(S, len(Q), 0), np.tile(Q, (len(S), 1))))
+        r = ref["req"][s]
+        ora_keys = np.sort(_key(r[:, :2], r[:, 2:]))
+        assert np.array_equal(lib_keys, ora_keys), f"stage {s}"
+    # every operation with its sign
+    for s in range(1, c["n_stages"]):
+        e = expand_ops(tl, s)
+        zk = _key(*e["z"])
+        xk = _key(*e["x"])
+        added = c["path"][s]
+        ysp = e["y"][0].astype(np.uint64)
+        yk = ((ysp << np.uint64(56 if added == 0 else 48)) |
+              (e["y"][1].astype(np.uint64) << np.uint64(24)) | e["y"][2].astype(np.uint64))
+        lib_ops = np.stack([zk, xk, yk, e["sign"].astype(np.int64).astype(np.uint64)], 1)
+        ops = ref["ops"][s - 1]
+        zr, xr = ref["req"][s][ops[:, 0]], ref["req"][s - 1][ops[:, 1]]
+        ysh = np.uint64(56 if added == 0 else 48)
+        yk2 = ((ops[:, 2].astype(np.uint64) << ysh) | (ops[:, 3].astype(np.uint64) << np.uint64(24)) |
+               ops[:, 4].astype(np.uint64))
+        ora_ops = np.stack([_key(zr[:, :2], zr[:, 2:]), _key(xr[:, :2], xr[:, 2:]), yk2,
+                            ops[:, 5].astype(np.int64).astype(np.uint64)], 1)
+        a1 = lib_ops[np.lexsort(lib_ops.T[::-1])]
+        a2 = ora_ops[np.lexsort(ora_ops.T[::-1])]
+        assert a1.shape == a2.shape and np.array_equal(a1, a2), f"step {s}"
+    assert c["n_lambda"] == ref["n_lambda"]
+
+
+_ROWS = rows()
+_HEAVY = {"T1-13-all", "T1-14-all", "T1-23-all", "T1-24-all", "T1-33-all", "T1-34-all",
+          "T3-33-all", "T3-34-all", "T3-24-all", "T3-14-all"}
+
+
+@pytest.mark.parametrize("r", [pytest.param(r, id=row_id(r),
+                                            marks=pytest.mark.slow if row_id(r) in _HEAVY else ())
+                               for r in _ROWS])
+def test_library_counts_match_paper(r):
+    tl = lib_termlist(r["rel"], r["nsrc"], r["nP"], r["nN"], r["spins"], counts_only=True)
+    c = tl.counts()
+    assert c["n_lambda"] == r["n_lambda"]
+    if r["n_L"] is not None:
+        assert c["n_L"] == r["n_L"]
+    # every step's count is its required components times the splits per component
+    for s in range(1, c["n_stages"]):
+        kP = sum(1 for t in c["path"][:s + 1] if t == 0)
+        kN = s + 1 - kP
+        nu, nd = 2 * kP + kN, kP + 2 * kN
+        if c["path"][s] == 0:
+            per = kP * math.comb(nu, 2) * nd
+        else:
+            per = kN * nu * math.comb(nd, 2)
+        assert c["n_lambda_step"][s] == c["n_req"][s] * per
+
+
+def test_headline_term_lists():
+    # 4He relativistic, all components (Table 1) and 8Be nonrelativistic with
+    # two sources (Tables 3, 6): the two workloads of the throughput metric
+    c = lib_termlist(True, 1, 2, 2, None).counts()
+    assert c["n_lambda"] == 531321120 and c["n_U"] == 50790 and c["n_delta"] == 36 and c["n_alpha"] == 36
+    assert c["n_req"] == [3168, 191880, 6586560, 1828440]
+    c = lib_termlist(False, 2, 4, 4, (0, 1, 2, 3, 0, 1, 2, 3)).counts()
+    assert c["n_lambda"] == 448496928 and c["n_U"] == 1 and c["n_L"] == 1
+    for s, n in enumerate(c["n_req"]):
+        kP = sum(1 for t in c["path"][:s + 1] if t == 0)
+        assert n == O.bound_P(2, 2, kP, s + 1 - kP)
+
+
+def test_path_rule():
+    # Sec. 7: the more numerous species first; neutrons first on a tie
+    assert lib_termlist(False, 1, 2, 1, None).counts()["path"] == [0, 0, 1]
+    assert lib_termlist(False, 1, 1, 2, None).counts()["path"] == [1, 1, 0]
+    assert lib_termlist(False, 1, 1, 1, None).counts()["path"] == [1, 0]
+    # 3He (2,1) NR all components: PPN gives the mirror of Table 2's (1,2) row
+    assert lib_termlist(False, 1, 2, 1, None).counts()["n_lambda"] == 6048
+    tl = B.TermList(2, 1, False, 1, all_components=True, path=B.MB_PATH_NEUTRONS_FIRST, counts_only=True)
+    assert tl.counts()["n_lambda"] == 15480
+
+
+def test_error_codes():
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 3, False, 1, all_components=True)   # 3 neutrons, 2 spin indices
+    assert e.value.code == B.MB_EPAULI
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 5, True, 1, all_components=True)
+    assert e.value.code == B.MB_EPAULI
+    with pytest.raises(B.MBError) as e:
+        B.TermList(1, 1, False, 3, all_components=True)
+    assert e.value.code == B.MB_EUNSUPPORTED
+    with pytest.raises(B.MBError) as e:
+        B.TermList(1, 1, False, 1, sink_P=1, sink_N=1, alphas=[(3, 1)])  # wrong popcount
+    assert e.value.code == B.MB_EINVAL
+    with pytest.raises(B.MBError) as e:
+        B.TermList(1, 1, False, 1, sink_P=4, sink_N=1, alphas=[(1, 1)])  # index beyond D
+    assert e.value.code == B.MB_EINVAL
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 0, False, 1, all_components=True)
+    assert e.value.code == B.MB_EINVAL
+    L = B.lib()
+    import ctypes as C
+    h = C.c_void_p()
+    assert L.mb_build_term_list(None, None, C.byref(h)) == B.MB_EINVAL
+    assert b"null" in L.mb_last_error()
+
+
+def test_device_calls_validate_before_launch():
+    """Bad arguments are rejected on the host without touching a GPU."""
+    import ctypes as C
+    tl = lib_termlist(False, 1, 1, 1, None)
+    L = B.lib()
+    p = B.mb_problem(8, 64, 7, B.MB_FP64, 1, 1, None, None)      # bad dtype
+    assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, C.c_void_p(1), 1 << 40, None) == B.MB_EINVAL
+    p = B.mb_problem(0, 64, B.MB_C64, B.MB_FP64, 1, 1, None, None)  # empty batch
+    assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, C.c_void_p(1), 1 << 40, None) == B.MB_EINVAL
+    p = B.mb_problem(8, 64, B.MB_C64, B.MB_FP64, 1, 1, None, None)
+    a, b, w = B.workspace_query(tl, p)
+    assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), a - 1, C.c_void_p(1), b, None) == B.MB_ENOWORKSPACE
+    # not uploaded
+    assert L.mb_contract_correlator(tl.h, C.byref(p), C.c_void_p(1), a, C.c_void_p(1), None,
+                                    C.c_void_p(1), w, None) == B.MB_EINVAL
+    tc = lib_termlist(False, 1, 1, 1, None, counts_only=True)
+    assert L.mb_workspace_query(tc.h, C.byref(p), None, None, None) == B.MB_EINVAL
+
+
+def test_library_exports_every_declared_symbol():
+    import os
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "mbcontract.h")).read()
+    declared = set(re.findall(r"\b(mb_[a-z_]+)\s*\(", hdr))
+    assert declared == set(B.EXPORTED_SYMBOLS)
+    L = B.lib()
+    for name in declared:
+        assert hasattr(L, name), name
