@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Throughput of the recursive multibaryon correlator path on one MI355X.
+
+One step = blocks + recursion + final sum for every (problem, timeslice) lane
+of the workload, propagators already resident in HBM.  The metric is
+correlator timeslices per second for the mixed-precision path, with the
+plain FP64 path timed on the same inputs, the relative error between them,
+per-kernel times from HIP events on the launch stream, the roofline of the
+dominant kernel and the oracle timed on a bounded sample on the host.
+
+  python bench.py [--config c3|c4|c2|c1] [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Workloads: synthetic propagators shaped like the paper's (Sec. 7 nuclei).
+CONFIGS = {
+    "c1": dict(workload="p+n NR, all components, L=4 T=8, 1 problem, complex128",
+               nP=1, nN=1, rel=False, nsrc=1, spins=None, L=4, T=8, nprob=1, c128=True),
+    "c2": dict(workload="4He NR (0,1,0,1), L=16 T=32, 8 problems, complex128",
+               nP=2, nN=2, rel=False, nsrc=1, spins=(0, 1, 0, 1), L=16, T=32, nprob=8, c128=True),
+    "c3": dict(workload="4He relativistic, all 36x36 spin components, L=24 T=48, 16 problems, complex64",
+               nP=2, nN=2, rel=True, nsrc=1, spins=None, L=24, T=48, nprob=16, c128=False),
+    "c4": dict(workload="8Be NR, two sources, (0,1,2,3,0,1,2,3), L=32 T=64, 16 problems, complex64",
+               nP=4, nN=4, rel=False, nsrc=2, spins=(0, 1, 2, 3, 0, 1, 2, 3), L=32, T=64, nprob=16,
+               c128=False),
+}
+M_DECAY = 0.5
+VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("blocks.hip", "contract.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1301_4895_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
+    ap.add_argument("--chunk", type=int, default=256, help="lanes per launch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(lanes are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1301_4895_amd import binding as B
+    from paper_1301_4895_amd.runner import Runner
+    from synth.gpu import fill_props
+    from synth.props import momentum_phase
+
+    cfg = CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    V, T, nprob, nsrc = cfg["L"] ** 3, cfg["T"], cfg["nprob"], cfg["nsrc"]
+    lanes = nprob * T
+    t0 = time.time()
+    if cfg["spins"] is None:
+        tl = B.TermList(cfg["nP"], cfg["nN"], cfg["rel"], nsrc, all_components=True)
+    else:
+        tl = B.TermList.spin_state(cfg["nP"], cfg["nN"], cfg["rel"], nsrc, cfg["spins"])
+    tl.upload(dev)
+    counts = tl.counts()
+    t_list = time.time() - t0
+    log(f"[bench] {args.config}: term list {counts['n_lambda']} ops, built+uploaded in {t_list:.1f}s")
+
+    cdt = torch.complex128 if cfg["c128"] else torch.complex64
+    props = torch.empty((lanes, V, nsrc, 12, 12), dtype=cdt, device=dev)
+    chunk_gen = max(1, (1 << 31) // (V * nsrc * 144))
+    for b0 in range(0, lanes, chunk_gen):
+        fill_props(props[b0:b0 + chunk_gen], seed=2013, stream_id=0, V=V, nsrc=nsrc, T=T, first_bt=b0,
+                   m=M_DECAY)
+    kexp = torch.tensor([int(math.floor(M_DECAY * (b % T) / math.log(2.0) + 0.5)) for b in range(lanes)],
+                        dtype=torch.int32, device=dev)
+    sink = None
+    if nsrc == 2:
+        w = np.stack([np.ones(V, np.complex128), momentum_phase(cfg["L"], 1)])
+        sink = torch.from_numpy(w).to(dev)
+    log(f"[bench] propagators {props.numel() * props.element_size() / 1e9:.1f} GB generated")
+
+    chunk = min(args.chunk, lanes)
+    assert lanes % chunk == 0
+    nchunk = lanes // chunk
+    A = cfg["nP"] + cfg["nN"]
+    steps_idx = list(range(A + 1))
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    results = {}
+    outs = {}
+    for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
+        if args.only and prec_name != args.only:
+            continue
+        r = Runner(tl, props[:chunk], props[:chunk], prec, sink, kexp[:chunk])
+        corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
+        ev = {}
+
+        def one_pass(record):
+            for c in range(nchunk):
+                sl = slice(c * chunk, (c + 1) * chunk)
+                r.set_props(props[sl], props[sl], kexp[sl])
+                evs = [torch.cuda.Event(enable_timing=True) for _ in range(A + 3)] if record else None
+                if record:
+                    evs[0].record(stream)
+                B.make_blocks(tl, r.p, r.blocks, r.bws, sh)
+                if record:
+                    evs[1].record(stream)
+                for s in steps_idx:
+                    B.contract_step(tl, r.p, r.blocks, s, r.corr, r.exp, r.cws, sh)
+                    if record:
+                        evs[2 + s].record(stream)
+                corr_all[sl].copy_(r.corr)
+                if record:
+                    ev.setdefault("chunks", []).append(evs)
+
+        for _ in range(args.warmup):
+            one_pass(False)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            one_pass(True)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        # per-kernel times
+        names = ["blocks"] + [f"step{s}" for s in steps_idx]
+        ktime = {n: 0.0 for n in names}
+        for evs in ev["chunks"]:
+            for i, n in enumerate(names):
+                ktime[n] += evs[i].elapsed_time(evs[i + 1])
+        nlaunch = args.steps * nchunk
+        kavg = {n: ktime[n] / nlaunch for n in names}
+        ms_per_step = total_ms / args.steps
+        results[prec_name] = dict(ms_per_step=ms_per_step, value=lanes / (ms_per_step / 1e3),
+                                  kernel_avg_ms=kavg)
+        outs[prec_name] = corr_all.cpu().numpy()
+        log(f"[bench] {prec_name}: {ms_per_step:.2f} ms/step, {lanes / (ms_per_step / 1e3):.1f} timeslices/s, "
+            f"kernels(avg ms/launch of {chunk} lanes): " +
+            ", ".join(f"{n}={kavg[n]:.3f}" for n in names))
+        del r
+        torch.cuda.empty_cache()
+
+    err = None
+    if "mixed" in outs and "fp64" in outs:
+        a, b = outs["mixed"], outs["fp64"]
+        num = np.linalg.norm((a - b).reshape(lanes, -1), axis=1)
+        den = np.linalg.norm(b.reshape(lanes, -1), axis=1)
+        err = float(np.max(num / den))
+        log(f"[bench] max rel err mixed vs fp64 over {lanes} lanes: {err:.3e}")
+
+    main_name = "mixed" if "mixed" in results else "fp64"
+    res = results[main_name]
+    # dominant kernel: the recursion step with the largest time
+    step_names = [f"step{s}" for s in range(1, A)]
+    dom = max(step_names, key=lambda n: res["kernel_avg_ms"][n])
+    s = int(dom[4:])
+    flops = counts["n_lambda_step"][s] * 8.0 * chunk
+    achieved = flops / (res["kernel_avg_ms"][dom] / 1e3) / 1e12
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        key = f"{args.config}:{main_name}:{dom}"
+        if t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {}):
+            traffic = t["bytes_per_launch"][key]
+    roofline = dict(bound="alu", kernel=f"recursion {dom} ({'proton' if counts['path'][s] == 0 else 'neutron'} added)",
+                    achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=traffic,
+                    flops_per_launch=flops, launch_ms=round(res["kernel_avg_ms"][dom], 4))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, args.config)
+
+    line = {
+        "metric": "correlator timeslices/s (4He rel., 8Be NR): mixed vs FP64 GPU, rel err<=1e-6",
+        "value": round(res["value"], 2),
+        "unit": "timeslices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_name == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["workload"], "lanes": lanes, "V": V, "n_lambda": counts["n_lambda"],
+                   "lanes_per_launch": chunk, "precision": main_name},
+        "fp64": ({"value": round(results["fp64"]["value"], 2), "ms_per_step": round(results["fp64"]["ms_per_step"], 3),
+                  "speedup_mixed_over_fp64": round(res["value"] / results["fp64"]["value"], 3)}
+                 if "fp64" in results and main_name == "mixed" else None),
+        "max_rel_err_mixed_vs_fp64": err,
+        "kernel_avg_ms": {k: round(v, 4) for k, v in res["kernel_avg_ms"].items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "term_list_build_s": round(t_list, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(cfg, name):
+    """The oracle on a bounded sample of one timeslice: its brute-force blocks
+    over a slice of the sites and its correlator for one (sink set, source
+    set) pair, scaled to one full timeslice."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from synth import props as SP
+    V = cfg["L"] ** 3
+    D = 4 if cfg["rel"] else 2
+    if cfg["nP"] + cfg["nN"] > 4:
+        return {"value": None, "unit": "timeslices/s", "cores": 1, "kind": "oracle",
+                "sample": "infeasible: the oracle's permutation sum has n_u! n_d! = (12!)^2 terms per "
+                          "component for 8Be; see DESIGN.md"}
+    nsite = min(V, 64 if cfg["rel"] else 512)
+    S = SP.props(2013, 0, cfg["nprob"], cfg["T"], V, cfg["nsrc"], M_DECAY, np.complex128, probs=[0],
+                 ts=[1])[0, 0]
+    t = time.time()
+    fP, fN = O.blocks(cfg["rel"], cfg["nsrc"], S[:nsite], S[:nsite], None, 2.0)
+    t_blocks = (time.time() - t) * V / nsite
+    req = (O.all_components_request(cfg["nP"], cfg["nN"], D, cfg["nsrc"]) if cfg["spins"] is None
+           else O.spin_state_request(cfg["nP"], cfg["nN"], cfg["spins"]))
+    types = [0] * cfg["nP"] + [1] * cfg["nN"]
+    a = req["alphas"][0]
+    d = O.delta_sets(cfg["nP"], cfg["nN"], req)[0]
+    um, dm, cf = O.L_for_alpha(cfg["rel"], cfg["nsrc"], cfg["nP"], cfg["nN"], a)
+    psis = O._bits(d[0]) + O._bits(d[1])
+    t = time.time()
+    O.corr_from_L(types, psis, fP, fN, um, dm, cf)
+    t_pair = time.time() - t
+    # every (delta, alpha) pair costs about N_L(alpha) permutation sums
+    nL_tot = sum(len(O.L_for_alpha(cfg["rel"], cfg["nsrc"], cfg["nP"], cfg["nN"], al)[0]) for al in req["alphas"])
+    n_delta = len(O.delta_sets(cfg["nP"], cfg["nN"], req))
+    t_corr = t_pair * n_delta * nL_tot / max(len(um), 1)
+    per_ts = t_blocks + t_corr
+    return {"value": 1.0 / per_ts, "unit": "timeslices/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one timeslice: oracle blocks on {nsite} of {V} sites scaled by {V / nsite:.0f}; "
+                       f"oracle correlator for one of {n_delta}x{len(req['alphas'])} component pairs "
+                       f"({len(um)} L entries, {t_pair:.2f}s) scaled by total L entries x sink sets"),
+            "seconds_measured": round((t_blocks * nsite / V) + t_pair, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -256,6 +256,16 @@ int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p,
                            const void *blocks, size_t blocks_bytes, double *corr_out,
                            int32_t *exp_out, void *ws, size_t ws_bytes, void *stream);
 
+/* One part of mb_contract_correlator, for timing the parts separately:
+ * step 0 copies the first baryon's block into stage 0, step s in 1..A-1 is
+ * recursion step s (eq. recr_F), step A is the final sum (corr_out, exp_out
+ * as above; ignored for the other steps).  Running steps 0..A in order on
+ * one stream is exactly mb_contract_correlator; the workspace carries the
+ * stages between the calls.                                                 */
+int mb_contract_step(const mb_term_list *tl, const mb_problem *p, const void *blocks,
+                     size_t blocks_bytes, int step, double *corr_out, int32_t *exp_out, void *ws,
+                     size_t ws_bytes, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *mb_last_error(void);
 

@@ -26,7 +26,7 @@ MB_MAX_STAGES = 16
 EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_term_list_free",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
-    "mb_make_blocks", "mb_contract_correlator", "mb_last_error",
+    "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_last_error",
 ]
 
 
@@ -84,6 +84,8 @@ def lib():
         L.mb_make_blocks.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, C.c_size_t, P]
         L.mb_contract_correlator.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, P, P,
                                              C.c_size_t, P]
+        L.mb_contract_step.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, C.c_int, P, P, P,
+                                       C.c_size_t, P]
         L.mb_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -183,4 +185,14 @@ def contract_correlator(tl: TermList, p: mb_problem, blocks, corr, exp_out, ws, 
     _check(lib().mb_contract_correlator(
         tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()), blocks.numel() * blocks.element_size(),
         C.c_void_p(corr.data_ptr()), C.c_void_p(exp_out.data_ptr()) if exp_out is not None else None,
+        C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))
+
+
+def contract_step(tl: TermList, p: mb_problem, blocks, step, corr, exp_out, ws, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().mb_contract_step(
+        tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()), blocks.numel() * blocks.element_size(), step,
+        C.c_void_p(corr.data_ptr()) if corr is not None else None,
+        C.c_void_p(exp_out.data_ptr()) if exp_out is not None else None,
         C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))

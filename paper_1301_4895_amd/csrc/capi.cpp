@@ -186,13 +186,14 @@ int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks, si
   return MB_OK;
 }
 
-int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p, const void *blocks,
-                           size_t blocks_bytes, double *corr_out, int32_t *exp_out, void *ws,
-                           size_t ws_bytes, void *stream) {
+static int contract_steps(const mb_term_list *tl, const mb_problem *p, const void *blocks,
+                          size_t blocks_bytes, double *corr_out, int32_t *exp_out, void *ws,
+                          size_t ws_bytes, void *stream, int first_step, int last_step) {
   int rc = check_problem(tl, p);
   if (rc) return rc;
   if (!tl->dev) return fail(MB_EINVAL, "term list not uploaded");
-  if (!blocks || !corr_out || !ws) return fail(MB_EINVAL, "null device buffer");
+  if (!blocks || !ws) return fail(MB_EINVAL, "null device buffer");
+  if (last_step == tl->nstages && !corr_out) return fail(MB_EINVAL, "null correlator buffer");
   if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
   size_t ev, od;
   stage_buffer_sizes(tl, p, &ev, &od);
@@ -208,59 +209,76 @@ int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p, const vo
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
   const char *img = static_cast<const char *>(tl->dev);
 
-  // stage 0: the first baryon's block restricted to the required components
-  {
-    const Stage &S0 = tl->st[0];
-    Stage0Args a{};
-    a.fblk = fblk[S0.type];
-    a.Fout = buf[0];
-    a.first = reinterpret_cast<const uint32_t *>(img + tl->off_first);
-    a.nq = int64_t(S0.quark.size());
-    a.Bp = Bp;
-    a.nyq = nyq;
-    a.ns = int(S0.nspin());
-    psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
-    if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
-  }
-  for (int st = 1; st < tl->nstages; st++) {
-    const Stage &S = tl->st[st], &Pv = tl->st[st - 1];
-    StageArgs a{};
-    a.Fin = buf[(st - 1) % 2];
-    a.Fout = buf[st % 2];
-    a.fblk = fblk[S.type];
-    a.qsplit = reinterpret_cast<const uint32_t *>(img + tl->off_qsplit[st]);
-    a.nq_out = int64_t(S.quark.size());
-    a.Bp = Bp;
-    a.Sq = S.Sq;
-    a.nyq = nyq;
-    a.act_is_P = S.type == PROTON;
-    a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
-    a.K = S.type == PROTON ? Pv.kP : Pv.kN;
-    a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
-    psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
-    if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
-    if (a.nq_out > 0) HIP_CHECK(launch_stage(a, mixed, s));
-  }
-  {
-    const Stage &SN = tl->st[tl->nstages - 1];
-    FinalArgs a{};
-    a.F = buf[(tl->nstages - 1) % 2];
-    a.crow = reinterpret_cast<const int64_t *>(img + tl->off_crow);
-    a.ccol = reinterpret_cast<const int32_t *>(img + tl->off_ccol);
-    a.cval = reinterpret_cast<const double *>(img + tl->off_cval);
-    a.corr = corr_out;
-    a.exp_out = exp_out;
-    a.scale_exp = p->scale_exp;
-    a.B = p->batch;
-    a.Bp = Bp;
-    a.n_delta = int(SN.nspin());
-    a.n_alpha = int(tl->alphas.size());
-    a.A = tl->A;
-    a.norm = std::ldexp(1.0, tl->A * block_norm_exp(p->V)) /
-             (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
-    HIP_CHECK(launch_final(a, mixed, s));
+  for (int step = first_step; step <= last_step; step++) {
+    if (step == 0) {
+      // the first baryon's block restricted to the required components
+      const Stage &S0 = tl->st[0];
+      Stage0Args a{};
+      a.fblk = fblk[S0.type];
+      a.Fout = buf[0];
+      a.first = reinterpret_cast<const uint32_t *>(img + tl->off_first);
+      a.nq = int64_t(S0.quark.size());
+      a.Bp = Bp;
+      a.nyq = nyq;
+      a.ns = int(S0.nspin());
+      psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+      if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
+    } else if (step < tl->nstages) {
+      const Stage &S = tl->st[step], &Pv = tl->st[step - 1];
+      StageArgs a{};
+      a.Fin = buf[(step - 1) % 2];
+      a.Fout = buf[step % 2];
+      a.fblk = fblk[S.type];
+      a.qsplit = reinterpret_cast<const uint32_t *>(img + tl->off_qsplit[step]);
+      a.nq_out = int64_t(S.quark.size());
+      a.Bp = Bp;
+      a.Sq = S.Sq;
+      a.nyq = nyq;
+      a.act_is_P = S.type == PROTON;
+      a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
+      a.K = S.type == PROTON ? Pv.kP : Pv.kN;
+      a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
+      psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+      if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
+      if (a.nq_out > 0) HIP_CHECK(launch_stage(a, mixed, s));
+    } else {
+      const Stage &SN = tl->st[tl->nstages - 1];
+      FinalArgs a{};
+      a.F = buf[(tl->nstages - 1) % 2];
+      a.crow = reinterpret_cast<const int64_t *>(img + tl->off_crow);
+      a.ccol = reinterpret_cast<const int32_t *>(img + tl->off_ccol);
+      a.cval = reinterpret_cast<const double *>(img + tl->off_cval);
+      a.corr = corr_out;
+      a.exp_out = exp_out;
+      a.scale_exp = p->scale_exp;
+      a.B = p->batch;
+      a.Bp = Bp;
+      a.n_delta = int(SN.nspin());
+      a.n_alpha = int(tl->alphas.size());
+      a.A = tl->A;
+      a.norm = std::ldexp(1.0, tl->A * block_norm_exp(p->V)) /
+               (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
+      HIP_CHECK(launch_final(a, mixed, s));
+    }
   }
   return MB_OK;
+}
+
+int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p, const void *blocks,
+                           size_t blocks_bytes, double *corr_out, int32_t *exp_out, void *ws,
+                           size_t ws_bytes, void *stream) {
+  if (!tl) return fail(MB_EINVAL, "null argument");
+  return contract_steps(tl, p, blocks, blocks_bytes, corr_out, exp_out, ws, ws_bytes, stream, 0,
+                        tl->nstages);
+}
+
+int mb_contract_step(const mb_term_list *tl, const mb_problem *p, const void *blocks,
+                     size_t blocks_bytes, int step, double *corr_out, int32_t *exp_out, void *ws,
+                     size_t ws_bytes, void *stream) {
+  if (!tl) return fail(MB_EINVAL, "null argument");
+  if (step < 0 || step > tl->nstages) return fail(MB_EINVAL, "step out of range");
+  return contract_steps(tl, p, blocks, blocks_bytes, corr_out, exp_out, ws, ws_bytes, stream, step,
+                        step);
 }
 
 }  // extern "C"

@@ -1,0 +1,196 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, on an MI355X.
+
+Every input is seeded and synthetic (synth.props).  Tolerances:
+  * FP64 path vs oracle: 1e-12 relative (Frobenius norm per lane over all
+    requested components), blocks and correlators;
+  * mixed path vs FP64 path and vs oracle: 1e-6 relative, the same norm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_1301_4895_amd import binding as B
+from paper_1301_4895_amd.runner import Runner
+from tests.gpu_helpers import host_props, oracle_blocks_lib_layout, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def block_norm_exp(V):
+    e = 0
+    while 4 ** (e + 1) <= V:
+        e += 1
+    return e
+
+
+def _tl(rel, nsrc, nP, nN, spins):
+    if spins is None:
+        return B.TermList(nP, nN, rel, nsrc, all_components=True)
+    return B.TermList.spin_state(nP, nN, rel, nsrc, spins)
+
+
+def _inputs(seed, nlanes, V, nsrc, dtype, same_ud, with_sink, rng_k=True):
+    Su = host_props(seed, 0, nlanes, 1, V, nsrc, dtype)[:, 0]
+    Sd = Su if same_ud else host_props(seed, 1, nlanes, 1, V, nsrc, dtype)[:, 0]
+    rng = np.random.default_rng(seed)
+    w = None
+    if with_sink:
+        w = rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))
+    k = rng.integers(-3, 4, size=nlanes).astype(np.int32) if rng_k else np.zeros(nlanes, np.int32)
+    return Su, Sd, w, k
+
+
+def _run(tl, Su, Sd, w, k, precision):
+    tu = torch.from_numpy(np.ascontiguousarray(Su)).to(DEV)
+    td = tu if Sd is Su else torch.from_numpy(np.ascontiguousarray(Sd)).to(DEV)
+    tw = None if w is None else torch.from_numpy(np.ascontiguousarray(w)).to(DEV)
+    tk = torch.from_numpy(k).to(DEV)
+    r = Runner(tl, tu, td, precision, tw, tk)
+    corr, ex = r.run()
+    torch.cuda.synchronize()
+    c = tl.counts()
+    nxi, npsi = c["n_xi"], c["n_psi"]
+    nyq = nxi * (nxi - 1) // 2 * nxi
+    Bp = (len(Su) + 63) // 64 * 64
+    cd = torch.complex128 if precision == B.MB_FP64 else torch.complex64
+    blocks = r.blocks.view(cd).view(2, npsi, nyq, Bp)[..., :len(Su)].cpu().numpy()
+    return blocks, corr.cpu().numpy(), ex.cpu().numpy()
+
+
+def _oracle_corr(tl, rel, nsrc, nP, nN, Su, Sd, w, k):
+    """Oracle correlators in the library's [delta][alpha] order, one lane."""
+    dsets = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    asets = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+    req = dict(sinkP=int(np.bitwise_or.reduce(dsets[:, 0])), sinkN=int(np.bitwise_or.reduce(dsets[:, 1])),
+               alphas=[tuple(map(int, a)) for a in asets])
+    Cd = O.correlators(rel, nsrc, nP, nN, req, Su.astype(np.complex128), Sd.astype(np.complex128), w,
+                       2.0 ** int(k))
+    out = np.zeros((len(dsets), len(asets)), np.complex128)
+    for i, d in enumerate(map(tuple, dsets.tolist())):
+        for j, a in enumerate(map(tuple, asets.tolist())):
+            out[i, j] = Cd[(d, a)]
+    return out
+
+
+# --------------------------------------------------------------------- inputs
+
+def test_device_generator_matches_host():
+    from synth.gpu import fill_props
+    for dt, tdt in [(np.complex128, torch.complex128), (np.complex64, torch.complex64)]:
+        host = host_props(7, 3, 2, 3, 5, 2, dt).reshape(6, 5, 2, 12, 12)
+        dev = torch.empty((4, 5, 2, 12, 12), dtype=tdt, device=DEV)
+        fill_props(dev, 7, 3, 5, 2, 3, 1)          # units 1..4 of a (2 problems x 3 t) set
+        assert np.array_equal(dev.cpu().numpy(), host[1:5])
+
+
+# --------------------------------------------------------------------- blocks
+
+@pytest.mark.parametrize("rel,nsrc", [(False, 1), (True, 1), (False, 2)])
+@pytest.mark.parametrize("same_ud", [True, False])
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_blocks_match_oracle(rel, nsrc, same_ud, dtype):
+    V, nl = 27, 3
+    Su, Sd, w, k = _inputs(11, nl, V, nsrc, dtype, same_ud, with_sink=nsrc == 2 or rel)
+    tl = _tl(rel, nsrc, 1, 1, None)
+    for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)]:
+        blocks, _, _ = _run(tl, Su, Sd, w, k, prec)
+        j = block_norm_exp(V)
+        for b in range(nl):
+            fP, fN = O.blocks(rel, nsrc, Su[b].astype(np.complex128), Sd[b].astype(np.complex128), w,
+                              2.0 ** int(k[b]))
+            ref = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -j
+            for sp in range(2):
+                assert rel_err(blocks[sp, :, :, b], ref[sp]) <= tol, (prec, sp, b)
+
+
+# --------------------------------------------------------------------- correlators
+
+CORR_CASES = [
+    # rel, nsrc, nP, nN, spins, V, lanes, same_ud
+    (False, 1, 1, 1, None, 64, 4, True),          # p+n, the small configuration
+    (False, 1, 1, 1, None, 8, 2, False),          # p+n with u != d
+    (False, 1, 2, 0, None, 8, 2, True),           # pp
+    (False, 1, 0, 2, None, 8, 2, True),           # nn
+    (False, 1, 2, 1, None, 8, 2, True),           # 3He
+    (False, 1, 1, 2, None, 8, 2, False),          # 3H, u != d
+    (False, 1, 2, 2, (0, 1, 0, 1), 27, 2, True),  # 4He NR
+    (False, 1, 1, 0, None, 8, 2, False),          # single proton
+    (True, 1, 1, 1, None, 8, 1, True),            # p+n relativistic, all components
+    (True, 1, 1, 2, (0, 0, 1), 8, 1, True),       # 3H relativistic
+    (True, 1, 2, 2, (0, 1, 0, 1), 8, 1, True),    # 4He relativistic
+    (False, 2, 1, 1, None, 8, 2, True),           # p+n, two sources
+    (False, 2, 2, 2, (0, 2, 0, 2), 8, 1, True),   # 4He NR, two sources
+    (False, 2, 0, 3, (0, 1, 2), 8, 1, True),      # 3n, two sources
+]
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins,V,nl,same_ud", CORR_CASES)
+def test_correlators_fp64_match_oracle(rel, nsrc, nP, nN, spins, V, nl, same_ud):
+    Su, Sd, w, k = _inputs(5 + nP + 3 * nN, nl, V, nsrc, np.complex128, same_ud, with_sink=nsrc == 2)
+    tl = _tl(rel, nsrc, nP, nN, spins)
+    _, corr, ex = _run(tl, Su, Sd, w, k, B.MB_FP64)
+    A = nP + nN
+    assert np.array_equal(ex, 3 * A * k)
+    for b in range(nl):
+        ref = _oracle_corr(tl, rel, nsrc, nP, nN, Su[b], Sd[b], w, k[b])
+        assert np.linalg.norm(ref) > 0
+        assert rel_err(corr[b], ref) <= 1e-12, b
+
+
+def test_pauli_zero_with_identical_sink_functions():
+    # 4He with two sources and the same sink function on both: the two rows
+    # with equal alpha coincide and the antisymmetrised product vanishes.
+    V, nl = 8, 1
+    Su, Sd, _, k = _inputs(3, nl, V, 2, np.complex128, True, False)
+    tl = _tl(False, 2, 2, 2, (0, 1, 0, 1))
+    _, corr, _ = _run(tl, Su, Sd, None, k, B.MB_FP64)
+    tl2 = _tl(False, 2, 2, 2, (0, 2, 0, 2))
+    _, corr2, _ = _run(tl2, Su, Sd, None, k, B.MB_FP64)
+    assert abs(corr[0, 0, 0]) <= 1e-12 * abs(corr2[0, 0, 0])
+
+
+def test_8be_two_source_factorisation():
+    """8Be (NR, two sources) on disjoint regions equals the product of two
+    one-source 4He correlators, each from the oracle (Sec. 6)."""
+    V = 8
+    half = V // 2
+    S = host_props(21, 0, 1, 1, V, 2, np.complex128)[0, 0].copy()
+    S[half:, 0] = 0
+    S[:half, 1] = 0
+    rng = np.random.default_rng(4)
+    w = np.zeros((2, V), np.complex128)
+    w[0, :half] = rng.normal(size=half) + 1j * rng.normal(size=half)
+    w[1, half:] = rng.normal(size=half) + 1j * rng.normal(size=half)
+    tl = _tl(False, 2, 4, 4, (0, 1, 2, 3, 0, 1, 2, 3))
+    k = np.array([1], np.int32)
+    _, corr, _ = _run(tl, S[None], S[None], w, k, B.MB_FP64)
+    req = O.spin_state_request(2, 2, (0, 1, 0, 1))
+    c0 = O.correlators(False, 1, 2, 2, req, S[:, :1], S[:, :1], w[:1], 2.0)[((3, 3), (3, 3))]
+    c1 = O.correlators(False, 1, 2, 2, req, S[:, 1:], S[:, 1:], w[1:], 2.0)[((3, 3), (3, 3))]
+    assert abs(c0 * c1) > 0
+    assert abs(corr[0, 0, 0] - c0 * c1) <= 1e-12 * abs(c0 * c1)
+
+
+# --------------------------------------------------------------------- mixed precision
+
+MIXED_CASES = [
+    (False, 1, 2, 2, (0, 1, 0, 1), 512, 64, np.complex128),    # 4He NR (C2 kind)
+    (True, 1, 2, 2, None, 216, 64, np.complex64),               # 4He rel, all components (C3 kind)
+    (False, 2, 4, 4, (0, 1, 2, 3, 0, 1, 2, 3), 512, 64, np.complex64),  # 8Be NR (C4 kind)
+]
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins,V,nl,dtype", MIXED_CASES)
+def test_mixed_matches_fp64(rel, nsrc, nP, nN, spins, V, nl, dtype):
+    Su, Sd, w, k = _inputs(9, nl, V, nsrc, dtype, True, with_sink=nsrc == 2)
+    tl = _tl(rel, nsrc, nP, nN, spins)
+    _, c64, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
+    _, c32, _ = _run(tl, Su, Sd, w, k, B.MB_MIXED)
+    errs = [rel_err(c32[b], c64[b]) for b in range(nl)]
+    assert max(errs) <= 1e-6, max(errs)
