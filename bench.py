@@ -166,12 +166,16 @@ def main():
         torch.cuda.empty_cache()
 
     err = None
+    err_stats = None
     if "mixed" in outs and "fp64" in outs:
         a, b = outs["mixed"], outs["fp64"]
         num = np.linalg.norm((a - b).reshape(lanes, -1), axis=1)
         den = np.linalg.norm(b.reshape(lanes, -1), axis=1)
-        err = float(np.max(num / den))
-        log(f"[bench] max rel err mixed vs fp64 over {lanes} lanes: {err:.3e}")
+        per_lane = num / den
+        err = float(np.max(per_lane))
+        err_stats = dict(median=float(np.median(per_lane)), p99=float(np.quantile(per_lane, 0.99)), max=err)
+        log(f"[bench] rel err mixed vs fp64 over {lanes} lanes: median {err_stats['median']:.2e} "
+            f"p99 {err_stats['p99']:.2e} max {err:.3e}")
 
     main_name = "mixed" if "mixed" in results else "fp64"
     res = results[main_name]
@@ -216,6 +220,7 @@ def main():
                   "speedup_mixed_over_fp64": round(res["value"] / results["fp64"]["value"], 3)}
                  if "fp64" in results and main_name == "mixed" else None),
         "max_rel_err_mixed_vs_fp64": err,
+        "rel_err_mixed_vs_fp64_per_lane": err_stats,
         "kernel_avg_ms": {k: round(v, 4) for k, v in res["kernel_avg_ms"].items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

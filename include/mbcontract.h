@@ -65,9 +65,11 @@ extern "C" {
 #define MB_C64 0               /* complex float (re, im)   */
 #define MB_C128 1              /* complex double (re, im)  */
 
-#define MB_FP64 0              /* blocks, products and sums in double            */
-#define MB_MIXED 1             /* float products and block partial sums; double
-                                  site reduction and final signed sum            */
+#define MB_FP64 0              /* recursion stages stored in double              */
+#define MB_MIXED 1             /* recursion stages stored in float (half the
+                                  memory traffic of the bandwidth-bound gathers);
+                                  blocks stored in double, every product and sum
+                                  formed in double                                */
 
 /* A nucleus of n_P protons and n_N neutrons (Sec. 7).
  *   rel    1: Gamma_1 = 1, Gamma_2 = C gamma_5; 0: the nonrelativistic
@@ -163,8 +165,9 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
 /* Export of the term list for inspection and tests (host memory).  If buf is
  * NULL, *bytes receives the size; otherwise *bytes must be at least that
  * size.  `stage` selects the stage where relevant.
- *   MB_EXPORT_QUARK  uint32 [n_quark][2]: (u mask, d mask), ascending in
- *                    (u, d); the order of the stage's quark parts
+ *   MB_EXPORT_QUARK  uint32 [n_quark][2]: (u mask, d mask) in the stage's
+ *                    order: ascending in (d, u) for a stage reached by adding
+ *                    a proton (after the first), else ascending in (u, d)
  *   MB_EXPORT_SPIN   uint32 [n_spin][2]: (proton mask, neutron mask) in the
  *                    stage's order (proton rank major)
  *   MB_EXPORT_QSPLIT uint32 [n_quark][S][2] for stage >= 1: per output quark
@@ -238,9 +241,9 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
  *        S_q1[(beta,a), xi1] S_q2[(gamma,b), xi2] S_q3[(delta,c), xi3]
  * for the proton (u,u,d) and neutron (d,u,d), antisymmetrised without
  * normalisation in the two same-flavour slots (Sec. 4), for every lane.
- * The sum over sites runs in double precision in both precision modes.
- * Output layout (precision MB_FP64: complex double, MB_MIXED: complex float):
- * proton block [psi][block quark index][lane] followed by the neutron block,
+ * The sum over sites runs in double precision and the blocks are stored in
+ * double in both precision modes.
+ * Output layout (complex double in both precision modes): proton block [psi][block quark index][lane] followed by the neutron block,
  * lanes padded to a multiple of 64.                                        */
 int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
                    size_t blocks_bytes, void *ws, size_t ws_bytes, void *stream);

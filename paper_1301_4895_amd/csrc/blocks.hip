@@ -243,8 +243,9 @@ static hipError_t dispatch_bp(const BlocksArgs &a, bool sym, hipStream_t s) {
 }
 
 hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipStream_t s) {
-  if (mixed)
-    return a.in_c128 ? dispatch_bp<float, double2>(a, sym, s) : dispatch_bp<float, float2>(a, sym, s);
+  // Both precision modes form the site sums in double (double FMA issues at
+  // the single-precision rate on CDNA4) and store the blocks in double.
+  (void)mixed;
   return a.in_c128 ? dispatch_bp<double, double2>(a, sym, s) : dispatch_bp<double, float2>(a, sym, s);
 }
 
@@ -311,10 +312,8 @@ hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s) 
   const int npsi = a.D * a.nsrc, nxi = 3 * a.D * a.nsrc;
   const int nyq = nxi * (nxi - 1) / 2 * nxi;
   dim3 grid(unsigned((a.Bp + 255) / 256), unsigned(2 * npsi * nyq));
-  if (mixed)
-    hipLaunchKernelGGL(blocks_finish_kernel<float2>, grid, dim3(256), 0, s, a, nxi, npsi);
-  else
-    hipLaunchKernelGGL(blocks_finish_kernel<double2>, grid, dim3(256), 0, s, a, nxi, npsi);
+  (void)mixed;  // blocks are stored in double in both modes
+  hipLaunchKernelGGL(blocks_finish_kernel<double2>, grid, dim3(256), 0, s, a, nxi, npsi);
   return hipGetLastError();
 }
 

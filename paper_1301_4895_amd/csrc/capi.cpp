@@ -51,9 +51,11 @@ int check_problem(const mb_term_list *tl, const mb_problem *p) {
 
 size_t elem_bytes(const mb_problem *p) { return p->precision == MB_MIXED ? 8 : 16; }
 
+// Blocks are stored in double in both precision modes (they are small and
+// every block entry enters every component).
 size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
   const int64_t nyq = int64_t(tl->nxi) * (tl->nxi - 1) / 2 * tl->nxi;
-  return size_t(2 * tl->npsi * nyq) * size_t(lanes_padded(p->batch)) * elem_bytes(p);
+  return size_t(2 * tl->npsi * nyq) * size_t(lanes_padded(p->batch)) * 16;
 }
 
 size_t blocks_ws_of(const mb_term_list *tl, const mb_problem *p) {
@@ -203,9 +205,8 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   const int64_t Bp = lanes_padded(p->batch);
   const int nxi = tl->nxi;
   const int nyq = nxi * (nxi - 1) / 2 * nxi;
-  const size_t eb = elem_bytes(p);
   const char *blk = static_cast<const char *>(blocks);
-  const void *fblk[2] = {blk, blk + size_t(tl->npsi) * nyq * Bp * eb};  // proton, neutron
+  const void *fblk[2] = {blk, blk + size_t(tl->npsi) * nyq * Bp * 16};  // proton, neutron
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
   const char *img = static_cast<const char *>(tl->dev);
 

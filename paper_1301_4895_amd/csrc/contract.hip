@@ -42,15 +42,19 @@ __host__ __device__ constexpr int rank_c(int mask) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void stage0_kernel(Stage0Args a) {
-  using C2 = typename c2<T>::type;
+  using C2 = typename c2<T>::type;  // storage of F; blocks are double
   const int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   const int64_t comp = blockIdx.y + int64_t(gridDim.y) * blockIdx.z;  // q * ns + sigma
   if (b >= a.Bp || comp >= a.nq * a.ns) return;
   const int64_t q = comp / a.ns;
   const int sig = int(comp % a.ns);
-  const C2 *f = static_cast<const C2 *>(a.fblk);
+  const double2 *f = static_cast<const double2 *>(a.fblk);
   C2 *F = static_cast<C2 *>(a.Fout);
-  F[comp * a.Bp + b] = f[(int64_t(a.psi_of_pos[sig]) * a.nyq + a.first[q]) * a.Bp + b];
+  const double2 v = f[(int64_t(a.psi_of_pos[sig]) * a.nyq + a.first[q]) * a.Bp + b];
+  C2 o;
+  o.x = T(v.x);
+  o.y = T(v.y);
+  F[comp * a.Bp + b] = o;
 }
 
 hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
@@ -66,22 +70,31 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int M, int K>
+// TS: storage type of F (float for MB_MIXED, double for MB_FP64); blocks are
+// stored in double.
+// Products and sums run in double in both cases: on CDNA4 double FMA issues at
+// the rate of single FMA, so only the bandwidth-bound storage is narrowed.
+template <typename TS, int M, int K>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
-  using C2 = typename c2<T>::type;
+  using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   const int64_t b = blockIdx.y * 64 + threadIdx.x;
-  const int64_t qp = blockIdx.x;               // output quark part * npass + pass
-  const int64_t q = qp / a.npass;
-  const int pass = int(qp % a.npass);
+  // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
+  // contiguous segment of the output order (consecutive outputs share
+  // operands in its L2) and let the passthrough spin part vary slowest.
+  const int64_t n8 = (a.nq_out + 7) / 8 * 8;
+  const int pass = int(blockIdx.x / n8);
+  const int64_t r = blockIdx.x % n8;
+  const int64_t q = (r % 8) * (n8 / 8) + r / 8;
+  if (q >= a.nq_out) return;
   const int64_t Bp = a.Bp;
   const int ns_in = NIN * a.npass, ns_out = NOUT * a.npass;
   // spin index of active rank r with the passthrough rank
   auto sig_in = [&](int r) { return a.act_is_P ? r * a.npass + pass : pass * NIN + r; };
   auto sig_out = [&](int r) { return a.act_is_P ? r * a.npass + pass : pass * NOUT + r; };
 
-  const C2 *Fin = static_cast<const C2 *>(a.Fin);
-  const C2 *fb = static_cast<const C2 *>(a.fblk);
+  const CS *Fin = static_cast<const CS *>(a.Fin);
+  const double2 *fb = static_cast<const double2 *>(a.fblk);
   const uint2 *qs = reinterpret_cast<const uint2 *>(a.qsplit) + q * a.Sq;
 
   int64_t in_off[NIN];
@@ -91,25 +104,24 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
 #pragma unroll
   for (int d = 0; d < M; d++) f_off[d] = int64_t(a.psi_of_pos[d]) * a.nyq * Bp + b;
 
-  C2 acc[NOUT];
+  double2 acc[NOUT];
 #pragma unroll
-  for (int r = 0; r < NOUT; r++) {
-    acc[r].x = T(0);
-    acc[r].y = T(0);
-  }
+  for (int r = 0; r < NOUT; r++) acc[r] = make_double2(0.0, 0.0);
   for (int s = 0; s < a.Sq; s++) {
     const uint2 e = qs[s];
     const int64_t xbase = int64_t(e.x) * ns_in * Bp;
     const int64_t ybase = int64_t(e.y & 0x7fffffffu) * Bp;
-    const T sgn = (e.y >> 31) ? T(-1) : T(1);
-    C2 fin[NIN], fy[M];
+    const double sgn = (e.y >> 31) ? -1.0 : 1.0;
+    double2 fin[NIN], fy[M];
 #pragma unroll
-    for (int r = 0; r < NIN; r++) fin[r] = Fin[xbase + in_off[r]];
+    for (int r = 0; r < NIN; r++) {
+      const CS v = Fin[xbase + in_off[r]];
+      fin[r] = make_double2(double(v.x), double(v.y));
+    }
 #pragma unroll
     for (int d = 0; d < M; d++) {
-      C2 v = fb[ybase + f_off[d]];
-      fy[d].x = sgn * v.x;
-      fy[d].y = sgn * v.y;
+      const double2 v = fb[ybase + f_off[d]];
+      fy[d] = make_double2(sgn * v.x, sgn * v.y);
     }
 #pragma unroll
     for (int out = 0; out < (1 << M); out++) {
@@ -122,7 +134,7 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
         const int ri = rank_c(in);
         // moving element d behind the remaining elements of the set
         const bool neg = popc(in >> (d + 1)) & 1;
-        const C2 x = fin[ri], y = fy[d];
+        const double2 x = fin[ri], y = fy[d];
         if (neg) {
           acc[ro].x -= x.x * y.x - x.y * y.y;
           acc[ro].y -= x.x * y.y + x.y * y.x;
@@ -133,14 +145,20 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
       }
     }
   }
-  C2 *Fout = static_cast<C2 *>(a.Fout);
+  CS *Fout = static_cast<CS *>(a.Fout);
 #pragma unroll
-  for (int r = 0; r < NOUT; r++) Fout[(q * ns_out + sig_out(r)) * Bp + b] = acc[r];
+  for (int r = 0; r < NOUT; r++) {
+    CS o;
+    o.x = TS(acc[r].x);
+    o.y = TS(acc[r].y);
+    Fout[(q * ns_out + sig_out(r)) * Bp + b] = o;
+  }
 }
 
 template <typename T, int M, int K>
 static hipError_t launch_stage_mk(const StageArgs &a, hipStream_t s) {
-  dim3 grid(unsigned(a.nq_out * a.npass), unsigned(a.Bp / 64));
+  const int64_t n8 = (a.nq_out + 7) / 8 * 8;
+  dim3 grid(unsigned(n8 * a.npass), unsigned(a.Bp / 64));
   hipLaunchKernelGGL((stage_kernel<T, M, K>), grid, dim3(64), 0, s, a);
   return hipGetLastError();
 }
@@ -162,48 +180,35 @@ hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Final contraction, in double: C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b]
-constexpr int kDeltaChunk = 36;
-
-template <typename T>
+// Final contraction, in double: C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b].
+// One thread per (alpha, delta, lane): the coefficient list of alpha is read
+// with scalar loads, F with one coalesced load per entry.
+template <typename TS>
 __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
-  using C2 = typename c2<T>::type;
-  const int64_t b = blockIdx.y * 64 + threadIdx.x;
+  using CS = typename c2<TS>::type;
+  const int64_t b = blockIdx.z * 64 + threadIdx.x;
   const int alpha = blockIdx.x;
-  const int d0 = blockIdx.z * kDeltaChunk;
-  const int nd = min(kDeltaChunk, a.n_delta - d0);
-  const C2 *F = static_cast<const C2 *>(a.F);
-  double2 acc[kDeltaChunk];
-#pragma unroll
-  for (int d = 0; d < kDeltaChunk; d++) acc[d] = make_double2(0.0, 0.0);
+  const int delta = blockIdx.y;
+  const CS *F = static_cast<const CS *>(a.F);
+  double ar = 0.0, ai = 0.0;
   const int64_t e0 = a.crow[alpha], e1 = a.crow[alpha + 1];
+  const int64_t off = int64_t(delta) * a.Bp + b;
+  const int64_t rowstride = int64_t(a.n_delta) * a.Bp;
   for (int64_t e = e0; e < e1; e++) {
-    const int64_t base = (int64_t(a.ccol[e]) * a.n_delta + d0) * a.Bp + b;
+    const CS v = F[int64_t(a.ccol[e]) * rowstride + off];
     const double c = a.cval[e];
-#pragma unroll
-    for (int d = 0; d < kDeltaChunk; d++) {
-      if (d < nd) {
-        C2 v = F[base + int64_t(d) * a.Bp];
-        acc[d].x += c * double(v.x);
-        acc[d].y += c * double(v.y);
-      }
-    }
+    ar += c * double(v.x);
+    ai += c * double(v.y);
   }
   if (b < a.B) {
-#pragma unroll
-    for (int d = 0; d < kDeltaChunk; d++) {
-      if (d < nd) {
-        double2 v = make_double2(acc[d].x * a.norm, acc[d].y * a.norm);
-        reinterpret_cast<double2 *>(a.corr)[(b * a.n_delta + d0 + d) * a.n_alpha + alpha] = v;
-      }
-    }
-    if (a.exp_out && alpha == 0 && blockIdx.z == 0)
-      a.exp_out[b] = a.scale_exp ? 3 * a.A * a.scale_exp[b] : 0;
+    reinterpret_cast<double2 *>(a.corr)[(b * a.n_delta + delta) * a.n_alpha + alpha] =
+        make_double2(ar * a.norm, ai * a.norm);
+    if (a.exp_out && alpha == 0 && delta == 0) a.exp_out[b] = a.scale_exp ? 3 * a.A * a.scale_exp[b] : 0;
   }
 }
 
 hipError_t launch_final(const FinalArgs &a, bool mixed, hipStream_t s) {
-  dim3 grid(unsigned(a.n_alpha), unsigned(a.Bp / 64), unsigned((a.n_delta + kDeltaChunk - 1) / kDeltaChunk));
+  dim3 grid(unsigned(a.n_alpha), unsigned(a.n_delta), unsigned(a.Bp / 64));
   if (mixed)
     hipLaunchKernelGGL(final_kernel<float>, grid, dim3(64), 0, s, a);
   else

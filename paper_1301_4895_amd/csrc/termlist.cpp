@@ -215,6 +215,27 @@ struct KeySet {
   }
 };
 
+// Processing (and storage) order of a stage's quark parts.  A step that adds
+// a proton splits off a u pair and one d index; its outputs are ordered d set
+// major so that consecutive outputs share previous components (and a neutron
+// step, which splits off one u index, u set major).  The order only affects
+// memory locality.
+static inline uint64_t order_key(uint64_t q, bool d_major) {
+  return d_major ? ((q << 32) | (q >> 32)) : q;
+}
+
+static void sort_stage(std::vector<uint64_t> &v, bool d_major) {
+  std::sort(v.begin(), v.end(),
+            [d_major](uint64_t a, uint64_t b) { return order_key(a, d_major) < order_key(b, d_major); });
+}
+
+static uint32_t find_stage(const std::vector<uint64_t> &v, bool d_major, uint64_t k) {
+  auto it = std::lower_bound(v.begin(), v.end(), k, [d_major](uint64_t a, uint64_t b) {
+    return order_key(a, d_major) < order_key(b, d_major);
+  });
+  return uint32_t(it - v.begin());
+}
+
 // Enumerates the quark splits of quark part (u, d) for the added species:
 // proton: u pair (colex order of pairs) x d single; neutron: u single x d
 // pair.  f(yu, yd) is called for every split in this canonical order.
@@ -389,18 +410,20 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
       per_alpha[it->second].push_back({qkey(u, d), kv.second / norm});
     }
   }
+  const bool last_d_major = tl->path[A - 1] == PROTON && A > 1;
   std::vector<uint64_t> U;
-  for (auto &v : per_alpha) {
-    std::sort(v.begin(), v.end());
+  for (auto &v : per_alpha)
     for (auto &e : v) U.push_back(e.first);
-  }
-  std::sort(U.begin(), U.end());
+  sort_stage(U, last_d_major);
   U.erase(std::unique(U.begin(), U.end()), U.end());
   tl->nU = int64_t(U.size());
   tl->crow.assign(1, 0);
   for (auto &v : per_alpha) {
-    for (auto &e : v) {
-      tl->ccol.push_back(std::lower_bound(U.begin(), U.end(), e.first) - U.begin());
+    std::vector<std::pair<uint32_t, int64_t>> row;
+    for (auto &e : v) row.push_back({find_stage(U, last_d_major, e.first), e.second});
+    std::sort(row.begin(), row.end());
+    for (auto &e : row) {
+      tl->ccol.push_back(e.first);
       tl->cval.push_back(e.second);
     }
     tl->crow.push_back(int64_t(tl->ccol.size()));
@@ -433,6 +456,8 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
       for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(u & ~yu, d & ~yd)); });
     }
     P.quark = X.sorted();
+    const bool pd = P.type == PROTON && s - 1 > 0;
+    sort_stage(P.quark, pd);
     S.Sq = T == PROTON ? binom(S.ku, 2) * S.kd : S.ku * binom(S.kd, 2);
     const int kT = T == PROTON ? S.kP : S.kN;
     S.n_lambda = S.nreq() * kT * S.Sq;
@@ -447,8 +472,7 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
         uint32_t u = qkey_u(q), d = qkey_d(q);
         for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) {
           uint32_t xu = u & ~yu, xd = d & ~yd;
-          uint64_t xk = qkey(xu, xd);
-          uint32_t xi = uint32_t(std::lower_bound(P.quark.begin(), P.quark.end(), xk) - P.quark.begin());
+          uint32_t xi = find_stage(P.quark, pd, qkey(xu, xd));
           int sg = split_sign(xu, yu) * split_sign(xd, yd);
           S.qsplit[o++] = xi;
           S.qsplit[o++] = block_qidx(T, yu, yd, nxi) | (sg < 0 ? 0x80000000u : 0u);

@@ -58,8 +58,7 @@ def _run(tl, Su, Sd, w, k, precision):
     nxi, npsi = c["n_xi"], c["n_psi"]
     nyq = nxi * (nxi - 1) // 2 * nxi
     Bp = (len(Su) + 63) // 64 * 64
-    cd = torch.complex128 if precision == B.MB_FP64 else torch.complex64
-    blocks = r.blocks.view(cd).view(2, npsi, nyq, Bp)[..., :len(Su)].cpu().numpy()
+    blocks = r.blocks.view(torch.complex128).view(2, npsi, nyq, Bp)[..., :len(Su)].cpu().numpy()
     return blocks, corr.cpu().numpy(), ex.cpu().numpy()
 
 
@@ -98,7 +97,7 @@ def test_blocks_match_oracle(rel, nsrc, same_ud, dtype):
     V, nl = 27, 3
     Su, Sd, w, k = _inputs(11, nl, V, nsrc, dtype, same_ud, with_sink=nsrc == 2 or rel)
     tl = _tl(rel, nsrc, 1, 1, None)
-    for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)]:
+    for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-12)]:
         blocks, _, _ = _run(tl, Su, Sd, w, k, prec)
         j = block_norm_exp(V)
         for b in range(nl):
