@@ -17,6 +17,8 @@
 // in double; MB_FP64 works in double throughout.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace mb {
@@ -222,6 +224,185 @@ __global__ __launch_bounds__(kThreads) void blocks_partial_kernel(BlocksArgs a) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same site sums as one complex GEMM per lane on the matrix cores:
+//   f[m = (psi, xi1)][n = pair] += sum_k A[m][k] B[k][n],  k = (site, colour a)
+//   A[m][k] = w_{s'(psi)}(x) S_q1[(alpha(psi), a), xi1],  B[k][n] = D_a(x)[pair]
+// with v_mfma_f64_16x16x4f64 (double products and sums).  Operand layout:
+// A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.  A complex product
+// is four real MFMAs: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br.  The 16x16
+// output tiles are spread over the four waves of the workgroup; operands of a
+// group of sites are built in LDS (k-major), the diquark on the vector units.
+typedef double mb_d4 __attribute__((ext_vector_type(4)));
+
+template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
+__global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
+  constexpr int NPAIR = SYM ? NXI * (NXI + 1) / 2 : NXI * NXI;
+  constexpr int M = NPSI * NXI;
+  constexpr int MT = (M + 15) / 16, NT = (NPAIR + 15) / 16;
+  constexpr int MP = MT * 16, NP = NT * 16;
+  constexpr int NS = 4;                // sites per group
+  constexpr int KG = 3 * NS;           // k = 3 * site + colour, multiple of 4
+  constexpr int NTILE = MT * NT;
+  constexpr int TPW = (NTILE + 3) / 4;  // tiles per wave
+  constexpr int D = NROW / 3;
+
+  __shared__ double2 su[NS][NROW][NXI];
+  __shared__ double2 s1[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
+  __shared__ double2 sd[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
+  __shared__ double Ar[KG][MP], Ai[KG][MP];
+  __shared__ double Br[KG][NP], Bi[KG][NP];
+  __shared__ double2 wsh[NS][2];
+  __shared__ unsigned char px2[NP], px3[NP];  // pair index -> (xi2, xi3)
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int p = tid; p < NP; p += 256) {
+    int x2 = 0, x3 = 0;
+    if (p < NPAIR) {
+      if (SYM) {
+        while ((x3 + 1) * (x3 + 2) / 2 <= p) x3++;
+        x2 = p - x3 * (x3 + 1) / 2;
+      } else {
+        x2 = p / NXI;
+        x3 = p % NXI;
+      }
+    }
+    px2[p] = (unsigned char)x2;
+    px3[p] = (unsigned char)x3;
+  }
+  const int64_t ln = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int nsrc = a.nsrc;
+  const int64_t x0 = int64_t(chunk) * a.sites_per_chunk;
+  const int64_t x1 = min(a.V, x0 + a.sites_per_chunk);
+  const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[ln]) : 1.0;
+  const bool same1 = a.prop_q1 == a.prop_u;
+
+  mb_d4 accr[TPW], acci[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; j++) {
+    accr[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    acci[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  for (int64_t xg = x0; xg < x1; xg += NS) {
+    const int ns = int(min<int64_t>(NS, x1 - xg));
+    for (int i = tid; i < ns * NROW * NXI; i += 256) {
+      const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
+      const int s = xi % nsrc, kap = xi / nsrc;
+      const int64_t off = (((ln * a.V + xg + n) * nsrc + s) * 12 + r) * 12 + kap;
+      const double2 vu = load_c<TIN>(a.prop_u, off);
+      su[n][r][xi] = make_double2(vu.x * scale, vu.y * scale);
+      if constexpr (!SYM) {
+        const double2 vd = load_c<TIN>(a.prop_d, off);
+        sd[n][r][xi] = make_double2(vd.x * scale, vd.y * scale);
+        if (!same1) {
+          const double2 v1 = load_c<TIN>(a.prop_q1, off);
+          s1[n][r][xi] = make_double2(v1.x * scale, v1.y * scale);
+        }
+      }
+    }
+    if (tid < ns * nsrc) {
+      const int n = tid / nsrc, s = tid % nsrc;
+      wsh[n][s] = a.sink_w ? reinterpret_cast<const double2 *>(a.sink_w)[int64_t(s) * a.V + xg + n]
+                           : make_double2(1.0, 0.0);
+    }
+    __syncthreads();
+    // A operand: w S_q1[(alpha, a), xi1]
+    for (int i = tid; i < KG * MP; i += 256) {
+      const int k = i / MP, m = i % MP, n = k / 3, ac = k % 3;
+      double re = 0.0, im = 0.0;
+      if (n < ns && m < M) {
+        const int psi = m / NXI, xi1 = m % NXI, alpha = psi / nsrc, sk = psi % nsrc;
+        const double2 w = wsh[n][sk];
+        const double2 v = (SYM || same1) ? su[n][3 * alpha + ac][xi1] : s1[SYM ? 0 : n][SYM ? 0 : 3 * alpha + ac][SYM ? 0 : xi1];
+        re = w.x * v.x - w.y * v.y;
+        im = w.x * v.y + w.y * v.x;
+      }
+      Ar[k][m] = re;
+      Ai[k][m] = im;
+    }
+    // B operand: the diquark D_a[pair] = sum eps_abc (C g5)_{gd} S_u[(g,b)] S_d[(d,c)]
+    for (int i = tid; i < KG * NP; i += 256) {
+      const int k = i / NP, p = i % NP, n = k / 3, ac = k % 3;
+      double re = 0.0, im = 0.0;
+      if (n < ns && p < NPAIR) {
+        const int x2 = px2[p], x3 = px3[p];
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+          const int b = e == 0 ? (ac + 1) % 3 : (ac + 2) % 3;
+          const int c = e == 0 ? (ac + 2) % 3 : (ac + 1) % 3;
+          const double es = e == 0 ? 1.0 : -1.0;
+#pragma unroll
+          for (int g = 0; g < D; g++) {
+            // (C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1
+            const int gam = g, del = g ^ 1;
+            const double sg = es * ((g & 1) ? 1.0 : -1.0);
+            const double2 l = su[n][3 * gam + b][x2];
+            const double2 r = SYM ? su[n][3 * del + c][x3] : sd[SYM ? 0 : n][SYM ? 0 : 3 * del + c][SYM ? 0 : x3];
+            re += sg * (l.x * r.x - l.y * r.y);
+            im += sg * (l.x * r.y + l.y * r.x);
+          }
+        }
+      }
+      Br[k][p] = re;
+      Bi[k][p] = im;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int ks = 0; ks < KG / 4; ks++) {
+      const int k = 4 * ks + (lane >> 4);
+#pragma unroll
+      for (int j = 0; j < TPW; j++) {
+        const int t = wave + 4 * j;
+        if (t < NTILE) {
+          const int mt = t / NT, nt = t % NT;
+          const double ar = Ar[k][mt * 16 + (lane & 15)], ai = Ai[k][mt * 16 + (lane & 15)];
+          const double br = Br[k][nt * 16 + (lane & 15)], bi = Bi[k][nt * 16 + (lane & 15)];
+          accr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr[j], 0, 0, 0);
+          accr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accr[j], 0, 0, 0);
+          acci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci[j], 0, 0, 0);
+          acci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci[j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double2 *out = reinterpret_cast<double2 *>(a.partial) + ((ln * a.nchunk + chunk) * NPSI) * int64_t(NXI) * NPAIR;
+#pragma unroll
+  for (int j = 0; j < TPW; j++) {
+    const int t = wave + 4 * j;
+    if (t < NTILE) {
+      const int mt = t / NT, nt = t % NT;
+      const int n = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        // v_mfma_f64_16x16x4f64 output: D[i][j] in lane j + 16 (i % 4), register i / 4
+        const int m = mt * 16 + (lane >> 4) + 4 * r;
+        if (m < M && n < NPAIR) out[int64_t(m) * NPAIR + n] = make_double2(accr[j][r], acci[j][r]);
+      }
+    }
+  }
+}
+
+template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
+static hipError_t launch_bm(const BlocksArgs &a, hipStream_t s) {
+  dim3 grid(a.nchunk, unsigned(a.B));
+  hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename TIN>
+static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
+  if (a.D == 4 && a.nsrc == 1)
+    return sym ? launch_bm<TIN, 12, 4, 12, true>(a, s) : launch_bm<TIN, 12, 4, 12, false>(a, s);
+  if (a.D == 2 && a.nsrc == 1)
+    return sym ? launch_bm<TIN, 6, 2, 6, true>(a, s) : launch_bm<TIN, 6, 2, 6, false>(a, s);
+  if (a.D == 2 && a.nsrc == 2)
+    return sym ? launch_bm<TIN, 12, 4, 6, true>(a, s) : launch_bm<TIN, 12, 4, 6, false>(a, s);
+  return hipErrorInvalidValue;
+}
+
 template <typename T, typename TIN, int NXI, int NPSI, int NROW, bool SYM>
 static hipError_t launch_bp(const BlocksArgs &a, hipStream_t s) {
   dim3 grid(a.nchunk, unsigned(a.B));
@@ -243,10 +424,17 @@ static hipError_t dispatch_bp(const BlocksArgs &a, bool sym, hipStream_t s) {
 }
 
 hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipStream_t s) {
-  // Both precision modes form the site sums in double (double FMA issues at
-  // the single-precision rate on CDNA4) and store the blocks in double.
+  // Both precision modes form the site sums in double on the matrix cores
+  // (FP64 MFMA) and store the blocks in double.  MB_BLOCKS_VALU=1 selects the
+  // vector-unit kernel instead (same arithmetic, for comparison).
   (void)mixed;
-  return a.in_c128 ? dispatch_bp<double, double2>(a, sym, s) : dispatch_bp<double, float2>(a, sym, s);
+  static const bool valu = [] {
+    const char *e = getenv("MB_BLOCKS_VALU");
+    return e && e[0] == '1';
+  }();
+  if (valu)
+    return a.in_c128 ? dispatch_bp<double, double2>(a, sym, s) : dispatch_bp<double, float2>(a, sym, s);
+  return a.in_c128 ? dispatch_bm<double2>(a, sym, s) : dispatch_bm<float2>(a, sym, s);
 }
 
 // ---------------------------------------------------------------------------

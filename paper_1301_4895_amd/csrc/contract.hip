@@ -71,96 +71,110 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // TS: storage type of F (float for MB_MIXED, double for MB_FP64); blocks are
-// stored in double.
-// Products and sums run in double in both cases: on CDNA4 double FMA issues at
-// the rate of single FMA, so only the bandwidth-bound storage is narrowed.
-template <typename TS, int M, int K>
+// stored in double.  Products and sums run in double in both cases: on CDNA4
+// double FMA issues at the rate of single FMA, so only the bandwidth-bound
+// storage is narrowed.  PG passthrough parts share each thread so that the
+// block entries of a split are loaded once for all of them.
+template <typename TS, int M, int K, int PG>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   const int64_t b = blockIdx.y * 64 + threadIdx.x;
   // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
   // contiguous segment of the output order (consecutive outputs share
-  // operands in its L2) and let the passthrough spin part vary slowest.
+  // operands in its L2) and let the passthrough group vary slowest.
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
-  const int pass = int(blockIdx.x / n8);
+  const int pass0 = int(blockIdx.x / n8) * PG;
   const int64_t r = blockIdx.x % n8;
   const int64_t q = (r % 8) * (n8 / 8) + r / 8;
   if (q >= a.nq_out) return;
   const int64_t Bp = a.Bp;
   const int ns_in = NIN * a.npass, ns_out = NOUT * a.npass;
-  // spin index of active rank r with the passthrough rank
-  auto sig_in = [&](int r) { return a.act_is_P ? r * a.npass + pass : pass * NIN + r; };
-  auto sig_out = [&](int r) { return a.act_is_P ? r * a.npass + pass : pass * NOUT + r; };
+  // spin index of active rank r with passthrough rank p
+  auto sig_in = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NIN + r; };
+  auto sig_out = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NOUT + r; };
 
   const CS *Fin = static_cast<const CS *>(a.Fin);
   const double2 *fb = static_cast<const double2 *>(a.fblk);
   const uint2 *qs = reinterpret_cast<const uint2 *>(a.qsplit) + q * a.Sq;
 
-  int64_t in_off[NIN];
-#pragma unroll
-  for (int r = 0; r < NIN; r++) in_off[r] = int64_t(sig_in(r)) * Bp + b;
   int64_t f_off[M];
 #pragma unroll
   for (int d = 0; d < M; d++) f_off[d] = int64_t(a.psi_of_pos[d]) * a.nyq * Bp + b;
 
-  double2 acc[NOUT];
+  double2 acc[PG][NOUT];
 #pragma unroll
-  for (int r = 0; r < NOUT; r++) acc[r] = make_double2(0.0, 0.0);
+  for (int g = 0; g < PG; g++)
+#pragma unroll
+    for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
   for (int s = 0; s < a.Sq; s++) {
     const uint2 e = qs[s];
-    const int64_t xbase = int64_t(e.x) * ns_in * Bp;
+    const int64_t xbase = int64_t(e.x) * ns_in * Bp + b;
     const int64_t ybase = int64_t(e.y & 0x7fffffffu) * Bp;
     const double sgn = (e.y >> 31) ? -1.0 : 1.0;
-    double2 fin[NIN], fy[M];
-#pragma unroll
-    for (int r = 0; r < NIN; r++) {
-      const CS v = Fin[xbase + in_off[r]];
-      fin[r] = make_double2(double(v.x), double(v.y));
-    }
+    double2 fy[M];
 #pragma unroll
     for (int d = 0; d < M; d++) {
       const double2 v = fb[ybase + f_off[d]];
       fy[d] = make_double2(sgn * v.x, sgn * v.y);
     }
 #pragma unroll
-    for (int out = 0; out < (1 << M); out++) {
-      if (popc(out) != K + 1) continue;
-      const int ro = rank_c(out);
+    for (int g = 0; g < PG; g++) {
+      double2 fin[NIN];
 #pragma unroll
-      for (int d = 0; d < M; d++) {
-        if (!((out >> d) & 1)) continue;
-        const int in = out & ~(1 << d);
-        const int ri = rank_c(in);
-        // moving element d behind the remaining elements of the set
-        const bool neg = popc(in >> (d + 1)) & 1;
-        const double2 x = fin[ri], y = fy[d];
-        if (neg) {
-          acc[ro].x -= x.x * y.x - x.y * y.y;
-          acc[ro].y -= x.x * y.y + x.y * y.x;
-        } else {
-          acc[ro].x += x.x * y.x - x.y * y.y;
-          acc[ro].y += x.x * y.y + x.y * y.x;
+      for (int r = 0; r < NIN; r++) {
+        const CS v = Fin[xbase + int64_t(sig_in(r, pass0 + g)) * Bp];
+        fin[r] = make_double2(double(v.x), double(v.y));
+      }
+#pragma unroll
+      for (int out = 0; out < (1 << M); out++) {
+        if (popc(out) != K + 1) continue;
+        const int ro = rank_c(out);
+#pragma unroll
+        for (int d = 0; d < M; d++) {
+          if (!((out >> d) & 1)) continue;
+          const int in = out & ~(1 << d);
+          const int ri = rank_c(in);
+          // moving element d behind the remaining elements of the set
+          const bool neg = popc(in >> (d + 1)) & 1;
+          const double2 x = fin[ri], y = fy[d];
+          if (neg) {
+            acc[g][ro].x -= x.x * y.x - x.y * y.y;
+            acc[g][ro].y -= x.x * y.y + x.y * y.x;
+          } else {
+            acc[g][ro].x += x.x * y.x - x.y * y.y;
+            acc[g][ro].y += x.x * y.y + x.y * y.x;
+          }
         }
       }
     }
   }
   CS *Fout = static_cast<CS *>(a.Fout);
 #pragma unroll
-  for (int r = 0; r < NOUT; r++) {
-    CS o;
-    o.x = TS(acc[r].x);
-    o.y = TS(acc[r].y);
-    Fout[(q * ns_out + sig_out(r)) * Bp + b] = o;
-  }
+  for (int g = 0; g < PG; g++)
+#pragma unroll
+    for (int r = 0; r < NOUT; r++) {
+      CS o;
+      o.x = TS(acc[g][r].x);
+      o.y = TS(acc[g][r].y);
+      Fout[(q * ns_out + sig_out(r, pass0 + g)) * Bp + b] = o;
+    }
 }
 
+template <typename T, int M, int K, int PG>
+static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
+  const int64_t n8 = (a.nq_out + 7) / 8 * 8;
+  dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / 64));
+  hipLaunchKernelGGL((stage_kernel<T, M, K, PG>), grid, dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// passthrough group: 3 if it divides the passthrough count, else 2, else 1
 template <typename T, int M, int K>
 static hipError_t launch_stage_mk(const StageArgs &a, hipStream_t s) {
-  const int64_t n8 = (a.nq_out + 7) / 8 * 8;
-  dim3 grid(unsigned(n8 * a.npass), unsigned(a.Bp / 64));
-  hipLaunchKernelGGL((stage_kernel<T, M, K>), grid, dim3(64), 0, s, a);
-  return hipGetLastError();
+  if (a.npass % 3 == 0) return launch_stage_mkp<T, M, K, 3>(a, s);
+  if (a.npass % 2 == 0) return launch_stage_mkp<T, M, K, 2>(a, s);
+  return launch_stage_mkp<T, M, K, 1>(a, s);
 }
 
 template <typename T>
