@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=256, help="lanes per launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -112,10 +113,17 @@ def main():
 
     results = {}
     outs = {}
+    tuning = {}
     for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
         r = Runner(tl, props[:chunk], props[:chunk], prec, sink, kexp[:chunk])
+        tuning[prec_name] = None
+        if not args.no_autotune:
+            from paper_1301_4895_amd import autotune
+            best = autotune.tune(tl, r, log=log)
+            tuning[prec_name] = {str(k): {"pass_group": v[0], "lds_bytes": v[1], "lane_tile": v[2],
+                                          "ms": round(v[3], 3)} for k, v in best.items()}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
         ev = {}
 
@@ -225,6 +233,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "term_list_build_s": round(t_list, 2),
+        "autotune": tuning,
     }
     print(json.dumps(line), flush=True)
 

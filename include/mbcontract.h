@@ -194,6 +194,22 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
 int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
                         size_t *bytes);
 
+/* Launch tuning of recursion step `step` (1..A-1; -1 = every step), chosen by
+ * an autotuner; results do not depend on it.
+ *   MB_TUNE_PASS_GROUP  passthrough spin parts per thread: 0 = automatic
+ *                       (3, 2 or 1, the largest that divides their count),
+ *                       or 1, 2, 3 (must divide the count)
+ *   MB_TUNE_LDS_BYTES   LDS reserved per workgroup (0..65536), which caps the
+ *                       number of resident workgroups per CU (fewer operands
+ *                       in flight per L2)
+ *   MB_TUNE_LANE_TILE   lanes per wavefront, 64 (default) or 16 (four
+ *                       sub-waves share the quark splits of an output)
+ * Returns MB_EINVAL for an unknown item, step or value.                      */
+#define MB_TUNE_PASS_GROUP 1
+#define MB_TUNE_LDS_BYTES 2
+#define MB_TUNE_LANE_TILE 3
+int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
+
 /* Copies the operation tables to device memory `dev` (caller-owned, at least
  * counts.device_bytes, 256-byte aligned) and binds the term list to it; the
  * buffer must stay alive while the term list is used on the device.  A term

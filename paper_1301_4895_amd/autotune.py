@@ -1,0 +1,101 @@
+"""Autotuner for the recursion-step launches.
+
+For every step of a term list it times the candidate launch settings exposed
+by ``mb_term_list_tune`` -- passthrough spin parts per thread and LDS
+reserved per workgroup (which caps resident workgroups, hence operands in
+flight per L2) -- on the caller's own buffers, keeps the fastest, and records
+the choice in a JSON cache keyed by workload, precision, lanes and device.
+Results of the method do not depend on the settings.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import binding as B
+
+LDS_CANDIDATES = (0, 16384)
+TILES = (64, 16)
+
+
+def _candidates(npass):
+    pgs = [g for g in (1, 2, 3) if npass % g == 0]
+    return [(pg, lds, t) for pg in pgs for lds in LDS_CANDIDATES for t in TILES]
+
+
+def _time_step(tl, runner, step, reps, stream):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        B.contract_step(tl, runner.p, runner.blocks, step, runner.corr, runner.exp, runner.cws,
+                        stream.cuda_stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return min(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+
+
+def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = None, reps: int = 2,
+         log=None):
+    """Tunes every step on ``runner``'s buffers.
+    Returns {step: (pass_group, lds_bytes, lane_tile, ms)}."""
+    c = tl.counts()
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    full_key = f"{key}|{dev}" if key else None
+    if cache and full_key and os.path.exists(cache):
+        table = json.load(open(cache))
+        if full_key in table:
+            best = {int(s): tuple(v) for s, v in table[full_key].items()}
+            for s, (pg, lds, t, _) in best.items():
+                tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
+                tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
+                tl.tune(s, B.MB_TUNE_LANE_TILE, t)
+            return best
+    stream = torch.cuda.current_stream()
+    # bring every stage to a valid state once
+    runner.run_blocks()
+    for s in range(c["n_stages"] + 1):
+        B.contract_step(tl, runner.p, runner.blocks, s, runner.corr, runner.exp, runner.cws,
+                        stream.cuda_stream)
+    torch.cuda.synchronize()
+    best = {}
+    for s in range(1, c["n_stages"]):
+        # the step reads stage s-1, written by the previous step: rerun it first
+        B.contract_step(tl, runner.p, runner.blocks, s - 1, runner.corr, runner.exp, runner.cws,
+                        stream.cuda_stream)
+        added = c["path"][s]
+        # passthrough parts of the step: spin parts of the other species
+        kP = sum(1 for t in c["path"][:s + 1] if t == 0)
+        kN = s + 1 - kP
+        other = 1 - added
+        npass = math.comb(_base(tl, other), kN if other == 1 else kP)
+        results = []
+        for pg, lds, tile in _candidates(npass):
+            tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
+            tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
+            tl.tune(s, B.MB_TUNE_LANE_TILE, tile)
+            results.append((_time_step(tl, runner, s, reps, stream), pg, lds, tile))
+        ms, pg, lds, tile = min(results)
+        tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
+        tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
+        tl.tune(s, B.MB_TUNE_LANE_TILE, tile)
+        best[s] = (pg, lds, tile, ms)
+        if log:
+            log(f"[autotune] step {s}: " + ", ".join(f"pg{g}/lds{l}/t{t}={m:.2f}ms"
+                                                     for m, g, l, t in sorted(results)[:4]))
+    if cache and full_key:
+        table = json.load(open(cache)) if os.path.exists(cache) else {}
+        table[full_key] = {str(s): list(v) for s, v in best.items()}
+        json.dump(table, open(cache, "w"), indent=1)
+    return best
+
+
+def _base(tl, species):
+    """Size of the sink base set of a species."""
+    d = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    m = 0
+    for v in d[:, species]:
+        m |= int(v)
+    return bin(m).count("1")

@@ -20,13 +20,15 @@ MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST = 0, 1, 2
 MB_C64, MB_C128 = 0, 1
 MB_FP64, MB_MIXED = 0, 1
 MB_MAX_STAGES = 16
+MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE = 1, 2, 3
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
  MB_EXPORT_DELTA, MB_EXPORT_ALPHA) = range(1, 8)
 
 EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_term_list_free",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
-    "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_last_error",
+    "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune",
+    "mb_last_error",
 ]
 
 
@@ -86,6 +88,7 @@ def lib():
                                              C.c_size_t, P]
         L.mb_contract_step.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, C.c_int, P, P, P,
                                        C.c_size_t, P]
+        L.mb_term_list_tune.argtypes = [P, C.c_int, C.c_int, C.c_int]
         L.mb_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -143,6 +146,10 @@ class TermList:
         buf = np.zeros(max(n.value, 1), np.uint8)
         _check(lib().mb_term_list_export(self.h, what, stage, buf.ctypes.data_as(C.c_void_p), C.byref(n)))
         return buf[:n.value].view(dtype)
+
+    def tune(self, step, what, value):
+        """Launch tuning of a recursion step (results do not depend on it)."""
+        _check(lib().mb_term_list_tune(self.h, step, what, value))
 
     def upload(self, torch_device="cuda"):
         """Allocates the device image (a torch tensor) and uploads the tables."""

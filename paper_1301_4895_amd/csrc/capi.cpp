@@ -126,6 +126,32 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
   return MB_OK;
 }
 
+int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
+  if (!tl) return fail(MB_EINVAL, "null argument");
+  if (step != -1 && (step < 1 || step >= tl->nstages)) return fail(MB_EINVAL, "step out of range");
+  for (int s = 1; s < tl->nstages; s++) {
+    if (step != -1 && s != step) continue;
+    Stage &S = tl->st[s];
+    const int npass = S.type == PROTON ? S.nNsets : S.nPsets;
+    if (what == MB_TUNE_PASS_GROUP) {
+      if (value < 0 || value > 3 || (value > 0 && npass % value != 0)) {
+        if (step != -1) return fail(MB_EINVAL, "passthrough group must divide the passthrough count");
+        continue;
+      }
+      S.tune_pg = value;
+    } else if (what == MB_TUNE_LANE_TILE) {
+      if (value != 16 && value != 64) return fail(MB_EINVAL, "lane tile must be 16 or 64");
+      S.tune_tile = value;
+    } else if (what == MB_TUNE_LDS_BYTES) {
+      if (value < 0 || value > 65536) return fail(MB_EINVAL, "LDS bytes out of range");
+      S.tune_lds = value;
+    } else {
+      return fail(MB_EINVAL, "unknown tuning item");
+    }
+  }
+  return MB_OK;
+}
+
 int mb_workspace_query(const mb_term_list *tl, const mb_problem *p, size_t *blocks_bytes,
                        size_t *blocks_ws_bytes, size_t *contract_ws_bytes) {
   int rc = check_problem(tl, p);
@@ -239,6 +265,9 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
       a.K = S.type == PROTON ? Pv.kP : Pv.kN;
       a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
+      a.pg = S.tune_pg;
+      a.lds_bytes = S.tune_lds;
+      a.tile = S.tune_tile;
       psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
       if (a.nq_out > 0) HIP_CHECK(launch_stage(a, mixed, s));

@@ -12,7 +12,7 @@
 // sign) times the splits of the T spin set of sigma (one element moves to the
 // new baryon; sign = parity of moving it behind the rest).  The spins of the
 // other species pass through.  A thread owns one lane, one output quark part
-// and one passthrough spin part; for every quark split it loads the C(M,K)
+// and a group of passthrough spin parts; for every quark split it loads the C(M,K)
 // previous components and the M block entries once and forms the C(M,K+1) x
 // (K+1) products of the spin wedge in registers (M = size of the T sink base
 // set, K = T baryons already present), with the spin tables resolved at
@@ -75,11 +75,20 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 // double FMA issues at the rate of single FMA, so only the bandwidth-bound
 // storage is narrowed.  PG passthrough parts share each thread so that the
 // block entries of a split are loaded once for all of them.
-template <typename TS, int M, int K, int PG>
+//
+// A wavefront owns TILE lanes (64 or 16) of one output quark part.  With
+// TILE = 16 its four quarter-waves take every fourth quark split and their
+// partial sums are added with two cross-lane exchanges at the end; every
+// operand load is then a 16-lane row segment (one 128-byte line of a float
+// stage), which keeps four times more previous-stage rows in L2.  Which tile
+// is faster depends on the step; the autotuner decides.
+template <typename TS, int M, int K, int PG, int TILE>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
-  const int64_t b = blockIdx.y * 64 + threadIdx.x;
+  constexpr int SUB = 64 / TILE;   // sub-waves splitting the quark splits
+  const int quarter = SUB == 1 ? 0 : int(threadIdx.x) / TILE;
+  const int64_t b = blockIdx.y * TILE + (threadIdx.x & (TILE - 1));
   // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
   // contiguous segment of the output order (consecutive outputs share
   // operands in its L2) and let the passthrough group vary slowest.
@@ -107,8 +116,21 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   for (int g = 0; g < PG; g++)
 #pragma unroll
     for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
-  for (int s = 0; s < a.Sq; s++) {
-    const uint2 e = qs[s];
+  // The split table is read with wave-uniform (scalar) loads; every
+  // sub-wave then selects its own entry.
+  for (int s0 = 0; s0 < a.Sq; s0 += SUB) {
+    uint2 e = qs[s0];
+    bool valid = true;
+    if constexpr (SUB > 1) {
+      uint2 ee[SUB];
+#pragma unroll
+      for (int j = 0; j < SUB; j++) ee[j] = (s0 + j < a.Sq) ? qs[s0 + j] : make_uint2(0u, 0u);
+#pragma unroll
+      for (int j = 1; j < SUB; j++)
+        if (quarter == j) e = ee[j];
+      valid = s0 + quarter < a.Sq;
+    }
+    if (!valid) continue;
     const int64_t xbase = int64_t(e.x) * ns_in * Bp + b;
     const int64_t ybase = int64_t(e.y & 0x7fffffffu) * Bp;
     const double sgn = (e.y >> 31) ? -1.0 : 1.0;
@@ -149,11 +171,28 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
       }
     }
   }
+  // sum the sub-waves (every lane ends with the total), then let sub-wave j
+  // write the outputs r = j, j+SUB, ...
+  if constexpr (SUB > 1) {
+#pragma unroll
+    for (int g = 0; g < PG; g++)
+#pragma unroll
+      for (int r = 0; r < NOUT; r++) {
+        double x = acc[g][r].x, y = acc[g][r].y;
+#pragma unroll
+        for (int w = TILE; w < 64; w *= 2) {
+          x += __shfl_xor(x, w);
+          y += __shfl_xor(y, w);
+        }
+        acc[g][r] = make_double2(x, y);
+      }
+  }
   CS *Fout = static_cast<CS *>(a.Fout);
 #pragma unroll
   for (int g = 0; g < PG; g++)
 #pragma unroll
     for (int r = 0; r < NOUT; r++) {
+      if (r % SUB != quarter) continue;
       CS o;
       o.x = TS(acc[g][r].x);
       o.y = TS(acc[g][r].y);
@@ -161,17 +200,26 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
     }
 }
 
-template <typename T, int M, int K, int PG>
-static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
+template <typename T, int M, int K, int PG, int TILE>
+static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
-  dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / 64));
-  hipLaunchKernelGGL((stage_kernel<T, M, K, PG>), grid, dim3(64), 0, s, a);
+  dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / TILE));
+  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
-// passthrough group: 3 if it divides the passthrough count, else 2, else 1
+template <typename T, int M, int K, int PG>
+static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
+  return a.tile == 16 ? launch_stage_mkpt<T, M, K, PG, 16>(a, s) : launch_stage_mkpt<T, M, K, PG, 64>(a, s);
+}
+
+// passthrough group: as tuned, else 3 if it divides the passthrough count,
+// else 2, else 1
 template <typename T, int M, int K>
 static hipError_t launch_stage_mk(const StageArgs &a, hipStream_t s) {
+  if (a.pg == 1) return launch_stage_mkp<T, M, K, 1>(a, s);
+  if (a.pg == 2) return launch_stage_mkp<T, M, K, 2>(a, s);
+  if (a.pg == 3) return launch_stage_mkp<T, M, K, 3>(a, s);
   if (a.npass % 3 == 0) return launch_stage_mkp<T, M, K, 3>(a, s);
   if (a.npass % 2 == 0) return launch_stage_mkp<T, M, K, 2>(a, s);
   return launch_stage_mkp<T, M, K, 1>(a, s);

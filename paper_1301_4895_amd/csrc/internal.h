@@ -33,6 +33,7 @@ struct Stage {
   std::vector<uint32_t> qsplit;  // [nq][Sq][2]: x index, y block index | sign<<31
   std::vector<uint32_t> first;   // stage 0: block quark index of every quark part
   int64_t n_lambda = 0;
+  int tune_pg = 0, tune_lds = 0, tune_tile = 64;  // launch tuning (see mb_term_list_tune)
   int64_t nspin() const { return int64_t(nPsets) * nNsets; }
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };

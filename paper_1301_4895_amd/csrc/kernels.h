@@ -55,6 +55,9 @@ struct StageArgs {
   int Sq, nyq, npass;
   int act_is_P;              // 1: added species is the proton
   int M, K;                  // active base-set size, active input subset size
+  int pg;                    // passthrough parts per thread (0 = automatic)
+  int lds_bytes;             // LDS reserved per workgroup
+  int tile;                  // lanes per wavefront: 64 or 16
   int psi_of_pos[8];
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);

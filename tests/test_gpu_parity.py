@@ -193,3 +193,24 @@ def test_mixed_matches_fp64(rel, nsrc, nP, nN, spins, V, nl, dtype):
     _, c32, _ = _run(tl, Su, Sd, w, k, B.MB_MIXED)
     errs = [rel_err(c32[b], c64[b]) for b in range(nl)]
     assert max(errs) <= 1e-6, max(errs)
+
+
+@pytest.mark.parametrize("precision,tol", [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)])
+def test_launch_tuning_keeps_results(precision, tol):
+    """Every launch setting the autotuner may pick gives the same correlators
+    (up to summation order)."""
+    V, nl = 27, 64
+    Su, Sd, w, k = _inputs(13, nl, V, 1, np.complex64, True, with_sink=False)
+    tl = _tl(True, 1, 2, 2, None)
+    _, ref, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
+    for pg, tile, lds in [(1, 16, 0), (2, 64, 16384), (3, 16, 0), (3, 64, 0), (1, 64, 0)]:
+        for s in range(1, 4):
+            try:
+                tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
+            except B.MBError:
+                tl.tune(s, B.MB_TUNE_PASS_GROUP, 1)
+            tl.tune(s, B.MB_TUNE_LANE_TILE, tile)
+            tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
+        _, got, _ = _run(tl, Su, Sd, w, k, precision)
+        errs = [rel_err(got[b], ref[b]) for b in range(nl)]
+        assert max(errs) <= tol, (pg, tile, lds, max(errs))
