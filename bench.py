@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="JSON file of tuned launch settings (read/write)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -121,7 +122,8 @@ def main():
         tuning[prec_name] = None
         if not args.no_autotune:
             from paper_1301_4895_amd import autotune
-            best = autotune.tune(tl, r, log=log)
+            best = autotune.tune(tl, r, key=f"{args.config}|{prec_name}|{chunk}", cache=args.tune_cache,
+                                 log=log)
             tuning[prec_name] = {str(k): {"pass_group": v[0], "lds_bytes": v[1], "lane_tile": v[2],
                                           "ms": round(v[3], 3)} for k, v in best.items()}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)

@@ -259,8 +259,9 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
  * normalisation in the two same-flavour slots (Sec. 4), for every lane.
  * The sum over sites runs in double precision and the blocks are stored in
  * double in both precision modes.
- * Output layout (complex double in both precision modes): proton block [psi][block quark index][lane] followed by the neutron block,
- * lanes padded to a multiple of 64.                                        */
+ * Output layout (complex double in both precision modes): proton block
+ * [block quark index][lane / 16][psi][lane % 16] followed by the neutron
+ * block, lanes padded to a multiple of 64.                                  */
 int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
                    size_t blocks_bytes, void *ws, size_t ws_bytes, void *stream);
 

@@ -21,11 +21,16 @@
  * Complex numbers are C99 `double complex` (layout re, im).
  */
 #include <complex.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef double complex cplx;
+
+/* Threads used by the parallel loops (over independent outputs only). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Dirac algebra in the Dirac representation (Sec. 7: the nonrelativistic
@@ -148,9 +153,11 @@ void orc_blocks(int rel, int nsrc, int npsi, int nxi, int V, const cplx *Su,
     memset(fN, 0, nout * sizeof(cplx));
 #define SP(S, x, row, xi) \
     (scale * (S)[(((long)(x) * nsrc + (xi) % nsrc) * 12 + (row)) * 12 + (xi) / nsrc])
+    /* every output entry is one independent sum, computed by one thread */
+#pragma omp parallel for collapse(2) schedule(dynamic)
     for (int psi = 0; psi < npsi; psi++) {
-        int alpha = psi / nsrc, sk = psi % nsrc;
-        for (int x1 = 0; x1 < nxi; x1++)
+        for (int x1 = 0; x1 < nxi; x1++) {
+            int alpha = psi / nsrc, sk = psi % nsrc;
             for (int x2 = 0; x2 < nxi; x2++)
                 for (int x3 = 0; x3 < nxi; x3++) {
                     cplx sp = 0, sn = 0;
@@ -183,6 +190,7 @@ void orc_blocks(int rel, int nsrc, int npsi, int nxi, int V, const cplx *Su,
                     fP[o] = sp;
                     fN[o] = sn;
                 }
+        }
     }
 #undef SP
 }
@@ -444,7 +452,10 @@ void orc_corr(int nb, const int *types, const int *psis, int npsi, int nxi,
     int *pd = malloc(sizeof(int) * nd * fd), *sd = malloc(sizeof(int) * fd);
     nperms(nu, pu, su, fu);
     nperms(nd, pd, sd, fd);
-    cplx total = 0;
+    /* W(delta; z) for every z (independent, one thread each), then the sum
+     * over z in order */
+    cplx *Wz = malloc(sizeof(cplx) * (nz > 0 ? nz : 1));
+#pragma omp parallel for schedule(dynamic)
     for (long iz = 0; iz < nz; iz++) {
         int ul[32], dl[32], a = 0, b = 0;
         for (int i = 0; i < 32; i++) {
@@ -466,8 +477,11 @@ void orc_corr(int nb, const int *types, const int *psis, int npsi, int nxi,
                 W += prod;
             }
         }
-        total += (double)coef[iz] * W;
+        Wz[iz] = W;
     }
+    cplx total = 0;
+    for (long iz = 0; iz < nz; iz++) total += (double)coef[iz] * Wz[iz];
+    free(Wz);
     (void)npsi;
     *out = total;
     free(pu); free(su); free(pd); free(sd);

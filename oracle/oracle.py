@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         src = os.path.join(_HERE, "oracle.c")
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-shared", "-fPIC",
                                "-o", tmp, src, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -60,6 +60,16 @@ def lib():
         _lib.orc_req_stage.restype = C.c_long
         _lib.orc_lambda_stage.restype = C.c_long
     return _lib
+
+
+def set_threads(n: int):
+    """Threads for the oracle's parallel loops (each output is one thread's
+    sum, so results do not depend on the count)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _p(a):

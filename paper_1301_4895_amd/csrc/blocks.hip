@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void blocks_finish_kernel(FinishArgs a, int nx
   TO o;
   o.x = decltype(o.x)(v.x);
   o.y = decltype(o.y)(v.y);
-  out[comp * a.Bp + b] = o;
+  out[(int64_t(species) * nyq + yq) * npsi * a.Bp + lane_off(b, npsi) + psi * 16] = o;
 }
 
 hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s) {

@@ -248,6 +248,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.Bp = Bp;
       a.nyq = nyq;
       a.ns = int(S0.nspin());
+      a.npsi = tl->npsi;
       psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
     } else if (step < tl->nstages) {
@@ -268,6 +269,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.pg = S.tune_pg;
       a.lds_bytes = S.tune_lds;
       a.tile = S.tune_tile;
+      a.npsi = tl->npsi;
       psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
       if (a.nq_out > 0) HIP_CHECK(launch_stage(a, mixed, s));

@@ -1,10 +1,11 @@
 // Recursion F_-^(s) = F_-^(s-1) . f_T (eq. recr_F) and final contraction with L
 // (eq. C_final) on gfx950.
 //
-// Layout: every stage holds F[q][sigma][lane] -- quark part q (sorted (u, d)
-// sets), spin part sigma = (proton rank) * (#neutron sets) + (neutron rank),
-// lanes (problem, timeslice) innermost, padded to 64, so that one wavefront
-// reads or writes 64 consecutive complex numbers of one component.
+// Layout: every stage holds F[q][tile][sigma][16] -- quark part q, spin part
+// sigma = (proton rank) * (#neutron sets) + (neutron rank), lanes (problem,
+// timeslice) in tiles of 16 (padded to 64 in all), so that 16 lanes of one
+// component are one contiguous row and the rows of one component's spin
+// parts are adjacent.
 //
 // A step adds one baryon of species T.  Its operation list factorises
 // (Sec. 3 with eq. antis_product_2): an output (sigma, q) is a sum over the
@@ -50,11 +51,11 @@ __global__ __launch_bounds__(256) void stage0_kernel(Stage0Args a) {
   const int sig = int(comp % a.ns);
   const double2 *f = static_cast<const double2 *>(a.fblk);
   C2 *F = static_cast<C2 *>(a.Fout);
-  const double2 v = f[(int64_t(a.psi_of_pos[sig]) * a.nyq + a.first[q]) * a.Bp + b];
+  const double2 v = f[int64_t(a.first[q]) * a.npsi * a.Bp + lane_off(b, a.npsi) + a.psi_of_pos[sig] * 16];
   C2 o;
   o.x = T(v.x);
   o.y = T(v.y);
-  F[comp * a.Bp + b] = o;
+  F[q * a.ns * a.Bp + lane_off(b, a.ns) + sig * 16] = o;
 }
 
 hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
 
   int64_t f_off[M];
 #pragma unroll
-  for (int d = 0; d < M; d++) f_off[d] = int64_t(a.psi_of_pos[d]) * a.nyq * Bp + b;
+  for (int d = 0; d < M; d++) f_off[d] = lane_off(b, a.npsi) + a.psi_of_pos[d] * 16;
+  const int64_t in_lane = lane_off(b, ns_in), out_lane = lane_off(b, ns_out);
 
   double2 acc[PG][NOUT];
 #pragma unroll
@@ -131,8 +133,8 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
       valid = s0 + quarter < a.Sq;
     }
     if (!valid) continue;
-    const int64_t xbase = int64_t(e.x) * ns_in * Bp + b;
-    const int64_t ybase = int64_t(e.y & 0x7fffffffu) * Bp;
+    const int64_t xbase = int64_t(e.x) * ns_in * Bp + in_lane;
+    const int64_t ybase = int64_t(e.y & 0x7fffffffu) * a.npsi * Bp;
     const double sgn = (e.y >> 31) ? -1.0 : 1.0;
     double2 fy[M];
 #pragma unroll
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
       double2 fin[NIN];
 #pragma unroll
       for (int r = 0; r < NIN; r++) {
-        const CS v = Fin[xbase + int64_t(sig_in(r, pass0 + g)) * Bp];
+        const CS v = Fin[xbase + sig_in(r, pass0 + g) * 16];
         fin[r] = make_double2(double(v.x), double(v.y));
       }
 #pragma unroll
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
       CS o;
       o.x = TS(acc[g][r].x);
       o.y = TS(acc[g][r].y);
-      Fout[(q * ns_out + sig_out(r, pass0 + g)) * Bp + b] = o;
+      Fout[q * ns_out * Bp + out_lane + sig_out(r, pass0 + g) * 16] = o;
     }
 }
 
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
   const CS *F = static_cast<const CS *>(a.F);
   double ar = 0.0, ai = 0.0;
   const int64_t e0 = a.crow[alpha], e1 = a.crow[alpha + 1];
-  const int64_t off = int64_t(delta) * a.Bp + b;
+  const int64_t off = lane_off(b, a.n_delta) + delta * 16;
   const int64_t rowstride = int64_t(a.n_delta) * a.Bp;
   for (int64_t e = e0; e < e1; e++) {
     const CS v = F[int64_t(a.ccol[e]) * rowstride + off];

@@ -34,13 +34,20 @@ struct FinishArgs {
 };
 hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s);
 
-// Stage 0: F0[q][sigma][b] = f_T0[psi(sigma)][first[q]][b].
+// Lane-blocked layouts (lanes grouped in tiles of 16, Bp = padded lanes):
+//   stage   F[q][tile][sigma][16]     index q*ns*Bp + tile*ns*16 + sigma*16 + l
+//   blocks  f[y][tile][psi][16]       index y*npsi*Bp + tile*npsi*16 + psi*16 + l
+// (species blocks follow each other), so that the rows one thread needs for
+// one operand (its spin parts, its baryon indices) are adjacent in memory.
+__host__ __device__ inline int64_t lane_off(int64_t b, int n) { return (b >> 4) * n * 16 + (b & 15); }
+
+// Stage 0: F0[q][sigma] = f_T0[psi(sigma)][first[q]].
 struct Stage0Args {
   const void *fblk;
   void *Fout;
   const uint32_t *first;
   int64_t nq, Bp;
-  int nyq, ns;
+  int nyq, ns, npsi;
   int psi_of_pos[8];
 };
 hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s);
@@ -58,6 +65,7 @@ struct StageArgs {
   int pg;                    // passthrough parts per thread (0 = automatic)
   int lds_bytes;             // LDS reserved per workgroup
   int tile;                  // lanes per wavefront: 64 or 16
+  int npsi;                  // baryon indices of the block layout
   int psi_of_pos[8];
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);

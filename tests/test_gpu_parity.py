@@ -58,7 +58,8 @@ def _run(tl, Su, Sd, w, k, precision):
     nxi, npsi = c["n_xi"], c["n_psi"]
     nyq = nxi * (nxi - 1) // 2 * nxi
     Bp = (len(Su) + 63) // 64 * 64
-    blocks = r.blocks.view(torch.complex128).view(2, npsi, nyq, Bp)[..., :len(Su)].cpu().numpy()
+    blocks = (r.blocks.view(torch.complex128).view(2, nyq, Bp // 16, npsi, 16).permute(0, 3, 1, 2, 4)
+              .reshape(2, npsi, nyq, Bp)[..., :len(Su)].cpu().numpy())
     return blocks, corr.cpu().numpy(), ex.cpu().numpy()
 
 
