@@ -42,10 +42,12 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
     """Tunes every step on ``runner``'s buffers.
     Returns {step: (pass_group, lds_bytes, lane_tile, ms)}."""
     c = tl.counts()
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
     full_key = f"{key}|{dev}" if key else None
     if cache and full_key and os.path.exists(cache):
         table = json.load(open(cache))
+        if full_key not in table and log:
+            log(f"[autotune] {full_key} not in {cache}: tuning")
         if full_key in table:
             best = {int(s): tuple(v) for s, v in table[full_key].items()}
             for s, (pg, lds, t, _) in best.items():
