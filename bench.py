@@ -36,6 +36,61 @@ CONFIGS = {
                c128=False),
 }
 M_DECAY = 0.5
+
+# The uneven batch: 64 problems drawn by seed from four nuclei, L in
+# {16, 24, 32}, T in {32, 64, 96}, complex64 propagators, 2^k(t) rescale.
+MIX_TYPES = [
+    dict(name="p+n NR all", nP=1, nN=1, rel=False, nsrc=1, spins=None),
+    dict(name="3He NR all", nP=2, nN=1, rel=False, nsrc=1, spins=None),
+    dict(name="4He rel all", nP=2, nN=2, rel=True, nsrc=1, spins=None),
+    dict(name="8Be NR 2src", nP=4, nN=4, rel=False, nsrc=2, spins=(0, 1, 2, 3, 0, 1, 2, 3)),
+]
+MIX_SEED, MIX_N, MIX_STREAM0 = 2013, 64, 1000
+
+
+def mix_groups(dev, types=None, n=MIX_N, seed=MIX_SEED):
+    """Groups (nucleus, L) of the uneven batch with device propagators; the
+    propagators of problem p are dataset stream MIX_STREAM0 + p (one problem
+    of its own T).  Returns (groups, term lists by type, problem list)."""
+    import numpy as np
+    import torch
+
+    from paper_1301_4895_amd import binding as B
+    from synth.gpu import fill_props
+    from synth.props import mix_problems, momentum_phase
+    probs = mix_problems(seed, n, len(MIX_TYPES))
+    types = sorted({t for t, _, _ in probs}) if types is None else types
+    tls = {}
+    for t in types:
+        m = MIX_TYPES[t]
+        tls[t] = (B.TermList(m["nP"], m["nN"], m["rel"], m["nsrc"], all_components=True) if m["spins"] is None
+                  else B.TermList.spin_state(m["nP"], m["nN"], m["rel"], m["nsrc"], m["spins"]))
+        tls[t].upload(dev)
+    groups = []
+    for t in types:
+        for L in sorted({L for tt, L, _ in probs if tt == t}):
+            members = [(p, T) for p, (tt, LL, T) in enumerate(probs) if tt == t and LL == L]
+            lanes = sum(T for _, T in members)
+            nsrc = MIX_TYPES[t]["nsrc"]
+            V = L ** 3
+            props = torch.empty((lanes, V, nsrc, 12, 12), dtype=torch.complex64, device=dev)
+            kexp, units, off = [], [], 0
+            for p, T in members:
+                per = max(1, (1 << 31) // (V * nsrc * 144))
+                for b0 in range(0, T, per):
+                    b1 = min(T, b0 + per)
+                    fill_props(props[off + b0:off + b1], seed=seed, stream_id=MIX_STREAM0 + p, V=V, nsrc=nsrc,
+                               T=T, first_bt=b0, m=M_DECAY)
+                kexp += [int(math.floor(M_DECAY * t_ / math.log(2.0) + 0.5)) for t_ in range(T)]
+                units += [(p, t_, T) for t_ in range(T)]
+                off += T
+            sink = None
+            if nsrc == 2:
+                sink = torch.from_numpy(np.stack([np.ones(V, np.complex128), momentum_phase(L, 1)])).to(dev)
+            groups.append(dict(name=f"{MIX_TYPES[t]['name']} L={L}", type=t, L=L, tl=tls[t], props=props,
+                               sink_w=sink, scale_exp=torch.tensor(kexp, dtype=torch.int32, device=dev),
+                               units=units))
+    return groups, tls, probs
 VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
 HBM_PEAK_GBS = 8000.0
 
@@ -51,23 +106,8 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS))
-    ap.add_argument("--chunk", type=int, default=256, help="lanes per launch")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tune-cache", default=None, help="JSON file of tuned launch settings (read/write)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(lanes are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
-
+def run_workload(name, args):
+    """Times one workload on both paths; returns its summary."""
     import numpy as np
     import torch
 
@@ -76,7 +116,7 @@ def main():
     from synth.gpu import fill_props
     from synth.props import momentum_phase
 
-    cfg = CONFIGS[args.config]
+    cfg = CONFIGS[name]
     dev = torch.device("cuda:0")
     V, T, nprob, nsrc = cfg["L"] ** 3, cfg["T"], cfg["nprob"], cfg["nsrc"]
     lanes = nprob * T
@@ -88,7 +128,7 @@ def main():
     tl.upload(dev)
     counts = tl.counts()
     t_list = time.time() - t0
-    log(f"[bench] {args.config}: term list {counts['n_lambda']} ops, built+uploaded in {t_list:.1f}s")
+    log(f"[bench] {name}: term list {counts['n_lambda']} ops, built+uploaded in {t_list:.1f}s")
 
     cdt = torch.complex128 if cfg["c128"] else torch.complex64
     props = torch.empty((lanes, V, nsrc, 12, 12), dtype=cdt, device=dev)
@@ -122,10 +162,11 @@ def main():
         tuning[prec_name] = None
         if not args.no_autotune:
             from paper_1301_4895_amd import autotune
-            best = autotune.tune(tl, r, key=f"{args.config}|{prec_name}|{chunk}", cache=args.tune_cache,
+            best = autotune.tune(tl, r, key=f"{name}|{prec_name}|{chunk}", cache=args.tune_cache,
                                  log=log)
-            tuning[prec_name] = {str(k): {"pass_group": v[0], "lds_bytes": v[1], "lane_tile": v[2],
-                                          "ms": round(v[3], 3)} for k, v in best.items()}
+            tuning[prec_name] = {str(k): {"kernel": "lds-staged" if v[0] else "direct", "pass_group": v[1],
+                                          "lds_bytes": v[2], "lane_tile": v[3], "ms": round(v[4], 3)}
+                                 for k, v in best.items()}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
         ev = {}
 
@@ -199,7 +240,7 @@ def main():
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         t = json.load(open(tf))
-        key = f"{args.config}:{main_name}:{dom}"
+        key = f"{name}:{main_name}:{dom}"
         if t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {}):
             traffic = t["bytes_per_launch"][key]
     roofline = dict(bound="alu", kernel=f"recursion {dom} ({'proton' if counts['path'][s] == 0 else 'neutron'} added)",
@@ -207,36 +248,158 @@ def main():
                     frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=traffic,
                     flops_per_launch=flops, launch_ms=round(res["kernel_avg_ms"][dom], 4))
 
+    return dict(name=name, cfg=cfg, lanes=lanes, V=V, counts=counts, chunk=chunk, results=results,
+                main=main_name, err=err, err_stats=err_stats, roofline=roofline, tuning=tuning, t_list=t_list)
+
+
+def run_mix(args):
+    """The uneven batch as one graph launch per step, mixed and FP64."""
+    import numpy as np
+    import torch
+
+    from paper_1301_4895_amd import binding as B
+    from paper_1301_4895_amd.batch import BatchRunner, tune_nuclei
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    groups, tls, probs = mix_groups(dev)
+    lanes = sum(g["props"].shape[0] for g in groups)
+    log(f"[bench] mix: {len(probs)} problems, {len(groups)} groups, {lanes} lanes, "
+        f"{sum(g['props'].numel() * 8 for g in groups) / 1e9:.1f} GB of propagators ({time.time() - t0:.1f}s)")
+    results, outs, tuning = {}, {}, {}
+    for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
+        if args.only and prec_name != args.only:
+            continue
+        if not args.no_autotune:
+            tune_nuclei(groups, prec, args.chunk, cache=args.tune_cache, key="c5", log=log)
+        br = BatchRunner(groups, prec, n_branches=4, chunk=args.chunk)
+        times = br.tune_branches(log=log) if not args.no_autotune else None
+        tuning[prec_name] = dict(branches=br.n_branches, graph_ms_by_branches=times)
+        for _ in range(args.warmup):
+            br.launch()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            br.launch()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.steps
+        results[prec_name] = dict(ms_per_step=ms, value=lanes / (ms / 1e3), kernel_avg_ms={},
+                                  kernels_per_graph=br.kernel_count())
+        outs[prec_name] = [c.cpu().numpy() for c in br.corr]
+        log(f"[bench] mix {prec_name}: {ms:.2f} ms per graph launch ({br.kernel_count()} kernels, "
+            f"{br.n_branches} branches), {lanes / (ms / 1e3):.1f} timeslices/s")
+        br.batch.close()
+        del br
+        torch.cuda.empty_cache()
+    err = err_stats = None
+    if len(outs) == 2:
+        per_lane = np.concatenate([
+            np.linalg.norm((a - b).reshape(a.shape[0], -1), axis=1) / np.linalg.norm(b.reshape(b.shape[0], -1), axis=1)
+            for a, b in zip(outs["mixed"], outs["fp64"])])
+        err = float(per_lane.max())
+        err_stats = dict(median=float(np.median(per_lane)), p99=float(np.quantile(per_lane, 0.99)), max=err)
+        log(f"[bench] mix rel err mixed vs fp64: median {err_stats['median']:.2e} max {err:.3e}")
+    main_name = "mixed" if "mixed" in results else "fp64"
+    cfg = dict(workload=f"uneven batch: {len(probs)} problems drawn by seed {MIX_SEED} from "
+                        f"{', '.join(m['name'] for m in MIX_TYPES)}; L in {{16,24,32}}, T in {{32,64,96}}; "
+                        f"complex64, one graph launch")
+    return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=args.chunk,
+                results=results, main=main_name, err=err, err_stats=err_stats, roofline=None, tuning=tuning,
+                t_list=0.0)
+
+
+def summary(w):
+    res = w["results"][w["main"]]
+    fp = w["results"].get("fp64")
+    return {
+        "value": round(res["value"], 2),
+        "ms_per_step": round(res["ms_per_step"], 3),
+        "config": {"workload": w["cfg"]["workload"], "lanes": w["lanes"], "V": w["V"],
+                   "n_lambda": w["counts"]["n_lambda"], "lanes_per_launch": w["chunk"], "precision": w["main"]},
+        "fp64": ({"value": round(fp["value"], 2), "ms_per_step": round(fp["ms_per_step"], 3),
+                  "speedup_mixed_over_fp64": round(res["value"] / fp["value"], 3)}
+                 if fp is not None and w["main"] == "mixed" else None),
+        "max_rel_err_mixed_vs_fp64": w["err"],
+        "rel_err_mixed_vs_fp64_per_lane": w["err_stats"],
+        "kernel_avg_ms": {k: round(v, 4) for k, v in res["kernel_avg_ms"].items()},
+        "roofline": w["roofline"],
+        "term_list_build_s": round(w["t_list"], 2),
+        "autotune": w["tuning"],
+    }
+
+
+def calibrate_copy():
+    """A plain device copy of known size (1 GiB, three times), the yardstick
+    for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied 3 x {n} bytes", flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3+c4", choices=sorted(CONFIGS) + ["c3+c4", "c5"],
+                    help="workload; c3+c4 times 4He relativistic (the reported value) and 8Be NR")
+    ap.add_argument("--chunk", type=int, default=256, help="lanes per launch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="JSON file of tuned launch settings (read/write)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(lanes are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    names = ["c3", "c4"] if args.config == "c3+c4" else [args.config]
+    ws = [run_mix(args) if n == "c5" else run_workload(n, args) for n in names]
+    first = summary(ws[0])
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, args.config)
+    if not args.no_cpu_baseline and names[0] != "c5":
+        cpu = cpu_baseline(ws[0]["cfg"], names[0])
 
     line = {
         "metric": "correlator timeslices/s (4He rel., 8Be NR): mixed vs FP64 GPU, rel err<=1e-6",
-        "value": round(res["value"], 2),
+        "value": first["value"],
         "unit": "timeslices/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(res["ms_per_step"], 3),
+        "ms_per_step": first["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if main_name == "mixed" else "f64",
+        # both paths multiply and add in double; the mixed path stores the
+        # recursion stages in float
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["workload"], "lanes": lanes, "V": V, "n_lambda": counts["n_lambda"],
-                   "lanes_per_launch": chunk, "precision": main_name},
-        "fp64": ({"value": round(results["fp64"]["value"], 2), "ms_per_step": round(results["fp64"]["ms_per_step"], 3),
-                  "speedup_mixed_over_fp64": round(res["value"] / results["fp64"]["value"], 3)}
-                 if "fp64" in results and main_name == "mixed" else None),
-        "max_rel_err_mixed_vs_fp64": err,
-        "rel_err_mixed_vs_fp64_per_lane": err_stats,
-        "kernel_avg_ms": {k: round(v, 4) for k, v in res["kernel_avg_ms"].items()},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "term_list_build_s": round(t_list, 2),
-        "autotune": tuning,
+        "config": dict(first["config"], storage=("f32 stages, f64 blocks" if ws[0]["main"] == "mixed"
+                                                 else "f64")),
     }
+    for k in ("fp64", "max_rel_err_mixed_vs_fp64", "rel_err_mixed_vs_fp64_per_lane", "kernel_avg_ms",
+              "roofline"):
+        line[k] = first[k]
+    line["cpu_baseline"] = cpu
+    for k in ("term_list_build_s", "autotune"):
+        line[k] = first[k]
+    if len(ws) > 1:
+        line["second_workload"] = summary(ws[1])
     print(json.dumps(line), flush=True)
 
 
@@ -256,7 +419,7 @@ def cpu_baseline(cfg, name):
         return {"value": None, "unit": "timeslices/s", "cores": threads, "kind": "oracle",
                 "sample": "infeasible: the oracle's permutation sum has n_u! n_d! = (12!)^2 terms per "
                           "component for 8Be"}
-    nsite = min(V, 2048 if cfg["rel"] else 4096)
+    nsite = V
     S = SP.props(2013, 0, cfg["nprob"], cfg["T"], V, cfg["nsrc"], M_DECAY, np.complex128, probs=[0],
                  ts=[1])[0, 0]
     t = time.time()
@@ -267,7 +430,10 @@ def cpu_baseline(cfg, name):
     types = [0] * cfg["nP"] + [1] * cfg["nN"]
     dsets = O.delta_sets(cfg["nP"], cfg["nN"], req)
     nL = {a: len(O.L_for_alpha(cfg["rel"], cfg["nsrc"], cfg["nP"], cfg["nN"], a)[0]) for a in req["alphas"]}
-    sample_pairs = [(dsets[i % len(dsets)], req["alphas"][i % len(req["alphas"])]) for i in range(3)]
+    # 12 (sink set, source set) pairs spread over the requested ones
+    npairs = min(12, len(dsets) * len(req["alphas"]))
+    sample_pairs = [(dsets[(7 * i) % len(dsets)], req["alphas"][(11 * i) % len(req["alphas"])])
+                    for i in range(npairs)]
     t = time.time()
     nl_sample = 0
     for d, a in sample_pairs:

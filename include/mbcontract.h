@@ -130,6 +130,7 @@ int mb_build_term_list_counts_only(const mb_nucleus *nuc, const mb_spin_request 
 void mb_term_list_free(mb_term_list *tl);
 
 #define MB_MAX_STAGES 16
+#define MB_MAX_BATCH 65535     /* lanes per call */
 
 /* Sizes of a term list.  Stage s (0-based) holds the components with the
  * first s+1 baryons of the path; step s (s >= 1) forms stage s from stage
@@ -172,7 +173,10 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
  *                    stage's order (proton rank major)
  *   MB_EXPORT_QSPLIT uint32 [n_quark][S][2] for stage >= 1: per output quark
  *                    part, per split: (quark part index in stage-1,
- *                    block quark index | sign bit 31 set for -1)
+ *                    block quark index | sign bit 31 set for -1); the splits
+ *                    of an output are ordered by the added baryon's single
+ *                    quark index (d of a proton, u of a neutron), then by
+ *                    the rank of its same-flavour pair
  *   MB_EXPORT_SSPLIT int32 [n_spin][k][3] for stage >= 1: per output spin
  *                    part, per split: (spin part index in stage-1, baryon
  *                    index psi of the added baryon, sign +1/-1)
@@ -198,16 +202,23 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
  * an autotuner; results do not depend on it.
  *   MB_TUNE_PASS_GROUP  passthrough spin parts per thread: 0 = automatic
  *                       (3, 2 or 1, the largest that divides their count),
- *                       or 1, 2, 3 (must divide the count)
+ *                       or 1, 2, 3, 6 (must divide the count; the LDS kernel
+ *                       takes 6 as automatic)
  *   MB_TUNE_LDS_BYTES   LDS reserved per workgroup (0..65536), which caps the
  *                       number of resident workgroups per CU (fewer operands
  *                       in flight per L2)
  *   MB_TUNE_LANE_TILE   lanes per wavefront, 64 (default) or 16 (four
  *                       sub-waves share the quark splits of an output)
+ *   MB_TUNE_KERNEL      0 (default): every thread gathers its block entries
+ *                       from global memory; 1: the block rows of one single
+ *                       quark index at a time are staged in LDS per
+ *                       workgroup of 16 lanes x 16 outputs (lane tile and
+ *                       LDS bytes are then fixed)
  * Returns MB_EINVAL for an unknown item, step or value.                      */
 #define MB_TUNE_PASS_GROUP 1
 #define MB_TUNE_LDS_BYTES 2
 #define MB_TUNE_LANE_TILE 3
+#define MB_TUNE_KERNEL 4
 int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
 
 /* Copies the operation tables to device memory `dev` (caller-owned, at least
@@ -219,7 +230,8 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
 int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream);
 
 /* One batch of independent (problem, timeslice) units ("lanes").
- *   batch      B, number of lanes
+ *   batch      B, number of lanes, 1..MB_MAX_BATCH (MB_EUNSUPPORTED above;
+ *              larger sets of lanes are cut into several calls)
  *   V          sink sites per timeslice
  *   in_dtype   MB_C64 or MB_C128, element type of the propagators
  *   precision  MB_FP64 or MB_MIXED
@@ -285,6 +297,58 @@ int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p,
 int mb_contract_step(const mb_term_list *tl, const mb_problem *p, const void *blocks,
                      size_t blocks_bytes, int step, double *corr_out, int32_t *exp_out, void *ws,
                      size_t ws_bytes, void *stream);
+
+/* ---- Batched runs of uneven work (many nuclei, volumes, lanes) ----------
+ * Lanes of different nuclei or volumes cannot share a launch, so a batch is
+ * a list of items, each one (term list, problem) with its own buffers, run
+ * as one captured HIP graph: the items are spread over n_branches
+ * concurrent branches (forked from and joined back into the launch stream),
+ * every branch running its items one after the other (blocks, then every
+ * contraction step).  Small items then overlap with large ones.  Every
+ * computation is that of mb_make_blocks + mb_contract_correlator (Sec. 2,
+ * eq. recr_F, eq. C_final); only the order of independent launches differs. */
+typedef struct {
+    const mb_term_list *tl;   /* uploaded; its launch tuning is read at capture */
+    mb_problem prob;
+    void *blocks;             /* device buffers sized by mb_workspace_query  */
+    size_t blocks_bytes;
+    void *blocks_ws;
+    size_t blocks_ws_bytes;
+    void *contract_ws;
+    size_t contract_ws_bytes;
+    double *corr_out;         /* as for mb_contract_correlator               */
+    int32_t *exp_out;         /* may be NULL                                 */
+    int branch;               /* 0..n_branches-1                             */
+} mb_batch_item;
+
+/* Host-side scheduler: estimates the cost of every item (algorithmic flops
+ * of its blocks and of its recursion, over its lanes; written to cost_out
+ * if not NULL) and assigns the items to branches longest first, each to the
+ * branch with the least work so far (branch_out[n_items]).  Items on one
+ * branch run one after the other, so they may share their blocks and
+ * workspace buffers; items on different branches may not.                 */
+int mb_batch_plan(const mb_term_list *const *tls, const mb_problem *probs, int n_items,
+                  int n_branches, int *branch_out, double *cost_out);
+
+typedef struct mb_batch mb_batch;
+
+/* Validates every item (as the single calls would), checks that no two
+ * items on different branches share a blocks or workspace buffer, and
+ * records the launches of all items into a HIP graph (on streams of its own,
+ * default priority) which it instantiates.  Items on one branch run in the
+ * order given.  Nothing runs until mb_batch_launch.  The buffers and term
+ * lists must stay alive and keep their addresses while the batch exists;
+ * their contents are read at launch time.  MB_EHIP if capture fails.       */
+int mb_batch_create(const mb_batch_item *items, int n_items, int n_branches, mb_batch **out);
+
+/* Launches the whole batch on `stream` (one graph launch).  Launches of one
+ * batch on streams that are not ordered with each other race.              */
+int mb_batch_launch(mb_batch *b, void *stream);
+
+/* Number of kernel nodes of the recorded graph. */
+int mb_batch_kernel_count(const mb_batch *b, int64_t *out);
+
+void mb_batch_free(mb_batch *b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *mb_last_error(void);

@@ -20,7 +20,7 @@ MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST = 0, 1, 2
 MB_C64, MB_C128 = 0, 1
 MB_FP64, MB_MIXED = 0, 1
 MB_MAX_STAGES = 16
-MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE = 1, 2, 3
+MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL = 1, 2, 3, 4
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
  MB_EXPORT_DELTA, MB_EXPORT_ALPHA) = range(1, 8)
 
@@ -28,6 +28,7 @@ EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_term_list_free",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
     "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune",
+    "mb_batch_plan", "mb_batch_create", "mb_batch_launch", "mb_batch_kernel_count", "mb_batch_free",
     "mb_last_error",
 ]
 
@@ -63,6 +64,13 @@ class mb_problem(C.Structure):
                 ("sink_w", C.c_void_p), ("scale_exp", C.c_void_p)]
 
 
+class mb_batch_item(C.Structure):
+    _fields_ = [("tl", C.c_void_p), ("prob", mb_problem), ("blocks", C.c_void_p),
+                ("blocks_bytes", C.c_size_t), ("blocks_ws", C.c_void_p), ("blocks_ws_bytes", C.c_size_t),
+                ("contract_ws", C.c_void_p), ("contract_ws_bytes", C.c_size_t), ("corr_out", C.c_void_p),
+                ("exp_out", C.c_void_p), ("branch", C.c_int)]
+
+
 _lib = None
 
 
@@ -89,6 +97,13 @@ def lib():
         L.mb_contract_step.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, C.c_int, P, P, P,
                                        C.c_size_t, P]
         L.mb_term_list_tune.argtypes = [P, C.c_int, C.c_int, C.c_int]
+        L.mb_batch_plan.argtypes = [C.POINTER(P), C.POINTER(mb_problem), C.c_int, C.c_int,
+                                    C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.mb_batch_create.argtypes = [C.POINTER(mb_batch_item), C.c_int, C.c_int, C.POINTER(P)]
+        L.mb_batch_launch.argtypes = [P, P]
+        L.mb_batch_kernel_count.argtypes = [P, C.POINTER(C.c_int64)]
+        L.mb_batch_free.argtypes = [P]
+        L.mb_batch_free.restype = None
         L.mb_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -203,3 +218,60 @@ def contract_step(tl: TermList, p: mb_problem, blocks, step, corr, exp_out, ws, 
         C.c_void_p(corr.data_ptr()) if corr is not None else None,
         C.c_void_p(exp_out.data_ptr()) if exp_out is not None else None,
         C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))
+
+
+def batch_plan(tls, probs, n_branches):
+    """Branch of every item (longest first onto the least loaded branch) and
+    the cost estimate of every item (algorithmic flops)."""
+    n = len(tls)
+    ta = (C.c_void_p * n)(*[t.h for t in tls])
+    pa = (mb_problem * n)(*probs)
+    br = (C.c_int * n)()
+    cost = (C.c_double * n)()
+    _check(lib().mb_batch_plan(ta, pa, n, n_branches, br, cost))
+    return list(br), list(cost)
+
+
+class Batch:
+    """A recorded batch (mb_batch_create): items are dicts with keys tl,
+    prob, blocks, blocks_ws, contract_ws, corr, exp (torch tensors or None)
+    and branch."""
+
+    def __init__(self, items, n_branches):
+        n = len(items)
+        arr = (mb_batch_item * n)()
+
+        def nbytes(t):
+            return t.numel() * t.element_size()
+        for i, it in enumerate(items):
+            arr[i] = mb_batch_item(it["tl"].h, it["prob"], it["blocks"].data_ptr(), nbytes(it["blocks"]),
+                                   it["blocks_ws"].data_ptr(), nbytes(it["blocks_ws"]),
+                                   it["contract_ws"].data_ptr(), nbytes(it["contract_ws"]),
+                                   it["corr"].data_ptr(),
+                                   it["exp"].data_ptr() if it.get("exp") is not None else None,
+                                   it["branch"])
+        h = C.c_void_p()
+        _check(lib().mb_batch_create(arr, n, n_branches, C.byref(h)))
+        self.h = h
+        self._items = items   # keeps the buffers alive
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib().mb_batch_launch(self.h, C.c_void_p(s)))
+
+    def kernel_count(self):
+        n = C.c_int64()
+        _check(lib().mb_batch_kernel_count(self.h, C.byref(n)))
+        return n.value
+
+    def close(self):
+        if self.h:
+            lib().mb_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

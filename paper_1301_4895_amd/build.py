@@ -38,7 +38,7 @@ def _compile(src, obj, kind):
 def build_library(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs = []
-    for name, kind in [("termlist.cpp", "host"), ("capi.cpp", "hipapi"), ("blocks.hip", "hip"),
+    for name, kind in [("termlist.cpp", "host"), ("capi.cpp", "hipapi"), ("batch.cpp", "hipapi"), ("blocks.hip", "hip"),
                        ("contract.hip", "hip")]:
         obj = os.path.join(BUILD_DIR, name + ".o")
         _compile(os.path.join(CSRC, name), obj, kind)

@@ -41,7 +41,7 @@ int nchunks_for(int64_t B, int64_t V) {
 int check_problem(const mb_term_list *tl, const mb_problem *p) {
   if (!tl || !p) return fail(MB_EINVAL, "null argument");
   if (p->batch < 1 || p->V < 1) return fail(MB_EINVAL, "batch and V must be positive");
-  if (p->batch > (int64_t(1) << 26)) return fail(MB_EUNSUPPORTED, "batch too large");
+  if (p->batch > MB_MAX_BATCH) return fail(MB_EUNSUPPORTED, "batch above MB_MAX_BATCH lanes");
   if (p->in_dtype != MB_C64 && p->in_dtype != MB_C128) return fail(MB_EINVAL, "bad in_dtype");
   if (p->precision != MB_FP64 && p->precision != MB_MIXED) return fail(MB_EINVAL, "bad precision");
   if (tl->counts_only) return fail(MB_EINVAL, "counts-only term list");
@@ -94,32 +94,54 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
   if (bytes < need) return fail(MB_ENOWORKSPACE, "device buffer smaller than device_bytes");
   if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(MB_EINVAL, "device buffer not 256-byte aligned");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // a failed copy still waits for the copies already queued: their host
+  // sources are locals of this function
+#define UPLOAD_CHECK(expr)                                                        \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      (void)hipStreamSynchronize(s);                                              \
+      return fail(MB_EHIP, std::string(#expr ": ") + hipGetErrorString(e_));      \
+    }                                                                             \
+  } while (0)
   char *base = static_cast<char *>(dev);
   size_t o = 0;
   tl->off_qsplit.assign(tl->nstages, 0);
+  tl->off_masks.assign(tl->nstages, 0);
+  std::vector<std::vector<uint32_t>> masks(tl->nstages);   // kept alive until the copies finish
   for (int st = 1; st < tl->nstages; st++) {
     tl->off_qsplit[st] = o;
     const auto &v = tl->st[st].qsplit;
-    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    if (!v.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
     o += al256(v.size() * 4);
+    tl->off_masks[st] = o;
+    auto &m = masks[st];
+    m.resize(tl->st[st].quark.size() * 2);
+    for (size_t i = 0; i < tl->st[st].quark.size(); i++) {
+      m[2 * i] = qkey_u(tl->st[st].quark[i]);
+      m[2 * i + 1] = qkey_d(tl->st[st].quark[i]);
+    }
+    if (!m.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, m.data(), m.size() * 4, hipMemcpyHostToDevice, s));
+    o += al256(m.size() * 4);
   }
   tl->off_first = o;
   {
     const auto &v = tl->st[0].first;
-    if (!v.empty()) HIP_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    if (!v.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
     o += al256(v.size() * 4);
   }
   tl->off_crow = o;
-  HIP_CHECK(hipMemcpyAsync(base + o, tl->crow.data(), tl->crow.size() * 8, hipMemcpyHostToDevice, s));
+  UPLOAD_CHECK(hipMemcpyAsync(base + o, tl->crow.data(), tl->crow.size() * 8, hipMemcpyHostToDevice, s));
   o += al256(tl->crow.size() * 8);
   tl->off_ccol = o;
   std::vector<int32_t> col(tl->ccol.begin(), tl->ccol.end());
   std::vector<double> val(tl->cval.begin(), tl->cval.end());
-  if (!col.empty()) HIP_CHECK(hipMemcpyAsync(base + o, col.data(), col.size() * 4, hipMemcpyHostToDevice, s));
+  if (!col.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, col.data(), col.size() * 4, hipMemcpyHostToDevice, s));
   o += al256(col.size() * 4);
   tl->off_cval = o;
-  if (!val.empty()) HIP_CHECK(hipMemcpyAsync(base + o, val.data(), val.size() * 8, hipMemcpyHostToDevice, s));
+  if (!val.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, val.data(), val.size() * 8, hipMemcpyHostToDevice, s));
   o += al256(val.size() * 8);
+#undef UPLOAD_CHECK
   HIP_CHECK(hipStreamSynchronize(s));
   tl->dev = dev;
   tl->dev_bytes = bytes;
@@ -134,7 +156,7 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
     Stage &S = tl->st[s];
     const int npass = S.type == PROTON ? S.nNsets : S.nPsets;
     if (what == MB_TUNE_PASS_GROUP) {
-      if (value < 0 || value > 3 || (value > 0 && npass % value != 0)) {
+      if (value < 0 || value > 6 || value == 4 || value == 5 || (value > 0 && npass % value != 0)) {
         if (step != -1) return fail(MB_EINVAL, "passthrough group must divide the passthrough count");
         continue;
       }
@@ -142,6 +164,9 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
     } else if (what == MB_TUNE_LANE_TILE) {
       if (value != 16 && value != 64) return fail(MB_EINVAL, "lane tile must be 16 or 64");
       S.tune_tile = value;
+    } else if (what == MB_TUNE_KERNEL) {
+      if (value != 0 && value != 1) return fail(MB_EINVAL, "kernel must be 0 or 1");
+      S.tune_kernel = value;
     } else if (what == MB_TUNE_LDS_BYTES) {
       if (value < 0 || value > 65536) return fail(MB_EINVAL, "LDS bytes out of range");
       S.tune_lds = value;
@@ -272,7 +297,33 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.npsi = tl->npsi;
       psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
-      if (a.nq_out > 0) HIP_CHECK(launch_stage(a, mixed, s));
+      if (a.nq_out > 0 && S.tune_kernel == 1) {
+        StageLdsArgs b{};
+        b.Fin = a.Fin;
+        b.Fout = a.Fout;
+        b.fblk = a.fblk;
+        b.qsplit = a.qsplit;
+        b.masks = reinterpret_cast<const uint32_t *>(img + tl->off_masks[step]);
+        b.nq_out = a.nq_out;
+        b.Bp = Bp;
+        b.Sq = S.Sq;
+        b.pp = S.Sq / (S.type == PROTON ? S.kd : S.ku);
+        b.npass = a.npass;
+        b.pg = (S.tune_pg >= 1 && S.tune_pg <= 3) ? S.tune_pg : (a.npass % 3 == 0 ? 3 : a.npass % 2 == 0 ? 2 : 1);
+        b.npg = a.npass / b.pg;
+        b.act_is_P = a.act_is_P;
+        b.M = a.M;
+        b.K = a.K;
+        b.nxi = nxi;
+        b.npair = nxi * (nxi - 1) / 2;
+        b.npsi = tl->npsi;
+        b.bsplit = nxi > 9 ? 9 : nxi;
+        b.div_magic = uint32_t(((uint64_t(1) << 32) + uint64_t(nxi) - 1) / uint64_t(nxi));
+        for (int i = 0; i < 8; i++) b.psi_of_pos[i] = a.psi_of_pos[i];
+        HIP_CHECK(launch_stage_lds(b, mixed, s));
+      } else if (a.nq_out > 0) {
+        HIP_CHECK(launch_stage(a, mixed, s));
+      }
     } else {
       const Stage &SN = tl->st[tl->nstages - 1];
       FinalArgs a{};

@@ -40,6 +40,34 @@ __host__ __device__ constexpr int rank_c(int mask) {
   return r;
 }
 
+// The spin wedge of one quark split: out-set (K+1 elements of the M-element
+// base set) += sum over its elements d of sgn(d) x fin[out minus d] x fy[d],
+// sgn(d) = parity of moving d behind the other elements (eq. antis_product_2
+// restricted to one species).  Resolved at compile time.
+template <int M, int K>
+__device__ __forceinline__ void wedge_accumulate(const double2 *fin, const double2 *fy, double2 *acc) {
+#pragma unroll
+  for (int out = 0; out < (1 << M); out++) {
+    if (popc(out) != K + 1) continue;
+    const int ro = rank_c(out);
+#pragma unroll
+    for (int d = 0; d < M; d++) {
+      if (!((out >> d) & 1)) continue;
+      const int in = out & ~(1 << d);
+      const int ri = rank_c(in);
+      const bool neg = popc(in >> (d + 1)) & 1;
+      const double2 x = fin[ri], y = fy[d];
+      if (neg) {
+        acc[ro].x -= x.x * y.x - x.y * y.y;
+        acc[ro].y -= x.x * y.y + x.y * y.x;
+      } else {
+        acc[ro].x += x.x * y.x - x.y * y.y;
+        acc[ro].y += x.x * y.y + x.y * y.x;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void stage0_kernel(Stage0Args a) {
@@ -150,27 +178,7 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
         const CS v = Fin[xbase + sig_in(r, pass0 + g) * 16];
         fin[r] = make_double2(double(v.x), double(v.y));
       }
-#pragma unroll
-      for (int out = 0; out < (1 << M); out++) {
-        if (popc(out) != K + 1) continue;
-        const int ro = rank_c(out);
-#pragma unroll
-        for (int d = 0; d < M; d++) {
-          if (!((out >> d) & 1)) continue;
-          const int in = out & ~(1 << d);
-          const int ri = rank_c(in);
-          // moving element d behind the remaining elements of the set
-          const bool neg = popc(in >> (d + 1)) & 1;
-          const double2 x = fin[ri], y = fy[d];
-          if (neg) {
-            acc[g][ro].x -= x.x * y.x - x.y * y.y;
-            acc[g][ro].y -= x.x * y.y + x.y * y.x;
-          } else {
-            acc[g][ro].x += x.x * y.x - x.y * y.y;
-            acc[g][ro].y += x.x * y.y + x.y * y.x;
-          }
-        }
-      }
+      wedge_accumulate<M, K>(fin, fy, acc[g]);
     }
   }
   // sum the sub-waves (every lane ends with the total), then let sub-wave j
@@ -202,6 +210,168 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Recursion step with the block of the added species staged in LDS.
+//
+// A workgroup owns 16 lanes (one lane tile) and NSLOT consecutive (output
+// quark part, passthrough group) slots; thread = (slot, lane).  The block
+// entries of a split are f_T[y][psi] with y = (pair of the same-flavour
+// quarks, single quark): every split of an output with single index p reads
+// rows y = (*, p) only.  So the workgroup walks the single indices its
+// outputs contain ("phases"), loads the rows (pair, p) of its lane tile into
+// LDS -- in two ranges of pairs, so that one range of M baryon indices x 16
+// lanes stays within 36 KB -- and every thread then runs the splits of its
+// output that belong to the phase and range, reading the previous stage
+// from global memory and the block from LDS.  Per split the global traffic
+// is the NIN x PG previous components only; the block rows are fetched once
+// per workgroup and phase.
+template <typename TS, int M, int K, int PG>
+__global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
+  using CS = typename c2<TS>::type;
+  constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
+  constexpr int NSLOT = 16;
+  extern __shared__ double2 ylds[];   // [row][d][16 lanes]
+  __shared__ uint32_t wg_single;
+  const int l = threadIdx.x & 15, slot = threadIdx.x >> 4;
+  const int64_t tile = blockIdx.y;
+  const int64_t nwg = gridDim.x;      // a multiple of 8
+  const int64_t wr = blockIdx.x;
+  // workgroups are dispatched round-robin over the 8 XCDs: give every XCD a
+  // contiguous range of outputs
+  const int64_t w = (wr % 8) * (nwg / 8) + wr / 8;
+  const int64_t gs = w * NSLOT + slot;
+  const bool active = gs < a.nq_out * a.npg;
+  const int64_t q = active ? gs / a.npg : 0;
+  const int pass0 = active ? int(gs % a.npg) * PG : 0;
+  const int64_t Bp = a.Bp;
+  const int64_t b = tile * 16 + l;
+  uint32_t pm = 0, sm = 0;   // masks of the pair flavour and of the single flavour
+  if (active) {
+    const uint32_t mu = a.masks[2 * q], md = a.masks[2 * q + 1];
+    pm = a.act_is_P ? mu : md;
+    sm = a.act_is_P ? md : mu;
+  }
+  if (threadIdx.x == 0) wg_single = 0;
+  __syncthreads();
+  if (active && l == 0) atomicOr(&wg_single, sm);
+  __syncthreads();
+  const uint32_t phases = wg_single;
+  const int R1 = a.bsplit * (a.bsplit - 1) / 2;          // rows of the first range
+  const int nrange = R1 < a.npair ? 2 : 1;
+  const int c0 = [&] {                                    // splits per phase in the first range
+    const int n = __builtin_popcount(pm & ((1u << a.bsplit) - 1u));
+    return n * (n - 1) / 2;
+  }();
+  const int ns_in = NIN * a.npass, ns_out = NOUT * a.npass;
+  auto sig_in = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NIN + r; };
+  auto sig_out = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NOUT + r; };
+  const CS *Fin = static_cast<const CS *>(a.Fin);
+  const double2 *fb = static_cast<const double2 *>(a.fblk);
+  const uint2 *qs = reinterpret_cast<const uint2 *>(a.qsplit) + q * a.Sq;
+  const int64_t in_lane = lane_off(b, ns_in), out_lane = lane_off(b, ns_out);
+  const int64_t ftile = tile * a.npsi * 16;
+
+  double2 acc[PG][NOUT];
+#pragma unroll
+  for (int g = 0; g < PG; g++)
+#pragma unroll
+    for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
+
+  for (int p = 0; p < a.nxi; p++) {
+    if (!((phases >> p) & 1u)) continue;   // uniform over the workgroup
+    const bool mine = active && ((sm >> p) & 1u);
+    const int j = __builtin_popcount(sm & ((1u << p) - 1u));
+    for (int h = 0; h < nrange; h++) {
+      const int r0 = h ? R1 : 0, r1 = (h || nrange == 1) ? a.npair : R1;
+      __syncthreads();   // the previous range is no longer read
+      const int nel = (r1 - r0) * M * 16;
+      for (int e = threadIdx.x; e < nel; e += 256) {
+        const int row = r0 + e / (M * 16), d = (e / 16) % M, ll = e & 15;
+        const int64_t y = a.act_is_P ? int64_t(row) * a.nxi + p : int64_t(p) * a.npair + row;
+        ylds[e] = fb[y * a.npsi * Bp + ftile + a.psi_of_pos[d] * 16 + ll];
+      }
+      __syncthreads();
+      if (!mine) continue;
+      const int t0 = j * a.pp + (h ? c0 : 0);
+      const int t1 = j * a.pp + ((h || nrange == 1) ? a.pp : c0);
+      for (int t = t0; t < t1; t++) {
+        const uint2 e = qs[t];
+        const uint32_t y = e.y & 0x7fffffffu;
+        const int row = a.act_is_P ? int(__umulhi(y - uint32_t(p), a.div_magic)) : int(y) - p * a.npair;
+        const double sgn = (e.y >> 31) ? -1.0 : 1.0;
+        double2 fy[M];
+#pragma unroll
+        for (int d = 0; d < M; d++) {
+          const double2 v = ylds[((row - r0) * M + d) * 16 + l];
+          fy[d] = make_double2(sgn * v.x, sgn * v.y);
+        }
+        const int64_t xbase = int64_t(e.x) * ns_in * Bp + in_lane;
+#pragma unroll
+        for (int g = 0; g < PG; g++) {
+          double2 fin[NIN];
+#pragma unroll
+          for (int r = 0; r < NIN; r++) {
+            const CS v = Fin[xbase + sig_in(r, pass0 + g) * 16];
+            fin[r] = make_double2(double(v.x), double(v.y));
+          }
+          wedge_accumulate<M, K>(fin, fy, acc[g]);
+        }
+      }
+    }
+  }
+  if (!active) return;
+  CS *Fout = static_cast<CS *>(a.Fout);
+#pragma unroll
+  for (int g = 0; g < PG; g++)
+#pragma unroll
+    for (int r = 0; r < NOUT; r++) {
+      CS o;
+      o.x = TS(acc[g][r].x);
+      o.y = TS(acc[g][r].y);
+      Fout[q * ns_out * Bp + out_lane + sig_out(r, pass0 + g) * 16] = o;
+    }
+}
+
+int stage_lds_bytes(int nxi, int M) {
+  const int npair = nxi * (nxi - 1) / 2;
+  const int bsplit = nxi > 9 ? 9 : nxi;
+  const int R1 = bsplit * (bsplit - 1) / 2;
+  const int rows = R1 > npair - R1 ? R1 : npair - R1;
+  return rows * M * 16 * int(sizeof(double2));
+}
+
+template <typename T, int M, int K, int PG>
+static hipError_t launch_stage_lds_mkp(const StageLdsArgs &a, hipStream_t s) {
+  const int64_t nslot = a.nq_out * a.npg;
+  const int64_t nwg = ((nslot + 15) / 16 + 7) / 8 * 8;
+  dim3 grid(unsigned(nwg), unsigned(a.Bp / 16));
+  hipLaunchKernelGGL((stage_lds_kernel<T, M, K, PG>), grid, dim3(256), stage_lds_bytes(a.nxi, M), s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int M, int K>
+static hipError_t launch_stage_lds_mk(const StageLdsArgs &a, hipStream_t s) {
+  if (a.pg == 3) return launch_stage_lds_mkp<T, M, K, 3>(a, s);
+  if (a.pg == 2) return launch_stage_lds_mkp<T, M, K, 2>(a, s);
+  return launch_stage_lds_mkp<T, M, K, 1>(a, s);
+}
+
+template <typename T>
+static hipError_t launch_stage_lds_t(const StageLdsArgs &a, hipStream_t s) {
+#define MB_CASE(m, k) \
+  if (a.M == m && a.K == k) return launch_stage_lds_mk<T, m, k>(a, s);
+  MB_CASE(1, 0)
+  MB_CASE(2, 0) MB_CASE(2, 1)
+  MB_CASE(3, 0) MB_CASE(3, 1) MB_CASE(3, 2)
+  MB_CASE(4, 0) MB_CASE(4, 1) MB_CASE(4, 2) MB_CASE(4, 3)
+#undef MB_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s) {
+  return mixed ? launch_stage_lds_t<float>(a, s) : launch_stage_lds_t<double>(a, s);
+}
+
 template <typename T, int M, int K, int PG, int TILE>
 static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
@@ -215,13 +385,14 @@ static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
   return a.tile == 16 ? launch_stage_mkpt<T, M, K, PG, 16>(a, s) : launch_stage_mkpt<T, M, K, PG, 64>(a, s);
 }
 
-// passthrough group: as tuned, else 3 if it divides the passthrough count,
-// else 2, else 1
+// passthrough group: as tuned (1, 2, 3 or 6), else 3 if it divides the
+// passthrough count, else 2, else 1
 template <typename T, int M, int K>
 static hipError_t launch_stage_mk(const StageArgs &a, hipStream_t s) {
   if (a.pg == 1) return launch_stage_mkp<T, M, K, 1>(a, s);
   if (a.pg == 2) return launch_stage_mkp<T, M, K, 2>(a, s);
   if (a.pg == 3) return launch_stage_mkp<T, M, K, 3>(a, s);
+  if (a.pg == 6) return launch_stage_mkp<T, M, K, 6>(a, s);
   if (a.npass % 3 == 0) return launch_stage_mkp<T, M, K, 3>(a, s);
   if (a.npass % 2 == 0) return launch_stage_mkp<T, M, K, 2>(a, s);
   return launch_stage_mkp<T, M, K, 1>(a, s);

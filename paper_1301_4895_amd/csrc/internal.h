@@ -34,6 +34,7 @@ struct Stage {
   std::vector<uint32_t> first;   // stage 0: block quark index of every quark part
   int64_t n_lambda = 0;
   int tune_pg = 0, tune_lds = 0, tune_tile = 64;  // launch tuning (see mb_term_list_tune)
+  int tune_kernel = 0;                            // 0 direct gather, 1 blocks staged in LDS
   int64_t nspin() const { return int64_t(nPsets) * nNsets; }
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };
@@ -56,6 +57,7 @@ struct mb_term_list {
   void *dev = nullptr;
   size_t dev_bytes = 0;
   std::vector<size_t> off_qsplit;  // per stage (s >= 1)
+  std::vector<size_t> off_masks;   // per stage (s >= 1): (u mask, d mask) of every quark part
   size_t off_first = 0, off_crow = 0, off_ccol = 0, off_cval = 0;
   size_t image_bytes() const;
 };

@@ -70,6 +70,31 @@ struct StageArgs {
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);
 
+// The same step with the block of the added species staged in LDS.  Splits
+// of an output are ordered by the single index of the added baryon, then by
+// pair rank; the kernel walks the single indices in phases and, inside a
+// phase, two ranges of pair rows (pairs (a,b) with b < bsplit, then the
+// rest), holding only that part of the block in LDS.
+struct StageLdsArgs {
+  const void *Fin;
+  void *Fout;
+  const void *fblk;
+  const uint32_t *qsplit;    // [nq_out][Sq][2]
+  const uint32_t *masks;     // [nq_out][2]: (u mask, d mask) of every output
+  int64_t nq_out, Bp;
+  int Sq, pp;                // splits per output, per single index
+  int npass, npg;            // passthrough parts, passthrough groups (npass / PG)
+  int act_is_P;
+  int M, K, pg;
+  int nxi, npair, npsi, bsplit;
+  uint32_t div_magic;        // ceil(2^32 / nxi): exact division of multiples of nxi
+  int psi_of_pos[8];
+};
+hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s);
+// LDS bytes the staged kernel uses for a term list with nxi quark indices
+// and base-set size M.
+int stage_lds_bytes(int nxi, int M);
+
 // Final signed sum C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b].
 struct FinalArgs {
   const void *F;

@@ -241,14 +241,18 @@ static uint32_t find_stage(const std::vector<uint64_t> &v, bool d_major, uint64_
 // pair.  f(yu, yd) is called for every split in this canonical order.
 template <class F>
 static inline void for_quark_splits(int type, uint32_t u, uint32_t d, F &&f) {
+  // Both species: the single index of the added baryon (d for a proton, u
+  // for a neutron) varies slowest, then the same-flavour pair (a < b) in
+  // increasing b, then a, i.e. in increasing pair rank.
   if (type == PROTON) {
-    for (uint32_t tb = u; tb; tb &= tb - 1) {
-      int b = __builtin_ctz(tb);
-      for (uint32_t ta = u & ((1u << b) - 1); ta; ta &= ta - 1) {
-        int a = __builtin_ctz(ta);
-        for (uint32_t tc = d; tc; tc &= tc - 1) f((1u << a) | (1u << b), tc & (~tc + 1));
+    for (uint32_t tc = d; tc; tc &= tc - 1)
+      for (uint32_t tb = u; tb; tb &= tb - 1) {
+        int b = __builtin_ctz(tb);
+        for (uint32_t ta = u & ((1u << b) - 1); ta; ta &= ta - 1) {
+          int a = __builtin_ctz(ta);
+          f((1u << a) | (1u << b), tc & (~tc + 1));
+        }
       }
-    }
   } else {
     for (uint32_t tc = u; tc; tc &= tc - 1)
       for (uint32_t tb = d; tb; tb &= tb - 1) {
@@ -499,7 +503,7 @@ size_t mb_term_list::image_bytes() const {
   if (counts_only) return 0;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t o = 0;
-  for (int s = 1; s < nstages; s++) o += al(st[s].qsplit.size() * 4);
+  for (int s = 1; s < nstages; s++) o += al(st[s].qsplit.size() * 4) + al(st[s].quark.size() * 8);
   o += al(st[0].first.size() * 4);
   o += al(crow.size() * 8) + al(ccol.size() * 4) + al(cval.size() * 8);
   return o + 256;

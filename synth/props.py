@@ -88,3 +88,17 @@ def momentum_phase(L: int, p3: int) -> np.ndarray:
     x3 = np.arange(L**3) // (L * L)
     ph = 2.0 * np.pi * p3 * x3 / L
     return np.cos(ph) + 1j * np.sin(ph)
+
+
+def mix_problems(seed: int, n: int, n_types: int, Ls=(16, 24, 32), Ts=(32, 64, 96)):
+    """An uneven batch of n problems drawn by seed: for problem p the first
+    three Philox words of counter (p, 0, MIX_STREAM, 0) pick a type index
+    (of n_types), a lattice size from Ls and a time extent from Ts.  Returns
+    a list of (type, L, T)."""
+    w = philox4x32_10(np.arange(n, dtype=np.uint64), 0, MIX_STREAM, 0, seed & 0xFFFFFFFF,
+                      (seed >> 32) & 0xFFFFFFFF)
+    return [(int(w[0][p] % n_types), int(Ls[int(w[1][p] % len(Ls))]), int(Ts[int(w[2][p] % len(Ts))]))
+            for p in range(n)]
+
+
+MIX_STREAM = 0x4D495800   # stream word of the mix draw (propagator streams are small integers)

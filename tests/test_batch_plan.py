@@ -1,0 +1,66 @@
+"""Host logic of batched runs: the scheduler's cost estimate and branch
+assignment (mb_batch_plan), and the seeded draw of the uneven batch."""
+import numpy as np
+import pytest
+
+from paper_1301_4895_amd import binding as B
+from synth.props import mix_problems
+
+
+def _prob(batch, V, same=True):
+    # placeholder device addresses: the scheduler only compares them
+    return B.mb_problem(batch, V, B.MB_C64, B.MB_MIXED, 0x1000, 0x1000 if same else 0x2000, None, None)
+
+
+def test_plan_longest_first_onto_least_loaded():
+    tl_pn = B.TermList(1, 1, False, 1, all_components=True)
+    tl_he = B.TermList(2, 2, True, 1, all_components=True)
+    tls = [tl_pn, tl_he, tl_pn, tl_he, tl_pn]
+    probs = [_prob(64, 4096), _prob(256, 13824), _prob(32, 4096), _prob(100, 13824), _prob(256, 32768)]
+    br, cost = B.batch_plan(tls, probs, 2)
+    # cost: blocks (dense, symmetric pairs) + 8 flops per recursion operation, per lane
+    for t, p, c in zip(tls, probs, cost):
+        cnt = t.counts()
+        nxi, npsi = cnt["n_xi"], cnt["n_psi"]
+        want = p.batch * (8.0 * 3 * npsi * nxi * nxi * (nxi + 1) / 2 * p.V + 8.0 * cnt["n_lambda"])
+        assert c == pytest.approx(want, rel=1e-12)
+    # greedy longest-processing-time assignment, replayed here
+    load = [0.0, 0.0]
+    want = [None] * len(tls)
+    for i in sorted(range(len(tls)), key=lambda i: -cost[i]):
+        k = int(np.argmin(load))
+        want[i] = k
+        load[k] += cost[i]
+    assert br == want
+    # the two 4He items are the largest and go to different branches
+    assert br[1] != br[3]
+    # one branch takes everything
+    br1, _ = B.batch_plan(tls, probs, 1)
+    assert br1 == [0] * len(tls)
+
+
+def test_plan_costs_scale_with_lanes_and_flavours():
+    tl = B.TermList(1, 1, False, 1, all_components=True)
+    _, c1 = B.batch_plan([tl], [_prob(10, 512)], 1)
+    _, c2 = B.batch_plan([tl], [_prob(20, 512)], 1)
+    assert c2[0] == pytest.approx(2 * c1[0])
+    _, cu = B.batch_plan([tl], [_prob(10, 512, same=False)], 1)   # u != d: full pair set, two diquarks
+    assert cu[0] > c1[0]
+
+
+def test_plan_rejects_bad_arguments():
+    tl = B.TermList(1, 1, False, 1, all_components=True)
+    with pytest.raises(B.MBError):
+        B.batch_plan([tl], [_prob(0, 512)], 1)
+    with pytest.raises(B.MBError):
+        B.batch_plan([tl], [_prob(4, 512)], 0)
+
+
+def test_mix_draw_is_seeded_and_spans_the_choices():
+    a = mix_problems(2013, 64, 4)
+    assert a == mix_problems(2013, 64, 4)
+    assert a != mix_problems(2014, 64, 4)
+    assert a[:10] == mix_problems(2013, 10, 4)
+    assert {t for t, _, _ in a} == {0, 1, 2, 3}
+    assert {L for _, L, _ in a} == {16, 24, 32}
+    assert {T for _, _, T in a} == {32, 64, 96}

@@ -1,0 +1,186 @@
+"""Batched runs (mb_batch_*): uneven mixes of nuclei, volumes and lane counts
+recorded into one HIP graph with concurrent branches.
+
+  * small mix: every lane of the FP64 graph against the oracle (1e-12), the
+    mixed graph against FP64 (1e-6), graph against the single calls
+    (identical bits: same kernels, same launch settings), several replays
+    with other work in between;
+  * the full uneven batch (64 problems drawn by seed, L in {16,24,32}, T in
+    {32,64,96}): mixed against FP64 on every lane (1e-6), graph against the
+    single calls, and FP64 against the oracle on sampled p+n and 3He lanes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from bench import M_DECAY, MIX_SEED, MIX_STREAM0, MIX_TYPES, mix_groups
+from oracle import oracle as O
+from paper_1301_4895_amd import binding as B
+from paper_1301_4895_amd.batch import BatchRunner
+from synth import props as SP
+from tests.gpu_helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _oracle_lane(tl, m, S, w, k):
+    dsets = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    asets = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+    req = dict(sinkP=int(np.bitwise_or.reduce(dsets[:, 0])), sinkN=int(np.bitwise_or.reduce(dsets[:, 1])),
+               alphas=[tuple(map(int, a)) for a in asets])
+    Cd = O.correlators(m["rel"], m["nsrc"], m["nP"], m["nN"], req, S, S, w, 2.0 ** int(k))
+    out = np.zeros((len(dsets), len(asets)), np.complex128)
+    for i, d in enumerate(map(tuple, dsets.tolist())):
+        for j, a in enumerate(map(tuple, asets.tolist())):
+            out[i, j] = Cd[(d, a)]
+    return out
+
+
+def _oracle_pairs(tl, m, S, k, pairs):
+    """Oracle correlators of a few (sink set, source set) pairs, for nuclei
+    whose full set of pairs is too slow for the permutation sum."""
+    dsets = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    asets = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+    fP, fN = O.blocks(m["rel"], m["nsrc"], S, S, None, 2.0 ** int(k))
+    types = [0] * m["nP"] + [1] * m["nN"]
+    out = {}
+    for i, j in pairs:
+        d, a = tuple(map(int, dsets[i])), tuple(map(int, asets[j]))
+        um, dm, cf = O.L_for_alpha(m["rel"], m["nsrc"], m["nP"], m["nN"], a)
+        out[(i, j)] = O.corr_from_L(types, O._bits(d[0]) + O._bits(d[1]), fP, fN, um, dm, cf)
+    return out
+
+
+def _small_groups():
+    """p+n NR (V=27, 70 lanes: two chunks of 64 and 6), 3He NR (V=8, 5
+    lanes), 4He relativistic (V=8, 3 lanes), and p+n again at V=64 (17
+    lanes) sharing its term list."""
+    spec = [(0, 3, 70), (1, 2, 5), (2, 2, 3), (0, 4, 17)]
+    tls, groups = {}, []
+    for gi, (t, L, lanes) in enumerate(spec):
+        m = MIX_TYPES[t]
+        if t not in tls:
+            tls[t] = B.TermList(m["nP"], m["nN"], m["rel"], m["nsrc"], all_components=True)
+            tls[t].upload(DEV)
+        V = L ** 3
+        S = SP.props(77, 50 + gi, 1, lanes, V, 1, M_DECAY, np.complex128)[0]
+        k = np.array([int(math.floor(M_DECAY * t_ / math.log(2.0) + 0.5)) for t_ in range(lanes)], np.int32)
+        groups.append(dict(name=f"g{gi}", type=t, L=L, tl=tls[t], props=torch.from_numpy(S).to(DEV),
+                           sink_w=None, scale_exp=torch.from_numpy(k).to(DEV), host=S, k=k))
+    return groups, tls
+
+
+def test_small_mix_graph_vs_oracle_and_single_calls():
+    groups, tls = _small_groups()
+    res = {}
+    for prec in (B.MB_FP64, B.MB_MIXED):
+        br = BatchRunner(groups, prec, n_branches=3, chunk=64)
+        assert br.kernel_count() > 0
+        br.launch()
+        torch.cuda.synchronize()
+        graph = [c.cpu().numpy() for c in br.corr]
+        gexp = [e.cpu().numpy() for e in br.exp]
+        # replays with other device work in between give the same bits
+        for rep in range(3):
+            for c in br.corr:
+                c.zero_()
+            x = torch.randn(1 << 20, device=DEV)
+            (x * 2).sum().item()
+            br.launch()
+            torch.cuda.synchronize()
+            for g, c in enumerate(br.corr):
+                assert np.array_equal(c.cpu().numpy(), graph[g]), (prec, rep, g)
+        # the single calls, one after the other, give the same bits
+        for c in br.corr:
+            c.zero_()
+        br.run_eager()
+        torch.cuda.synchronize()
+        for g, c in enumerate(br.corr):
+            assert np.array_equal(c.cpu().numpy(), graph[g]), (prec, "eager", g)
+        res[prec] = graph
+        for g, grp in enumerate(groups):
+            assert np.array_equal(gexp[g], 3 * (MIX_TYPES[grp["type"]]["nP"] + MIX_TYPES[grp["type"]]["nN"])
+                                  * grp["k"])
+        br.batch.close()
+    O.set_threads(8)
+    for g, grp in enumerate(groups):
+        m = MIX_TYPES[grp["type"]]
+        lanes = grp["host"].shape[0]
+        check = range(lanes) if lanes <= 8 else sorted({0, 1, 63, 64, lanes - 1} & set(range(lanes)))
+        for b in check:
+            if m["rel"] and m["nP"] + m["nN"] == 4:
+                got = res[B.MB_FP64][g][b]
+                for (i, j), ref in _oracle_pairs(grp["tl"], m, grp["host"][b], grp["k"][b],
+                                                 [(0, 0), (14, 21), (35, 7)]).items():
+                    assert abs(got[i, j] - ref) <= 1e-12 * abs(ref), (g, b, i, j)
+                continue
+            ref = _oracle_lane(grp["tl"], m, grp["host"][b], None, grp["k"][b])
+            assert rel_err(res[B.MB_FP64][g][b], ref) <= 1e-12, (g, b)
+        for b in range(lanes):
+            assert rel_err(res[B.MB_MIXED][g][b], res[B.MB_FP64][g][b]) <= 1e-6, (g, b)
+
+
+def test_batch_rejects_shared_buffers_across_branches():
+    groups, tls = _small_groups()
+    br = BatchRunner(groups[:2], B.MB_FP64, n_branches=2, chunk=64)
+    items = br.items
+    # put two items on different branches but give them the same workspace
+    bad = [dict(it) for it in items[:2]]
+    bad[0]["branch"], bad[1]["branch"] = 0, 1
+    bad[1]["contract_ws"] = bad[0]["contract_ws"]
+    bad[1]["blocks"] = bad[0]["blocks"]
+    bad[1]["blocks_ws"] = bad[0]["blocks_ws"]
+    with pytest.raises(B.MBError) as e:
+        B.Batch(bad, 2)
+    assert e.value.code == B.MB_EINVAL
+    with pytest.raises(B.MBError):
+        B.Batch(bad, 1)   # branch index out of range
+    br.batch.close()
+
+
+def test_full_uneven_batch():
+    groups, tls, probs = mix_groups(torch.device(DEV))
+    assert sum(g["props"].shape[0] for g in groups) == sum(T for _, _, T in probs)
+    res = {}
+    for prec in (B.MB_MIXED, B.MB_FP64):
+        br = BatchRunner(groups, prec, n_branches=4, chunk=256)
+        br.launch()
+        torch.cuda.synchronize()
+        res[prec] = [c.cpu().numpy() for c in br.corr]
+        if prec == B.MB_MIXED:
+            for c in br.corr:
+                c.zero_()
+            br.run_eager()
+            torch.cuda.synchronize()
+            for g, c in enumerate(br.corr):
+                assert np.array_equal(c.cpu().numpy(), res[prec][g]), groups[g]["name"]
+        br.batch.close()
+        del br
+        torch.cuda.empty_cache()
+    worst = 0.0
+    for g, grp in enumerate(groups):
+        a, b = res[B.MB_MIXED][g], res[B.MB_FP64][g]
+        per = np.linalg.norm((a - b).reshape(len(a), -1), axis=1) / np.linalg.norm(b.reshape(len(b), -1), axis=1)
+        assert np.all(np.isfinite(per)), grp["name"]
+        worst = max(worst, float(per.max()))
+    assert worst <= 1e-6, worst
+    # FP64 against the oracle on sampled lanes of the nuclei the oracle can
+    # afford at these volumes
+    import os
+    O.set_threads(min(16, os.cpu_count() or 1))
+    for g, grp in enumerate(groups):
+        if grp["type"] not in (0, 1):
+            continue
+        m = MIX_TYPES[grp["type"]]
+        for lane in (0, len(grp["units"]) - 1):
+            p, t, T = grp["units"][lane]
+            S = SP.props(MIX_SEED, MIX_STREAM0 + p, 1, T, grp["L"] ** 3, 1, M_DECAY, np.complex64,
+                         probs=[0], ts=[t])[0, 0].astype(np.complex128)
+            k = int(math.floor(M_DECAY * t / math.log(2.0) + 0.5))
+            ref = _oracle_lane(grp["tl"], m, S, None, k)
+            assert rel_err(res[B.MB_FP64][g][lane], ref) <= 1e-12, (grp["name"], lane)

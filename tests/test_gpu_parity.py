@@ -197,15 +197,24 @@ def test_mixed_matches_fp64(rel, nsrc, nP, nN, spins, V, nl, dtype):
 
 
 @pytest.mark.parametrize("precision,tol", [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)])
-def test_launch_tuning_keeps_results(precision, tol):
-    """Every launch setting the autotuner may pick gives the same correlators
-    (up to summation order)."""
-    V, nl = 27, 64
-    Su, Sd, w, k = _inputs(13, nl, V, 1, np.complex64, True, with_sink=False)
-    tl = _tl(True, 1, 2, 2, None)
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins,V,nl", [
+    (True, 1, 2, 2, None, 27, 64),                       # n_xi = 12: two pair-row ranges
+    (False, 2, 2, 2, (0, 2, 0, 2), 8, 70),               # two sources, ragged lanes
+    (False, 1, 2, 1, None, 27, 33),                      # n_xi = 6: one pair-row range
+    (False, 2, 4, 4, (0, 1, 2, 3, 0, 1, 2, 3), 8, 20),   # 8Be: every step kind
+])
+def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V, nl):
+    """Every launch setting the autotuner may pick -- direct or LDS-staged
+    kernel, passthrough group, lane tile, LDS cap -- gives the same
+    correlators (up to summation order)."""
+    Su, Sd, w, k = _inputs(13, nl, V, nsrc, np.complex64, True, with_sink=nsrc == 2)
+    tl = _tl(rel, nsrc, nP, nN, spins)
     _, ref, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
-    for pg, tile, lds in [(1, 16, 0), (2, 64, 16384), (3, 16, 0), (3, 64, 0), (1, 64, 0)]:
-        for s in range(1, 4):
+    nst = tl.counts()["n_stages"]
+    for kern, pg, tile, lds in [(0, 1, 16, 0), (0, 2, 64, 16384), (0, 3, 16, 0), (0, 3, 64, 0), (0, 6, 64, 0),
+                                (0, 6, 16, 0), (1, 1, 16, 0), (1, 2, 16, 0), (1, 3, 16, 0)]:
+        for s in range(1, nst):
+            tl.tune(s, B.MB_TUNE_KERNEL, kern)
             try:
                 tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
             except B.MBError:
@@ -214,4 +223,4 @@ def test_launch_tuning_keeps_results(precision, tol):
             tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
         _, got, _ = _run(tl, Su, Sd, w, k, precision)
         errs = [rel_err(got[b], ref[b]) for b in range(nl)]
-        assert max(errs) <= tol, (pg, tile, lds, max(errs))
+        assert max(errs) <= tol, (kern, pg, tile, lds, max(errs))

@@ -227,6 +227,9 @@ def test_device_calls_validate_before_launch():
     assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, C.c_void_p(1), 1 << 40, None) == B.MB_EINVAL
     p = B.mb_problem(0, 64, B.MB_C64, B.MB_FP64, 1, 1, None, None)  # empty batch
     assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, C.c_void_p(1), 1 << 40, None) == B.MB_EINVAL
+    p = B.mb_problem(65536, 64, B.MB_C64, B.MB_FP64, 1, 1, None, None)  # above MB_MAX_BATCH lanes
+    assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, C.c_void_p(1), 1 << 40,
+                            None) == B.MB_EUNSUPPORTED
     p = B.mb_problem(8, 64, B.MB_C64, B.MB_FP64, 1, 1, None, None)
     a, b, w = B.workspace_query(tl, p)
     assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), a - 1, C.c_void_p(1), b, None) == B.MB_ENOWORKSPACE
@@ -311,3 +314,35 @@ def test_factorised_tables_reproduce_oracle_correlators(rel, nsrc, nP, nN, spins
     R = np.array([[ref[(tuple(map(int, d)), tuple(map(int, a)))] for a in asets] for d in dsets])
     assert np.linalg.norm(R) > 0
     assert np.linalg.norm(got - R) <= 1e-12 * np.linalg.norm(R)
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,spins", [(2, 2, True, 1, None), (1, 2, False, 1, None),
+                                                   (4, 4, False, 2, (0, 1, 2, 3, 0, 1, 2, 3))])
+def test_split_order_single_index_then_pair_rank(nP, nN, rel, nsrc, spins):
+    """The staged kernel walks the splits of an output by the added baryon's
+    single quark index (d of a proton, u of a neutron), then by the rank
+    b(b-1)/2 + a of its same-flavour pair (a < b); every single index of the
+    output carries the same number of splits."""
+    tl = (B.TermList(nP, nN, rel, nsrc, all_components=True) if spins is None
+          else B.TermList.spin_state(nP, nN, rel, nsrc, spins))
+    c = tl.counts()
+    nxi = c["n_xi"]
+    npair = nxi * (nxi - 1) // 2
+    for s in range(1, c["n_stages"]):
+        Q = tl.export(B.MB_EXPORT_QUARK, s).reshape(-1, 2).astype(np.int64)
+        qs = tl.export(B.MB_EXPORT_QSPLIT, s).reshape(len(Q), -1, 2)
+        y = (qs[:, :, 1] & 0x7FFFFFFF).astype(np.int64)
+        if c["path"][s] == 0:
+            single, rank, smask = y % nxi, y // nxi, Q[:, 1]
+        else:
+            single, rank, smask = y // npair, y % npair, Q[:, 0]
+        key = single * npair + rank
+        assert np.all(np.diff(key, axis=1) > 0), s
+        k = np.array([bin(int(m)).count("1") for m in smask])
+        assert np.all(k == k[0])
+        pp = qs.shape[1] // k[0]
+        assert pp * k[0] == qs.shape[1]
+        # the j-th run of pp splits uses the j-th single index of the output
+        for i in range(0, len(Q), max(1, len(Q) // 50)):
+            bits = [b for b in range(nxi) if smask[i] >> b & 1]
+            assert list(single[i].reshape(k[0], pp)[:, 0]) == bits
