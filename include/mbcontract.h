@@ -273,7 +273,12 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
  * double in both precision modes.
  * Output layout (complex double in both precision modes): proton block
  * [block quark index][lane / 16][psi][lane % 16] followed by the neutron
- * block, lanes padded to a multiple of 64.                                  */
+ * block, lanes padded to a multiple of 64, then int32 e[lane] (padded
+ * lanes included): the blocks of a lane are stored multiplied by 2^-e[lane]
+ * (exact), e chosen so that their largest real or imaginary part lies in
+ * [1/2, 1) (e = 0 for an all-zero lane).  Products of many blocks then stay
+ * near 1 in float stage storage whatever the size of the propagators; the
+ * final sum multiplies by 2^(A e).                                          */
 int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
                    size_t blocks_bytes, void *ws, size_t ws_bytes, void *stream);
 

@@ -486,14 +486,54 @@ __global__ __launch_bounds__(256) void blocks_finish_kernel(FinishArgs a, int nx
       v.x += x.x - y.x;
       v.y += x.y - y.y;
     }
-    v.x = ldexp(v.x, -a.norm_exp);
-    v.y = ldexp(v.y, -a.norm_exp);
   }
   TO *out = static_cast<TO *>(a.blocks);
   TO o;
   o.x = decltype(o.x)(v.x);
   o.y = decltype(o.y)(v.y);
   out[(int64_t(species) * nyq + yq) * npsi * a.Bp + lane_off(b, npsi) + psi * 16] = o;
+}
+
+// Per-lane exponent: e_b with 2^(e_b - 1) <= max |Re|, |Im| over the lane's
+// block entries (both species) < 2^e_b, and the entries multiplied by
+// 2^-e_b (exact), so that products of many blocks stay near 1 whatever the
+// size of the propagators.  A workgroup takes one tile of 16 lanes; its 16
+// thread groups stride over the entries of their lane.
+__global__ __launch_bounds__(256) void blocks_scale_kernel(double2 *blk, int32_t *lane_exp, int64_t Bp, int npsi,
+                                                           int nyq2) {
+  __shared__ int emax[16][16];
+  const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t tile = blockIdx.x;
+  const int64_t nent = int64_t(nyq2) * npsi;   // (species, block quark index) x psi
+  auto addr = [&](int64_t e) { return (e / npsi) * npsi * Bp + tile * npsi * 16 + (e % npsi) * 16 + l; };
+  int em = -100000;
+  for (int64_t e = g; e < nent; e += 16) {
+    const double2 v = blk[addr(e)];
+    const double m = fmax(fabs(v.x), fabs(v.y));
+    if (m > 0.0) em = max(em, ilogb(m) + 1);
+  }
+  emax[g][l] = em;
+  __syncthreads();
+  if (g == 0) {
+    int e = emax[0][l];
+    for (int i = 1; i < 16; i++) e = max(e, emax[i][l]);
+    emax[0][l] = e == -100000 ? 0 : e;   // an all-zero lane keeps its scale
+    lane_exp[tile * 16 + l] = emax[0][l];
+  }
+  __syncthreads();
+  const int sh = -emax[0][l];
+  for (int64_t e = g; e < nent; e += 16) {
+    double2 v = blk[addr(e)];
+    v.x = ldexp(v.x, sh);
+    v.y = ldexp(v.y, sh);
+    blk[addr(e)] = v;
+  }
+}
+
+hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s) {
+  hipLaunchKernelGGL(blocks_scale_kernel, dim3(unsigned(Bp / 16)), dim3(256), 0, s, static_cast<double2 *>(blocks),
+                     lane_exp, Bp, npsi, nyq2);
+  return hipGetLastError();
 }
 
 hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s) {

@@ -24,13 +24,6 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int64_t lanes_padded(int64_t B) { return (B + 63) / 64 * 64; }
 
-// Blocks are multiplied by 2^-norm_exp (exact) so that products of many
-// blocks stay well inside float range; the final sum undoes it.
-int block_norm_exp(int64_t V) {
-  int e = 0;
-  while ((int64_t(1) << (2 * (e + 1))) <= V) e++;
-  return e;
-}
 
 int nchunks_for(int64_t B, int64_t V) {
   int64_t want = std::max<int64_t>(1, (4096 + B - 1) / B);
@@ -53,9 +46,13 @@ size_t elem_bytes(const mb_problem *p) { return p->precision == MB_MIXED ? 8 : 1
 
 // Blocks are stored in double in both precision modes (they are small and
 // every block entry enters every component).
-size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+// followed by the per-lane block exponents (int32, padded lanes)
+size_t blocks_entry_bytes(const mb_term_list *tl, const mb_problem *p) {
   const int64_t nyq = int64_t(tl->nxi) * (tl->nxi - 1) / 2 * tl->nxi;
   return size_t(2 * tl->npsi * nyq) * size_t(lanes_padded(p->batch)) * 16;
+}
+size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+  return blocks_entry_bytes(tl, p) + al256(size_t(lanes_padded(p->batch)) * 4);
 }
 
 size_t blocks_ws_of(const mb_term_list *tl, const mb_problem *p) {
@@ -234,8 +231,11 @@ int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks, si
   f.D = tl->D;
   f.nchunk = a.nchunk;
   f.sym = sym;
-  f.norm_exp = block_norm_exp(p->V);
   HIP_CHECK(launch_blocks_finish(f, mixed, s));
+  const int nyq = tl->nxi * (tl->nxi - 1) / 2 * tl->nxi;
+  HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
+                                                                     blocks_entry_bytes(tl, p)),
+                                f.Bp, tl->npsi, 2 * nyq, s));
   return MB_OK;
 }
 
@@ -339,8 +339,8 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.n_delta = int(SN.nspin());
       a.n_alpha = int(tl->alphas.size());
       a.A = tl->A;
-      a.norm = std::ldexp(1.0, tl->A * block_norm_exp(p->V)) /
-               (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
+      a.lane_exp = reinterpret_cast<const int32_t *>(blk + blocks_entry_bytes(tl, p));
+      a.inv_fact = 1.0 / (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
       HIP_CHECK(launch_final(a, mixed, s));
     }
   }

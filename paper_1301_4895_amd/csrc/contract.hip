@@ -40,6 +40,11 @@ __host__ __device__ constexpr int rank_c(int mask) {
   return r;
 }
 
+// A split-table entry read with scalar loads: the same for every lane.
+__device__ __forceinline__ uint2 uniform(uint2 v) {
+  return make_uint2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y));
+}
+
 // The spin wedge of one quark split: out-set (K+1 elements of the M-element
 // base set) += sum over its elements d of sgn(d) x fin[out minus d] x fy[d],
 // sgn(d) = parity of moving d behind the other elements (eq. antis_product_2
@@ -146,39 +151,63 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   for (int g = 0; g < PG; g++)
 #pragma unroll
     for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
-  // The split table is read with wave-uniform (scalar) loads; every
-  // sub-wave then selects its own entry.
-  for (int s0 = 0; s0 < a.Sq; s0 += SUB) {
-    uint2 e = qs[s0];
-    bool valid = true;
-    if constexpr (SUB > 1) {
-      uint2 ee[SUB];
+  // U splits per round: the table entries and every operand load of the U
+  // splits are issued before the first product, so that a wavefront keeps
+  // U splits of loads in flight.  The split table is read with wave-uniform
+  // (scalar) loads; every sub-wave then selects its own entry.  Past the end
+  // of the list a sub-wave loads the last split again (in bounds) and drops
+  // it.
+  constexpr int VG_SPLIT = NIN * PG * int(sizeof(CS)) / 4 + 4 * M;   // VGPRs of one split's operands
+  constexpr int U = VG_SPLIT <= 16 ? 4 : VG_SPLIT <= 32 ? 2 : 1;
+  for (int s0 = 0; s0 < a.Sq; s0 += SUB * U) {
+    uint2 e[U];
+    bool valid[U];
 #pragma unroll
-      for (int j = 0; j < SUB; j++) ee[j] = (s0 + j < a.Sq) ? qs[s0 + j] : make_uint2(0u, 0u);
+    for (int u = 0; u < U; u++) {
+      const int base = s0 + u * SUB;
+      if constexpr (SUB > 1) {
+        uint2 ee[SUB];
 #pragma unroll
-      for (int j = 1; j < SUB; j++)
-        if (quarter == j) e = ee[j];
-      valid = s0 + quarter < a.Sq;
-    }
-    if (!valid) continue;
-    const int64_t xbase = int64_t(e.x) * ns_in * Bp + in_lane;
-    const int64_t ybase = int64_t(e.y & 0x7fffffffu) * a.npsi * Bp;
-    const double sgn = (e.y >> 31) ? -1.0 : 1.0;
-    double2 fy[M];
+        for (int j = 0; j < SUB; j++) ee[j] = uniform(qs[min(base + j, a.Sq - 1)]);
+        e[u] = ee[0];
 #pragma unroll
-    for (int d = 0; d < M; d++) {
-      const double2 v = fb[ybase + f_off[d]];
-      fy[d] = make_double2(sgn * v.x, sgn * v.y);
-    }
-#pragma unroll
-    for (int g = 0; g < PG; g++) {
-      double2 fin[NIN];
-#pragma unroll
-      for (int r = 0; r < NIN; r++) {
-        const CS v = Fin[xbase + sig_in(r, pass0 + g) * 16];
-        fin[r] = make_double2(double(v.x), double(v.y));
+        for (int j = 1; j < SUB; j++)
+          if (quarter == j) e[u] = ee[j];
+      } else {
+        e[u] = uniform(qs[min(base, a.Sq - 1)]);
       }
-      wedge_accumulate<M, K>(fin, fy, acc[g]);
+      valid[u] = base + quarter < a.Sq;
+    }
+    double2 fy[U][M];
+    CS xin[U][PG][NIN];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t xbase = int64_t(e[u].x) * ns_in * Bp + in_lane;
+      const int64_t ybase = int64_t(e[u].y & 0x7fffffffu) * a.npsi * Bp;
+#pragma unroll
+      for (int d = 0; d < M; d++) fy[u][d] = fb[ybase + f_off[d]];
+#pragma unroll
+      for (int g = 0; g < PG; g++)
+#pragma unroll
+        for (int r = 0; r < NIN; r++) xin[u][g][r] = Fin[xbase + sig_in(r, pass0 + g) * 16];
+    }
+    // keep the instruction scheduler from sinking loads below products
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      // a dropped split adds zeros (its operands are finite values of the
+      // last split), which keeps the loads above free of branches
+      const double sgn = valid[u] ? ((e[u].y >> 31) ? -1.0 : 1.0) : 0.0;
+      double2 y[M];
+#pragma unroll
+      for (int d = 0; d < M; d++) y[d] = make_double2(sgn * fy[u][d].x, sgn * fy[u][d].y);
+#pragma unroll
+      for (int g = 0; g < PG; g++) {
+        double2 fin[NIN];
+#pragma unroll
+        for (int r = 0; r < NIN; r++) fin[r] = make_double2(double(xin[u][g][r].x), double(xin[u][g][r].y));
+        wedge_accumulate<M, K>(fin, y, acc[g]);
+      }
     }
   }
   // sum the sub-waves (every lane ends with the total), then let sub-wave j
@@ -436,8 +465,9 @@ __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
     ai += c * double(v.y);
   }
   if (b < a.B) {
+    const int e = a.A * a.lane_exp[b];
     reinterpret_cast<double2 *>(a.corr)[(b * a.n_delta + delta) * a.n_alpha + alpha] =
-        make_double2(ar * a.norm, ai * a.norm);
+        make_double2(ldexp(ar * a.inv_fact, e), ldexp(ai * a.inv_fact, e));
     if (a.exp_out && alpha == 0 && delta == 0) a.exp_out[b] = a.scale_exp ? 3 * a.A * a.scale_exp[b] : 0;
   }
 }

@@ -24,15 +24,19 @@ struct BlocksArgs {
 hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipStream_t s);
 
 // Sums the chunks in double, antisymmetrises the same-flavour slots and
-// writes the block arrays [psi][block quark index][Bp] (float2 or double2),
-// multiplied by 2^-norm_exp.  partN may equal partP (isospin limit).
+// writes the block arrays (lane-blocked layout below).  partN may equal
+// partP (isospin limit).
 struct FinishArgs {
   const double *partP, *partN;
   void *blocks;
   int64_t B, Bp;
-  int nsrc, D, nchunk, sym, norm_exp;
+  int nsrc, D, nchunk, sym;
 };
 hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s);
+
+// Per-lane block exponents (see blocks_scale_kernel): blocks scaled in place
+// by 2^-lane_exp[b]; nyq2 = 2 * block quark indices (both species).
+hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s);
 
 // Lane-blocked layouts (lanes grouped in tiles of 16, Bp = padded lanes):
 //   stage   F[q][tile][sigma][16]     index q*ns*Bp + tile*ns*16 + sigma*16 + l
@@ -95,7 +99,8 @@ hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s);
 // and base-set size M.
 int stage_lds_bytes(int nxi, int M);
 
-// Final signed sum C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b].
+// Final signed sum C[b][delta][alpha] = 2^(A lane_exp[b]) / (n_P! n_N!) *
+// sum_e c_e F[q_e][delta][b].
 struct FinalArgs {
   const void *F;
   const int64_t *crow;
@@ -104,9 +109,10 @@ struct FinalArgs {
   double *corr;
   int32_t *exp_out;
   const int32_t *scale_exp;
+  const int32_t *lane_exp;   // per-lane block exponents (undone here)
   int64_t B, Bp;
   int n_delta, n_alpha, A;
-  double norm;
+  double inv_fact;           // 1 / (n_P! n_N!)
 };
 hipError_t launch_final(const FinalArgs &a, bool mixed, hipStream_t s);
 

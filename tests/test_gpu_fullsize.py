@@ -22,7 +22,7 @@ from oracle import oracle as O
 from paper_1301_4895_amd import binding as B
 from paper_1301_4895_amd.runner import Runner
 from synth import props as SP
-from tests.gpu_helpers import oracle_blocks_lib_layout, rel_err
+from tests.gpu_helpers import check_lane_exponent, lib_blocks, oracle_blocks_lib_layout, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -48,20 +48,13 @@ def host_lane(cfg, lane):
                     probs=[lane // T], ts=[lane % T])[0, 0].astype(np.complex128)
 
 
-def lib_blocks(r, tl, lane):
-    c = tl.counts()
-    nxi, npsi = c["n_xi"], c["n_psi"]
-    nyq = nxi * (nxi - 1) // 2 * nxi
-    Bp = (r.batch + 63) // 64 * 64
-    blk = r.blocks.view(torch.complex128).view(2, nyq, Bp // 16, npsi, 16)
-    return blk[:, :, lane // 16, :, lane % 16].permute(0, 2, 1).cpu().numpy()
-
-
-def block_norm_exp(V):
-    e = 0
-    while 4 ** (e + 1) <= V:
-        e += 1
-    return e
+def lane_blocks(r, tl, lane):
+    """Stored blocks [species][psi][block quark index] of one lane and its
+    exponent."""
+    blk, e = lib_blocks(r, tl)
+    out, ee = blk[..., lane].cpu().numpy(), int(e[lane])
+    check_lane_exponent(out, ee)
+    return out, ee
 
 
 @pytest.fixture(scope="module")
@@ -90,8 +83,8 @@ def test_4he_relativistic_full_size(oracle_threads):
         S = host_lane(cfg, lane)
         kk = int(kexp(LANES, cfg["T"])[lane])
         fP, fN = O.blocks(True, 1, S, S, None, 2.0 ** kk)
-        ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -block_norm_exp(V)
-        got_blocks = lib_blocks(out[B.MB_FP64][1], tl, lane)
+        got_blocks, e = lane_blocks(out[B.MB_FP64][1], tl, lane)
+        ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -e
         assert rel_err(got_blocks, ref_blocks) <= 1e-12
         for i, j in pairs:
             d, a = tuple(map(int, dsets[i])), tuple(map(int, asets[j]))
@@ -118,8 +111,9 @@ def test_8be_two_sources_full_size(oracle_threads):
     lane = 77
     S = host_lane(cfg, lane)
     fP, fN = O.blocks(False, 2, S, S, w, 2.0 ** int(kexp(LANES, cfg["T"])[lane]))
-    ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -block_norm_exp(V)
-    assert rel_err(lib_blocks(r, tl, lane), ref_blocks) <= 1e-12
+    got_blocks, e = lane_blocks(r, tl, lane)
+    ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -e
+    assert rel_err(got_blocks, ref_blocks) <= 1e-12
     del r
     # correlators through the factorisation: source 0 and sink function 0 live
     # on x3 < L/2, source 1 and sink function 1 on x3 >= L/2

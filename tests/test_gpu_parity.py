@@ -15,18 +15,11 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O
 from paper_1301_4895_amd import binding as B
 from paper_1301_4895_amd.runner import Runner
-from tests.gpu_helpers import host_props, oracle_blocks_lib_layout, rel_err
+from tests.gpu_helpers import check_lane_exponent, host_props, lib_blocks, oracle_blocks_lib_layout, rel_err
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
-
-
-def block_norm_exp(V):
-    e = 0
-    while 4 ** (e + 1) <= V:
-        e += 1
-    return e
 
 
 def _tl(rel, nsrc, nP, nN, spins):
@@ -54,13 +47,12 @@ def _run(tl, Su, Sd, w, k, precision):
     r = Runner(tl, tu, td, precision, tw, tk)
     corr, ex = r.run()
     torch.cuda.synchronize()
-    c = tl.counts()
-    nxi, npsi = c["n_xi"], c["n_psi"]
-    nyq = nxi * (nxi - 1) // 2 * nxi
-    Bp = (len(Su) + 63) // 64 * 64
-    blocks = (r.blocks.view(torch.complex128).view(2, nyq, Bp // 16, npsi, 16).permute(0, 3, 1, 2, 4)
-              .reshape(2, npsi, nyq, Bp)[..., :len(Su)].cpu().numpy())
-    return blocks, corr.cpu().numpy(), ex.cpu().numpy()
+    blk, e = lib_blocks(r, tl)
+    blocks = blk[..., :len(Su)].cpu().numpy()
+    e = e[:len(Su)].cpu().numpy()
+    for b in range(len(Su)):
+        check_lane_exponent(blocks[..., b], int(e[b]))
+    return (blocks, e), corr.cpu().numpy(), ex.cpu().numpy()
 
 
 def _oracle_corr(tl, rel, nsrc, nP, nN, Su, Sd, w, k):
@@ -99,12 +91,11 @@ def test_blocks_match_oracle(rel, nsrc, same_ud, dtype):
     Su, Sd, w, k = _inputs(11, nl, V, nsrc, dtype, same_ud, with_sink=nsrc == 2 or rel)
     tl = _tl(rel, nsrc, 1, 1, None)
     for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-12)]:
-        blocks, _, _ = _run(tl, Su, Sd, w, k, prec)
-        j = block_norm_exp(V)
+        (blocks, e), _, _ = _run(tl, Su, Sd, w, k, prec)
         for b in range(nl):
             fP, fN = O.blocks(rel, nsrc, Su[b].astype(np.complex128), Sd[b].astype(np.complex128), w,
                               2.0 ** int(k[b]))
-            ref = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -j
+            ref = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -int(e[b])
             for sp in range(2):
                 assert rel_err(blocks[sp, :, :, b], ref[sp]) <= tol, (prec, sp, b)
 
@@ -210,6 +201,9 @@ def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V
     Su, Sd, w, k = _inputs(13, nl, V, nsrc, np.complex64, True, with_sink=nsrc == 2)
     tl = _tl(rel, nsrc, nP, nN, spins)
     _, ref, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
+    # with 2^k, k up to 3, an eight-baryon correlator reaches ~1e50: far beyond
+    # float, which the per-lane block exponents keep out of the float stages
+    assert np.all(np.isfinite(ref))
     nst = tl.counts()["n_stages"]
     for kern, pg, tile, lds in [(0, 1, 16, 0), (0, 2, 64, 16384), (0, 3, 16, 0), (0, 3, 64, 0), (0, 6, 64, 0),
                                 (0, 6, 16, 0), (1, 1, 16, 0), (1, 2, 16, 0), (1, 3, 16, 0)]:
