@@ -40,16 +40,24 @@ __host__ __device__ constexpr int rank_c(int mask) {
   return r;
 }
 
+// Load at a base pointer plus a 32-bit byte offset.
+template <typename T>
+__device__ __forceinline__ T ld(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 // A split-table entry read with scalar loads: the same for every lane.
 __device__ __forceinline__ uint2 uniform(uint2 v) {
   return make_uint2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y));
 }
 
-// The spin wedge of one quark split: out-set (K+1 elements of the M-element
-// base set) += sum over its elements d of sgn(d) x fin[out minus d] x fy[d],
+// The spin wedge of one quark split:
+//   out-set (K+1 elements of the M-element base set) +=
+//       sum over its elements d of sgn(d) x fin[out minus d] x fy[d],
 // sgn(d) = parity of moving d behind the other elements (eq. antis_product_2
-// restricted to one species).  Resolved at compile time.
-template <int M, int K>
+// restricted to one species), times -1 when NEG.  Resolved at compile time;
+// every real product is one fused multiply-add into the accumulator.
+template <int M, int K, bool NEG = false>
 __device__ __forceinline__ void wedge_accumulate(const double2 *fin, const double2 *fy, double2 *acc) {
 #pragma unroll
   for (int out = 0; out < (1 << M); out++) {
@@ -60,15 +68,13 @@ __device__ __forceinline__ void wedge_accumulate(const double2 *fin, const doubl
       if (!((out >> d) & 1)) continue;
       const int in = out & ~(1 << d);
       const int ri = rank_c(in);
-      const bool neg = popc(in >> (d + 1)) & 1;
+      const bool neg = bool(popc(in >> (d + 1)) & 1) != NEG;
       const double2 x = fin[ri], y = fy[d];
-      if (neg) {
-        acc[ro].x -= x.x * y.x - x.y * y.y;
-        acc[ro].y -= x.x * y.y + x.y * y.x;
-      } else {
-        acc[ro].x += x.x * y.x - x.y * y.y;
-        acc[ro].y += x.x * y.y + x.y * y.x;
-      }
+      const double s = neg ? -1.0 : 1.0;   // folds into the operand's sign
+      acc[ro].x = fma(s * x.x, y.x, acc[ro].x);
+      acc[ro].x = fma(-s * x.y, y.y, acc[ro].x);
+      acc[ro].y = fma(s * x.x, y.y, acc[ro].y);
+      acc[ro].y = fma(s * x.y, y.x, acc[ro].y);
     }
   }
 }
@@ -141,10 +147,14 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   const double2 *fb = static_cast<const double2 *>(a.fblk);
   const uint2 *qs = reinterpret_cast<const uint2 *>(a.qsplit) + q * a.Sq;
 
-  int64_t f_off[M];
+  // per-lane offsets (32 bits: a lane tile holds at most 65536 lanes x 216
+  // spin parts); the row bases of a split are wave-uniform when SUB == 1
+  uint32_t f_off[M];
 #pragma unroll
-  for (int d = 0; d < M; d++) f_off[d] = lane_off(b, a.npsi) + a.psi_of_pos[d] * 16;
-  const int64_t in_lane = lane_off(b, ns_in), out_lane = lane_off(b, ns_out);
+  for (int d = 0; d < M; d++) f_off[d] = uint32_t(lane_off(b, a.npsi) + a.psi_of_pos[d] * 16);
+  const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
+  const int64_t out_lane = lane_off(b, ns_out);
+  const int64_t xstride = int64_t(ns_in) * Bp, ystride = int64_t(a.npsi) * Bp;
 
   double2 acc[PG][NOUT];
 #pragma unroll
@@ -154,11 +164,12 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   // U splits per round: the table entries and every operand load of the U
   // splits are issued before the first product, so that a wavefront keeps
   // U splits of loads in flight.  The split table is read with wave-uniform
-  // (scalar) loads; every sub-wave then selects its own entry.  Past the end
-  // of the list a sub-wave loads the last split again (in bounds) and drops
-  // it.
+  // (scalar) loads; with sub-waves every sub-wave then selects its own
+  // entry.  Past the end of the list a sub-wave loads the last split again
+  // (in bounds) and drops it.
   constexpr int VG_SPLIT = NIN * PG * int(sizeof(CS)) / 4 + 4 * M;   // VGPRs of one split's operands
   constexpr int U = VG_SPLIT <= 16 ? 4 : VG_SPLIT <= 32 ? 2 : 1;
+  constexpr bool SIGN_ON_X = NIN * PG < M;
   for (int s0 = 0; s0 < a.Sq; s0 += SUB * U) {
     uint2 e[U];
     bool valid[U];
@@ -182,31 +193,44 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
     CS xin[U][PG][NIN];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const int64_t xbase = int64_t(e[u].x) * ns_in * Bp + in_lane;
-      const int64_t ybase = int64_t(e[u].y & 0x7fffffffu) * a.npsi * Bp;
+      // row bases (wave-uniform when SUB == 1) plus 32-bit per-lane byte
+      // offsets, so that the loads take the scalar-base addressing form
+      const CS *xrow = Fin + int64_t(e[u].x) * xstride;
+      const double2 *yrow = fb + int64_t(e[u].y & 0x7fffffffu) * ystride;
 #pragma unroll
-      for (int d = 0; d < M; d++) fy[u][d] = fb[ybase + f_off[d]];
+      for (int d = 0; d < M; d++) fy[u][d] = ld(yrow, f_off[d] * uint32_t(sizeof(double2)));
 #pragma unroll
       for (int g = 0; g < PG; g++)
 #pragma unroll
-        for (int r = 0; r < NIN; r++) xin[u][g][r] = Fin[xbase + sig_in(r, pass0 + g) * 16];
+        for (int r = 0; r < NIN; r++)
+          xin[u][g][r] = ld(xrow, (in_lane + uint32_t(sig_in(r, pass0 + g) * 16)) * uint32_t(sizeof(CS)));
     }
     // keep the instruction scheduler from sinking loads below products
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      // a dropped split adds zeros (its operands are finite values of the
-      // last split), which keeps the loads above free of branches
+      double2 fin[PG][NIN];
+#pragma unroll
+      for (int g = 0; g < PG; g++)
+#pragma unroll
+        for (int r = 0; r < NIN; r++) fin[g][r] = make_double2(double(xin[u][g][r].x), double(xin[u][g][r].y));
+      // the split sign multiplies the smaller operand set; a dropped split
+      // adds zeros (its operands are finite values of the last split), which
+      // keeps the loads above free of branches
       const double sgn = valid[u] ? ((e[u].y >> 31) ? -1.0 : 1.0) : 0.0;
-      double2 y[M];
+      if constexpr (SIGN_ON_X) {
 #pragma unroll
-      for (int d = 0; d < M; d++) y[d] = make_double2(sgn * fy[u][d].x, sgn * fy[u][d].y);
+        for (int g = 0; g < PG; g++)
 #pragma unroll
-      for (int g = 0; g < PG; g++) {
-        double2 fin[NIN];
+          for (int r = 0; r < NIN; r++) fin[g][r] = make_double2(sgn * fin[g][r].x, sgn * fin[g][r].y);
 #pragma unroll
-        for (int r = 0; r < NIN; r++) fin[r] = make_double2(double(xin[u][g][r].x), double(xin[u][g][r].y));
-        wedge_accumulate<M, K>(fin, y, acc[g]);
+        for (int g = 0; g < PG; g++) wedge_accumulate<M, K>(fin[g], fy[u], acc[g]);
+      } else {
+        double2 y[M];
+#pragma unroll
+        for (int d = 0; d < M; d++) y[d] = make_double2(sgn * fy[u][d].x, sgn * fy[u][d].y);
+#pragma unroll
+        for (int g = 0; g < PG; g++) wedge_accumulate<M, K>(fin[g], y, acc[g]);
       }
     }
   }
