@@ -250,8 +250,8 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
   __shared__ double2 su[NS][NROW][NXI];
   __shared__ double2 s1[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
   __shared__ double2 sd[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
-  __shared__ double Ar[KG][MP], Ai[KG][MP];
-  __shared__ double Br[KG][NP], Bi[KG][NP];
+  __shared__ double Ar[KG][MP], Ai[KG][MP], As[KG][MP];   // As = Ar + Ai
+  __shared__ double Br[KG][NP], Bi[KG][NP], Bs[KG][NP];   // Bs = Br + Bi
   __shared__ double2 wsh[NS][2];
   __shared__ unsigned char px2[NP], px3[NP];  // pair index -> (xi2, xi3)
 
@@ -270,6 +270,7 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
     px2[p] = (unsigned char)x2;
     px3[p] = (unsigned char)x3;
   }
+  __syncthreads();   // the pair tables are read below
   const int64_t ln = blockIdx.y;
   const int chunk = blockIdx.x;
   const int nsrc = a.nsrc;
@@ -278,75 +279,137 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
   const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[ln]) : 1.0;
   const bool same1 = a.prop_q1 == a.prop_u;
 
-  mb_d4 accr[TPW], acci[TPW];
+  // Gauss's three-product form of the complex product: m1 = Ar Br,
+  // m2 = Ai Bi, m3 = (Ar + Ai)(Br + Bi); re = m1 - m2, im = m3 - m1 - m2.
+  mb_d4 m1[TPW], m2[TPW], m3[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; j++) {
-    accr[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
-    acci[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    m1[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    m2[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    m3[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
   }
+  // The entries of the A and B operands a thread builds are the same for
+  // every group of sites: resolve their LDS sources once.
+  constexpr int AJ = (KG * MP + 255) / 256, BJ = (KG * NP + 255) / 256;
+  int a_src[AJ], a_w[AJ], a_n[AJ];   // LDS index of S_q1 (-1: zero entry), sink weight, site
+#pragma unroll
+  for (int j = 0; j < AJ; j++) {
+    const int i = tid + 256 * j;
+    const int k = i / MP, m = i % MP, n = k / 3, ac = k % 3;
+    a_src[j] = -1;
+    a_w[j] = 0;
+    a_n[j] = n;
+    if (i < KG * MP && m < M) {
+      const int psi = m / NXI, xi1 = m % NXI, alpha = psi / nsrc, sk = psi % nsrc;
+      a_src[j] = (n * NROW + 3 * alpha + ac) * NXI + xi1;
+      a_w[j] = n * 2 + sk;
+    }
+  }
+  // diquark entry (site n, colour a, pair (x2, x3)): the eps terms are
+  // (b, c) = (a+1, a+2) with + and (a+2, a+1) with -; a term reads rows
+  // 3 g + b (at x2) and 3 (g^1) + c (at x3)
+  int b_l0[BJ], b_r0[BJ], b_sw[BJ], b_n[BJ];   // b_sw: row offset from (b, c) to (c, b)
+#pragma unroll
+  for (int j = 0; j < BJ; j++) {
+    const int i = tid + 256 * j;
+    const int k = i / NP, pp = i % NP, n = k / 3, ac = k % 3;
+    b_n[j] = (i < KG * NP && pp < NPAIR) ? n : NS;   // NS: zero entry
+    const int x2 = pp < NPAIR ? px2[pp] : 0, x3 = pp < NPAIR ? px3[pp] : 0;
+    const int bb = (ac + 1) % 3, cc = (ac + 2) % 3;
+    b_l0[j] = (n * NROW + bb) * NXI + x2;
+    b_r0[j] = (n * NROW + cc) * NXI + x3;
+    b_sw[j] = (cc - bb) * NXI;
+  }
+  const double2 *su_f = &su[0][0][0];
+  const double2 *sd_f = SYM ? su_f : &sd[0][0][0];
+  const double2 *s1_f = (SYM || same1) ? su_f : &s1[0][0][0];
+
+  // The propagator entries of the next group of sites are loaded into
+  // registers while the current group is built and multiplied.
+  constexpr int PFJ = (NS * NROW * NXI + 255) / 256;
+  double2 pu[PFJ], pd[PFJ], p1[PFJ], pw = make_double2(1.0, 0.0);
+  auto fetch = [&](int64_t xg) {
+    const int ns = int(min<int64_t>(NS, x1 - xg));
+#pragma unroll
+    for (int j = 0; j < PFJ; j++) {
+      const int i = tid + 256 * j;
+      if (i < ns * NROW * NXI) {
+        const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
+        const int s = xi % nsrc, kap = xi / nsrc;
+        const int64_t off = (((ln * a.V + xg + n) * nsrc + s) * 12 + r) * 12 + kap;
+        pu[j] = load_c<TIN>(a.prop_u, off);
+        if constexpr (!SYM) {
+          pd[j] = load_c<TIN>(a.prop_d, off);
+          if (!same1) p1[j] = load_c<TIN>(a.prop_q1, off);
+        }
+      }
+    }
+    if (tid < ns * nsrc && a.sink_w) {
+      const int n = tid / nsrc, s = tid % nsrc;
+      pw = reinterpret_cast<const double2 *>(a.sink_w)[int64_t(s) * a.V + xg + n];
+    }
+  };
+  if (x0 < x1) fetch(x0);
 
   for (int64_t xg = x0; xg < x1; xg += NS) {
     const int ns = int(min<int64_t>(NS, x1 - xg));
-    for (int i = tid; i < ns * NROW * NXI; i += 256) {
-      const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
-      const int s = xi % nsrc, kap = xi / nsrc;
-      const int64_t off = (((ln * a.V + xg + n) * nsrc + s) * 12 + r) * 12 + kap;
-      const double2 vu = load_c<TIN>(a.prop_u, off);
-      su[n][r][xi] = make_double2(vu.x * scale, vu.y * scale);
-      if constexpr (!SYM) {
-        const double2 vd = load_c<TIN>(a.prop_d, off);
-        sd[n][r][xi] = make_double2(vd.x * scale, vd.y * scale);
-        if (!same1) {
-          const double2 v1 = load_c<TIN>(a.prop_q1, off);
-          s1[n][r][xi] = make_double2(v1.x * scale, v1.y * scale);
+#pragma unroll
+    for (int j = 0; j < PFJ; j++) {
+      const int i = tid + 256 * j;
+      if (i < ns * NROW * NXI) {
+        const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
+        su[n][r][xi] = make_double2(pu[j].x * scale, pu[j].y * scale);
+        if constexpr (!SYM) {
+          sd[n][r][xi] = make_double2(pd[j].x * scale, pd[j].y * scale);
+          if (!same1) s1[n][r][xi] = make_double2(p1[j].x * scale, p1[j].y * scale);
         }
       }
     }
     if (tid < ns * nsrc) {
       const int n = tid / nsrc, s = tid % nsrc;
-      wsh[n][s] = a.sink_w ? reinterpret_cast<const double2 *>(a.sink_w)[int64_t(s) * a.V + xg + n]
-                           : make_double2(1.0, 0.0);
+      wsh[n][s] = pw;
     }
     __syncthreads();
+    if (xg + NS < x1) fetch(xg + NS);   // in flight during the work below
     // A operand: w S_q1[(alpha, a), xi1]
-    for (int i = tid; i < KG * MP; i += 256) {
-      const int k = i / MP, m = i % MP, n = k / 3, ac = k % 3;
-      double re = 0.0, im = 0.0;
-      if (n < ns && m < M) {
-        const int psi = m / NXI, xi1 = m % NXI, alpha = psi / nsrc, sk = psi % nsrc;
-        const double2 w = wsh[n][sk];
-        const double2 v = (SYM || same1) ? su[n][3 * alpha + ac][xi1] : s1[SYM ? 0 : n][SYM ? 0 : 3 * alpha + ac][SYM ? 0 : xi1];
-        re = w.x * v.x - w.y * v.y;
-        im = w.x * v.y + w.y * v.x;
+#pragma unroll
+    for (int j = 0; j < AJ; j++) {
+      const int i = tid + 256 * j;
+      if (i < KG * MP) {
+        double re = 0.0, im = 0.0;
+        if (a_src[j] >= 0 && a_n[j] < ns) {
+          const double2 w = (&wsh[0][0])[a_w[j]];
+          const double2 v = s1_f[a_src[j]];
+          re = w.x * v.x - w.y * v.y;
+          im = w.x * v.y + w.y * v.x;
+        }
+        (&Ar[0][0])[i] = re;
+        (&Ai[0][0])[i] = im;
+        (&As[0][0])[i] = re + im;
       }
-      Ar[k][m] = re;
-      Ai[k][m] = im;
     }
     // B operand: the diquark D_a[pair] = sum eps_abc (C g5)_{gd} S_u[(g,b)] S_d[(d,c)]
-    for (int i = tid; i < KG * NP; i += 256) {
-      const int k = i / NP, p = i % NP, n = k / 3, ac = k % 3;
-      double re = 0.0, im = 0.0;
-      if (n < ns && p < NPAIR) {
-        const int x2 = px2[p], x3 = px3[p];
+    // ((C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1)
 #pragma unroll
-        for (int e = 0; e < 2; e++) {
-          const int b = e == 0 ? (ac + 1) % 3 : (ac + 2) % 3;
-          const int c = e == 0 ? (ac + 2) % 3 : (ac + 1) % 3;
-          const double es = e == 0 ? 1.0 : -1.0;
+    for (int j = 0; j < BJ; j++) {
+      const int i = tid + 256 * j;
+      if (i < KG * NP) {
+        double re = 0.0, im = 0.0;
+        if (b_n[j] < ns) {
 #pragma unroll
           for (int g = 0; g < D; g++) {
-            // (C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1
-            const int gam = g, del = g ^ 1;
-            const double sg = es * ((g & 1) ? 1.0 : -1.0);
-            const double2 l = su[n][3 * gam + b][x2];
-            const double2 r = SYM ? su[n][3 * del + c][x3] : sd[SYM ? 0 : n][SYM ? 0 : 3 * del + c][SYM ? 0 : x3];
-            re += sg * (l.x * r.x - l.y * r.y);
-            im += sg * (l.x * r.y + l.y * r.x);
+            const double sg = (g & 1) ? 1.0 : -1.0;
+            const int go = 3 * g * NXI, gd = 3 * (g ^ 1) * NXI;
+            const double2 l0 = su_f[b_l0[j] + go], r0 = sd_f[b_r0[j] + gd];
+            const double2 l1 = su_f[b_l0[j] + b_sw[j] + go], r1 = sd_f[b_r0[j] - b_sw[j] + gd];
+            re += sg * ((l0.x * r0.x - l0.y * r0.y) - (l1.x * r1.x - l1.y * r1.y));
+            im += sg * ((l0.x * r0.y + l0.y * r0.x) - (l1.x * r1.y + l1.y * r1.x));
           }
         }
+        (&Br[0][0])[i] = re;
+        (&Bi[0][0])[i] = im;
+        (&Bs[0][0])[i] = re + im;
       }
-      Br[k][p] = re;
-      Bi[k][p] = im;
     }
     __syncthreads();
 #pragma unroll 1
@@ -357,12 +420,10 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
         const int t = wave + 4 * j;
         if (t < NTILE) {
           const int mt = t / NT, nt = t % NT;
-          const double ar = Ar[k][mt * 16 + (lane & 15)], ai = Ai[k][mt * 16 + (lane & 15)];
-          const double br = Br[k][nt * 16 + (lane & 15)], bi = Bi[k][nt * 16 + (lane & 15)];
-          accr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, accr[j], 0, 0, 0);
-          accr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, accr[j], 0, 0, 0);
-          acci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, acci[j], 0, 0, 0);
-          acci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acci[j], 0, 0, 0);
+          const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
+          m1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ar[k][am], Br[k][bn], m1[j], 0, 0, 0);
+          m2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ai[k][am], Bi[k][bn], m2[j], 0, 0, 0);
+          m3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[k][am], Bs[k][bn], m3[j], 0, 0, 0);
         }
       }
     }
@@ -379,7 +440,8 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
       for (int r = 0; r < 4; r++) {
         // v_mfma_f64_16x16x4f64 output: D[i][j] in lane j + 16 (i % 4), register i / 4
         const int m = mt * 16 + (lane >> 4) + 4 * r;
-        if (m < M && n < NPAIR) out[int64_t(m) * NPAIR + n] = make_double2(accr[j][r], acci[j][r]);
+        if (m < M && n < NPAIR)
+          out[int64_t(m) * NPAIR + n] = make_double2(m1[j][r] - m2[j][r], m3[j][r] - m1[j][r] - m2[j][r]);
       }
     }
   }

@@ -271,19 +271,32 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
 // entries of a split are f_T[y][psi] with y = (pair of the same-flavour
 // quarks, single quark): every split of an output with single index p reads
 // rows y = (*, p) only.  So the workgroup walks the single indices its
-// outputs contain ("phases"), loads the rows (pair, p) of its lane tile into
-// LDS -- in two ranges of pairs, so that one range of M baryon indices x 16
-// lanes stays within 36 KB -- and every thread then runs the splits of its
-// output that belong to the phase and range, reading the previous stage
-// from global memory and the block from LDS.  Per split the global traffic
-// is the NIN x PG previous components only; the block rows are fetched once
-// per workgroup and phase.
+// outputs contain ("phases"), each in two ranges of pair rows (pairs (a,b)
+// with b < bsplit, then the rest) so that one range of M baryon indices x 16
+// lanes stays within 36 KB of LDS, together with the split-table rows of
+// the phase.  Every thread then runs the splits of its output that belong to
+// the phase and range: previous-stage operands from global memory, block
+// entries and table entries from LDS.  The rows of the next range are
+// fetched into registers while the current one is computed.
+constexpr int LDS_SLOTS = 32, LDS_THREADS = 16 * LDS_SLOTS, LDS_MAX_ROWS = 36;
+
+// The y area holds LDS_MAX_ROWS rows (a range never has more for n_xi <= 12:
+// 36 and 30 rows for n_xi = 12, 15 for n_xi = 6); the table rows follow.
+int stage_lds_bytes(int nxi, int M, int pp) {
+  (void)nxi;
+  return LDS_MAX_ROWS * M * 16 * int(sizeof(double2)) + LDS_SLOTS * pp * int(sizeof(uint2));
+}
+
 template <typename TS, int M, int K, int PG>
-__global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
+__global__ __launch_bounds__(LDS_THREADS) void stage_lds_kernel(StageLdsArgs a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
-  constexpr int NSLOT = 16;
-  extern __shared__ double2 ylds[];   // [row][d][16 lanes]
+  constexpr int FPT = (LDS_MAX_ROWS * M * 16 + LDS_THREADS - 1) / LDS_THREADS;   // fill loads per thread
+  extern __shared__ double2 smem[];
+  double2 *ylds = smem;                                                        // [row][d][16 lanes]
+  uint2 *tlds = reinterpret_cast<uint2 *>(smem + LDS_MAX_ROWS * M * 16);      // [slot][pp]
+  __shared__ uint32_t s_single[LDS_SLOTS];
+  __shared__ int64_t s_q[LDS_SLOTS];
   __shared__ uint32_t wg_single;
   const int l = threadIdx.x & 15, slot = threadIdx.x >> 4;
   const int64_t tile = blockIdx.y;
@@ -292,7 +305,7 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
   // workgroups are dispatched round-robin over the 8 XCDs: give every XCD a
   // contiguous range of outputs
   const int64_t w = (wr % 8) * (nwg / 8) + wr / 8;
-  const int64_t gs = w * NSLOT + slot;
+  const int64_t gs = w * LDS_SLOTS + slot;
   const bool active = gs < a.nq_out * a.npg;
   const int64_t q = active ? gs / a.npg : 0;
   const int pass0 = active ? int(gs % a.npg) * PG : 0;
@@ -305,13 +318,17 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
     sm = a.act_is_P ? md : mu;
   }
   if (threadIdx.x == 0) wg_single = 0;
+  if (l == 0) {
+    s_single[slot] = sm;
+    s_q[slot] = q;
+  }
   __syncthreads();
   if (active && l == 0) atomicOr(&wg_single, sm);
   __syncthreads();
   const uint32_t phases = wg_single;
-  const int R1 = a.bsplit * (a.bsplit - 1) / 2;          // rows of the first range
+  const int R1 = a.bsplit * (a.bsplit - 1) / 2;   // rows of the first range
   const int nrange = R1 < a.npair ? 2 : 1;
-  const int c0 = [&] {                                    // splits per phase in the first range
+  const int c0 = [&] {                             // splits per phase in the first range
     const int n = __builtin_popcount(pm & ((1u << a.bsplit) - 1u));
     return n * (n - 1) / 2;
   }();
@@ -320,9 +337,41 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
   auto sig_out = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NOUT + r; };
   const CS *Fin = static_cast<const CS *>(a.Fin);
   const double2 *fb = static_cast<const double2 *>(a.fblk);
-  const uint2 *qs = reinterpret_cast<const uint2 *>(a.qsplit) + q * a.Sq;
-  const int64_t in_lane = lane_off(b, ns_in), out_lane = lane_off(b, ns_out);
+  const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
+  const int64_t out_lane = lane_off(b, ns_out);
   const int64_t ftile = tile * a.npsi * 16;
+  const int64_t xstride = int64_t(ns_in) * Bp;
+
+  // the (phase, range) sequence of the workgroup, walked with a cursor
+  auto next_step = [&](int p, int h, int &np, int &nh) {
+    if (h + 1 < nrange) {
+      np = p;
+      nh = h + 1;
+      return;
+    }
+    uint32_t rest = phases & ~((2u << p) - 1u);
+    np = rest ? __builtin_ctz(rest) : -1;
+    nh = 0;
+  };
+  auto range_rows = [&](int h, int &r0, int &r1) {
+    r0 = h ? R1 : 0;
+    r1 = (h || nrange == 1) ? a.npair : R1;
+  };
+  double2 pre[FPT];
+  auto prefetch = [&](int p, int h) {
+    int r0, r1;
+    range_rows(h, r0, r1);
+    const int nel = (r1 - r0) * M * 16;
+#pragma unroll
+    for (int i = 0; i < FPT; i++) {
+      const int e = int(threadIdx.x) + i * LDS_THREADS;
+      if (e < nel) {
+        const int row = r0 + e / (M * 16), d = (e / 16) % M, ll = e & 15;
+        const int64_t y = a.act_is_P ? int64_t(row) * a.nxi + p : int64_t(p) * a.npair + row;
+        pre[i] = fb[y * a.npsi * Bp + ftile + a.psi_of_pos[d] * 16 + ll];
+      }
+    }
+  };
 
   double2 acc[PG][NOUT];
 #pragma unroll
@@ -330,47 +379,65 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
 #pragma unroll
     for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
 
-  for (int p = 0; p < a.nxi; p++) {
-    if (!((phases >> p) & 1u)) continue;   // uniform over the workgroup
-    const bool mine = active && ((sm >> p) & 1u);
-    const int j = __builtin_popcount(sm & ((1u << p) - 1u));
-    for (int h = 0; h < nrange; h++) {
-      const int r0 = h ? R1 : 0, r1 = (h || nrange == 1) ? a.npair : R1;
-      __syncthreads();   // the previous range is no longer read
-      const int nel = (r1 - r0) * M * 16;
-      for (int e = threadIdx.x; e < nel; e += 256) {
-        const int row = r0 + e / (M * 16), d = (e / 16) % M, ll = e & 15;
-        const int64_t y = a.act_is_P ? int64_t(row) * a.nxi + p : int64_t(p) * a.npair + row;
-        ylds[e] = fb[y * a.npsi * Bp + ftile + a.psi_of_pos[d] * 16 + ll];
+  int p = phases ? __builtin_ctz(phases) : -1, h = 0;
+  if (p >= 0) prefetch(p, h);
+  while (p >= 0) {
+    int r0, r1;
+    range_rows(h, r0, r1);
+    __syncthreads();   // the previous range is no longer read
+#pragma unroll
+    for (int i = 0; i < FPT; i++) {
+      const int e = int(threadIdx.x) + i * LDS_THREADS;
+      if (e < (r1 - r0) * M * 16) ylds[e] = pre[i];
+    }
+    if (h == 0) {
+      // split-table rows of this phase: pp entries per slot whose output
+      // contains the single index p
+      for (int e = threadIdx.x; e < LDS_SLOTS * a.pp; e += LDS_THREADS) {
+        const int sl = e / a.pp, t = e - sl * a.pp;
+        const uint32_t ssm = s_single[sl];
+        if ((ssm >> p) & 1u) {
+          const int jj = __builtin_popcount(ssm & ((1u << p) - 1u));
+          tlds[e] = reinterpret_cast<const uint2 *>(a.qsplit)[s_q[sl] * a.Sq + jj * a.pp + t];
+        }
       }
-      __syncthreads();
-      if (!mine) continue;
-      const int t0 = j * a.pp + (h ? c0 : 0);
-      const int t1 = j * a.pp + ((h || nrange == 1) ? a.pp : c0);
+    }
+    __syncthreads();
+    int np, nh;
+    next_step(p, h, np, nh);
+    if (np >= 0) prefetch(np, nh);   // in flight during the products below
+    if (active && ((sm >> p) & 1u)) {
+      const int t0 = h ? c0 : 0, t1 = (h || nrange == 1) ? a.pp : c0;
+      const uint2 *trow = tlds + slot * a.pp;
       for (int t = t0; t < t1; t++) {
-        const uint2 e = qs[t];
+        const uint2 e = trow[t];
         const uint32_t y = e.y & 0x7fffffffu;
         const int row = a.act_is_P ? int(__umulhi(y - uint32_t(p), a.div_magic)) : int(y) - p * a.npair;
         const double sgn = (e.y >> 31) ? -1.0 : 1.0;
+        const CS *xrow = Fin + int64_t(e.x) * xstride;
+        CS xin[PG][NIN];
+#pragma unroll
+        for (int g = 0; g < PG; g++)
+#pragma unroll
+          for (int r = 0; r < NIN; r++)
+            xin[g][r] = ld(xrow, (in_lane + uint32_t(sig_in(r, pass0 + g) * 16)) * uint32_t(sizeof(CS)));
         double2 fy[M];
 #pragma unroll
         for (int d = 0; d < M; d++) {
           const double2 v = ylds[((row - r0) * M + d) * 16 + l];
           fy[d] = make_double2(sgn * v.x, sgn * v.y);
         }
-        const int64_t xbase = int64_t(e.x) * ns_in * Bp + in_lane;
 #pragma unroll
         for (int g = 0; g < PG; g++) {
           double2 fin[NIN];
 #pragma unroll
-          for (int r = 0; r < NIN; r++) {
-            const CS v = Fin[xbase + sig_in(r, pass0 + g) * 16];
-            fin[r] = make_double2(double(v.x), double(v.y));
-          }
+          for (int r = 0; r < NIN; r++) fin[r] = make_double2(double(xin[g][r].x), double(xin[g][r].y));
           wedge_accumulate<M, K>(fin, fy, acc[g]);
         }
       }
     }
+    p = np;
+    h = nh;
   }
   if (!active) return;
   CS *Fout = static_cast<CS *>(a.Fout);
@@ -385,20 +452,13 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageLdsArgs a) {
     }
 }
 
-int stage_lds_bytes(int nxi, int M) {
-  const int npair = nxi * (nxi - 1) / 2;
-  const int bsplit = nxi > 9 ? 9 : nxi;
-  const int R1 = bsplit * (bsplit - 1) / 2;
-  const int rows = R1 > npair - R1 ? R1 : npair - R1;
-  return rows * M * 16 * int(sizeof(double2));
-}
-
 template <typename T, int M, int K, int PG>
 static hipError_t launch_stage_lds_mkp(const StageLdsArgs &a, hipStream_t s) {
   const int64_t nslot = a.nq_out * a.npg;
-  const int64_t nwg = ((nslot + 15) / 16 + 7) / 8 * 8;
+  const int64_t nwg = ((nslot + LDS_SLOTS - 1) / LDS_SLOTS + 7) / 8 * 8;
   dim3 grid(unsigned(nwg), unsigned(a.Bp / 16));
-  hipLaunchKernelGGL((stage_lds_kernel<T, M, K, PG>), grid, dim3(256), stage_lds_bytes(a.nxi, M), s, a);
+  hipLaunchKernelGGL((stage_lds_kernel<T, M, K, PG>), grid, dim3(LDS_THREADS), stage_lds_bytes(a.nxi, M, a.pp), s,
+                     a);
   return hipGetLastError();
 }
 

@@ -95,9 +95,9 @@ struct StageLdsArgs {
   int psi_of_pos[8];
 };
 hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s);
-// LDS bytes the staged kernel uses for a term list with nxi quark indices
-// and base-set size M.
-int stage_lds_bytes(int nxi, int M);
+// LDS bytes the staged kernel uses for a term list with nxi quark indices,
+// base-set size M and pp splits per single index.
+int stage_lds_bytes(int nxi, int M, int pp);
 
 // Final signed sum C[b][delta][alpha] = 2^(A lane_exp[b]) / (n_P! n_N!) *
 // sum_e c_e F[q_e][delta][b].
