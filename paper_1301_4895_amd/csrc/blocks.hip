@@ -415,16 +415,26 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
 #pragma unroll 1
     for (int ks = 0; ks < KG / 4; ks++) {
       const int k = 4 * ks + (lane >> 4);
+      // every operand of the k-step first, then the products; a wave with
+      // fewer tiles repeats its last tile into an accumulator never stored
+      double oa[TPW][3], ob[TPW][3];
 #pragma unroll
       for (int j = 0; j < TPW; j++) {
-        const int t = wave + 4 * j;
-        if (t < NTILE) {
-          const int mt = t / NT, nt = t % NT;
-          const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
-          m1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ar[k][am], Br[k][bn], m1[j], 0, 0, 0);
-          m2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ai[k][am], Bi[k][bn], m2[j], 0, 0, 0);
-          m3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[k][am], Bs[k][bn], m3[j], 0, 0, 0);
-        }
+        const int t = min(wave + 4 * j, NTILE - 1);
+        const int mt = t / NT, nt = t % NT;
+        const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
+        oa[j][0] = Ar[k][am];
+        oa[j][1] = Ai[k][am];
+        oa[j][2] = As[k][am];
+        ob[j][0] = Br[k][bn];
+        ob[j][1] = Bi[k][bn];
+        ob[j][2] = Bs[k][bn];
+      }
+#pragma unroll
+      for (int j = 0; j < TPW; j++) {
+        m1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][0], ob[j][0], m1[j], 0, 0, 0);
+        m2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][1], ob[j][1], m2[j], 0, 0, 0);
+        m3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][2], ob[j][2], m3[j], 0, 0, 0);
       }
     }
     __syncthreads();
