@@ -143,7 +143,11 @@ class TermList:
             lib().mb_term_list_free(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: module globals may be gone
+            pass
 
     def counts(self):
         c = mb_counts()

@@ -9,23 +9,15 @@
 // eps is antisymmetric), so only xi2 <= xi3 is formed and one block serves
 // both species.
 //
-// A workgroup owns one lane and one chunk of sites.  Propagators of a group
-// of sites are staged in LDS, the diquark is formed in LDS, and every thread
-// accumulates a register tile (all psi) x (one xi1) x (several pairs), the
-// A values of its xi1 reused across the pairs.  MB_MIXED forms the products
-// and a partial sum over each site group in float and adds the partial sums
-// in double; MB_FP64 works in double throughout.
+// A workgroup owns one lane and one chunk of sites and sums its sites on the
+// matrix cores (below); a second kernel adds the chunk sums in double in a
+// fixed order, antisymmetrises and writes the block layout, and a third
+// scales every lane by its exponent.
 #include <hip/hip_runtime.h>
-
-#include <cstdlib>
 
 #include "kernels.h"
 
 namespace mb {
-
-template <typename T> struct cplx_t;
-template <> struct cplx_t<float> { using type = float2; };
-template <> struct cplx_t<double> { using type = double2; };
 
 template <typename TIN> __device__ inline double2 load_c(const void *p, int64_t i);
 template <> __device__ inline double2 load_c<float2>(const void *p, int64_t i) {
@@ -36,196 +28,8 @@ template <> __device__ inline double2 load_c<double2>(const void *p, int64_t i) 
   return static_cast<const double2 *>(p)[i];
 }
 
-constexpr int kThreads = 256;
-constexpr int kSitesPerGroup = 4;
-
-// NXI active quark indices (6 or 12), NPSI = D*nsrc baryon indices (2 or 4),
-// NROW = 3*D sink rows, SYM: u = d.
-template <typename T, typename TIN, int NXI, int NPSI, int NROW, bool SYM>
-__global__ __launch_bounds__(kThreads) void blocks_partial_kernel(BlocksArgs a) {
-  using C2 = typename cplx_t<T>::type;
-  constexpr int NPAIR = SYM ? NXI * (NXI + 1) / 2 : NXI * NXI;
-  constexpr int NG = kThreads / NXI;             // pair groups
-  constexpr int PPT = (NPAIR + NG - 1) / NG;     // pairs per thread
-  constexpr int NS = kSitesPerGroup;
-  constexpr int D = NROW / 3;
-
-  __shared__ C2 sq1[NS][NROW][NXI];
-  __shared__ C2 su[NS][NROW][NXI];
-  __shared__ C2 sd[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
-  __shared__ C2 dq[NS][3][NPAIR];
-  __shared__ C2 wsh[NS][2];
-
-  const int tid = threadIdx.x;
-  const int64_t lane = blockIdx.y;
-  const int chunk = blockIdx.x;
-  const int nsrc = a.nsrc;
-  const int64_t x0 = int64_t(chunk) * a.sites_per_chunk;
-  const int64_t x1 = min(a.V, x0 + a.sites_per_chunk);
-  const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[lane]) : 1.0;
-
-  const int xi1 = tid % NXI;
-  const int grp = tid / NXI;
-  const bool active = grp < NG;
-
-  double2 tot[NPSI][PPT];
-  C2 acc[NPSI][PPT];
-#pragma unroll
-  for (int p = 0; p < NPSI; p++)
-#pragma unroll
-    for (int j = 0; j < PPT; j++) {
-      tot[p][j] = make_double2(0.0, 0.0);
-      acc[p][j].x = T(0);
-      acc[p][j].y = T(0);
-    }
-
-  const bool same1 = a.prop_q1 == a.prop_u;
-  for (int64_t xg = x0; xg < x1; xg += NS) {
-    const int ns = int(min<int64_t>(NS, x1 - xg));
-    // ---- stage propagators of the site group (rows < 3D, active columns)
-    for (int i = tid; i < ns * NROW * NXI; i += kThreads) {
-      int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
-      int s = xi % nsrc, kap = xi / nsrc;
-      int64_t off = (((lane * a.V + xg + n) * nsrc + s) * 12 + r) * 12 + kap;
-      double2 vu = load_c<TIN>(a.prop_u, off);
-      C2 cu;
-      cu.x = T(vu.x * scale);
-      cu.y = T(vu.y * scale);
-      su[n][r][xi] = cu;
-      if (!same1) {
-        double2 v1 = load_c<TIN>(a.prop_q1, off);
-        C2 c1;
-        c1.x = T(v1.x * scale);
-        c1.y = T(v1.y * scale);
-        sq1[n][r][xi] = c1;
-      }
-      if constexpr (!SYM) {
-        double2 vd = load_c<TIN>(a.prop_d, off);
-        C2 cd;
-        cd.x = T(vd.x * scale);
-        cd.y = T(vd.y * scale);
-        sd[n][r][xi] = cd;
-      }
-    }
-    if (tid < ns * nsrc) {
-      int n = tid / nsrc, s = tid % nsrc;
-      C2 w;
-      if (a.sink_w) {
-        double2 wv = reinterpret_cast<const double2 *>(a.sink_w)[int64_t(s) * a.V + xg + n];
-        w.x = T(wv.x);
-        w.y = T(wv.y);
-      } else {
-        w.x = T(1);
-        w.y = T(0);
-      }
-      wsh[n][s] = w;
-    }
-    __syncthreads();
-    // ---- diquark D_a[pair]
-    for (int i = tid; i < ns * 3 * NPAIR; i += kThreads) {
-      int n = i / (3 * NPAIR), ac = (i / NPAIR) % 3, p = i % NPAIR;
-      int x2, x3;
-      if constexpr (SYM) {
-        x3 = 0;
-        while ((x3 + 1) * (x3 + 2) / 2 <= p) x3++;
-        x2 = p - x3 * (x3 + 1) / 2;
-      } else {
-        x2 = p / NXI;
-        x3 = p % NXI;
-      }
-      T re = 0, im = 0;
-#pragma unroll
-      for (int e = 0; e < 2; e++) {
-        const int b = e == 0 ? (ac + 1) % 3 : (ac + 2) % 3;
-        const int c = e == 0 ? (ac + 2) % 3 : (ac + 1) % 3;
-        const T es = e == 0 ? T(1) : T(-1);
-#pragma unroll
-        for (int g = 0; g < D; g++) {
-          // (C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1
-          const int gam = g, del = g ^ 1;
-          const T gs = (g & 1) ? T(1) : T(-1);
-          C2 l = su[n][3 * gam + b][x2];
-          C2 r = SYM ? su[n][3 * del + c][x3] : sd[SYM ? 0 : n][SYM ? 0 : 3 * del + c][SYM ? 0 : x3];
-          const T s = es * gs;
-          re += s * (l.x * r.x - l.y * r.y);
-          im += s * (l.x * r.y + l.y * r.x);
-        }
-      }
-      C2 v;
-      v.x = re;
-      v.y = im;
-      dq[n][ac][p] = v;
-    }
-    __syncthreads();
-    // ---- register-tile accumulation
-    if (active) {
-      for (int n = 0; n < ns; n++) {
-        C2 A[NPSI][3];
-#pragma unroll
-        for (int p = 0; p < NPSI; p++) {
-          const int alpha = p / nsrc, sk = p % nsrc;
-          const C2 w = wsh[n][sk];
-#pragma unroll
-          for (int ac = 0; ac < 3; ac++) {
-            const C2 s = same1 ? su[n][3 * alpha + ac][xi1] : sq1[n][3 * alpha + ac][xi1];
-            A[p][ac].x = w.x * s.x - w.y * s.y;
-            A[p][ac].y = w.x * s.y + w.y * s.x;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < PPT; j++) {
-          const int pr = grp + NG * j;
-          if (pr < NPAIR) {
-            const C2 d0 = dq[n][0][pr], d1 = dq[n][1][pr], d2 = dq[n][2][pr];
-#pragma unroll
-            for (int p = 0; p < NPSI; p++) {
-              T re = acc[p][j].x, im = acc[p][j].y;
-              re += A[p][0].x * d0.x - A[p][0].y * d0.y;
-              im += A[p][0].x * d0.y + A[p][0].y * d0.x;
-              re += A[p][1].x * d1.x - A[p][1].y * d1.y;
-              im += A[p][1].x * d1.y + A[p][1].y * d1.x;
-              re += A[p][2].x * d2.x - A[p][2].y * d2.y;
-              im += A[p][2].x * d2.y + A[p][2].y * d2.x;
-              acc[p][j].x = re;
-              acc[p][j].y = im;
-            }
-          }
-        }
-      }
-      // float partial sums of the site group go to double
-      if constexpr (sizeof(T) == 4) {
-#pragma unroll
-        for (int p = 0; p < NPSI; p++)
-#pragma unroll
-          for (int j = 0; j < PPT; j++) {
-            tot[p][j].x += double(acc[p][j].x);
-            tot[p][j].y += double(acc[p][j].y);
-            acc[p][j].x = T(0);
-            acc[p][j].y = T(0);
-          }
-      }
-    }
-    __syncthreads();
-  }
-  if (active) {
-    double2 *out = reinterpret_cast<double2 *>(a.partial) +
-                   ((lane * a.nchunk + chunk) * NPSI) * int64_t(NXI) * NPAIR;
-#pragma unroll
-    for (int p = 0; p < NPSI; p++)
-#pragma unroll
-      for (int j = 0; j < PPT; j++) {
-        const int pr = grp + NG * j;
-        if (pr < NPAIR) {
-          double2 v = tot[p][j];
-          if constexpr (sizeof(T) == 8) v = make_double2(double(acc[p][j].x), double(acc[p][j].y));
-          out[(int64_t(p) * NXI + xi1) * NPAIR + pr] = v;
-        }
-      }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// The same site sums as one complex GEMM per lane on the matrix cores:
+// The site sums as one complex GEMM per lane on the matrix cores:
 //   f[m = (psi, xi1)][n = pair] += sum_k A[m][k] B[k][n],  k = (site, colour a)
 //   A[m][k] = w_{s'(psi)}(x) S_q1[(alpha(psi), a), xi1],  B[k][n] = D_a(x)[pair]
 // with v_mfma_f64_16x16x4f64 (double products and sums).  Operand layout:
@@ -475,37 +279,10 @@ static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-template <typename T, typename TIN, int NXI, int NPSI, int NROW, bool SYM>
-static hipError_t launch_bp(const BlocksArgs &a, hipStream_t s) {
-  dim3 grid(a.nchunk, unsigned(a.B));
-  hipLaunchKernelGGL((blocks_partial_kernel<T, TIN, NXI, NPSI, NROW, SYM>), grid, dim3(kThreads), 0, s,
-                     a);
-  return hipGetLastError();
-}
-
-template <typename T, typename TIN>
-static hipError_t dispatch_bp(const BlocksArgs &a, bool sym, hipStream_t s) {
-  // (D, nsrc) -> (NXI, NPSI, NROW): (4,1) -> (12,4,12); (2,1) -> (6,2,6); (2,2) -> (12,4,6)
-  if (a.D == 4 && a.nsrc == 1)
-    return sym ? launch_bp<T, TIN, 12, 4, 12, true>(a, s) : launch_bp<T, TIN, 12, 4, 12, false>(a, s);
-  if (a.D == 2 && a.nsrc == 1)
-    return sym ? launch_bp<T, TIN, 6, 2, 6, true>(a, s) : launch_bp<T, TIN, 6, 2, 6, false>(a, s);
-  if (a.D == 2 && a.nsrc == 2)
-    return sym ? launch_bp<T, TIN, 12, 4, 6, true>(a, s) : launch_bp<T, TIN, 12, 4, 6, false>(a, s);
-  return hipErrorInvalidValue;
-}
-
 hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipStream_t s) {
   // Both precision modes form the site sums in double on the matrix cores
-  // (FP64 MFMA) and store the blocks in double.  MB_BLOCKS_VALU=1 selects the
-  // vector-unit kernel instead (same arithmetic, for comparison).
+  // (FP64 MFMA) and store the blocks in double.
   (void)mixed;
-  static const bool valu = [] {
-    const char *e = getenv("MB_BLOCKS_VALU");
-    return e && e[0] == '1';
-  }();
-  if (valu)
-    return a.in_c128 ? dispatch_bp<double, double2>(a, sym, s) : dispatch_bp<double, float2>(a, sym, s);
   return a.in_c128 ? dispatch_bm<double2>(a, sym, s) : dispatch_bm<float2>(a, sym, s);
 }
 
