@@ -122,7 +122,7 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 // operand load is then a 16-lane row segment (one 128-byte line of a float
 // stage), which keeps four times more previous-stage rows in L2.  Which tile
 // is faster depends on the step; the autotuner decides.
-template <typename TS, int M, int K, int PG, int TILE>
+template <typename TS, int M, int K, int PG, int TILE, int U>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
@@ -161,14 +161,12 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   for (int g = 0; g < PG; g++)
 #pragma unroll
     for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
-  // U splits per round: the table entries and every operand load of the U
-  // splits are issued before the first product, so that a wavefront keeps
-  // U splits of loads in flight.  The split table is read with wave-uniform
+  // U splits per round (1 or 2): the table entries and every operand load of
+  // the U splits are issued before the first product, so that a wavefront
+  // keeps U splits of loads in flight.  The split table is read with wave-uniform
   // (scalar) loads; with sub-waves every sub-wave then selects its own
   // entry.  Past the end of the list a sub-wave loads the last split again
   // (in bounds) and drops it.
-  constexpr int VG_SPLIT = NIN * PG * int(sizeof(CS)) / 4 + 4 * M;   // VGPRs of one split's operands
-  constexpr int U = VG_SPLIT <= 16 ? 4 : VG_SPLIT <= 32 ? 2 : 1;
   constexpr bool SIGN_ON_X = NIN * PG < M;
   for (int s0 = 0; s0 < a.Sq; s0 += SUB * U) {
     uint2 e[U];
@@ -485,12 +483,21 @@ hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s) {
   return mixed ? launch_stage_lds_t<float>(a, s) : launch_stage_lds_t<double>(a, s);
 }
 
-template <typename T, int M, int K, int PG, int TILE>
-static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
+template <typename T, int M, int K, int PG, int TILE, int U>
+static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
   dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / TILE));
-  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE>), grid, dim3(64), a.lds_bytes, s, a);
+  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
+}
+
+// splits in flight per wavefront: as tuned, else 2 when the operands of two
+// splits fit in 32 registers
+template <typename T, int M, int K, int PG, int TILE>
+static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
+  constexpr int VG_SPLIT = binom_c(M, K) * PG * int(sizeof(typename c2<T>::type)) / 4 + 4 * M;
+  const int u = a.unroll ? a.unroll : (VG_SPLIT <= 32 ? 2 : 1);
+  return u == 2 ? launch_stage_mkptu<T, M, K, PG, TILE, 2>(a, s) : launch_stage_mkptu<T, M, K, PG, TILE, 1>(a, s);
 }
 
 template <typename T, int M, int K, int PG>

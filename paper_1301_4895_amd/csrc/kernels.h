@@ -69,6 +69,7 @@ struct StageArgs {
   int pg;                    // passthrough parts per thread (0 = automatic)
   int lds_bytes;             // LDS reserved per workgroup
   int tile;                  // lanes per wavefront: 64 or 16
+  int unroll;                // splits in flight per wavefront: 1, 2 (0 = automatic)
   int npsi;                  // baryon indices of the block layout
   int psi_of_pos[8];
 };

@@ -346,3 +346,26 @@ def test_split_order_single_index_then_pair_rank(nP, nN, rel, nsrc, spins):
         for i in range(0, len(Q), max(1, len(Q) // 50)):
             bits = [b for b in range(nxi) if smask[i] >> b & 1]
             assert list(single[i].reshape(k[0], pp)[:, 0]) == bits
+
+
+def test_launch_tuning_validation():
+    """mb_term_list_tune accepts the documented values and rejects others
+    (host only; launch settings never change results, which the GPU tests
+    check)."""
+    tl = B.TermList(2, 2, True, 1, all_components=True)   # passthrough counts 1, 6, 6
+    ok = [(B.MB_TUNE_PASS_GROUP, 0), (B.MB_TUNE_LANE_TILE, 16), (B.MB_TUNE_LANE_TILE, 64),
+          (B.MB_TUNE_LDS_BYTES, 0), (B.MB_TUNE_LDS_BYTES, 65536), (B.MB_TUNE_KERNEL, 1), (B.MB_TUNE_KERNEL, 0),
+          (B.MB_TUNE_UNROLL, 0), (B.MB_TUNE_UNROLL, 2)]
+    for what, v in ok:
+        tl.tune(3, what, v)
+    for g in (1, 2, 3, 6):
+        tl.tune(3, B.MB_TUNE_PASS_GROUP, g)
+    bad = [(B.MB_TUNE_PASS_GROUP, 4), (B.MB_TUNE_PASS_GROUP, 5), (B.MB_TUNE_LANE_TILE, 32),
+           (B.MB_TUNE_LDS_BYTES, 65537), (B.MB_TUNE_KERNEL, 2), (B.MB_TUNE_UNROLL, 3), (99, 0)]
+    for what, v in bad:
+        with pytest.raises(B.MBError):
+            tl.tune(3, what, v)
+    with pytest.raises(B.MBError):
+        tl.tune(1, B.MB_TUNE_PASS_GROUP, 2)    # step 1 has one passthrough part
+    with pytest.raises(B.MBError):
+        tl.tune(4, B.MB_TUNE_LANE_TILE, 16)    # no step 4 in a 4-baryon list
