@@ -168,7 +168,7 @@ def run_workload(name, args):
                                  log=log)
             tuning[prec_name] = {str(k): {"kernel": "lds-staged" if v[0] else "direct", "pass_group": v[1],
                                           "lds_bytes": v[2], "lane_tile": v[3], "unroll": v[4],
-                                          "ms": round(v[5], 3)}
+                                          "outputs_per_wave": v[5], "ms": round(v[6], 3)}
                                  for k, v in best.items()}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
         ev = {}

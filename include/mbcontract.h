@@ -211,6 +211,10 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
  *                       sub-waves share the quark splits of an output)
  *   MB_TUNE_UNROLL      splits whose loads a wavefront of the direct kernel
  *                       issues together: 1 or 2 (0 = automatic)
+ *   MB_TUNE_GROUP       outputs per wavefront: 1 (default), or 2 or 4 with
+ *                       64 lanes, where neighbouring outputs share the block
+ *                       rows they read at the same split position (applies
+ *                       with passthrough groups up to 3)
  *   MB_TUNE_KERNEL      0 (default): every thread gathers its block entries
  *                       from global memory; 1: the block rows of one single
  *                       quark index at a time are staged in LDS per
@@ -222,6 +226,7 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
 #define MB_TUNE_LANE_TILE 3
 #define MB_TUNE_KERNEL 4
 #define MB_TUNE_UNROLL 5
+#define MB_TUNE_GROUP 6
 int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
 
 /* Copies the operation tables to device memory `dev` (caller-owned, at least

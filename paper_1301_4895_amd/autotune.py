@@ -2,8 +2,8 @@
 
 For every step of a term list it times the candidate launch settings exposed
 by ``mb_term_list_tune`` -- the kernel (direct gathers, or block rows staged
-in LDS), passthrough spin parts per thread, lanes per wavefront, splits in
-flight per wavefront and LDS
+in LDS), passthrough spin parts per thread, lanes per wavefront, outputs
+per wavefront, splits in flight per wavefront and LDS
 reserved per workgroup (which caps resident workgroups, hence operands in
 flight per L2) -- on the caller's own buffers, keeps the fastest, and records
 the choice in a JSON cache keyed by workload, precision, lanes and device.
@@ -23,24 +23,26 @@ LDS_CANDIDATES = (0, 16384)
 TILES = (64, 16)
 
 
-CACHE_VERSION = "v3"
+CACHE_VERSION = "v4"
 
 
 def _candidates(npass):
-    """(kernel, pass group, LDS bytes, lane tile, splits in flight)."""
+    """(kernel, pass group, LDS bytes, lane tile, splits in flight, outputs per wavefront)."""
     pgs = [pg for pg in (1, 2, 3, 6) if npass % pg == 0]
-    direct = [(0, pg, 0, t, u) for pg in pgs for t in TILES for u in (1, 2)]
-    capped = [(0, pg, lds, t, 0) for pg in pgs for t in TILES for lds in LDS_CANDIDATES if lds]
-    staged = [(1, pg, 0, 16, 0) for pg in (1, 2, 3) if npass % pg == 0]
-    return direct + capped + staged
+    direct = [(0, pg, 0, t, u, 1) for pg in pgs for t in TILES for u in (1, 2)]
+    capped = [(0, pg, lds, t, 0, 1) for pg in pgs for t in TILES for lds in LDS_CANDIDATES if lds]
+    grouped = [(0, pg, 0, 64, 0, gr) for pg in pgs if pg <= 3 for gr in (2, 4)]
+    staged = [(1, pg, 0, 16, 0, 1) for pg in (1, 2, 3) if npass % pg == 0]
+    return direct + capped + grouped + staged
 
 
-def _apply(tl, s, kernel, pg, lds, tile, unroll):
+def _apply(tl, s, kernel, pg, lds, tile, unroll, group):
     tl.tune(s, B.MB_TUNE_KERNEL, kernel)
     tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
     tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
     tl.tune(s, B.MB_TUNE_LANE_TILE, tile)
     tl.tune(s, B.MB_TUNE_UNROLL, unroll)
+    tl.tune(s, B.MB_TUNE_GROUP, group)
 
 
 def _time_step(tl, runner, step, reps, stream):
@@ -57,7 +59,7 @@ def _time_step(tl, runner, step, reps, stream):
 def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = None, reps: int = 2,
          log=None):
     """Tunes every step on ``runner``'s buffers.
-    Returns {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, ms)}."""
+    Returns {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group, ms)}."""
     c = tl.counts()
     dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
     full_key = f"{key}|{dev}|{CACHE_VERSION}" if key else None
@@ -67,8 +69,8 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
             log(f"[autotune] {full_key} not in {cache}: tuning")
         if full_key in table:
             best = {int(s): tuple(v) for s, v in table[full_key].items()}
-            for s, (kern, pg, lds, t, u, _) in best.items():
-                _apply(tl, s, kern, pg, lds, t, u)
+            for s, v in best.items():
+                _apply(tl, s, *v[:-1])
             return best
     stream = torch.cuda.current_stream()
     # bring every stage to a valid state once
@@ -92,12 +94,13 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
         for cand in _candidates(npass):
             _apply(tl, s, *cand)
             results.append((_time_step(tl, runner, s, reps, stream),) + cand)
-        ms, kern, pg, lds, tile, unroll = min(results)
-        _apply(tl, s, kern, pg, lds, tile, unroll)
-        best[s] = (kern, pg, lds, tile, unroll, ms)
+        ms, *cand = min(results)
+        _apply(tl, s, *cand)
+        best[s] = tuple(cand) + (ms,)
         if log:
             log(f"[autotune] step {s}: " + ", ".join(
-                f"{'lds' if k else 'dir'}/pg{g}/lds{l}/t{t}/u{u}={m:.2f}ms" for m, k, g, l, t, u in sorted(results)[:4]))
+                f"{'lds' if k else 'dir'}/pg{g}/lds{l}/t{t}/u{u}/g{gr}={m:.2f}ms"
+                for m, k, g, l, t, u, gr in sorted(results)[:4]))
     if cache and full_key:
         table = json.load(open(cache)) if os.path.exists(cache) else {}
         table[full_key] = {str(s): list(v) for s, v in best.items()}

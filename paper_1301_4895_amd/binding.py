@@ -20,7 +20,8 @@ MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST = 0, 1, 2
 MB_C64, MB_C128 = 0, 1
 MB_FP64, MB_MIXED = 0, 1
 MB_MAX_STAGES = 16
-MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUNE_UNROLL = 1, 2, 3, 4, 5
+MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUNE_UNROLL, MB_TUNE_GROUP = \
+    1, 2, 3, 4, 5, 6
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
  MB_EXPORT_DELTA, MB_EXPORT_ALPHA) = range(1, 8)
 

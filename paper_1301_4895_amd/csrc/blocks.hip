@@ -288,16 +288,18 @@ hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipS
 
 // ---------------------------------------------------------------------------
 // Finish: chunk sum (double, fixed order), antisymmetrisation, block layout.
+// One workgroup row per lane: the threads of a lane walk its components, so
+// that the chunk sums they read lie in the lane's own contiguous partial rows.
 template <typename TO>
 __global__ __launch_bounds__(256) void blocks_finish_kernel(FinishArgs a, int nxi, int npsi) {
-  const int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const int64_t b = blockIdx.x;
   const int npair2 = nxi * (nxi - 1) / 2;
   const int nyq = npair2 * nxi;
-  const int64_t comp = blockIdx.y;  // over 2 * npsi * nyq (proton then neutron)
+  const int64_t comp = blockIdx.y * int64_t(blockDim.x) + threadIdx.x;  // over 2 * npsi * nyq
+  if (comp >= 2 * int64_t(npsi) * nyq) return;
   const int species = int(comp / (int64_t(npsi) * nyq));
   const int rem = int(comp % (int64_t(npsi) * nyq));
   const int psi = rem / nyq, yq = rem % nyq;
-  if (b >= a.Bp) return;
   const int npair = a.sym ? nxi * (nxi + 1) / 2 : nxi * nxi;
   auto pidx = [&](int x2, int x3) {
     if (a.sym) {
@@ -388,7 +390,7 @@ hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int 
 hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s) {
   const int npsi = a.D * a.nsrc, nxi = 3 * a.D * a.nsrc;
   const int nyq = nxi * (nxi - 1) / 2 * nxi;
-  dim3 grid(unsigned((a.Bp + 255) / 256), unsigned(2 * npsi * nyq));
+  dim3 grid(unsigned(a.Bp), unsigned((2 * npsi * nyq + 255) / 256));
   (void)mixed;  // blocks are stored in double in both modes
   hipLaunchKernelGGL(blocks_finish_kernel<double2>, grid, dim3(256), 0, s, a, nxi, npsi);
   return hipGetLastError();

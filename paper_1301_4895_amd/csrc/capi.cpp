@@ -161,6 +161,9 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
     } else if (what == MB_TUNE_LANE_TILE) {
       if (value != 16 && value != 64) return fail(MB_EINVAL, "lane tile must be 16 or 64");
       S.tune_tile = value;
+    } else if (what == MB_TUNE_GROUP) {
+      if (value != 1 && value != 2 && value != 4) return fail(MB_EINVAL, "group must be 1, 2 or 4");
+      S.tune_group = value;
     } else if (what == MB_TUNE_UNROLL) {
       if (value < 0 || value > 2) return fail(MB_EINVAL, "unroll must be 0, 1 or 2");
       S.tune_unroll = value;
@@ -298,6 +301,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.lds_bytes = S.tune_lds;
       a.tile = S.tune_tile;
       a.unroll = S.tune_unroll;
+      a.group = S.tune_group;
       a.npsi = tl->npsi;
       psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");

@@ -483,6 +483,129 @@ hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s) {
   return mixed ? launch_stage_lds_t<float>(a, s) : launch_stage_lds_t<double>(a, s);
 }
 
+// ---------------------------------------------------------------------------
+// Recursion step for G consecutive output quark parts per wavefront (64
+// lanes).  Neighbouring outputs in the stage order often take the same block
+// entries at the same split position (the quark parts differ in one index of
+// the pair flavour, and every pair without it keeps its rank), so a
+// wavefront reads the split entries of its G outputs (scalar loads), loads
+// the block rows of the first output and of the first output whose row
+// differs, and every other distinct row only when it occurs; each output
+// still loads its own previous-stage operands.  Comparisons are on
+// wave-uniform values, so every branch is uniform.
+template <typename TS, int M, int K, int PG, int G>
+__global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
+  using CS = typename c2<TS>::type;
+  constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
+  const int64_t b = blockIdx.y * 64 + threadIdx.x;
+  const int64_t ngrp = (a.nq_out + G - 1) / G;
+  const int64_t n8 = (ngrp + 7) / 8 * 8;
+  const int pass0 = int(blockIdx.x / n8) * PG;
+  const int64_t r = blockIdx.x % n8;
+  const int64_t grp = (r % 8) * (n8 / 8) + r / 8;   // XCD-contiguous ranges of groups
+  if (grp >= ngrp) return;
+  const int64_t q0 = grp * G;
+  const int64_t Bp = a.Bp;
+  const int ns_in = NIN * a.npass, ns_out = NOUT * a.npass;
+  auto sig_in = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NIN + r; };
+  auto sig_out = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NOUT + r; };
+  const CS *Fin = static_cast<const CS *>(a.Fin);
+  const double2 *fb = static_cast<const double2 *>(a.fblk);
+  const uint2 *qs[G];
+#pragma unroll
+  for (int g = 0; g < G; g++) qs[g] = reinterpret_cast<const uint2 *>(a.qsplit) + min(q0 + g, a.nq_out - 1) * a.Sq;
+  uint32_t f_off[M];
+#pragma unroll
+  for (int d = 0; d < M; d++) f_off[d] = uint32_t(lane_off(b, a.npsi) + a.psi_of_pos[d] * 16);
+  const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
+  const int64_t out_lane = lane_off(b, ns_out);
+  const int64_t xstride = int64_t(ns_in) * Bp, ystride = int64_t(a.npsi) * Bp;
+
+  double2 acc[G][PG][NOUT];
+#pragma unroll
+  for (int g = 0; g < G; g++)
+#pragma unroll
+    for (int p = 0; p < PG; p++)
+#pragma unroll
+      for (int o = 0; o < NOUT; o++) acc[g][p][o] = make_double2(0.0, 0.0);
+
+  auto load_y = [&](uint32_t yi, double2 *y) {
+    const double2 *yrow = fb + int64_t(yi) * ystride;
+#pragma unroll
+    for (int d = 0; d < M; d++) y[d] = ld(yrow, f_off[d] * uint32_t(sizeof(double2)));
+  };
+  for (int t = 0; t < a.Sq; t++) {
+    uint2 e[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) e[g] = uniform(qs[g][t]);
+    const uint32_t ya = e[0].y & 0x7fffffffu;
+    uint32_t yb = ya;
+#pragma unroll
+    for (int g = G - 1; g >= 1; g--)
+      if ((e[g].y & 0x7fffffffu) != ya) yb = e[g].y & 0x7fffffffu;   // the first differing row
+    CS xin[G][PG][NIN];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+      const CS *xrow = Fin + int64_t(e[g].x) * xstride;
+#pragma unroll
+      for (int p = 0; p < PG; p++)
+#pragma unroll
+        for (int rr = 0; rr < NIN; rr++)
+          xin[g][p][rr] = ld(xrow, (in_lane + uint32_t(sig_in(rr, pass0 + p) * 16)) * uint32_t(sizeof(CS)));
+    }
+    double2 fya[M], fyb[M];
+    load_y(ya, fya);
+    if (yb != ya) load_y(yb, fyb);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+      const uint32_t yg = e[g].y & 0x7fffffffu;
+      const double sgn = (e[g].y >> 31) ? -1.0 : 1.0;
+      double2 fin[PG][NIN];
+#pragma unroll
+      for (int p = 0; p < PG; p++)
+#pragma unroll
+        for (int rr = 0; rr < NIN; rr++)
+          fin[p][rr] = make_double2(sgn * double(xin[g][p][rr].x), sgn * double(xin[g][p][rr].y));
+      if (yg == ya) {
+#pragma unroll
+        for (int p = 0; p < PG; p++) wedge_accumulate<M, K>(fin[p], fya, acc[g][p]);
+      } else if (yg == yb) {
+#pragma unroll
+        for (int p = 0; p < PG; p++) wedge_accumulate<M, K>(fin[p], fyb, acc[g][p]);
+      } else {
+        double2 fyc[M];
+        load_y(yg, fyc);
+#pragma unroll
+        for (int p = 0; p < PG; p++) wedge_accumulate<M, K>(fin[p], fyc, acc[g][p]);
+      }
+    }
+  }
+  CS *Fout = static_cast<CS *>(a.Fout);
+#pragma unroll
+  for (int g = 0; g < G; g++) {
+    if (q0 + g >= a.nq_out) break;
+#pragma unroll
+    for (int p = 0; p < PG; p++)
+#pragma unroll
+      for (int o = 0; o < NOUT; o++) {
+        CS v;
+        v.x = TS(acc[g][p][o].x);
+        v.y = TS(acc[g][p][o].y);
+        Fout[(q0 + g) * ns_out * Bp + out_lane + sig_out(o, pass0 + p) * 16] = v;
+      }
+  }
+}
+
+template <typename T, int M, int K, int PG, int G>
+static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
+  const int64_t ngrp = (a.nq_out + G - 1) / G;
+  const int64_t n8 = (ngrp + 7) / 8 * 8;
+  dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / 64));
+  hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G>), grid, dim3(64), a.lds_bytes, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int M, int K, int PG, int TILE, int U>
 static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
@@ -500,8 +623,14 @@ static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
   return u == 2 ? launch_stage_mkptu<T, M, K, PG, TILE, 2>(a, s) : launch_stage_mkptu<T, M, K, PG, TILE, 1>(a, s);
 }
 
+// outputs per wavefront (grouped kernel, 64 lanes, passthrough groups up to
+// 3), else lanes per wavefront
 template <typename T, int M, int K, int PG>
 static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
+  if constexpr (PG <= 3) {
+    if (a.group == 2) return launch_stage_group<T, M, K, PG, 2>(a, s);
+    if (a.group == 4) return launch_stage_group<T, M, K, PG, 4>(a, s);
+  }
   return a.tile == 16 ? launch_stage_mkpt<T, M, K, PG, 16>(a, s) : launch_stage_mkpt<T, M, K, PG, 64>(a, s);
 }
 

@@ -36,6 +36,7 @@ struct Stage {
   int tune_pg = 0, tune_lds = 0, tune_tile = 64;  // launch tuning (see mb_term_list_tune)
   int tune_kernel = 0;                            // 0 direct gather, 1 blocks staged in LDS
   int tune_unroll = 0;                            // splits in flight per wavefront (0 automatic)
+  int tune_group = 1;                             // outputs per wavefront (grouped kernel when > 1)
   int64_t nspin() const { return int64_t(nPsets) * nNsets; }
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };

@@ -70,6 +70,7 @@ struct StageArgs {
   int lds_bytes;             // LDS reserved per workgroup
   int tile;                  // lanes per wavefront: 64 or 16
   int unroll;                // splits in flight per wavefront: 1, 2 (0 = automatic)
+  int group;                 // outputs per wavefront of the grouped kernel: 1 (off), 2, 4
   int npsi;                  // baryon indices of the block layout
   int psi_of_pos[8];
 };

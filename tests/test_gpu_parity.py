@@ -205,12 +205,14 @@ def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V
     # float, which the per-lane block exponents keep out of the float stages
     assert np.all(np.isfinite(ref))
     nst = tl.counts()["n_stages"]
-    for kern, pg, tile, lds, unroll in [(0, 1, 16, 0, 1), (0, 2, 64, 16384, 0), (0, 3, 16, 0, 2), (0, 3, 64, 0, 1),
-                                        (0, 6, 64, 0, 2), (0, 6, 16, 0, 1), (0, 1, 64, 0, 2), (1, 1, 16, 0, 0),
-                                        (1, 2, 16, 0, 0), (1, 3, 16, 0, 0)]:
+    for kern, pg, tile, lds, unroll, group in [
+            (0, 1, 16, 0, 1, 1), (0, 2, 64, 16384, 0, 1), (0, 3, 16, 0, 2, 1), (0, 3, 64, 0, 1, 1),
+            (0, 6, 64, 0, 2, 1), (0, 6, 16, 0, 1, 1), (0, 1, 64, 0, 2, 1), (0, 1, 64, 0, 0, 2), (0, 2, 64, 0, 0, 4),
+            (0, 3, 64, 0, 0, 4), (1, 1, 16, 0, 0, 1), (1, 2, 16, 0, 0, 1), (1, 3, 16, 0, 0, 1)]:
         for s in range(1, nst):
             tl.tune(s, B.MB_TUNE_KERNEL, kern)
             tl.tune(s, B.MB_TUNE_UNROLL, unroll)
+            tl.tune(s, B.MB_TUNE_GROUP, group)
             try:
                 tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
             except B.MBError:
@@ -219,4 +221,4 @@ def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V
             tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
         _, got, _ = _run(tl, Su, Sd, w, k, precision)
         errs = [rel_err(got[b], ref[b]) for b in range(nl)]
-        assert max(errs) <= tol, (kern, pg, tile, lds, unroll, max(errs))
+        assert max(errs) <= tol, (kern, pg, tile, lds, unroll, group, max(errs))
