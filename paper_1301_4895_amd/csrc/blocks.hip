@@ -19,6 +19,14 @@
 
 namespace mb {
 
+template <typename TIN> __device__ inline TIN scaled(double2 v, double scale);
+template <> __device__ inline float2 scaled<float2>(double2 v, double scale) {
+  return make_float2(float(v.x * scale), float(v.y * scale));   // exact: scale is a power of two
+}
+template <> __device__ inline double2 scaled<double2>(double2 v, double scale) {
+  return make_double2(v.x * scale, v.y * scale);
+}
+
 template <typename TIN> __device__ inline double2 load_c(const void *p, int64_t i);
 template <> __device__ inline double2 load_c<float2>(const void *p, int64_t i) {
   float2 v = static_cast<const float2 *>(p)[i];
@@ -51,11 +59,13 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int TPW = (NTILE + 3) / 4;  // tiles per wave
   constexpr int D = NROW / 3;
 
-  __shared__ double2 su[NS][NROW][NXI];
-  __shared__ double2 s1[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
-  __shared__ double2 sd[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
-  __shared__ double Ar[KG][MP], Ai[KG][MP], As[KG][MP];   // As = Ar + Ai
-  __shared__ double Br[KG][NP], Bi[KG][NP], Bs[KG][NP];   // Bs = Br + Bi
+  // Propagators are staged in their input precision: a complex64 entry times
+  // 2^k is exact in float, and every product below is formed in double.
+  __shared__ TIN su[NS][NROW][NXI];
+  __shared__ TIN s1[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
+  __shared__ TIN sd[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
+  __shared__ double2 Ac[KG][MP];   // (re, im) of the A operand
+  __shared__ double2 Bc[KG][NP];   // (re, im) of the B operand
   __shared__ double2 wsh[NS][2];
   __shared__ unsigned char px2[NP], px3[NP];  // pair index -> (xi2, xi3)
 
@@ -124,9 +134,13 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
     b_r0[j] = (n * NROW + cc) * NXI + x3;
     b_sw[j] = (cc - bb) * NXI;
   }
-  const double2 *su_f = &su[0][0][0];
-  const double2 *sd_f = SYM ? su_f : &sd[0][0][0];
-  const double2 *s1_f = (SYM || same1) ? su_f : &s1[0][0][0];
+  const TIN *su_f = &su[0][0][0];
+  const TIN *sd_f = SYM ? su_f : &sd[0][0][0];
+  const TIN *s1_f = (SYM || same1) ? su_f : &s1[0][0][0];
+  auto rd = [](const TIN *p, int i) {   // a staged entry in double
+    const TIN v = p[i];
+    return make_double2(double(v.x), double(v.y));
+  };
 
   // The propagator entries of the next group of sites are loaded into
   // registers while the current group is built and multiplied.
@@ -162,10 +176,10 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
       const int i = tid + 256 * j;
       if (i < ns * NROW * NXI) {
         const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
-        su[n][r][xi] = make_double2(pu[j].x * scale, pu[j].y * scale);
+        su[n][r][xi] = scaled<TIN>(pu[j], scale);
         if constexpr (!SYM) {
-          sd[n][r][xi] = make_double2(pd[j].x * scale, pd[j].y * scale);
-          if (!same1) s1[n][r][xi] = make_double2(p1[j].x * scale, p1[j].y * scale);
+          sd[n][r][xi] = scaled<TIN>(pd[j], scale);
+          if (!same1) s1[n][r][xi] = scaled<TIN>(p1[j], scale);
         }
       }
     }
@@ -183,13 +197,11 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
         double re = 0.0, im = 0.0;
         if (a_src[j] >= 0 && a_n[j] < ns) {
           const double2 w = (&wsh[0][0])[a_w[j]];
-          const double2 v = s1_f[a_src[j]];
+          const double2 v = rd(s1_f, a_src[j]);
           re = w.x * v.x - w.y * v.y;
           im = w.x * v.y + w.y * v.x;
         }
-        (&Ar[0][0])[i] = re;
-        (&Ai[0][0])[i] = im;
-        (&As[0][0])[i] = re + im;
+        (&Ac[0][0])[i] = make_double2(re, im);
       }
     }
     // B operand: the diquark D_a[pair] = sum eps_abc (C g5)_{gd} S_u[(g,b)] S_d[(d,c)]
@@ -204,15 +216,13 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
           for (int g = 0; g < D; g++) {
             const double sg = (g & 1) ? 1.0 : -1.0;
             const int go = 3 * g * NXI, gd = 3 * (g ^ 1) * NXI;
-            const double2 l0 = su_f[b_l0[j] + go], r0 = sd_f[b_r0[j] + gd];
-            const double2 l1 = su_f[b_l0[j] + b_sw[j] + go], r1 = sd_f[b_r0[j] - b_sw[j] + gd];
+            const double2 l0 = rd(su_f, b_l0[j] + go), r0 = rd(sd_f, b_r0[j] + gd);
+            const double2 l1 = rd(su_f, b_l0[j] + b_sw[j] + go), r1 = rd(sd_f, b_r0[j] - b_sw[j] + gd);
             re += sg * ((l0.x * r0.x - l0.y * r0.y) - (l1.x * r1.x - l1.y * r1.y));
             im += sg * ((l0.x * r0.y + l0.y * r0.x) - (l1.x * r1.y + l1.y * r1.x));
           }
         }
-        (&Br[0][0])[i] = re;
-        (&Bi[0][0])[i] = im;
-        (&Bs[0][0])[i] = re + im;
+        (&Bc[0][0])[i] = make_double2(re, im);
       }
     }
     __syncthreads();
@@ -227,12 +237,13 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
         const int t = min(wave + 4 * j, NTILE - 1);
         const int mt = t / NT, nt = t % NT;
         const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
-        oa[j][0] = Ar[k][am];
-        oa[j][1] = Ai[k][am];
-        oa[j][2] = As[k][am];
-        ob[j][0] = Br[k][bn];
-        ob[j][1] = Bi[k][bn];
-        ob[j][2] = Bs[k][bn];
+        const double2 av = Ac[k][am], bv = Bc[k][bn];
+        oa[j][0] = av.x;
+        oa[j][1] = av.y;
+        oa[j][2] = av.x + av.y;
+        ob[j][0] = bv.x;
+        ob[j][1] = bv.y;
+        ob[j][2] = bv.x + bv.y;
       }
 #pragma unroll
       for (int j = 0; j < TPW; j++) {
