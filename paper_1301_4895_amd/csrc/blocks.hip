@@ -42,9 +42,9 @@ template <> __device__ inline double2 load_c<double2>(const void *p, int64_t i) 
 //   A[m][k] = w_{s'(psi)}(x) S_q1[(alpha(psi), a), xi1],  B[k][n] = D_a(x)[pair]
 // with v_mfma_f64_16x16x4f64 (double products and sums).  Operand layout:
 // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.  A complex product
-// is four real MFMAs: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br.  The 16x16
-// output tiles are spread over the four waves of the workgroup; operands of a
-// group of sites are built in LDS (k-major), the diquark on the vector units.
+// is three real MFMAs (below).  The 16x16 output tiles are spread over the
+// four waves of the workgroup; operands of a group of sites are built in LDS
+// (k-major, (re, im) interleaved), the diquark on the vector units.
 typedef double mb_d4 __attribute__((ext_vector_type(4)));
 
 template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
