@@ -93,6 +93,7 @@ def mix_groups(dev, types=None, n=MIX_N, seed=MIX_SEED):
     return groups, tls, probs
 VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFLOPS = 78.6  # FP64 matrix (dense)
 
 
 def log(*a):
@@ -250,6 +251,7 @@ def run_workload(name, args):
                     achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=traffic,
                     flops_per_launch=flops, launch_ms=round(res["kernel_avg_ms"][dom], 4))
+    roofline["blocks"] = blocks_roofline(cfg, counts, chunk, res["kernel_avg_ms"]["blocks"])
 
     return dict(name=name, cfg=cfg, lanes=lanes, V=V, counts=counts, chunk=chunk, results=results,
                 main=main_name, err=err, err_stats=err_stats, roofline=roofline, tuning=tuning, t_list=t_list)
@@ -311,6 +313,26 @@ def run_mix(args):
     return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=args.chunk,
                 results=results, main=main_name, err=err, err_stats=err_stats, roofline=None, tuning=tuning,
                 t_list=0.0)
+
+
+def blocks_roofline(cfg, counts, chunk, ms):
+    """The blocks call (site sums on FP64 MFMA, finish, lane exponents) against
+    its binding roof: dense contraction flops (rows psi x xi1, symmetric
+    diquark pairs, 3 colours, 8 flops per complex FMA) over the FP64 matrix
+    peak, or the propagator entries it must read over the HBM peak."""
+    V = cfg["L"] ** 3
+    npsi, nxi = counts["n_psi"], counts["n_xi"]
+    D = 4 if cfg["rel"] else 2
+    flops = chunk * V * 8.0 * 3 * npsi * nxi * nxi * (nxi + 1) / 2
+    nbytes = chunk * V * cfg["nsrc"] * (3 * D) ** 2 * (16 if cfg["c128"] else 8)
+    t_mfma, t_hbm = flops / (MFMA_F64_PEAK_TFLOPS * 1e12), nbytes / (HBM_PEAK_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        achieved = flops / (ms / 1e3) / 1e12
+        return dict(bound="mfma", achieved=round(achieved, 3), peak=MFMA_F64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / MFMA_F64_PEAK_TFLOPS, 4), launch_ms=round(ms, 4))
+    achieved = nbytes / (ms / 1e3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), launch_ms=round(ms, 4))
 
 
 def summary(w):
