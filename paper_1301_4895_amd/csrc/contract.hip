@@ -79,6 +79,32 @@ __device__ __forceinline__ void wedge_accumulate(const double2 *fin, const doubl
   }
 }
 
+// The same wedge ordered by input element: each previous component is
+// widened to double (and, when SX, multiplied by the split sign sx) just
+// before its M - K products, so that one widened value is live at a time.
+template <int M, int K, bool SX, typename CS>
+__device__ __forceinline__ void wedge_accumulate_x(const CS *xin, const double2 *fy, double sx, double2 *acc) {
+#pragma unroll
+  for (int in = 0; in < (1 << M); in++) {
+    if (popc(in) != K) continue;
+    const int ri = rank_c(in);
+    double2 x = make_double2(double(xin[ri].x), double(xin[ri].y));
+    if constexpr (SX) x = make_double2(sx * x.x, sx * x.y);
+#pragma unroll
+    for (int d = 0; d < M; d++) {
+      if ((in >> d) & 1) continue;
+      const int ro = rank_c(in | (1 << d));
+      const bool neg = bool(popc(in >> (d + 1)) & 1);
+      const double2 y = fy[d];
+      const double s = neg ? -1.0 : 1.0;   // folds into the operand's sign
+      acc[ro].x = fma(s * x.x, y.x, acc[ro].x);
+      acc[ro].x = fma(-s * x.y, y.y, acc[ro].x);
+      acc[ro].y = fma(s * x.x, y.y, acc[ro].y);
+      acc[ro].y = fma(s * x.y, y.x, acc[ro].y);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void stage0_kernel(Stage0Args a) {
@@ -110,20 +136,8 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// TS: storage type of F (float for MB_MIXED, double for MB_FP64); blocks are
-// stored in double.  Products and sums run in double in both cases: on CDNA4
-// double FMA issues at the rate of single FMA, so only the bandwidth-bound
-// storage is narrowed.  PG passthrough parts share each thread so that the
-// block entries of a split are loaded once for all of them.
-//
-// A wavefront owns TILE lanes (64 or 16) of one output quark part.  With
-// TILE = 16 its four quarter-waves take every fourth quark split and their
-// partial sums are added with two cross-lane exchanges at the end; every
-// operand load is then a 16-lane row segment (one 128-byte line of a float
-// stage), which keeps four times more previous-stage rows in L2.  Which tile
-// is faster depends on the step; the autotuner decides.
-template <typename TS, int M, int K, int PG, int TILE, int U>
-__global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
+template <typename TS, int M, int K, int PG, int TILE, int U, bool AP>
+__device__ __forceinline__ void stage_body(const StageArgs &a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   constexpr int SUB = 64 / TILE;   // sub-waves splitting the quark splits
@@ -140,125 +154,160 @@ __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   const int64_t Bp = a.Bp;
   const int ns_in = NIN * a.npass, ns_out = NOUT * a.npass;
   // spin index of active rank r with passthrough rank p
-  auto sig_in = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NIN + r; };
-  auto sig_out = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NOUT + r; };
+  auto sig_out = [&](int r, int p) { return AP ? r * a.npass + p : p * NOUT + r; };
 
-  const CS *Fin = static_cast<const CS *>(a.Fin);
-  const double2 *fb = static_cast<const double2 *>(a.fblk);
+  const char *Fin = static_cast<const char *>(a.Fin);
+  const char *fb = static_cast<const char *>(a.fblk);
   const uint2 *qs = reinterpret_cast<const uint2 *>(a.qsplit) + q * a.Sq;
 
-  // per-lane offsets (32 bits: a lane tile holds at most 65536 lanes x 216
-  // spin parts); the row bases of a split are wave-uniform when SUB == 1
-  uint32_t f_off[M];
+  // Byte offsets inside the rows of a split.  A spin row of a lane tile is
+  // 16 values; previous component (r, g) of a thread sits at
+  // roff[r] + g * GSTEP + lane offset, block entry d at yoff[d] + lane offset.
+  // roff and yoff are the same for every lane; GSTEP is a constant, so the
+  // passthrough parts of one r are loaded at immediate offsets.
+  constexpr uint32_t ROW = 16 * sizeof(CS);
+  constexpr uint32_t GSTEP = AP ? ROW : NIN * ROW;
+  uint32_t roff[NIN], yoff[M];
 #pragma unroll
-  for (int d = 0; d < M; d++) f_off[d] = uint32_t(lane_off(b, a.npsi) + a.psi_of_pos[d] * 16);
-  const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
+  for (int rr = 0; rr < NIN; rr++) roff[rr] = AP ? uint32_t(rr * a.npass + pass0) * ROW : uint32_t(pass0 * NIN + rr) * ROW;
+#pragma unroll
+  for (int d = 0; d < M; d++) yoff[d] = uint32_t(a.psi_of_pos[d]) * 16 * uint32_t(sizeof(double2));
+  const uint32_t x_lane = uint32_t(lane_off(b, ns_in)) * uint32_t(sizeof(CS));
+  const uint32_t y_lane = uint32_t(lane_off(b, a.npsi)) * uint32_t(sizeof(double2));
   const int64_t out_lane = lane_off(b, ns_out);
-  const int64_t xstride = int64_t(ns_in) * Bp, ystride = int64_t(a.npsi) * Bp;
+  const int64_t xstride = int64_t(ns_in) * Bp * int64_t(sizeof(CS));
+  const int64_t ystride = int64_t(a.npsi) * Bp * int64_t(sizeof(double2));
 
   double2 acc[PG][NOUT];
 #pragma unroll
   for (int g = 0; g < PG; g++)
 #pragma unroll
-    for (int r = 0; r < NOUT; r++) acc[g][r] = make_double2(0.0, 0.0);
-  // U splits per round (1 or 2): the table entries and every operand load of
-  // the U splits are issued before the first product, so that a wavefront
-  // keeps U splits of loads in flight.  The split table is read with wave-uniform
-  // (scalar) loads; with sub-waves every sub-wave then selects its own
-  // entry.  Past the end of the list a sub-wave loads the last split again
-  // (in bounds) and drops it.
+    for (int o = 0; o < NOUT; o++) acc[g][o] = make_double2(0.0, 0.0);
+
+  // Split-table entry of sub-wave `quarter` at position s (past the end of
+  // the list: the last split, loaded in bounds and dropped below).  One
+  // sub-wave: wave-uniform, read with scalar loads.  Several: every lane
+  // loads its sub-wave's entry, one round ahead of its use.
+  auto entry = [&](int s) -> uint2 {
+    if constexpr (SUB > 1) return qs[min(s + quarter, a.Sq - 1)];
+    else return uniform(qs[min(s, a.Sq - 1)]);
+  };
+  uint2 e[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) e[u] = entry(u * SUB);
+
+  // U splits per round (1 or 2): every operand load of the U splits is
+  // issued before the first product, so that a wavefront keeps U splits of
+  // loads in flight.
   constexpr bool SIGN_ON_X = NIN * PG < M;
   for (int s0 = 0; s0 < a.Sq; s0 += SUB * U) {
-    uint2 e[U];
-    bool valid[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const int base = s0 + u * SUB;
-      if constexpr (SUB > 1) {
-        uint2 ee[SUB];
-#pragma unroll
-        for (int j = 0; j < SUB; j++) ee[j] = uniform(qs[min(base + j, a.Sq - 1)]);
-        e[u] = ee[0];
-#pragma unroll
-        for (int j = 1; j < SUB; j++)
-          if (quarter == j) e[u] = ee[j];
-      } else {
-        e[u] = uniform(qs[min(base, a.Sq - 1)]);
-      }
-      valid[u] = base + quarter < a.Sq;
-    }
     double2 fy[U][M];
     CS xin[U][PG][NIN];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      // row bases (wave-uniform when SUB == 1) plus 32-bit per-lane byte
-      // offsets, so that the loads take the scalar-base addressing form
-      const CS *xrow = Fin + int64_t(e[u].x) * xstride;
-      const double2 *yrow = fb + int64_t(e[u].y & 0x7fffffffu) * ystride;
+      const char *xrow = Fin + int64_t(e[u].x) * xstride;
+      const char *yrow = fb + int64_t(e[u].y & 0x7fffffffu) * ystride;
+      if constexpr (SUB == 1) {
+        // wave-uniform row bases: scalar base plus a 32-bit lane offset
 #pragma unroll
-      for (int d = 0; d < M; d++) fy[u][d] = ld(yrow, f_off[d] * uint32_t(sizeof(double2)));
+        for (int d = 0; d < M; d++) fy[u][d] = ld(reinterpret_cast<const double2 *>(yrow + yoff[d]), y_lane);
 #pragma unroll
-      for (int g = 0; g < PG; g++)
+        for (int rr = 0; rr < NIN; rr++)
 #pragma unroll
-        for (int r = 0; r < NIN; r++)
-          xin[u][g][r] = ld(xrow, (in_lane + uint32_t(sig_in(r, pass0 + g) * 16)) * uint32_t(sizeof(CS)));
+          for (int g = 0; g < PG; g++)
+            xin[u][g][rr] = ld(reinterpret_cast<const CS *>(xrow + roff[rr]), x_lane + g * GSTEP);
+      } else {
+        // per-lane row bases: one 64-bit pointer per r (and per d), the
+        // passthrough parts at immediate offsets from it
+        const char *xl = xrow + x_lane, *yl = yrow + y_lane;
+#pragma unroll
+        for (int d = 0; d < M; d++) fy[u][d] = *reinterpret_cast<const double2 *>(yl + yoff[d]);
+#pragma unroll
+        for (int rr = 0; rr < NIN; rr++) {
+          const char *p = xl + roff[rr];
+#pragma unroll
+          for (int g = 0; g < PG; g++) xin[u][g][rr] = *reinterpret_cast<const CS *>(p + g * GSTEP);
+        }
+      }
+    }
+    bool valid[U];
+    double sgn[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      valid[u] = s0 + u * SUB + quarter < a.Sq;
+      sgn[u] = valid[u] ? ((e[u].y >> 31) ? -1.0 : 1.0) : 0.0;
+    }
+    if constexpr (SUB > 1) {
+#pragma unroll
+      for (int u = 0; u < U; u++) e[u] = entry(s0 + SUB * U + u * SUB);
     }
     // keep the instruction scheduler from sinking loads below products
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      double2 fin[PG][NIN];
-#pragma unroll
-      for (int g = 0; g < PG; g++)
-#pragma unroll
-        for (int r = 0; r < NIN; r++) fin[g][r] = make_double2(double(xin[u][g][r].x), double(xin[u][g][r].y));
       // the split sign multiplies the smaller operand set; a dropped split
-      // adds zeros (its operands are finite values of the last split), which
-      // keeps the loads above free of branches
-      const double sgn = valid[u] ? ((e[u].y >> 31) ? -1.0 : 1.0) : 0.0;
+      // adds zeros (its operands are finite values of the last split)
       if constexpr (SIGN_ON_X) {
 #pragma unroll
-        for (int g = 0; g < PG; g++)
-#pragma unroll
-          for (int r = 0; r < NIN; r++) fin[g][r] = make_double2(sgn * fin[g][r].x, sgn * fin[g][r].y);
-#pragma unroll
-        for (int g = 0; g < PG; g++) wedge_accumulate<M, K>(fin[g], fy[u], acc[g]);
+        for (int g = 0; g < PG; g++) wedge_accumulate_x<M, K, true>(xin[u][g], fy[u], sgn[u], acc[g]);
       } else {
-        double2 y[M];
 #pragma unroll
-        for (int d = 0; d < M; d++) y[d] = make_double2(sgn * fy[u][d].x, sgn * fy[u][d].y);
+        for (int d = 0; d < M; d++) fy[u][d] = make_double2(sgn[u] * fy[u][d].x, sgn[u] * fy[u][d].y);
 #pragma unroll
-        for (int g = 0; g < PG; g++) wedge_accumulate<M, K>(fin[g], y, acc[g]);
+        for (int g = 0; g < PG; g++) wedge_accumulate_x<M, K, false>(xin[u][g], fy[u], 1.0, acc[g]);
       }
+    }
+    if constexpr (SUB == 1) {
+#pragma unroll
+      for (int u = 0; u < U; u++) e[u] = entry(s0 + U + u);
     }
   }
   // sum the sub-waves (every lane ends with the total), then let sub-wave j
-  // write the outputs r = j, j+SUB, ...
+  // write the outputs o = j, j+SUB, ...
   if constexpr (SUB > 1) {
 #pragma unroll
     for (int g = 0; g < PG; g++)
 #pragma unroll
-      for (int r = 0; r < NOUT; r++) {
-        double x = acc[g][r].x, y = acc[g][r].y;
+      for (int o = 0; o < NOUT; o++) {
+        double x = acc[g][o].x, y = acc[g][o].y;
 #pragma unroll
         for (int w = TILE; w < 64; w *= 2) {
           x += __shfl_xor(x, w);
           y += __shfl_xor(y, w);
         }
-        acc[g][r] = make_double2(x, y);
+        acc[g][o] = make_double2(x, y);
       }
   }
   CS *Fout = static_cast<CS *>(a.Fout);
 #pragma unroll
   for (int g = 0; g < PG; g++)
 #pragma unroll
-    for (int r = 0; r < NOUT; r++) {
-      if (r % SUB != quarter) continue;
-      CS o;
-      o.x = TS(acc[g][r].x);
-      o.y = TS(acc[g][r].y);
-      Fout[q * ns_out * Bp + out_lane + sig_out(r, pass0 + g) * 16] = o;
+    for (int o = 0; o < NOUT; o++) {
+      if (o % SUB != quarter) continue;
+      CS v;
+      v.x = TS(acc[g][o].x);
+      v.y = TS(acc[g][o].y);
+      Fout[q * ns_out * Bp + out_lane + sig_out(o, pass0 + g) * 16] = v;
     }
+}
+
+// TS: storage type of F (float for MB_MIXED, double for MB_FP64); blocks are
+// stored in double.  Products and sums run in double in both cases: on CDNA4
+// double FMA issues at the rate of single FMA, so only the bandwidth-bound
+// storage is narrowed.  PG passthrough parts share each thread so that the
+// block entries of a split are loaded once for all of them.
+//
+// A wavefront owns TILE lanes (64 or 16) of one output quark part.  With
+// TILE = 16 its four quarter-waves take every fourth quark split and their
+// partial sums are added with two cross-lane exchanges at the end; every
+// operand load is then a 16-lane row segment (one 128-byte line of a float
+// stage), which keeps four times more previous-stage rows in L2.  Which tile
+// is faster depends on the step; the autotuner decides.  The spin layout of
+// the step (added species proton or neutron) selects one of two bodies.
+template <typename TS, int M, int K, int PG, int TILE, int U>
+__global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
+  if (a.act_is_P) stage_body<TS, M, K, PG, TILE, U, true>(a);
+  else stage_body<TS, M, K, PG, TILE, U, false>(a);
 }
 
 // ---------------------------------------------------------------------------
