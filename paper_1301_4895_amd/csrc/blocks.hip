@@ -19,22 +19,12 @@
 
 namespace mb {
 
-template <typename TIN> __device__ inline TIN scaled(double2 v, double scale);
-template <> __device__ inline float2 scaled<float2>(double2 v, double scale) {
-  return make_float2(float(v.x * scale), float(v.y * scale));   // exact: scale is a power of two
+// A propagator entry times scale (a power of two, so exact), in its input
+// precision.
+__device__ inline float2 scaled(float2 v, double scale) {
+  return make_float2(float(double(v.x) * scale), float(double(v.y) * scale));
 }
-template <> __device__ inline double2 scaled<double2>(double2 v, double scale) {
-  return make_double2(v.x * scale, v.y * scale);
-}
-
-template <typename TIN> __device__ inline double2 load_c(const void *p, int64_t i);
-template <> __device__ inline double2 load_c<float2>(const void *p, int64_t i) {
-  float2 v = static_cast<const float2 *>(p)[i];
-  return make_double2(v.x, v.y);
-}
-template <> __device__ inline double2 load_c<double2>(const void *p, int64_t i) {
-  return static_cast<const double2 *>(p)[i];
-}
+__device__ inline double2 scaled(double2 v, double scale) { return make_double2(v.x * scale, v.y * scale); }
 
 // ---------------------------------------------------------------------------
 // The site sums as one complex GEMM per lane on the matrix cores:
@@ -42,13 +32,19 @@ template <> __device__ inline double2 load_c<double2>(const void *p, int64_t i) 
 //   A[m][k] = w_{s'(psi)}(x) S_q1[(alpha(psi), a), xi1],  B[k][n] = D_a(x)[pair]
 // with v_mfma_f64_16x16x4f64 (double products and sums).  Operand layout:
 // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.  A complex product
-// is three real MFMAs (below).  The 16x16 output tiles are spread over the
-// four waves of the workgroup; operands of a group of sites are built in LDS
-// (k-major, (re, im) interleaved), the diquark on the vector units.
+// is three real MFMAs (below).
+//
+// The workgroup's eight waves take two roles.  Waves 4-7 (builders) stage
+// the propagators of a group of sites in LDS and build the operands of that
+// group there (the diquark on the vector units); waves 0-3 multiply the
+// previous group on the matrix cores, each owning a quarter of the 16x16
+// output tiles.  Operands and staged propagators are double-buffered, so one
+// barrier per group separates the roles, and every SIMD holds one wave of
+// each: its vector and matrix units work at the same time.
 typedef double mb_d4 __attribute__((ext_vector_type(4)));
 
 template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
-__global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
+__global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int NPAIR = SYM ? NXI * (NXI + 1) / 2 : NXI * NXI;
   constexpr int M = NPSI * NXI;
   constexpr int MT = (M + 15) / 16, NT = (NPAIR + 15) / 16;
@@ -56,21 +52,24 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int NS = 4;                // sites per group
   constexpr int KG = 3 * NS;           // k = 3 * site + colour, multiple of 4
   constexpr int NTILE = MT * NT;
-  constexpr int TPW = (NTILE + 3) / 4;  // tiles per wave
+  constexpr int TPW = (NTILE + 3) / 4;  // tiles per multiplying wave
   constexpr int D = NROW / 3;
+  constexpr int NB = SYM ? 1 : 2;      // buffers of the q1 and d slots
 
   // Propagators are staged in their input precision: a complex64 entry times
   // 2^k is exact in float, and every product below is formed in double.
-  __shared__ TIN su[NS][NROW][NXI];
-  __shared__ TIN s1[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
-  __shared__ TIN sd[SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
-  __shared__ double2 Ac[KG][MP];   // (re, im) of the A operand
-  __shared__ double2 Bc[KG][NP];   // (re, im) of the B operand
-  __shared__ double2 wsh[NS][2];
+  __shared__ TIN su[2][NS][NROW][NXI];
+  __shared__ TIN s1[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
+  __shared__ TIN sd[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
+  __shared__ double2 Ac[2][KG][MP];   // (re, im) of the A operand
+  __shared__ double2 Bc[2][KG][NP];   // (re, im) of the B operand
+  __shared__ double2 wsh[2][NS][2];
   __shared__ unsigned char px2[NP], px3[NP];  // pair index -> (xi2, xi3)
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int p = tid; p < NP; p += 256) {
+  const bool builder = wave >= 4;
+  const int bt = tid & 255;            // thread index within its role
+  for (int p = tid; p < NP; p += 512) {
     int x2 = 0, x3 = 0;
     if (p < NPAIR) {
       if (SYM) {
@@ -90,25 +89,17 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
   const int nsrc = a.nsrc;
   const int64_t x0 = int64_t(chunk) * a.sites_per_chunk;
   const int64_t x1 = min(a.V, x0 + a.sites_per_chunk);
+  const int ngroups = x1 > x0 ? int((x1 - x0 + NS - 1) / NS) : 0;
   const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[ln]) : 1.0;
   const bool same1 = a.prop_q1 == a.prop_u;
+  auto group_sites = [&](int g) { return int(min<int64_t>(NS, x1 - (x0 + int64_t(g) * NS))); };
 
-  // Gauss's three-product form of the complex product: m1 = Ar Br,
-  // m2 = Ai Bi, m3 = (Ar + Ai)(Br + Bi); re = m1 - m2, im = m3 - m1 - m2.
-  mb_d4 m1[TPW], m2[TPW], m3[TPW];
-#pragma unroll
-  for (int j = 0; j < TPW; j++) {
-    m1[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
-    m2[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
-    m3[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
-  }
-  // The entries of the A and B operands a thread builds are the same for
-  // every group of sites: resolve their LDS sources once.
+  // ---- builders: operand sources, resolved once ----
   constexpr int AJ = (KG * MP + 255) / 256, BJ = (KG * NP + 255) / 256;
   int a_src[AJ], a_w[AJ], a_n[AJ];   // LDS index of S_q1 (-1: zero entry), sink weight, site
 #pragma unroll
   for (int j = 0; j < AJ; j++) {
-    const int i = tid + 256 * j;
+    const int i = bt + 256 * j;
     const int k = i / MP, m = i % MP, n = k / 3, ac = k % 3;
     a_src[j] = -1;
     a_w[j] = 0;
@@ -125,7 +116,7 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
   int b_l0[BJ], b_r0[BJ], b_sw[BJ], b_n[BJ];   // b_sw: row offset from (b, c) to (c, b)
 #pragma unroll
   for (int j = 0; j < BJ; j++) {
-    const int i = tid + 256 * j;
+    const int i = bt + 256 * j;
     const int k = i / NP, pp = i % NP, n = k / 3, ac = k % 3;
     b_n[j] = (i < KG * NP && pp < NPAIR) ? n : NS;   // NS: zero entry
     const int x2 = pp < NPAIR ? px2[pp] : 0, x3 = pp < NPAIR ? px3[pp] : 0;
@@ -134,122 +125,163 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
     b_r0[j] = (n * NROW + cc) * NXI + x3;
     b_sw[j] = (cc - bb) * NXI;
   }
-  const TIN *su_f = &su[0][0][0];
-  const TIN *sd_f = SYM ? su_f : &sd[0][0][0];
-  const TIN *s1_f = (SYM || same1) ? su_f : &s1[0][0][0];
   auto rd = [](const TIN *p, int i) {   // a staged entry in double
     const TIN v = p[i];
     return make_double2(double(v.x), double(v.y));
   };
 
-  // The propagator entries of the next group of sites are loaded into
-  // registers while the current group is built and multiplied.
+  // The propagator entries of the group after next are loaded into
+  // registers while a group is built.
   constexpr int PFJ = (NS * NROW * NXI + 255) / 256;
-  double2 pu[PFJ], pd[PFJ], p1[PFJ], pw = make_double2(1.0, 0.0);
-  auto fetch = [&](int64_t xg) {
-    const int ns = int(min<int64_t>(NS, x1 - xg));
+  TIN pu[PFJ], pd[PFJ], p1[PFJ];
+  double2 pw = make_double2(1.0, 0.0);
+  auto fetch = [&](int g) {
+    const int64_t xg = x0 + int64_t(g) * NS;
+    const int ns = group_sites(g);
 #pragma unroll
     for (int j = 0; j < PFJ; j++) {
-      const int i = tid + 256 * j;
+      const int i = bt + 256 * j;
       if (i < ns * NROW * NXI) {
         const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
         const int s = xi % nsrc, kap = xi / nsrc;
         const int64_t off = (((ln * a.V + xg + n) * nsrc + s) * 12 + r) * 12 + kap;
-        pu[j] = load_c<TIN>(a.prop_u, off);
+        pu[j] = static_cast<const TIN *>(a.prop_u)[off];
         if constexpr (!SYM) {
-          pd[j] = load_c<TIN>(a.prop_d, off);
-          if (!same1) p1[j] = load_c<TIN>(a.prop_q1, off);
+          pd[j] = static_cast<const TIN *>(a.prop_d)[off];
+          if (!same1) p1[j] = static_cast<const TIN *>(a.prop_q1)[off];
         }
       }
     }
-    if (tid < ns * nsrc && a.sink_w) {
-      const int n = tid / nsrc, s = tid % nsrc;
+    if (bt < ns * nsrc && a.sink_w) {
+      const int n = bt / nsrc, s = bt % nsrc;
       pw = reinterpret_cast<const double2 *>(a.sink_w)[int64_t(s) * a.V + xg + n];
     }
   };
-  if (x0 < x1) fetch(x0);
-
-  for (int64_t xg = x0; xg < x1; xg += NS) {
-    const int ns = int(min<int64_t>(NS, x1 - xg));
+  auto stage = [&](int g) {
+    const int buf = g & 1, ns = group_sites(g);
 #pragma unroll
     for (int j = 0; j < PFJ; j++) {
-      const int i = tid + 256 * j;
+      const int i = bt + 256 * j;
       if (i < ns * NROW * NXI) {
         const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
-        su[n][r][xi] = scaled<TIN>(pu[j], scale);
+        su[buf][n][r][xi] = scaled(pu[j], scale);
         if constexpr (!SYM) {
-          sd[n][r][xi] = scaled<TIN>(pd[j], scale);
-          if (!same1) s1[n][r][xi] = scaled<TIN>(p1[j], scale);
+          sd[buf][n][r][xi] = scaled(pd[j], scale);
+          if (!same1) s1[buf][n][r][xi] = scaled(p1[j], scale);
         }
       }
     }
-    if (tid < ns * nsrc) {
-      const int n = tid / nsrc, s = tid % nsrc;
-      wsh[n][s] = pw;
+    if (bt < ns * nsrc) {
+      const int n = bt / nsrc, s = bt % nsrc;
+      wsh[buf][n][s] = pw;
     }
-    __syncthreads();
-    if (xg + NS < x1) fetch(xg + NS);   // in flight during the work below
+  };
+  auto build = [&](int g) {
+    const int buf = g & 1, ns = group_sites(g);
+    const TIN *su_f = &su[buf][0][0][0];
+    const TIN *sd_f = SYM ? su_f : &sd[SYM ? 0 : buf][0][0][0];
+    const TIN *s1_f = (SYM || same1) ? su_f : &s1[SYM ? 0 : buf][0][0][0];
     // A operand: w S_q1[(alpha, a), xi1]
 #pragma unroll
     for (int j = 0; j < AJ; j++) {
-      const int i = tid + 256 * j;
+      const int i = bt + 256 * j;
       if (i < KG * MP) {
         double re = 0.0, im = 0.0;
         if (a_src[j] >= 0 && a_n[j] < ns) {
-          const double2 w = (&wsh[0][0])[a_w[j]];
+          const double2 w = (&wsh[buf][0][0])[a_w[j]];
           const double2 v = rd(s1_f, a_src[j]);
           re = w.x * v.x - w.y * v.y;
           im = w.x * v.y + w.y * v.x;
         }
-        (&Ac[0][0])[i] = make_double2(re, im);
+        (&Ac[buf][0][0])[i] = make_double2(re, im);
       }
     }
     // B operand: the diquark D_a[pair] = sum eps_abc (C g5)_{gd} S_u[(g,b)] S_d[(d,c)]
     // ((C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1)
 #pragma unroll
     for (int j = 0; j < BJ; j++) {
-      const int i = tid + 256 * j;
+      const int i = bt + 256 * j;
       if (i < KG * NP) {
         double re = 0.0, im = 0.0;
         if (b_n[j] < ns) {
 #pragma unroll
-          for (int g = 0; g < D; g++) {
-            const double sg = (g & 1) ? 1.0 : -1.0;
-            const int go = 3 * g * NXI, gd = 3 * (g ^ 1) * NXI;
+          for (int gs = 0; gs < D; gs++) {
+            const double sg = (gs & 1) ? 1.0 : -1.0;
+            const int go = 3 * gs * NXI, gd = 3 * (gs ^ 1) * NXI;
             const double2 l0 = rd(su_f, b_l0[j] + go), r0 = rd(sd_f, b_r0[j] + gd);
             const double2 l1 = rd(su_f, b_l0[j] + b_sw[j] + go), r1 = rd(sd_f, b_r0[j] - b_sw[j] + gd);
             re += sg * ((l0.x * r0.x - l0.y * r0.y) - (l1.x * r1.x - l1.y * r1.y));
             im += sg * ((l0.x * r0.y + l0.y * r0.x) - (l1.x * r1.y + l1.y * r1.x));
           }
         }
-        (&Bc[0][0])[i] = make_double2(re, im);
+        (&Bc[buf][0][0])[i] = make_double2(re, im);
       }
     }
+  };
+
+  // Pipeline: in round r the builders build group r (staged in round r - 1)
+  // and stage group r + 1 (loaded in round r - 1), then load group r + 2;
+  // the multipliers multiply group r - 1.  The two roles run separate loops
+  // (the role is the same for the whole wave) with one barrier per round
+  // each, so that their registers are not live at the same time.
+  if (builder) {
+    if (ngroups > 0) {
+      fetch(0);
+      stage(0);
+      if (ngroups > 1) fetch(1);
+    }
     __syncthreads();
-#pragma unroll 1
-    for (int ks = 0; ks < KG / 4; ks++) {
-      const int k = 4 * ks + (lane >> 4);
-      // every operand of the k-step first, then the products; a wave with
-      // fewer tiles repeats its last tile into an accumulator never stored
-      double oa[TPW][3], ob[TPW][3];
-#pragma unroll
-      for (int j = 0; j < TPW; j++) {
-        const int t = min(wave + 4 * j, NTILE - 1);
-        const int mt = t / NT, nt = t % NT;
-        const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
-        const double2 av = Ac[k][am], bv = Bc[k][bn];
-        oa[j][0] = av.x;
-        oa[j][1] = av.y;
-        oa[j][2] = av.x + av.y;
-        ob[j][0] = bv.x;
-        ob[j][1] = bv.y;
-        ob[j][2] = bv.x + bv.y;
+    for (int r = 0; r <= ngroups; r++) {
+      if (r < ngroups) {
+        build(r);
+        if (r + 1 < ngroups) {
+          stage(r + 1);
+          if (r + 2 < ngroups) fetch(r + 2);
+        }
       }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // ---- multipliers: Gauss's three-product form of the complex product:
+  // m1 = Ar Br, m2 = Ai Bi, m3 = (Ar + Ai)(Br + Bi); re = m1 - m2,
+  // im = m3 - m1 - m2.  A wave with fewer tiles repeats its last tile into
+  // an accumulator never stored.
+  mb_d4 m1[TPW], m2[TPW], m3[TPW];
 #pragma unroll
-      for (int j = 0; j < TPW; j++) {
-        m1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][0], ob[j][0], m1[j], 0, 0, 0);
-        m2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][1], ob[j][1], m2[j], 0, 0, 0);
-        m3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][2], ob[j][2], m3[j], 0, 0, 0);
+  for (int j = 0; j < TPW; j++) {
+    m1[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    m2[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+    m3[j] = mb_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int r = 0; r <= ngroups; r++) {
+    if (r >= 1) {
+      const int buf = (r - 1) & 1;
+#pragma unroll
+      for (int ks = 0; ks < KG / 4; ks++) {
+        const int k = 4 * ks + (lane >> 4);
+        double oa[TPW][3], ob[TPW][3];
+#pragma unroll
+        for (int j = 0; j < TPW; j++) {
+          const int t = min(wave + 4 * j, NTILE - 1);
+          const int mt = t / NT, nt = t % NT;
+          const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
+          const double2 av = Ac[buf][k][am], bv = Bc[buf][k][bn];
+          oa[j][0] = av.x;
+          oa[j][1] = av.y;
+          oa[j][2] = av.x + av.y;
+          ob[j][0] = bv.x;
+          ob[j][1] = bv.y;
+          ob[j][2] = bv.x + bv.y;
+        }
+#pragma unroll
+        for (int j = 0; j < TPW; j++) {
+          m1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][0], ob[j][0], m1[j], 0, 0, 0);
+          m2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][1], ob[j][1], m2[j], 0, 0, 0);
+          m3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(oa[j][2], ob[j][2], m3[j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -262,11 +294,11 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
       const int mt = t / NT, nt = t % NT;
       const int n = nt * 16 + (lane & 15);
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
+      for (int rr = 0; rr < 4; rr++) {
         // v_mfma_f64_16x16x4f64 output: D[i][j] in lane j + 16 (i % 4), register i / 4
-        const int m = mt * 16 + (lane >> 4) + 4 * r;
+        const int m = mt * 16 + (lane >> 4) + 4 * rr;
         if (m < M && n < NPAIR)
-          out[int64_t(m) * NPAIR + n] = make_double2(m1[j][r] - m2[j][r], m3[j][r] - m1[j][r] - m2[j][r]);
+          out[int64_t(m) * NPAIR + n] = make_double2(m1[j][rr] - m2[j][rr], m3[j][rr] - m1[j][rr] - m2[j][rr]);
       }
     }
   }
@@ -275,7 +307,7 @@ __global__ __launch_bounds__(256, 2) void blocks_mfma_kernel(BlocksArgs a) {
 template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
 static hipError_t launch_bm(const BlocksArgs &a, hipStream_t s) {
   dim3 grid(a.nchunk, unsigned(a.B));
-  hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM>), grid, dim3(512), 0, s, a);
   return hipGetLastError();
 }
 
