@@ -19,11 +19,8 @@
 
 namespace mb {
 
-// A propagator entry times scale (a power of two, so exact), in its input
-// precision.
-__device__ inline float2 scaled(float2 v, double scale) {
-  return make_float2(float(double(v.x) * scale), float(double(v.y) * scale));
-}
+// A propagator entry times scale (a power of two, so exact), in double.
+__device__ inline double2 scaled(float2 v, double scale) { return make_double2(double(v.x) * scale, double(v.y) * scale); }
 __device__ inline double2 scaled(double2 v, double scale) { return make_double2(v.x * scale, v.y * scale); }
 
 // ---------------------------------------------------------------------------
@@ -56,11 +53,12 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int D = NROW / 3;
   constexpr int NB = SYM ? 1 : 2;      // buffers of the q1 and d slots
 
-  // Propagators are staged in their input precision: a complex64 entry times
-  // 2^k is exact in float, and every product below is formed in double.
-  __shared__ TIN su[2][NS][NROW][NXI];
-  __shared__ TIN s1[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
-  __shared__ TIN sd[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
+  // Propagators are staged in double: the vector and matrix units share the
+  // double-precision pipeline, so every entry is widened once, when it is
+  // staged, rather than at each of its uses in the diquark.
+  __shared__ double2 su[2][NS][NROW][NXI];
+  __shared__ double2 s1[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
+  __shared__ double2 sd[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
   __shared__ double2 Ac[2][KG][MP];   // (re, im) of the A operand
   __shared__ double2 Bc[2][KG][NP];   // (re, im) of the B operand
   __shared__ double2 wsh[2][NS][2];
@@ -125,10 +123,7 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
     b_r0[j] = (n * NROW + cc) * NXI + x3;
     b_sw[j] = (cc - bb) * NXI;
   }
-  auto rd = [](const TIN *p, int i) {   // a staged entry in double
-    const TIN v = p[i];
-    return make_double2(double(v.x), double(v.y));
-  };
+  auto rd = [](const double2 *p, int i) { return p[i]; };
 
   // The propagator entries of the group after next are loaded into
   // registers while a group is built.
@@ -178,9 +173,9 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   };
   auto build = [&](int g) {
     const int buf = g & 1, ns = group_sites(g);
-    const TIN *su_f = &su[buf][0][0][0];
-    const TIN *sd_f = SYM ? su_f : &sd[SYM ? 0 : buf][0][0][0];
-    const TIN *s1_f = (SYM || same1) ? su_f : &s1[SYM ? 0 : buf][0][0][0];
+    const double2 *su_f = &su[buf][0][0][0];
+    const double2 *sd_f = SYM ? su_f : &sd[SYM ? 0 : buf][0][0][0];
+    const double2 *s1_f = (SYM || same1) ? su_f : &s1[SYM ? 0 : buf][0][0][0];
     // A operand: w S_q1[(alpha, a), xi1]
 #pragma unroll
     for (int j = 0; j < AJ; j++) {
