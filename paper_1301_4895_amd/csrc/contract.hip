@@ -592,9 +592,18 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
 #pragma unroll
     for (int g = G - 1; g >= 1; g--)
       if ((e[g].y & 0x7fffffffu) != ya) yb = e[g].y & 0x7fffffffu;   // the first differing row
+    // previous-stage rows: an output whose row at this position equals its
+    // neighbour's reuses the neighbour's registers instead of loading again
     CS xin[G][PG][NIN];
 #pragma unroll
     for (int g = 0; g < G; g++) {
+      if (g > 0 && e[g].x == e[g - 1].x) {
+#pragma unroll
+        for (int p = 0; p < PG; p++)
+#pragma unroll
+          for (int rr = 0; rr < NIN; rr++) xin[g][p][rr] = xin[g - 1][p][rr];
+        continue;
+      }
       const CS *xrow = Fin + int64_t(e[g].x) * xstride;
 #pragma unroll
       for (int p = 0; p < PG; p++)
@@ -610,23 +619,17 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
     for (int g = 0; g < G; g++) {
       const uint32_t yg = e[g].y & 0x7fffffffu;
       const double sgn = (e[g].y >> 31) ? -1.0 : 1.0;
-      double2 fin[PG][NIN];
-#pragma unroll
-      for (int p = 0; p < PG; p++)
-#pragma unroll
-        for (int rr = 0; rr < NIN; rr++)
-          fin[p][rr] = make_double2(sgn * double(xin[g][p][rr].x), sgn * double(xin[g][p][rr].y));
       if (yg == ya) {
 #pragma unroll
-        for (int p = 0; p < PG; p++) wedge_accumulate<M, K>(fin[p], fya, acc[g][p]);
+        for (int p = 0; p < PG; p++) wedge_accumulate_x<M, K, true>(xin[g][p], fya, sgn, acc[g][p]);
       } else if (yg == yb) {
 #pragma unroll
-        for (int p = 0; p < PG; p++) wedge_accumulate<M, K>(fin[p], fyb, acc[g][p]);
+        for (int p = 0; p < PG; p++) wedge_accumulate_x<M, K, true>(xin[g][p], fyb, sgn, acc[g][p]);
       } else {
         double2 fyc[M];
         load_y(yg, fyc);
 #pragma unroll
-        for (int p = 0; p < PG; p++) wedge_accumulate<M, K>(fin[p], fyc, acc[g][p]);
+        for (int p = 0; p < PG; p++) wedge_accumulate_x<M, K, true>(xin[g][p], fyc, sgn, acc[g][p]);
       }
     }
   }
