@@ -136,20 +136,38 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Workgroup -> (lane tile, position o in the output order of the step; o runs
+// over the n8 padded outputs of each passthrough group in turn).  Workgroups
+// are dispatched round-robin over the 8 XCDs (linear id mod 8).  Every XCD
+// takes whole lane tiles when there are at least 8, else a contiguous
+// segment of the output order of one tile, so that its L2 holds only its own
+// lanes' rows, and walks its outputs in order (neighbouring outputs share
+// operands).  The grid is (n8 x passthrough groups, lane tiles).
+struct TileOut {
+  int64_t tile, o;
+};
+__device__ __forceinline__ TileOut xcd_map(int64_t n8) {
+  const int64_t nout = gridDim.x, nt = gridDim.y;
+  const int64_t L = blockIdx.x + nout * int64_t(blockIdx.y);
+  const int xcd = int(L % 8);
+  const int64_t iw = L / 8;   // rank of the workgroup on its XCD
+  if (nt % 8 == 0) return {xcd + 8 * (iw / nout), iw % nout};
+  if (8 % nt == 0) return {xcd % nt, (xcd / nt) * (nout / (8 / nt)) + iw};   // nout is a multiple of 8
+  const int64_t r = blockIdx.x % n8;   // otherwise XCD-contiguous segments per tile
+  return {int64_t(blockIdx.y), (blockIdx.x / n8) * n8 + (r % 8) * (n8 / 8) + r / 8};
+}
+
 template <typename TS, int M, int K, int PG, int TILE, int U, bool AP>
 __device__ __forceinline__ void stage_body(const StageArgs &a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   constexpr int SUB = 64 / TILE;   // sub-waves splitting the quark splits
   const int quarter = SUB == 1 ? 0 : int(threadIdx.x) / TILE;
-  const int64_t b = blockIdx.y * TILE + (threadIdx.x & (TILE - 1));
-  // Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-  // contiguous segment of the output order (consecutive outputs share
-  // operands in its L2) and let the passthrough group vary slowest.
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
-  const int pass0 = int(blockIdx.x / n8) * PG;
-  const int64_t r = blockIdx.x % n8;
-  const int64_t q = (r % 8) * (n8 / 8) + r / 8;
+  const TileOut to = xcd_map(n8);
+  const int64_t b = to.tile * TILE + (threadIdx.x & (TILE - 1));
+  const int pass0 = int(to.o / n8) * PG;
+  const int64_t q = to.o % n8;
   if (q >= a.nq_out) return;
   const int64_t Bp = a.Bp;
   const int ns_in = NIN * a.npass, ns_out = NOUT * a.npass;
@@ -546,12 +564,12 @@ template <typename TS, int M, int K, int PG, int G>
 __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
-  const int64_t b = blockIdx.y * 64 + threadIdx.x;
   const int64_t ngrp = (a.nq_out + G - 1) / G;
   const int64_t n8 = (ngrp + 7) / 8 * 8;
-  const int pass0 = int(blockIdx.x / n8) * PG;
-  const int64_t r = blockIdx.x % n8;
-  const int64_t grp = (r % 8) * (n8 / 8) + r / 8;   // XCD-contiguous ranges of groups
+  const TileOut to = xcd_map(n8);
+  const int64_t b = to.tile * 64 + threadIdx.x;
+  const int pass0 = int(to.o / n8) * PG;
+  const int64_t grp = to.o % n8;
   if (grp >= ngrp) return;
   const int64_t q0 = grp * G;
   const int64_t Bp = a.Bp;

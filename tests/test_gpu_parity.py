@@ -222,3 +222,35 @@ def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V
         _, got, _ = _run(tl, Su, Sd, w, k, precision)
         errs = [rel_err(got[b], ref[b]) for b in range(nl)]
         assert max(errs) <= tol, (kern, pg, tile, lds, unroll, group, max(errs))
+
+
+@pytest.mark.parametrize("nl", [150, 500, 520])
+def test_workgroup_mapping_covers_every_lane(nl):
+    """Lane counts whose lane tiles number fewer than 8, a multiple of 8, or
+    neither (the workgroup-to-XCD assignment of the recursion kernels has a
+    case for each): every lane of one large batch equals the same lane run
+    in batches of at most 64 lanes (one or four tiles), exactly, for every
+    lane tile and output grouping; two lanes are also checked against the
+    oracle."""
+    rel, nsrc, nP, nN, spins, V = False, 1, 2, 2, (0, 1, 0, 1), 8
+    Su, Sd, w, k = _inputs(17, nl, V, nsrc, np.complex128, True, with_sink=False)
+    tl = _tl(rel, nsrc, nP, nN, spins)
+    nst = tl.counts()["n_stages"]
+    for tile, group in [(16, 1), (64, 1), (64, 2), (64, 4)]:
+        for s in range(1, nst):
+            tl.tune(s, B.MB_TUNE_KERNEL, 0)
+            tl.tune(s, B.MB_TUNE_UNROLL, 0)
+            tl.tune(s, B.MB_TUNE_GROUP, group)
+            tl.tune(s, B.MB_TUNE_PASS_GROUP, 1)
+            tl.tune(s, B.MB_TUNE_LANE_TILE, tile)
+            tl.tune(s, B.MB_TUNE_LDS_BYTES, 0)
+        _, full, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
+        parts = []
+        for i in range(0, nl, 64):
+            su = Su[i:i + 64]   # one array for both flavours, as in the full batch
+            parts.append(_run(tl, su, su, w, k[i:i + 64], B.MB_FP64)[1])
+        chunked = np.concatenate(parts)
+        assert np.array_equal(full, chunked), (tile, group, np.argwhere(full != chunked)[:4])
+    for b in (0, nl - 1):
+        ref = _oracle_corr(tl, rel, nsrc, nP, nN, Su[b], Sd[b], w, k[b])
+        assert rel_err(full[b], ref) <= 1e-12, b
