@@ -736,7 +736,8 @@ hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Final contraction, in double: C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b].
 // One thread per (alpha, delta, lane): the coefficient list of alpha is read
-// with scalar loads, F with one coalesced load per entry.
+// with scalar loads, F with one coalesced load per entry, eight entries in
+// flight (the sum keeps the order of the list).
 template <typename TS>
 __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
   using CS = typename c2<TS>::type;
@@ -748,7 +749,20 @@ __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
   const int64_t e0 = a.crow[alpha], e1 = a.crow[alpha + 1];
   const int64_t off = lane_off(b, a.n_delta) + delta * 16;
   const int64_t rowstride = int64_t(a.n_delta) * a.Bp;
-  for (int64_t e = e0; e < e1; e++) {
+  constexpr int EB = 8;
+  int64_t e = e0;
+  for (; e + EB <= e1; e += EB) {
+    CS v[EB];
+#pragma unroll
+    for (int j = 0; j < EB; j++) v[j] = F[int64_t(a.ccol[e + j]) * rowstride + off];
+#pragma unroll
+    for (int j = 0; j < EB; j++) {
+      const double c = a.cval[e + j];
+      ar += c * double(v[j].x);
+      ai += c * double(v[j].y);
+    }
+  }
+  for (; e < e1; e++) {
     const CS v = F[int64_t(a.ccol[e]) * rowstride + off];
     const double c = a.cval[e];
     ar += c * double(v.x);
