@@ -147,7 +147,7 @@ def run_workload(name, args):
         sink = torch.from_numpy(w).to(dev)
     log(f"[bench] propagators {props.numel() * props.element_size() / 1e9:.1f} GB generated")
 
-    chunk = min(args.chunk, lanes)
+    chunk = lanes if args.chunk <= 0 else min(args.chunk, lanes)   # default: one launch for all lanes
     assert lanes % chunk == 0
     nchunk = lanes // chunk
     A = cfg["nP"] + cfg["nN"]
@@ -265,6 +265,7 @@ def run_mix(args):
     from paper_1301_4895_amd import binding as B
     from paper_1301_4895_amd.batch import BatchRunner, tune_nuclei
     dev = torch.device("cuda:0")
+    c5_chunk = args.chunk if args.chunk > 0 else 256   # lanes per batch item
     t0 = time.time()
     groups, tls, probs = mix_groups(dev)
     lanes = sum(g["props"].shape[0] for g in groups)
@@ -275,8 +276,8 @@ def run_mix(args):
         if args.only and prec_name != args.only:
             continue
         if not args.no_autotune:
-            tune_nuclei(groups, prec, args.chunk, cache=args.tune_cache, key="c5", log=log)
-        br = BatchRunner(groups, prec, n_branches=4, chunk=args.chunk)
+            tune_nuclei(groups, prec, c5_chunk, cache=args.tune_cache, key="c5", log=log)
+        br = BatchRunner(groups, prec, n_branches=4, chunk=c5_chunk)
         times = br.tune_branches(log=log) if not args.no_autotune else None
         tuning[prec_name] = dict(branches=br.n_branches, graph_ms_by_branches=times)
         for _ in range(args.warmup):
@@ -310,7 +311,7 @@ def run_mix(args):
     cfg = dict(workload=f"uneven batch: {len(probs)} problems drawn by seed {MIX_SEED} from "
                         f"{', '.join(m['name'] for m in MIX_TYPES)}; L in {{16,24,32}}, T in {{32,64,96}}; "
                         f"complex64, one graph launch")
-    return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=args.chunk,
+    return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=c5_chunk,
                 results=results, main=main_name, err=err, err_stats=err_stats, roofline=None, tuning=tuning,
                 t_list=0.0)
 
@@ -377,7 +378,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3+c4", choices=sorted(CONFIGS) + ["c3+c4", "c5"],
                     help="workload; c3+c4 times 4He relativistic (the reported value) and 8Be NR")
-    ap.add_argument("--chunk", type=int, default=256, help="lanes per launch")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="lanes per launch (default: every lane of the workload in one launch; batch items of at most 256 lanes for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
     ap.add_argument("--no-autotune", action="store_true")

@@ -138,23 +138,21 @@ hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Workgroup -> (lane tile, position o in the output order of the step; o runs
 // over the n8 padded outputs of each passthrough group in turn).  Workgroups
-// are dispatched round-robin over the 8 XCDs (linear id mod 8).  Every XCD
-// takes whole lane tiles when there are at least 8, else a contiguous
-// segment of the output order of one tile, so that its L2 holds only its own
-// lanes' rows, and walks its outputs in order (neighbouring outputs share
-// operands).  The grid is (n8 x passthrough groups, lane tiles).
+// are dispatched round-robin over the 8 XCDs (linear id mod 8).  The work
+// (lane tile major, then o) is cut into 8 contiguous ranges, one per XCD:
+// an XCD walks whole lane tiles, or a segment of one or two, so that its L2
+// holds only its own lanes' rows, and it walks its outputs in order
+// (neighbouring outputs share operands).  The grid is (n8 x passthrough
+// groups, lane tiles), so the work is a multiple of 8.
 struct TileOut {
   int64_t tile, o;
 };
-__device__ __forceinline__ TileOut xcd_map(int64_t n8) {
-  const int64_t nout = gridDim.x, nt = gridDim.y;
+__device__ __forceinline__ TileOut xcd_map() {
+  const int64_t nout = gridDim.x;
   const int64_t L = blockIdx.x + nout * int64_t(blockIdx.y);
-  const int xcd = int(L % 8);
-  const int64_t iw = L / 8;   // rank of the workgroup on its XCD
-  if (nt % 8 == 0) return {xcd + 8 * (iw / nout), iw % nout};
-  if (8 % nt == 0) return {xcd % nt, (xcd / nt) * (nout / (8 / nt)) + iw};   // nout is a multiple of 8
-  const int64_t r = blockIdx.x % n8;   // otherwise XCD-contiguous segments per tile
-  return {int64_t(blockIdx.y), (blockIdx.x / n8) * n8 + (r % 8) * (n8 / 8) + r / 8};
+  const int64_t per = nout * int64_t(gridDim.y) / 8;   // workgroups per XCD
+  const int64_t g = (L % 8) * per + L / 8;             // position in the tile-major work order
+  return {g / nout, g % nout};
 }
 
 template <typename TS, int M, int K, int PG, int TILE, int U, bool AP>
@@ -164,7 +162,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
   constexpr int SUB = 64 / TILE;   // sub-waves splitting the quark splits
   const int quarter = SUB == 1 ? 0 : int(threadIdx.x) / TILE;
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
-  const TileOut to = xcd_map(n8);
+  const TileOut to = xcd_map();
   const int64_t b = to.tile * TILE + (threadIdx.x & (TILE - 1));
   const int pass0 = int(to.o / n8) * PG;
   const int64_t q = to.o % n8;
@@ -566,7 +564,7 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   const int64_t ngrp = (a.nq_out + G - 1) / G;
   const int64_t n8 = (ngrp + 7) / 8 * 8;
-  const TileOut to = xcd_map(n8);
+  const TileOut to = xcd_map();
   const int64_t b = to.tile * 64 + threadIdx.x;
   const int pass0 = int(to.o / n8) * PG;
   const int64_t grp = to.o % n8;
