@@ -58,16 +58,24 @@ extern "C" {
 int mb_synth_props(void *out, int c128, uint64_t seed, uint32_t stream, int64_t V, int nsrc, int T,
                    int64_t first_bt, int64_t nbt, const double *decay, void *hip_stream) {
   const int64_t per_t = V * nsrc * 144;
-  const int64_t n = nbt * per_t;
-  if (n <= 0) return 0;
-  dim3 grid(unsigned((n + 255) / 256));
+  if (nbt <= 0 || per_t <= 0) return 0;
+  // a launch covers at most 2^31 work-items (the dispatch grid size is 32-bit)
+  const int64_t max_items = int64_t(1) << 31;
+  if (per_t > max_items) return int(hipErrorInvalidValue);
+  const int64_t units = max_items / per_t;   // whole units per launch
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (c128)
-    hipLaunchKernelGGL(props_kernel<double2>, grid, dim3(256), 0, s, static_cast<double2 *>(out), seed,
-                       stream, per_t, T, first_bt, nbt, decay);
-  else
-    hipLaunchKernelGGL(props_kernel<float2>, grid, dim3(256), 0, s, static_cast<float2 *>(out), seed,
-                       stream, per_t, T, first_bt, nbt, decay);
-  return int(hipGetLastError());
+  for (int64_t u0 = 0; u0 < nbt; u0 += units) {
+    const int64_t nu = nbt - u0 < units ? nbt - u0 : units;
+    dim3 grid(unsigned((nu * per_t + 255) / 256));
+    if (c128)
+      hipLaunchKernelGGL(props_kernel<double2>, grid, dim3(256), 0, s, static_cast<double2 *>(out) + u0 * per_t,
+                         seed, stream, per_t, T, first_bt + u0, nu, decay);
+    else
+      hipLaunchKernelGGL(props_kernel<float2>, grid, dim3(256), 0, s, static_cast<float2 *>(out) + u0 * per_t,
+                         seed, stream, per_t, T, first_bt + u0, nu, decay);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return int(e);
+  }
+  return 0;
 }
 }

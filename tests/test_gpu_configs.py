@@ -1,5 +1,5 @@
 """The two small workloads at their full sizes, as bench.py runs them
-(device-generated propagators, 2^k(t) rescale, at most 256 lanes per launch):
+(device-generated propagators, 2^k(t) rescale, every lane in one launch):
 
   * p+n NR, all components, L=4 T=8, one problem, complex128: every lane of
     the FP64 path against the oracle (1e-12), mixed against FP64 (1e-6);

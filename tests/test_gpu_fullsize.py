@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
-times (256 lanes per launch, device-generated propagators, 2^k(t) rescale).
+times (every lane of the workload in one launch: 768 lanes for 4He, 1024 for
+8Be; device-generated propagators, 2^k(t) rescale).
 
 The oracle checks sampled lanes one by one:
-  * 4He relativistic, all components, V = 24^3: blocks of two lanes (every
+  * 4He relativistic, all components, V = 24^3: blocks of three lanes (every
     entry) and their correlators for a few (sink set, source set) pairs;
   * 8Be nonrelativistic with two sources, V = 32^3: blocks of one lane, and
     the full correlator through the two-source factorisation on disjoint
@@ -26,8 +27,11 @@ from tests.gpu_helpers import check_lane_exponent, lib_blocks, oracle_blocks_lib
 
 pytestmark = pytest.mark.gpu
 
-LANES = 256
 SEED = 2013
+
+
+def all_lanes(cfg):
+    return cfg["nprob"] * cfg["T"]
 
 
 def kexp(lanes, T):
@@ -68,8 +72,9 @@ def test_4he_relativistic_full_size(oracle_threads):
     cfg = CONFIGS["c3"]
     V = cfg["L"] ** 3
     tl = B.TermList(2, 2, True, 1, all_components=True)
-    props = device_props(cfg, LANES)
-    k = torch.from_numpy(kexp(LANES, cfg["T"])).cuda()
+    lanes = all_lanes(cfg)
+    props = device_props(cfg, lanes)
+    k = torch.from_numpy(kexp(lanes, cfg["T"])).cuda()
     out = {}
     for prec in (B.MB_FP64, B.MB_MIXED):
         r = Runner(tl, props, props, prec, None, k)
@@ -79,9 +84,9 @@ def test_4he_relativistic_full_size(oracle_threads):
     dsets = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
     asets = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
     pairs = [(i, j) for i in (0, 14, 35) for j in (0, 21)]
-    for lane in (3, 197):
+    for lane in (3, 197, 700):
         S = host_lane(cfg, lane)
-        kk = int(kexp(LANES, cfg["T"])[lane])
+        kk = int(kexp(lanes, cfg["T"])[lane])
         fP, fN = O.blocks(True, 1, S, S, None, 2.0 ** kk)
         got_blocks, e = lane_blocks(out[B.MB_FP64][1], tl, lane)
         ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -e
@@ -101,16 +106,17 @@ def test_8be_two_sources_full_size(oracle_threads):
     L = cfg["L"]
     V = L ** 3
     tl = B.TermList.spin_state(4, 4, False, 2, (0, 1, 2, 3, 0, 1, 2, 3))
-    props = device_props(cfg, LANES)
-    k = torch.from_numpy(kexp(LANES, cfg["T"])).cuda()
+    lanes = all_lanes(cfg)
+    props = device_props(cfg, lanes)
+    k = torch.from_numpy(kexp(lanes, cfg["T"])).cuda()
     w = np.stack([np.ones(V, np.complex128), SP.momentum_phase(L, 1)])
     # blocks of one lane of the benchmark inputs, every entry
     r = Runner(tl, props, props, B.MB_FP64, torch.from_numpy(w).cuda(), k)
     r.run_blocks()
     torch.cuda.synchronize()
-    lane = 77
+    lane = 877
     S = host_lane(cfg, lane)
-    fP, fN = O.blocks(False, 2, S, S, w, 2.0 ** int(kexp(LANES, cfg["T"])[lane]))
+    fP, fN = O.blocks(False, 2, S, S, w, 2.0 ** int(kexp(lanes, cfg["T"])[lane]))
     got_blocks, e = lane_blocks(r, tl, lane)
     ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -e
     assert rel_err(got_blocks, ref_blocks) <= 1e-12
@@ -132,11 +138,11 @@ def test_8be_two_sources_full_size(oracle_threads):
         res[prec] = corr.cpu().numpy()[:, 0, 0]
         del rr
     req = O.spin_state_request(2, 2, (0, 1, 0, 1))
-    for lane in (0, 130, 255):
+    for lane in (0, 130, 611, 1023):
         S = host_lane(cfg, lane)
         S[x3 >= L // 2, 0] = 0   # same regions as on the device
         S[x3 < L // 2, 1] = 0
-        sc = 2.0 ** int(kexp(LANES, cfg["T"])[lane])
+        sc = 2.0 ** int(kexp(lanes, cfg["T"])[lane])
         c0 = O.correlators(False, 1, 2, 2, req, S[:, :1], S[:, :1], wr[:1], sc)[((3, 3), (3, 3))]
         c1 = O.correlators(False, 1, 2, 2, req, S[:, 1:], S[:, 1:], wr[1:], sc)[((3, 3), (3, 3))]
         ref = c0 * c1
