@@ -519,6 +519,7 @@ template <typename T, int M, int K, int PG>
 static hipError_t launch_stage_lds_mkp(const StageLdsArgs &a, hipStream_t s) {
   const int64_t nslot = a.nq_out * a.npg;
   const int64_t nwg = ((nslot + LDS_SLOTS - 1) / LDS_SLOTS + 7) / 8 * 8;
+  if (!grid_x_fits(nwg, LDS_THREADS)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(nwg), unsigned(a.Bp / 16));
   hipLaunchKernelGGL((stage_lds_kernel<T, M, K, PG>), grid, dim3(LDS_THREADS), stage_lds_bytes(a.nxi, M, a.pp), s,
                      a);
@@ -669,6 +670,7 @@ template <typename T, int M, int K, int PG, int G>
 static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
   const int64_t ngrp = (a.nq_out + G - 1) / G;
   const int64_t n8 = (ngrp + 7) / 8 * 8;
+  if (!grid_x_fits(n8 * (a.npass / PG), 64)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / 64));
   hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
@@ -677,6 +679,7 @@ static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
 template <typename T, int M, int K, int PG, int TILE, int U>
 static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
+  if (!grid_x_fits(n8 * (a.npass / PG), 64)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / TILE));
   hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();

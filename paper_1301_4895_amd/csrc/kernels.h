@@ -45,6 +45,11 @@ hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int 
 // one operand (its spin parts, its baryon indices) are adjacent in memory.
 __host__ __device__ inline int64_t lane_off(int64_t b, int n) { return (b >> 4) * n * 16 + (b & 15); }
 
+// A dispatch covers fewer than 2^32 work-items per dimension (the grid size
+// of the dispatch packet is 32-bit); larger launches are refused, never
+// truncated.
+inline bool grid_x_fits(int64_t groups, int threads) { return groups * threads < (int64_t(1) << 32); }
+
 // Stage 0: F0[q][sigma] = f_T0[psi(sigma)][first[q]].
 struct Stage0Args {
   const void *fblk;
