@@ -95,12 +95,26 @@ typedef struct {
  *          n_N-subset of sink_N.  alpha[2*i], alpha[2*i+1] are the proton
  *          and neutron source index sets (bit masks, popcounts n_P and n_N)
  *          of output column i, 0 <= i < n_alpha.  A single spin component
- *          (Sec. 8) has sink_P = alpha[0], sink_N = alpha[1], n_alpha = 1.  */
+ *          (Sec. 8) has sink_P = alpha[0], sink_N = alpha[1], n_alpha = 1.
+ *   proj   NULL: every (sink set, source set) component is an output.
+ *          Otherwise the projection of Sec. 5: real weights
+ *          proj[delta * n_alpha + alpha] over the sink sets (in the order
+ *          of MB_EXPORT_DELTA) and source sets (MB_EXPORT_ALPHA) that the
+ *          same request without proj gives; the output is the single value
+ *          C_M = sum_{delta, alpha} proj[delta][alpha] C(delta set; alpha set)
+ *          per lane.  The final sum uses the projected list
+ *          L_M(delta; z) = sum_alpha proj[delta][alpha] c_alpha(z), and only
+ *          the quark parts z with a nonzero L_M for some delta are kept,
+ *          together with the components of earlier stages they need.  Every
+ *          sink set of the masks stays a spin part (the stage layout is
+ *          spin parts x quark parts), so restrict sink_P / sink_N to prune
+ *          spin parts.  The weights are read during the build only.         */
 typedef struct {
     int all_components;
     uint32_t sink_P, sink_N;
     int n_alpha;
     const uint32_t *alpha;
+    const double *proj;
 } mb_spin_request;
 
 typedef struct mb_term_list mb_term_list;
@@ -143,9 +157,14 @@ void mb_term_list_free(mb_term_list *tl);
  *   n_spin          distinct (proton set, neutron set) parts of stage s
  *   n_L             nonzero entries of L over all requested source sets
  *   n_U             distinct quark parts with a nonzero L (final stage)
- *   n_delta, n_alpha  output rows / columns
+ *   n_delta, n_alpha  sink sets / source sets of the request (the output
+ *                   rows / columns unless projected)
  *   n_psi, n_xi     D*N_s and 3*D*N_s
- *   device_bytes    size of the device image (0 in counts-only mode)      */
+ *   device_bytes    size of the device image (0 in counts-only mode)
+ *   projected       1 for a projected request (one output per lane), else 0
+ *   n_LM            nonzero entries of the projected list L_M (0 if not
+ *                   projected); n_L then counts the entries of c on the
+ *                   kept quark parts                                        */
 typedef struct {
     int n_stages;
     int path[MB_MAX_STAGES];
@@ -159,6 +178,8 @@ typedef struct {
     int32_t n_delta, n_alpha;
     int32_t n_psi, n_xi;
     int64_t device_bytes;
+    int32_t projected;
+    int64_t n_LM;
 } mb_counts;
 
 int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
@@ -185,6 +206,9 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
  *                    sorted sets (the coefficient c of the final sum)
  *   MB_EXPORT_DELTA  uint32 [n_delta][2] sink sets, MB_EXPORT_ALPHA uint32
  *                    [n_alpha][2] source sets (proton mask, neutron mask)
+ *   MB_EXPORT_PROJ   projected lists only: int64 [n_delta+1] row starts,
+ *                    int64 [n_LM] final quark part indices, double [n_LM]
+ *                    values of L_M(delta; z)
  * The block quark index of a proton split with u pair (a<b) and d index c is
  * (b*(b-1)/2 + a)*n_xi + c; of a neutron split with u index c and d pair
  * (a<b) it is c*(n_xi*(n_xi-1)/2) + b*(b-1)/2 + a.                          */
@@ -195,6 +219,7 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
 #define MB_EXPORT_COEF 5
 #define MB_EXPORT_DELTA 6
 #define MB_EXPORT_ALPHA 7
+#define MB_EXPORT_PROJ 8
 int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
                         size_t *bytes);
 
@@ -266,7 +291,8 @@ typedef struct {
 /* Device buffer sizes for one batch:
  *   blocks_bytes     output of mb_make_blocks / input of the contraction
  *   blocks_ws_bytes  workspace of mb_make_blocks (site-chunk partial sums)
- *   contract_ws_bytes workspace of mb_contract_correlator (two stages of F) */
+ *   contract_ws_bytes workspace of mb_contract_correlator (two stages of F;
+ *                    for a projected term list also the per-sink-set sums) */
 int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
                        size_t *blocks_bytes, size_t *blocks_ws_bytes,
                        size_t *contract_ws_bytes);
@@ -293,7 +319,10 @@ int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
 /* Correlators from blocks: the recursion of eq. recr_F over the operation
  * lists, then C(delta; alpha) = sum_z F_-(delta; z) L(alpha; z) / (n_P! n_N!)
  * (eq. C_final with the sum over sorted index sets), the final sum in double.
- *   corr_out  device, complex double [B][n_delta][n_alpha]
+ *   corr_out  device, complex double [B][n_delta][n_alpha]; for a projected
+ *             term list [B]: C_M = sum_z F_-(delta; z) L_M(delta; z) /
+ *             (n_P! n_N!) summed over delta (eq. CM_final), the sum over
+ *             delta in a fixed order
  *   exp_out   device, int32 [B] or NULL: 3*A*scale_exp[b], so that the
  *             correlator of the unscaled propagators is corr_out * 2^-exp_out
  * The term list must be uploaded.                                           */
@@ -351,7 +380,8 @@ typedef struct mb_batch mb_batch;
  * default priority) which it instantiates.  Items on one branch run in the
  * order given.  Nothing runs until mb_batch_launch.  The buffers and term
  * lists must stay alive and keep their addresses while the batch exists;
- * their contents are read at launch time.  MB_EHIP if capture fails.       */
+ * their contents are read at launch time.  MB_EHIP if capture fails;
+ * MB_EUNSUPPORTED for a projected term list.                                */
 int mb_batch_create(const mb_batch_item *items, int n_items, int n_branches, mb_batch **out);
 
 /* Launches the whole batch on `stream` (one graph launch).  Launches of one

@@ -23,7 +23,7 @@ MB_MAX_STAGES = 16
 MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUNE_UNROLL, MB_TUNE_GROUP = \
     1, 2, 3, 4, 5, 6
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
- MB_EXPORT_DELTA, MB_EXPORT_ALPHA) = range(1, 8)
+ MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ) = range(1, 9)
 
 EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_term_list_free",
@@ -47,7 +47,7 @@ class mb_nucleus(C.Structure):
 
 class mb_spin_request(C.Structure):
     _fields_ = [("all_components", C.c_int), ("sink_P", C.c_uint32), ("sink_N", C.c_uint32),
-                ("n_alpha", C.c_int), ("alpha", C.POINTER(C.c_uint32))]
+                ("n_alpha", C.c_int), ("alpha", C.POINTER(C.c_uint32)), ("proj", C.POINTER(C.c_double))]
 
 
 class mb_counts(C.Structure):
@@ -56,7 +56,7 @@ class mb_counts(C.Structure):
                 ("n_quark", C.c_int64 * MB_MAX_STAGES), ("n_spin", C.c_int32 * MB_MAX_STAGES),
                 ("n_L", C.c_int64), ("n_U", C.c_int64), ("n_delta", C.c_int32),
                 ("n_alpha", C.c_int32), ("n_psi", C.c_int32), ("n_xi", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("projected", C.c_int32), ("n_LM", C.c_int64)]
 
 
 class mb_problem(C.Structure):
@@ -116,15 +116,19 @@ def _check(rc):
 
 
 class TermList:
-    """Owner of an mb_term_list handle."""
+    """Owner of an mb_term_list handle.  ``proj``: optional real weights
+    [n_delta][n_alpha] of the spin projection (Sec. 5), over the sink and
+    source sets of the same request without it."""
 
     def __init__(self, n_P, n_N, rel, n_src=1, *, all_components=False, sink_P=0, sink_N=0,
-                 alphas=(), path=MB_PATH_AUTO, counts_only=False):
+                 alphas=(), path=MB_PATH_AUTO, counts_only=False, proj=None):
         nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path)
         arr = np.ascontiguousarray(np.asarray(alphas, np.uint32).reshape(-1))
         self._alpha_keep = arr
+        w = None if proj is None else np.ascontiguousarray(np.asarray(proj, np.float64).reshape(-1))
         req = mb_spin_request(int(all_components), sink_P, sink_N, len(arr) // 2,
-                              arr.ctypes.data_as(C.POINTER(C.c_uint32)) if len(arr) else None)
+                              arr.ctypes.data_as(C.POINTER(C.c_uint32)) if len(arr) else None,
+                              w.ctypes.data_as(C.POINTER(C.c_double)) if w is not None else None)
         h = C.c_void_p()
         fn = lib().mb_build_term_list_counts_only if counts_only else lib().mb_build_term_list
         _check(fn(C.byref(nuc), C.byref(req), C.byref(h)))
@@ -158,7 +162,7 @@ class TermList:
                     n_lambda_step=list(c.n_lambda_step[:n]), n_req=list(c.n_req[:n]),
                     n_quark=list(c.n_quark[:n]), n_spin=list(c.n_spin[:n]), n_L=c.n_L, n_U=c.n_U,
                     n_delta=c.n_delta, n_alpha=c.n_alpha, n_psi=c.n_psi, n_xi=c.n_xi,
-                    device_bytes=c.device_bytes)
+                    device_bytes=c.device_bytes, projected=bool(c.projected), n_LM=c.n_LM)
 
     def export(self, what, stage=0, dtype=np.uint32):
         n = C.c_size_t(0)

@@ -62,6 +62,11 @@ size_t blocks_ws_of(const mb_term_list *tl, const mb_problem *p) {
   return al256(per * size_t(p->batch)) * (sym ? 1 : 2);
 }
 
+// Per-sink-set sums of a projected final sum: complex double [Bp][n_delta].
+size_t proj_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+  return tl->projected ? al256(size_t(lanes_padded(p->batch)) * size_t(tl->st.back().nspin()) * 16) : 0;
+}
+
 void stage_buffer_sizes(const mb_term_list *tl, const mb_problem *p, size_t *even, size_t *odd) {
   size_t e = 0, o = 0;
   for (int s = 0; s < tl->nstages; s++) {
@@ -127,12 +132,22 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
     if (!v.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
     o += al256(v.size() * 4);
   }
+  // the coefficients of the final sum: c over the source sets, or the
+  // projected list L_M over the sink sets
+  const std::vector<int64_t> &row = tl->projected ? tl->prow : tl->crow;
   tl->off_crow = o;
-  UPLOAD_CHECK(hipMemcpyAsync(base + o, tl->crow.data(), tl->crow.size() * 8, hipMemcpyHostToDevice, s));
-  o += al256(tl->crow.size() * 8);
+  UPLOAD_CHECK(hipMemcpyAsync(base + o, row.data(), row.size() * 8, hipMemcpyHostToDevice, s));
+  o += al256(row.size() * 8);
   tl->off_ccol = o;
-  std::vector<int32_t> col(tl->ccol.begin(), tl->ccol.end());
-  std::vector<double> val(tl->cval.begin(), tl->cval.end());
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  if (tl->projected) {
+    col.assign(tl->pcol.begin(), tl->pcol.end());
+    val = tl->pval;
+  } else {
+    col.assign(tl->ccol.begin(), tl->ccol.end());
+    val.assign(tl->cval.begin(), tl->cval.end());
+  }
   if (!col.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, col.data(), col.size() * 4, hipMemcpyHostToDevice, s));
   o += al256(col.size() * 4);
   tl->off_cval = o;
@@ -189,7 +204,7 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p, size_t *bloc
   if (contract_ws_bytes) {
     size_t e, o;
     stage_buffer_sizes(tl, p, &e, &o);
-    *contract_ws_bytes = e + o;
+    *contract_ws_bytes = e + o + proj_bytes_of(tl, p);
   }
   return MB_OK;
 }
@@ -256,7 +271,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
   size_t ev, od;
   stage_buffer_sizes(tl, p, &ev, &od);
-  if (ws_bytes < ev + od) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
+  if (ws_bytes < ev + od + proj_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool mixed = p->precision == MB_MIXED;
   const int64_t Bp = lanes_padded(p->batch);
@@ -349,7 +364,16 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.A = tl->A;
       a.lane_exp = reinterpret_cast<const int32_t *>(blk + blocks_entry_bytes(tl, p));
       a.inv_fact = 1.0 / (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
-      HIP_CHECK(launch_final(a, mixed, s));
+      if (tl->projected) {
+        // row delta of the list pairs with sink set delta only; the sums per
+        // delta go to the workspace and are then added in delta order
+        a.diag = 1;
+        a.corr = reinterpret_cast<double *>(buf[1] + od);
+        HIP_CHECK(launch_final(a, mixed, s));
+        HIP_CHECK(launch_project(a.corr, corr_out, p->batch, a.n_delta, s));
+      } else {
+        HIP_CHECK(launch_final(a, mixed, s));
+      }
     }
   }
   return MB_OK;

@@ -738,13 +738,15 @@ hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s) {
 // Final contraction, in double: C[b][delta][alpha] = norm * sum_e c_e F[q_e][delta][b].
 // One thread per (alpha, delta, lane): the coefficient list of alpha is read
 // with scalar loads, F with one coalesced load per entry, eight entries in
-// flight (the sum keeps the order of the list).
+// flight (the sum keeps the order of the list).  A projected list (Sec. 5,
+// eq. CM_final) has one row per sink set delta, used with that delta only
+// (diag): then alpha = delta and the output is C[b][delta].
 template <typename TS>
 __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
   using CS = typename c2<TS>::type;
   const int64_t b = blockIdx.z * 64 + threadIdx.x;
-  const int alpha = blockIdx.x;
   const int delta = blockIdx.y;
+  const int alpha = a.diag ? delta : int(blockIdx.x);
   const CS *F = static_cast<const CS *>(a.F);
   double ar = 0.0, ai = 0.0;
   const int64_t e0 = a.crow[alpha], e1 = a.crow[alpha + 1];
@@ -771,18 +773,38 @@ __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
   }
   if (b < a.B) {
     const int e = a.A * a.lane_exp[b];
-    reinterpret_cast<double2 *>(a.corr)[(b * a.n_delta + delta) * a.n_alpha + alpha] =
-        make_double2(ldexp(ar * a.inv_fact, e), ldexp(ai * a.inv_fact, e));
+    const int64_t oi = a.diag ? b * a.n_delta + delta : (b * a.n_delta + delta) * a.n_alpha + alpha;
+    reinterpret_cast<double2 *>(a.corr)[oi] = make_double2(ldexp(ar * a.inv_fact, e), ldexp(ai * a.inv_fact, e));
     if (a.exp_out && alpha == 0 && delta == 0) a.exp_out[b] = a.scale_exp ? 3 * a.A * a.scale_exp[b] : 0;
   }
 }
 
 hipError_t launch_final(const FinalArgs &a, bool mixed, hipStream_t s) {
-  dim3 grid(unsigned(a.n_alpha), unsigned(a.n_delta), unsigned(a.Bp / 64));
+  dim3 grid(unsigned(a.diag ? 1 : a.n_alpha), unsigned(a.n_delta), unsigned(a.Bp / 64));
   if (mixed)
     hipLaunchKernelGGL(final_kernel<float>, grid, dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(final_kernel<double>, grid, dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// Sum of a projected correlator over the sink sets, in delta order (one
+// thread per lane).
+__global__ __launch_bounds__(256) void project_kernel(const double2 *part, double2 *out, int64_t B, int n_delta) {
+  const int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (b >= B) return;
+  double re = 0.0, im = 0.0;
+  for (int d = 0; d < n_delta; d++) {
+    const double2 v = part[b * n_delta + d];
+    re += v.x;
+    im += v.y;
+  }
+  out[b] = make_double2(re, im);
+}
+
+hipError_t launch_project(const double *part, double *out, int64_t B, int n_delta, hipStream_t s) {
+  hipLaunchKernelGGL(project_kernel, dim3(unsigned((B + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2 *>(part), reinterpret_cast<double2 *>(out), B, n_delta);
   return hipGetLastError();
 }
 

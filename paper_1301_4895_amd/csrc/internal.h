@@ -54,6 +54,11 @@ struct mb_term_list {
   // final coefficients c_alpha(q) = L(alpha; q) on sorted sets, CSR over alpha
   std::vector<int64_t> crow, ccol, cval;
   int64_t nL = 0, nU = 0;
+  // projection (Sec. 5): L_M(delta; q) = sum_alpha w[delta][alpha] c_alpha(q),
+  // CSR over the sink sets delta; the final sum uses it in place of c
+  bool projected = false;
+  std::vector<int64_t> prow, pcol;
+  std::vector<double> pval;
   bool counts_only = false;
   // device image
   void *dev = nullptr;

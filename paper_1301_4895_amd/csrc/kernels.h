@@ -120,7 +120,11 @@ struct FinalArgs {
   int64_t B, Bp;
   int n_delta, n_alpha, A;
   double inv_fact;           // 1 / (n_P! n_N!)
+  int diag;                  // projected list: row delta of the list with sink set delta only,
+                             // corr[b][delta]
 };
 hipError_t launch_final(const FinalArgs &a, bool mixed, hipStream_t s);
+// Projected correlator: out[b] = sum over delta (in order) of part[b][delta].
+hipError_t launch_project(const double *part, double *out, int64_t B, int n_delta, hipStream_t s);
 
 }  // namespace mb

@@ -13,6 +13,7 @@
 //     its quark part times a split of its baryon-index part, and the sign of
 //     eq. antis_product_2 is the product of the per-group signs.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -416,15 +417,60 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
   }
   const bool last_d_major = tl->path[A - 1] == PROTON && A > 1;
   std::vector<uint64_t> U;
-  for (auto &v : per_alpha)
-    for (auto &e : v) U.push_back(e.first);
+  // Projection (Sec. 5): L_M(delta; q) = sum_alpha w[delta][alpha] c_alpha(q)
+  // for every sink set delta (proton rank major, as the final stage's spin
+  // parts), summed in alpha order; the final quark parts are those with a
+  // nonzero L_M for some delta.
+  std::vector<std::vector<std::pair<uint64_t, double>>> lm;
+  tl->projected = req->proj != nullptr;
+  if (tl->projected) {
+    const int64_t ndel = int64_t(binom(__builtin_popcount(tl->SP), nP)) * binom(__builtin_popcount(tl->SN), nN);
+    const size_t nal = tl->alphas.size();
+    for (size_t i = 0; i < size_t(ndel) * nal; i++)
+      if (!std::isfinite(req->proj[i])) return fail(MB_EINVAL, "projection weight not finite");
+    lm.resize(size_t(ndel));
+    for (int64_t dl = 0; dl < ndel; dl++) {
+      std::unordered_map<uint64_t, double> m;
+      for (size_t al = 0; al < nal; al++) {
+        const double w = req->proj[size_t(dl) * nal + al];
+        if (w == 0.0) continue;
+        for (auto &e : per_alpha[al]) m[e.first] += w * double(e.second);
+      }
+      for (auto &kv : m)
+        if (kv.second != 0.0) {   // entries that cancel exactly leave the list
+          lm[dl].push_back(kv);
+          U.push_back(kv.first);
+        }
+    }
+  } else {
+    for (auto &v : per_alpha)
+      for (auto &e : v) U.push_back(e.first);
+  }
   sort_stage(U, last_d_major);
   U.erase(std::unique(U.begin(), U.end()), U.end());
   tl->nU = int64_t(U.size());
+  auto kept = [&](uint64_t q) {
+    const uint32_t i = find_stage(U, last_d_major, q);
+    return i < U.size() && U[i] == q;
+  };
+  if (tl->projected) {
+    tl->prow.assign(1, 0);
+    for (auto &v : lm) {
+      std::vector<std::pair<uint32_t, double>> row;
+      for (auto &e : v) row.push_back({find_stage(U, last_d_major, e.first), e.second});
+      std::sort(row.begin(), row.end());
+      for (auto &e : row) {
+        tl->pcol.push_back(e.first);
+        tl->pval.push_back(e.second);
+      }
+      tl->prow.push_back(int64_t(tl->pcol.size()));
+    }
+  }
   tl->crow.assign(1, 0);
   for (auto &v : per_alpha) {
     std::vector<std::pair<uint32_t, int64_t>> row;
-    for (auto &e : v) row.push_back({find_stage(U, last_d_major, e.first), e.second});
+    for (auto &e : v)
+      if (!tl->projected || kept(e.first)) row.push_back({find_stage(U, last_d_major, e.first), e.second});
     std::sort(row.begin(), row.end());
     for (auto &e : row) {
       tl->ccol.push_back(e.first);
@@ -505,7 +551,8 @@ size_t mb_term_list::image_bytes() const {
   size_t o = 0;
   for (int s = 1; s < nstages; s++) o += al(st[s].qsplit.size() * 4) + al(st[s].quark.size() * 8);
   o += al(st[0].first.size() * 4);
-  o += al(crow.size() * 8) + al(ccol.size() * 4) + al(cval.size() * 8);
+  if (projected) o += al(prow.size() * 8) + al(pcol.size() * 4) + al(pval.size() * 8);
+  else o += al(crow.size() * 8) + al(ccol.size() * 4) + al(cval.size() * 8);
   return o + 256;
 }
 
@@ -552,6 +599,8 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *c) {
   c->n_psi = tl->npsi;
   c->n_xi = tl->nxi;
   c->device_bytes = int64_t(tl->image_bytes());
+  c->projected = tl->projected ? 1 : 0;
+  c->n_LM = int64_t(tl->pcol.size());
   return MB_OK;
 }
 
@@ -633,6 +682,12 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, 
     }
     case MB_EXPORT_ALPHA:
       for (auto &a : tl->alphas) put(a.data(), 8);
+      break;
+    case MB_EXPORT_PROJ:
+      if (!tl->projected) return fail(MB_EINVAL, "not a projected term list");
+      put(tl->prow.data(), tl->prow.size() * 8);
+      put(tl->pcol.data(), tl->pcol.size() * 8);
+      put(tl->pval.data(), tl->pval.size() * 8);
       break;
     default:
       return fail(MB_EINVAL, "unknown export item");

@@ -28,8 +28,8 @@ class Runner:
         self.bws = torch.empty(max(nbw, 1), dtype=torch.uint8, device=dev)
         self.cws = torch.empty(max(ncw, 1), dtype=torch.uint8, device=dev)
         c = tl.counts()
-        self.corr = torch.empty((self.batch, c["n_delta"], c["n_alpha"]), dtype=torch.complex128,
-                                device=dev)
+        shape = (self.batch, 1, 1) if c["projected"] else (self.batch, c["n_delta"], c["n_alpha"])
+        self.corr = torch.empty(shape, dtype=torch.complex128, device=dev)
         self.exp = torch.empty(self.batch, dtype=torch.int32, device=dev)
 
     def set_props(self, props_u, props_d, scale_exp=None):

@@ -254,3 +254,42 @@ def test_workgroup_mapping_covers_every_lane(nl):
     for b in (0, nl - 1):
         ref = _oracle_corr(tl, rel, nsrc, nP, nN, Su[b], Sd[b], w, k[b])
         assert rel_err(full[b], ref) <= 1e-12, b
+
+
+# --------------------------------------------------------------------- projection (Sec. 5)
+
+PROJ_CASES = [
+    # rel, nsrc, nP, nN, V, lanes, weights
+    (False, 1, 1, 1, 27, 3, "deuteron"),   # p+n, spin 1, m = 0
+    (False, 1, 2, 1, 8, 2, "sparse"),      # 3He
+    (True, 1, 1, 1, 8, 1, "sparse"),       # p+n relativistic
+    (False, 2, 1, 1, 8, 2, "sparse"),      # p+n, two sources
+]
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,V,nl,kind", PROJ_CASES)
+def test_projected_correlator_matches_oracle(rel, nsrc, nP, nN, V, nl, kind):
+    """The projected correlator C_M (one value per lane, eq. CM_final) equals
+    sum W[delta][alpha] C(delta; alpha) with C from the oracle, and with C
+    from the unprojected library path; the error bound is relative to
+    sum |W| |C|, the size of the terms of the projection."""
+    from tests.spin_weights import deuteron_weights, sparse_weights
+    Su, Sd, w, k = _inputs(31 + nP + nN, nl, V, nsrc, np.complex128, True, with_sink=nsrc == 2)
+    full = B.TermList(nP, nN, rel, nsrc, all_components=True)
+    cf = full.counts()
+    W = (deuteron_weights(full) if kind == "deuteron"
+         else sparse_weights((cf["n_delta"], cf["n_alpha"]), 3 * nP + nN + nsrc, 0.3))
+    tl = B.TermList(nP, nN, rel, nsrc, all_components=True, proj=W)
+    assert tl.counts()["projected"]
+    _, cfull, _ = _run(full, Su, Sd, w, k, B.MB_FP64)
+    refs = [_oracle_corr(full, rel, nsrc, nP, nN, Su[b], Sd[b], w, k[b]) for b in range(nl)]
+    for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)]:
+        _, cp, ex = _run(tl, Su, Sd, w, k, prec)
+        assert cp.shape == (nl, 1, 1)
+        assert np.array_equal(ex, 3 * (nP + nN) * k)
+        for b in range(nl):
+            R = refs[b]
+            scale = (np.abs(W) * np.abs(R)).sum()
+            assert scale > 0
+            assert abs(cp[b, 0, 0] - (W * R).sum()) <= tol * scale, (prec, b)
+            assert abs(cp[b, 0, 0] - (W * cfull[b]).sum()) <= tol * scale, (prec, b)

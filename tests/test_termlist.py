@@ -17,6 +17,7 @@ import pytest
 from oracle import oracle as O
 from paper_1301_4895_amd import binding as B
 from tests.paper_tables import row_id, rows
+from tests.spin_weights import deuteron_weights, sparse_weights
 
 
 def lib_termlist(rel, nsrc, nP, nN, spins=None, counts_only=False):
@@ -253,6 +254,11 @@ def test_library_exports_every_declared_symbol():
 def _replay_tables(tl, fb):
     """Applies the exported tables to blocks fb[species][psi][block quark
     index] the way the device recursion does, in numpy, for one lane."""
+    return _final_sum(tl, _replay_stages(tl, fb))
+
+
+def _replay_stages(tl, fb):
+    """The last stage F[final quark part][sink set] from the exported tables."""
     c = tl.counts()
     nxi = c["n_xi"]
     pr = {(a, b): i for i, (a, b) in enumerate(_pairs(nxi))}
@@ -279,6 +285,11 @@ def _replay_tables(tl, fb):
             for sin, psi, sg in ss[so]:
                 G[:, so] += (sg * sq * F[xi, sin] * fb[T][psi][yi]).sum(1)
         F = G
+    return F
+
+
+def _final_sum(tl, F):
+    c = tl.counts()
     coef = tl.export(B.MB_EXPORT_COEF, dtype=np.int64)
     na = c["n_alpha"]
     row, col = coef[:na + 1], coef[na + 1:na + 1 + coef[na]]
@@ -372,3 +383,129 @@ def test_launch_tuning_validation():
         tl.tune(1, B.MB_TUNE_PASS_GROUP, 2)    # step 1 has one passthrough part
     with pytest.raises(B.MBError):
         tl.tune(4, B.MB_TUNE_LANE_TILE, 16)    # no step 4 in a 4-baryon list
+
+
+# ----------------------------------------------------------------- projection (Sec. 5)
+
+def _lm_from_coefficients(tl, W):
+    """L_M(delta; q) = sum_alpha W[delta][alpha] c_alpha(q) from the integer
+    coefficients of an unprojected list (numpy), as {delta: {q key: value}}."""
+    c = tl.counts()
+    na = c["n_alpha"]
+    coef = tl.export(B.MB_EXPORT_COEF, dtype=np.int64)
+    row, col = coef[:na + 1], coef[na + 1:na + 1 + coef[na]]
+    val = coef[na + 1 + coef[na]:]
+    Q = tl.export(B.MB_EXPORT_QUARK, c["n_stages"] - 1).reshape(-1, 2)
+    out = {}
+    for dl in range(c["n_delta"]):
+        acc = {}
+        for a in range(na):
+            if W[dl, a] == 0.0:
+                continue
+            for e in range(row[a], row[a + 1]):
+                k = tuple(map(int, Q[col[e]]))
+                acc[k] = acc.get(k, 0.0) + W[dl, a] * float(val[e])
+        out[dl] = {k: v for k, v in acc.items() if v != 0.0}
+    return out
+
+
+def _projected_sum(tl, F):
+    c = tl.counts()
+    nd = c["n_delta"]
+    proj = tl.export(B.MB_EXPORT_PROJ, dtype=np.uint8)
+    row = proj[:8 * (nd + 1)].view(np.int64)
+    n = int(row[-1])
+    col = proj[8 * (nd + 1):8 * (nd + 1 + n)].view(np.int64)
+    val = proj[8 * (nd + 1 + n):].view(np.float64)
+    nP, nN = tl.nucleus["n_P"], tl.nucleus["n_N"]
+    tot = sum((val[row[d]:row[d + 1]] * F[col[row[d]:row[d + 1]], d]).sum() for d in range(nd))
+    return tot / (math.factorial(nP) * math.factorial(nN)), row, col, val
+
+
+def test_projection_one_hot_is_the_single_spin_state():
+    """A projection onto one (sink set, source set) pair of a one-component
+    request keeps the term list of that spin state (Sec. 8, Tables 4-6)
+    and its coefficient list."""
+    for nP, nN, rel, spins, n_lambda in [(1, 1, True, (1, 0), 2358), (2, 2, False, (0, 1, 0, 1), 10980),
+                                          (1, 2, True, (0, 0, 1), 381978)]:
+        ref = B.TermList.spin_state(nP, nN, rel, 1, spins)
+        pm = sum(1 << s for s in spins[:nP])
+        nm = sum(1 << s for s in spins[nP:])
+        tl = B.TermList(nP, nN, rel, 1, sink_P=pm, sink_N=nm, alphas=[(pm, nm)], proj=[[1.0]])
+        c, cr = tl.counts(), ref.counts()
+        assert c["projected"] and not cr["projected"]
+        assert c["n_lambda"] == cr["n_lambda"] == n_lambda
+        assert c["n_req"] == cr["n_req"] and c["n_L"] == cr["n_L"] == c["n_LM"]
+        coef = ref.export(B.MB_EXPORT_COEF, dtype=np.int64)
+        _, _, col, val = _projected_sum(tl, np.zeros((c["n_quark"][-1], 1)))
+        assert np.array_equal(col, coef[2:2 + coef[1]])
+        assert np.array_equal(val, coef[2 + coef[1]:].astype(np.float64))
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,kind", [(1, 1, False, 1, "deuteron"), (2, 1, False, 1, "sparse"),
+                                                 (1, 1, True, 1, "sparse"), (2, 2, True, 1, "sparse"),
+                                                 (1, 1, False, 2, "sparse")])
+def test_projected_list_keeps_the_support_of_LM(nP, nN, rel, nsrc, kind):
+    """The projected list L_M equals sum_alpha W c_alpha recomputed in numpy
+    from the unprojected list, and the kept final quark parts are exactly
+    those with a nonzero L_M (Sec. 5 pruning); earlier stages shrink with
+    them."""
+    full = B.TermList(nP, nN, rel, nsrc, all_components=True)
+    cf = full.counts()
+    W = (deuteron_weights(full) if kind == "deuteron"
+         else sparse_weights((cf["n_delta"], cf["n_alpha"]), 7 * nP + nN + nsrc, 0.05 if rel else 0.3))
+    tl = B.TermList(nP, nN, rel, nsrc, all_components=True, proj=W)
+    c = tl.counts()
+    want = _lm_from_coefficients(full, W)
+    keys = sorted({k for d in want.values() for k in d})
+    Q = tl.export(B.MB_EXPORT_QUARK, c["n_stages"] - 1).reshape(-1, 2)
+    assert sorted(map(tuple, Q.tolist())) == keys and c["n_U"] == len(keys)
+    _, row, col, val = _projected_sum(tl, np.zeros((len(Q), c["n_delta"])))
+    for d in range(c["n_delta"]):
+        got = {tuple(map(int, Q[col[e]])): val[e] for e in range(row[d], row[d + 1])}
+        assert got == want[d], d
+    assert c["n_LM"] == sum(len(v) for v in want.values())
+    assert c["n_lambda"] <= cf["n_lambda"]
+    assert all(a <= b for a, b in zip(c["n_req"], cf["n_req"]))
+    if kind == "sparse" and rel and nP == 2:
+        assert c["n_lambda"] < cf["n_lambda"]   # a sparse projection prunes 4He
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,kind", [(1, 1, False, 1, "deuteron"), (2, 1, False, 1, "sparse"),
+                                                 (1, 1, True, 1, "sparse"), (1, 1, False, 2, "sparse")])
+def test_projected_tables_reproduce_oracle(nP, nN, rel, nsrc, kind):
+    """The projected tables, replayed on oracle blocks, give
+    C_M = sum W[delta][alpha] C(delta; alpha) with C from the oracle's Wick
+    contraction (eq. CM_final)."""
+    from tests.gpu_helpers import oracle_blocks_lib_layout
+    rng = np.random.default_rng(3 * nP + nN + nsrc)
+    V = 2
+    Su = rng.normal(size=(V, nsrc, 12, 12)) + 1j * rng.normal(size=(V, nsrc, 12, 12))
+    w = rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))
+    full = B.TermList(nP, nN, rel, nsrc, all_components=True)
+    cf = full.counts()
+    W = (deuteron_weights(full) if kind == "deuteron"
+         else sparse_weights((cf["n_delta"], cf["n_alpha"]), 5 * nP + nN, 0.3))
+    tl = B.TermList(nP, nN, rel, nsrc, all_components=True, proj=W)
+    fP, fN = O.blocks(rel, nsrc, Su, Su, w)
+    got, _, _, _ = _projected_sum(tl, _replay_stages(tl, oracle_blocks_lib_layout(fP, fN)))
+    dsets = full.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    asets = full.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+    req = dict(sinkP=int(np.bitwise_or.reduce(dsets[:, 0])), sinkN=int(np.bitwise_or.reduce(dsets[:, 1])),
+               alphas=[tuple(map(int, a)) for a in asets])
+    ref = O.correlators(rel, nsrc, nP, nN, req, Su, Su, w)
+    R = np.array([[ref[(tuple(map(int, d)), tuple(map(int, a)))] for a in asets] for d in dsets])
+    scale = (np.abs(W) * np.abs(R)).sum()
+    assert scale > 0
+    assert abs(got - (W * R).sum()) <= 1e-12 * scale
+
+
+def test_projection_rejects_weights_that_are_not_finite():
+    full = B.TermList(1, 1, False, 1, all_components=True)
+    W = np.ones((full.counts()["n_delta"], full.counts()["n_alpha"]))
+    W[1, 2] = np.nan
+    with pytest.raises(B.MBError) as e:
+        B.TermList(1, 1, False, 1, all_components=True, proj=W)
+    assert e.value.code == B.MB_EINVAL
+    with pytest.raises(B.MBError):
+        full.export(B.MB_EXPORT_PROJ, dtype=np.uint8)   # not a projected list
