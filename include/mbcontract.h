@@ -117,6 +117,22 @@ typedef struct {
     const double *proj;
 } mb_spin_request;
 
+/* A smaller nucleus on the recursion path (Sec. 7): the nucleus of the
+ * first stage+1 baryons of the path, whose correlators are read from stage
+ * `stage` of the same recursion with their own list L, so that the stages
+ * are shared.  Its sink sets are the spin parts of that stage (every subset
+ * of the main request's sink base sets with the nucleus' baryon counts, in
+ * the order of MB_EXPORT_SPIN for that stage).
+ *   stage           0 <= stage < A - 1
+ *   all_components  every source set (as in mb_spin_request), else
+ *   alpha           [n_alpha][2] proton and neutron source sets             */
+typedef struct {
+    int stage;
+    int all_components;
+    int n_alpha;
+    const uint32_t *alpha;
+} mb_side_request;
+
 typedef struct mb_term_list mb_term_list;
 
 /* Builds the term list of a nucleus and spin request (Sec. 3-5, 7): the
@@ -141,6 +157,14 @@ int mb_build_term_list(const mb_nucleus *nuc, const mb_spin_request *req,
 int mb_build_term_list_counts_only(const mb_nucleus *nuc, const mb_spin_request *req,
                                    mb_term_list **out);
 
+/* mb_build_term_list with n_side smaller nuclei on the path (Sec. 7): every
+ * stage a side request reads also keeps the quark parts its list L needs,
+ * and the operations of the earlier steps grow accordingly (n_lambda counts
+ * them once).  The contraction writes the side correlators after the main
+ * output (see mb_contract_correlator).  MB_EUNSUPPORTED with a projection. */
+int mb_build_term_list_path(const mb_nucleus *nuc, const mb_spin_request *req, int n_side,
+                            const mb_side_request *side, mb_term_list **out);
+
 void mb_term_list_free(mb_term_list *tl);
 
 #define MB_MAX_STAGES 16
@@ -164,7 +188,9 @@ void mb_term_list_free(mb_term_list *tl);
  *   projected       1 for a projected request (one output per lane), else 0
  *   n_LM            nonzero entries of the projected list L_M (0 if not
  *                   projected); n_L then counts the entries of c on the
- *                   kept quark parts                                        */
+ *                   kept quark parts
+ *   n_side          side requests (smaller nuclei on the path)
+ *   n_out           complex outputs per lane: main output and side outputs */
 typedef struct {
     int n_stages;
     int path[MB_MAX_STAGES];
@@ -180,6 +206,8 @@ typedef struct {
     int64_t device_bytes;
     int32_t projected;
     int64_t n_LM;
+    int32_t n_side;
+    int64_t n_out;
 } mb_counts;
 
 int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
@@ -209,6 +237,10 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
  *   MB_EXPORT_PROJ   projected lists only: int64 [n_delta+1] row starts,
  *                    int64 [n_LM] final quark part indices, double [n_LM]
  *                    values of L_M(delta; z)
+ *   MB_EXPORT_SIDE   side request `stage` (its index, not a stage): int64
+ *                    stage, int64 n_alpha, then uint32 [n_alpha][2] source
+ *                    sets, then the coefficients as for MB_EXPORT_COEF with
+ *                    quark part indices of that stage
  * The block quark index of a proton split with u pair (a<b) and d index c is
  * (b*(b-1)/2 + a)*n_xi + c; of a neutron split with u index c and d pair
  * (a<b) it is c*(n_xi*(n_xi-1)/2) + b*(b-1)/2 + a.                          */
@@ -220,6 +252,7 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
 #define MB_EXPORT_DELTA 6
 #define MB_EXPORT_ALPHA 7
 #define MB_EXPORT_PROJ 8
+#define MB_EXPORT_SIDE 9
 int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
                         size_t *bytes);
 
@@ -322,7 +355,10 @@ int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
  *   corr_out  device, complex double [B][n_delta][n_alpha]; for a projected
  *             term list [B]: C_M = sum_z F_-(delta; z) L_M(delta; z) /
  *             (n_P! n_N!) summed over delta (eq. CM_final), the sum over
- *             delta in a fixed order
+ *             delta in a fixed order.  Side requests follow in order, each
+ *             [B][n_spin of its stage][its n_alpha]; a side nucleus of A_i
+ *             baryons carries the exponent 3*A_i*scale_exp[b] (exp_out holds
+ *             the main nucleus' 3*A*scale_exp[b])
  *   exp_out   device, int32 [B] or NULL: 3*A*scale_exp[b], so that the
  *             correlator of the unscaled propagators is corr_out * 2^-exp_out
  * The term list must be uploaded.                                           */

@@ -23,10 +23,10 @@ MB_MAX_STAGES = 16
 MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUNE_UNROLL, MB_TUNE_GROUP = \
     1, 2, 3, 4, 5, 6
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
- MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ) = range(1, 9)
+ MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ, MB_EXPORT_SIDE) = range(1, 10)
 
 EXPORTED_SYMBOLS = [
-    "mb_build_term_list", "mb_build_term_list_counts_only", "mb_term_list_free",
+    "mb_build_term_list", "mb_build_term_list_counts_only", "mb_build_term_list_path", "mb_term_list_free",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
     "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune",
     "mb_batch_plan", "mb_batch_create", "mb_batch_launch", "mb_batch_kernel_count", "mb_batch_free",
@@ -50,13 +50,19 @@ class mb_spin_request(C.Structure):
                 ("n_alpha", C.c_int), ("alpha", C.POINTER(C.c_uint32)), ("proj", C.POINTER(C.c_double))]
 
 
+class mb_side_request(C.Structure):
+    _fields_ = [("stage", C.c_int), ("all_components", C.c_int), ("n_alpha", C.c_int),
+                ("alpha", C.POINTER(C.c_uint32))]
+
+
 class mb_counts(C.Structure):
     _fields_ = [("n_stages", C.c_int), ("path", C.c_int * MB_MAX_STAGES), ("n_lambda", C.c_int64),
                 ("n_lambda_step", C.c_int64 * MB_MAX_STAGES), ("n_req", C.c_int64 * MB_MAX_STAGES),
                 ("n_quark", C.c_int64 * MB_MAX_STAGES), ("n_spin", C.c_int32 * MB_MAX_STAGES),
                 ("n_L", C.c_int64), ("n_U", C.c_int64), ("n_delta", C.c_int32),
                 ("n_alpha", C.c_int32), ("n_psi", C.c_int32), ("n_xi", C.c_int32),
-                ("device_bytes", C.c_int64), ("projected", C.c_int32), ("n_LM", C.c_int64)]
+                ("device_bytes", C.c_int64), ("projected", C.c_int32), ("n_LM", C.c_int64),
+                ("n_side", C.c_int32), ("n_out", C.c_int64)]
 
 
 class mb_problem(C.Structure):
@@ -85,6 +91,8 @@ def lib():
         P = C.c_void_p
         L.mb_build_term_list.argtypes = [C.POINTER(mb_nucleus), C.POINTER(mb_spin_request), C.POINTER(P)]
         L.mb_build_term_list_counts_only.argtypes = L.mb_build_term_list.argtypes
+        L.mb_build_term_list_path.argtypes = [C.POINTER(mb_nucleus), C.POINTER(mb_spin_request), C.c_int,
+                                              C.POINTER(mb_side_request), C.POINTER(P)]
         L.mb_term_list_free.argtypes = [P]
         L.mb_term_list_free.restype = None
         L.mb_term_list_counts.argtypes = [P, C.POINTER(mb_counts)]
@@ -118,10 +126,12 @@ def _check(rc):
 class TermList:
     """Owner of an mb_term_list handle.  ``proj``: optional real weights
     [n_delta][n_alpha] of the spin projection (Sec. 5), over the sink and
-    source sets of the same request without it."""
+    source sets of the same request without it.  ``sides``: smaller nuclei
+    on the path (Sec. 7), as (stage, source sets) with source sets None for
+    all of them."""
 
     def __init__(self, n_P, n_N, rel, n_src=1, *, all_components=False, sink_P=0, sink_N=0,
-                 alphas=(), path=MB_PATH_AUTO, counts_only=False, proj=None):
+                 alphas=(), path=MB_PATH_AUTO, counts_only=False, proj=None, sides=()):
         nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path)
         arr = np.ascontiguousarray(np.asarray(alphas, np.uint32).reshape(-1))
         self._alpha_keep = arr
@@ -130,8 +140,19 @@ class TermList:
                               arr.ctypes.data_as(C.POINTER(C.c_uint32)) if len(arr) else None,
                               w.ctypes.data_as(C.POINTER(C.c_double)) if w is not None else None)
         h = C.c_void_p()
-        fn = lib().mb_build_term_list_counts_only if counts_only else lib().mb_build_term_list
-        _check(fn(C.byref(nuc), C.byref(req), C.byref(h)))
+        if sides:
+            if counts_only:
+                raise ValueError("side nuclei need a full term list")
+            self._side_keep = [np.ascontiguousarray(np.asarray(a if a is not None else (), np.uint32).reshape(-1))
+                               for _, a in sides]
+            sr = (mb_side_request * len(sides))(*[
+                mb_side_request(st, int(a is None), len(k) // 2,
+                                k.ctypes.data_as(C.POINTER(C.c_uint32)) if len(k) else None)
+                for (st, a), k in zip(sides, self._side_keep)])
+            _check(lib().mb_build_term_list_path(C.byref(nuc), C.byref(req), len(sides), sr, C.byref(h)))
+        else:
+            fn = lib().mb_build_term_list_counts_only if counts_only else lib().mb_build_term_list
+            _check(fn(C.byref(nuc), C.byref(req), C.byref(h)))
         self.h = h
         self.nucleus = dict(n_P=n_P, n_N=n_N, rel=bool(rel), n_src=n_src)
         self._dev = None
@@ -162,7 +183,22 @@ class TermList:
                     n_lambda_step=list(c.n_lambda_step[:n]), n_req=list(c.n_req[:n]),
                     n_quark=list(c.n_quark[:n]), n_spin=list(c.n_spin[:n]), n_L=c.n_L, n_U=c.n_U,
                     n_delta=c.n_delta, n_alpha=c.n_alpha, n_psi=c.n_psi, n_xi=c.n_xi,
-                    device_bytes=c.device_bytes, projected=bool(c.projected), n_LM=c.n_LM)
+                    device_bytes=c.device_bytes, projected=bool(c.projected), n_LM=c.n_LM,
+                    n_side=c.n_side, n_out=c.n_out)
+
+    def side(self, i):
+        """Side request i: (stage, source sets [n][2], CSR row starts, quark
+        part indices of its stage, integer coefficients)."""
+        raw = self.export(MB_EXPORT_SIDE, i, np.uint8)
+        stage, na = (int(v) for v in raw[:16].view(np.int64))
+        o = 16 + 8 * na
+        alphas = raw[16:o].view(np.uint32).reshape(-1, 2)
+        row = raw[o:o + 8 * (na + 1)].view(np.int64)
+        n = int(row[-1])
+        o += 8 * (na + 1)
+        col = raw[o:o + 8 * n].view(np.int64)
+        val = raw[o + 8 * n:o + 16 * n].view(np.int64)
+        return stage, alphas, row, col, val
 
     def export(self, what, stage=0, dtype=np.uint32):
         n = C.c_size_t(0)

@@ -91,7 +91,8 @@ int mb_batch_create(const mb_batch_item *items, int n_items, int n_branches, mb_
     const mb_batch_item &it = items[i];
     if (it.branch < 0 || it.branch >= n_branches) return fail(MB_EINVAL, "item branch out of range");
     if (!it.tl || !it.tl->dev) return fail(MB_EINVAL, "batch item without an uploaded term list");
-    if (it.tl->projected) return fail(MB_EUNSUPPORTED, "projected term lists are not batched");
+    if (it.tl->projected || !it.tl->sides.empty())
+      return fail(MB_EUNSUPPORTED, "projected term lists and side nuclei are not batched");
     size_t bb, bw, cw;
     int rc = mb_workspace_query(it.tl, &it.prob, &bb, &bw, &cw);
     if (rc) return rc;

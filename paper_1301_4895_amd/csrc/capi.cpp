@@ -153,6 +153,25 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
   tl->off_cval = o;
   if (!val.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, val.data(), val.size() * 8, hipMemcpyHostToDevice, s));
   o += al256(val.size() * 8);
+  // the coefficients of every side nucleus, laid out the same way
+  std::vector<std::vector<int32_t>> side_col(tl->sides.size());
+  std::vector<std::vector<double>> side_val(tl->sides.size());
+  for (size_t i = 0; i < tl->sides.size(); i++) {
+    mb::Side &sd = tl->sides[i];
+    sd.off_crow = o;
+    UPLOAD_CHECK(hipMemcpyAsync(base + o, sd.crow.data(), sd.crow.size() * 8, hipMemcpyHostToDevice, s));
+    o += al256(sd.crow.size() * 8);
+    sd.off_ccol = o;
+    side_col[i].assign(sd.ccol.begin(), sd.ccol.end());
+    if (!side_col[i].empty())
+      UPLOAD_CHECK(hipMemcpyAsync(base + o, side_col[i].data(), side_col[i].size() * 4, hipMemcpyHostToDevice, s));
+    o += al256(sd.ccol.size() * 4);
+    sd.off_cval = o;
+    side_val[i].assign(sd.cval.begin(), sd.cval.end());
+    if (!side_val[i].empty())
+      UPLOAD_CHECK(hipMemcpyAsync(base + o, side_val[i].data(), side_val[i].size() * 8, hipMemcpyHostToDevice, s));
+    o += al256(sd.cval.size() * 8);
+  }
 #undef UPLOAD_CHECK
   HIP_CHECK(hipStreamSynchronize(s));
   tl->dev = dev;
@@ -268,6 +287,9 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   if (!tl->dev) return fail(MB_EINVAL, "term list not uploaded");
   if (!blocks || !ws) return fail(MB_EINVAL, "null device buffer");
   if (last_step == tl->nstages && !corr_out) return fail(MB_EINVAL, "null correlator buffer");
+  for (const mb::Side &sd : tl->sides)
+    if (sd.stage >= first_step && sd.stage <= last_step && !corr_out)
+      return fail(MB_EINVAL, "null correlator buffer (side nucleus output)");
   if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
   size_t ev, od;
   stage_buffer_sizes(tl, p, &ev, &od);
@@ -374,6 +396,29 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       } else {
         HIP_CHECK(launch_final(a, mixed, s));
       }
+    }
+    // side nuclei read from the stage just formed (before a later step
+    // overwrites its buffer): C_i = sum_z F(delta; z) c_i(alpha; z) / (k_P! k_N!)
+    for (size_t i = 0; step < tl->nstages && i < tl->sides.size(); i++) {
+      const mb::Side &sd = tl->sides[i];
+      if (sd.stage != step) continue;
+      const Stage &S = tl->st[step];
+      FinalArgs a{};
+      a.F = buf[step % 2];
+      a.crow = reinterpret_cast<const int64_t *>(img + sd.off_crow);
+      a.ccol = reinterpret_cast<const int32_t *>(img + sd.off_ccol);
+      a.cval = reinterpret_cast<const double *>(img + sd.off_cval);
+      a.corr = corr_out + 2 * p->batch * tl->side_offset(i);
+      a.exp_out = nullptr;
+      a.scale_exp = p->scale_exp;
+      a.B = p->batch;
+      a.Bp = Bp;
+      a.n_delta = int(S.nspin());
+      a.n_alpha = int(sd.alphas.size());
+      a.A = step + 1;
+      a.lane_exp = reinterpret_cast<const int32_t *>(blk + blocks_entry_bytes(tl, p));
+      a.inv_fact = 1.0 / (double(factorial(S.kP)) * double(factorial(S.kN)));
+      HIP_CHECK(launch_final(a, mixed, s));
     }
   }
   return MB_OK;

@@ -41,6 +41,14 @@ struct Stage {
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };
 
+// A smaller nucleus on the path (Sec. 7), read from stage `stage`.
+struct Side {
+  int stage = 0;
+  std::vector<std::array<uint32_t, 2>> alphas;   // source sets
+  std::vector<int64_t> crow, ccol, cval;         // c_alpha(q) on the stage's quark parts, CSR over alpha
+  size_t off_crow = 0, off_ccol = 0, off_cval = 0;
+};
+
 }  // namespace mb
 
 struct mb_term_list {
@@ -59,6 +67,10 @@ struct mb_term_list {
   bool projected = false;
   std::vector<int64_t> prow, pcol;
   std::vector<double> pval;
+  std::vector<mb::Side> sides;
+  // complex outputs per lane of the main request, and before side request i
+  int64_t main_outputs() const;
+  int64_t side_offset(size_t i) const;
   bool counts_only = false;
   // device image
   void *dev = nullptr;

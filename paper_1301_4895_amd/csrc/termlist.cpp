@@ -266,9 +266,103 @@ static inline void for_quark_splits(int type, uint32_t u, uint32_t d, F &&f) {
   }
 }
 
-static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_only,
-                 mb_term_list **out) {
+// c_alpha(q) = L^(n)(alpha; q) / (k_P! k_N!) on sorted sets for the nucleus
+// of the first n baryons of the path (k_P protons, k_N neutrons), for every
+// source set alpha in `alphas` (eq. recr_L).  The recursion antisymmetrises
+// the baryon indices too, which multiplies L on sorted sets by k_P! k_N!.
+static int source_coefficients(const mb_term_list *tl, int n, const std::vector<std::array<uint32_t, 2>> &alphas,
+                               std::vector<std::vector<std::pair<uint64_t, int64_t>>> &per_alpha) {
+  const int nsrc = tl->nsrc, npsi = tl->npsi, nxi = tl->nxi;
+  uint32_t allowP = 0, allowN = 0;
+  for (auto &a : alphas) {
+    allowP |= a[0];
+    allowN |= a[1];
+  }
+  const std::vector<GEnt> gP = g_antisym(PROTON, nsrc, npsi, nxi, allowP);
+  const std::vector<GEnt> gN = g_antisym(NEUTRON, nsrc, npsi, nxi, allowN);
+  auto wanted_spins = [&](uint32_t p, uint32_t nm) {
+    for (auto &a : alphas)
+      if (!(p & ~a[0]) && !(nm & ~a[1])) return true;
+    return false;
+  };
+  std::unordered_map<uint64_t, int64_t> L, L2;
+  for (const GEnt &g : (tl->path[0] == PROTON ? gP : gN)) {
+    uint32_t p = tl->path[0] == PROTON ? (1u << g.chi) : 0, nm = tl->path[0] == PROTON ? 0 : (1u << g.chi);
+    L[lkey(p, nm, g.u, g.d)] += g.c;
+  }
+  for (int s = 1; s < n; s++) {
+    const int T = tl->path[s];
+    const std::vector<GEnt> &G = T == PROTON ? gP : gN;
+    L2.clear();
+    L2.reserve(L.size() * 8);
+    for (auto &kv : L) {
+      uint64_t k = kv.first;
+      uint32_t p = uint32_t(k >> 56), nm = uint32_t(k >> 48) & 0xff, u = uint32_t(k >> 24) & 0xffffff,
+               d = uint32_t(k) & 0xffffff;
+      for (const GEnt &g : G) {
+        uint32_t sb = 1u << g.chi;
+        uint32_t xs = T == PROTON ? p : nm;
+        if ((xs & sb) || (u & g.u) || (d & g.d)) continue;
+        uint32_t p2 = T == PROTON ? (p | sb) : p, n2 = T == PROTON ? nm : (nm | sb);
+        if (!wanted_spins(p2, n2)) continue;
+        int sg = split_sign(xs, sb) * split_sign(u, g.u) * split_sign(d, g.d);
+        L2[lkey(p2, n2, u | g.u, d | g.d)] += sg * kv.second * g.c;
+      }
+    }
+    L.clear();
+    for (auto &kv : L2)
+      if (kv.second != 0) L.insert(kv);
+  }
+  int kP = 0, kN = 0;
+  for (int s = 0; s < n; s++) (tl->path[s] == PROTON ? kP : kN)++;
+  const int64_t norm = int64_t(factorial(kP)) * factorial(kN);
+  per_alpha.assign(alphas.size(), {});
+  std::unordered_map<uint64_t, int> aidx;
+  for (size_t i = 0; i < alphas.size(); i++) aidx[(uint64_t(alphas[i][0]) << 32) | alphas[i][1]] = int(i);
+  for (auto &kv : L) {
+    uint64_t k = kv.first;
+    uint32_t p = uint32_t(k >> 56), nm = uint32_t(k >> 48) & 0xff, u = uint32_t(k >> 24) & 0xffffff,
+             d = uint32_t(k) & 0xffffff;
+    auto it = aidx.find((uint64_t(p) << 32) | nm);
+    if (it == aidx.end()) continue;
+    if (kv.second % norm != 0) return fail(MB_EINVAL, "internal: L not divisible by k_P! k_N!");
+    per_alpha[it->second].push_back({qkey(u, d), kv.second / norm});
+  }
+  return MB_OK;
+}
+
+// Source sets of `n` baryons of one species with all spins: every n-subset
+// of the D*N_s indices with one source; with two sources, min(n, D) on
+// source 0 and the rest on source 1 (the convention of Tables 1-3).
+static std::vector<uint32_t> all_source_sets(int n, int D, int nsrc) {
+  const uint32_t all = (1u << (D * nsrc)) - 1;
+  std::vector<uint32_t> v;
+  if (nsrc == 1) {
+    for (uint32_t m = 0; m <= all; m++)
+      if (__builtin_popcount(m) == n) v.push_back(m);
+  } else {
+    int n0 = std::min(n, D), n1 = n - n0;
+    for (uint32_t m0 = 0; m0 < (1u << D); m0++) {
+      if (__builtin_popcount(m0) != n0) continue;
+      for (uint32_t m1 = 0; m1 < (1u << D); m1++) {
+        if (__builtin_popcount(m1) != n1) continue;
+        uint32_t m = 0;
+        for (int a = 0; a < D; a++) {
+          if (m0 >> a & 1) m |= 1u << (nsrc * a + 0);
+          if (m1 >> a & 1) m |= 1u << (nsrc * a + 1);
+        }
+        v.push_back(m);
+      }
+    }
+    std::sort(v.begin(), v.end());
+  }
+  return v;
+}
+
+static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, const mb_side_request *side,
+                 bool counts_only, mb_term_list **out) {
   if (!nuc || !req || !out) return fail(MB_EINVAL, "null argument");
+  if (n_side < 0 || (n_side > 0 && !side)) return fail(MB_EINVAL, "bad side requests");
   *out = nullptr;
   const int nP = nuc->n_P, nN = nuc->n_N;
   if (nP < 0 || nN < 0 || nP + nN < 1) return fail(MB_EINVAL, "need at least one baryon");
@@ -312,31 +406,8 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
   if (req->all_components) {
     tl->SP = nP ? all : 0;
     tl->SN = nN ? all : 0;
-    auto src_sets = [&](int n) {
-      std::vector<uint32_t> v;
-      if (nsrc == 1) {
-        for (uint32_t m = 0; m <= all; m++)
-          if (__builtin_popcount(m) == n) v.push_back(m);
-      } else {
-        int n0 = std::min(n, D), n1 = n - n0;
-        for (uint32_t m0 = 0; m0 < (1u << D); m0++) {
-          if (__builtin_popcount(m0) != n0) continue;
-          for (uint32_t m1 = 0; m1 < (1u << D); m1++) {
-            if (__builtin_popcount(m1) != n1) continue;
-            uint32_t m = 0;
-            for (int a = 0; a < D; a++) {
-              if (m0 >> a & 1) m |= 1u << (nsrc * a + 0);
-              if (m1 >> a & 1) m |= 1u << (nsrc * a + 1);
-            }
-            v.push_back(m);
-          }
-        }
-        std::sort(v.begin(), v.end());
-      }
-      return v;
-    };
-    for (uint32_t p : src_sets(nP))
-      for (uint32_t n : src_sets(nN)) tl->alphas.push_back({p, n});
+    for (uint32_t p : all_source_sets(nP, D, nsrc))
+      for (uint32_t n : all_source_sets(nN, D, nsrc)) tl->alphas.push_back({p, n});
   } else {
     if ((req->sink_P & ~all) || (req->sink_N & ~all))
       return fail(MB_EINVAL, "sink set has indices beyond D*N_s");
@@ -355,66 +426,13 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
   if (nP == 0) tl->SP = 0;
   if (nN == 0) tl->SN = 0;
 
-  // ---- L by the recursion L^(n+1) = L^(n) . G (eq. recr_L)
-  uint32_t allowP = 0, allowN = 0;
-  for (auto &a : tl->alphas) {
-    allowP |= a[0];
-    allowN |= a[1];
-  }
-  const std::vector<GEnt> gP = g_antisym(PROTON, nsrc, npsi, nxi, allowP);
-  const std::vector<GEnt> gN = g_antisym(NEUTRON, nsrc, npsi, nxi, allowN);
-  auto wanted_spins = [&](uint32_t p, uint32_t n) {
-    for (auto &a : tl->alphas)
-      if (!(p & ~a[0]) && !(n & ~a[1])) return true;
-    return false;
-  };
-  std::unordered_map<uint64_t, int64_t> L, L2;
-  for (const GEnt &g : (tl->path[0] == PROTON ? gP : gN)) {
-    uint32_t p = tl->path[0] == PROTON ? (1u << g.chi) : 0, n = tl->path[0] == PROTON ? 0 : (1u << g.chi);
-    L[lkey(p, n, g.u, g.d)] += g.c;
-  }
-  for (int s = 1; s < A; s++) {
-    const int T = tl->path[s];
-    const std::vector<GEnt> &G = T == PROTON ? gP : gN;
-    L2.clear();
-    L2.reserve(L.size() * 8);
-    for (auto &kv : L) {
-      uint64_t k = kv.first;
-      uint32_t p = uint32_t(k >> 56), n = uint32_t(k >> 48) & 0xff, u = uint32_t(k >> 24) & 0xffffff,
-               d = uint32_t(k) & 0xffffff;
-      for (const GEnt &g : G) {
-        uint32_t sb = 1u << g.chi;
-        uint32_t xs = T == PROTON ? p : n;
-        if ((xs & sb) || (u & g.u) || (d & g.d)) continue;
-        uint32_t p2 = T == PROTON ? (p | sb) : p, n2 = T == PROTON ? n : (n | sb);
-        if (!wanted_spins(p2, n2)) continue;
-        int sg = split_sign(xs, sb) * split_sign(u, g.u) * split_sign(d, g.d);
-        L2[lkey(p2, n2, u | g.u, d | g.d)] += sg * kv.second * g.c;
-      }
-    }
-    L.clear();
-    for (auto &kv : L2)
-      if (kv.second != 0) L.insert(kv);
+  // ---- L by the recursion L^(n+1) = L^(n) . G (eq. recr_L); c_alpha per source set
+  std::vector<std::vector<std::pair<uint64_t, int64_t>>> per_alpha;
+  {
+    const int rc = source_coefficients(tl, A, tl->alphas, per_alpha);
+    if (rc) return rc;
   }
 
-  // c_alpha(q) = L^(N)(alpha; q) / (n_P! n_N!): the recursion antisymmetrises
-  // the baryon indices too, which multiplies L on sorted sets by n_P! n_N!.
-  const int64_t norm = int64_t(factorial(nP)) * factorial(nN);
-  std::vector<std::vector<std::pair<uint64_t, int64_t>>> per_alpha(tl->alphas.size());
-  {
-    std::unordered_map<uint64_t, int> aidx;
-    for (size_t i = 0; i < tl->alphas.size(); i++)
-      aidx[(uint64_t(tl->alphas[i][0]) << 32) | tl->alphas[i][1]] = int(i);
-    for (auto &kv : L) {
-      uint64_t k = kv.first;
-      uint32_t p = uint32_t(k >> 56), n = uint32_t(k >> 48) & 0xff, u = uint32_t(k >> 24) & 0xffffff,
-               d = uint32_t(k) & 0xffffff;
-      auto it = aidx.find((uint64_t(p) << 32) | n);
-      if (it == aidx.end()) continue;
-      if (kv.second % norm != 0) return fail(MB_EINVAL, "internal: L not divisible by n_P! n_N!");
-      per_alpha[it->second].push_back({qkey(u, d), kv.second / norm});
-    }
-  }
   const bool last_d_major = tl->path[A - 1] == PROTON && A > 1;
   std::vector<uint64_t> U;
   // Projection (Sec. 5): L_M(delta; q) = sum_alpha w[delta][alpha] c_alpha(q)
@@ -480,6 +498,34 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
   }
   tl->nL = int64_t(tl->ccol.size());
 
+  // ---- smaller nuclei on the path (Sec. 7): the nucleus of the first
+  // stage+1 baryons, read from that stage with its own coefficients
+  if (n_side > 0 && tl->projected) return fail(MB_EUNSUPPORTED, "side requests with a projection");
+  std::vector<std::vector<std::vector<std::pair<uint64_t, int64_t>>>> side_coef(static_cast<size_t>(n_side));
+  for (int i = 0; i < n_side; i++) {
+    const mb_side_request &r = side[i];
+    if (r.stage < 0 || r.stage >= A - 1) return fail(MB_EINVAL, "side stage must lie before the last stage");
+    int kP = 0, kN = 0;
+    for (int s = 0; s <= r.stage; s++) (tl->path[s] == PROTON ? kP : kN)++;
+    Side sd;
+    sd.stage = r.stage;
+    if (r.all_components) {
+      for (uint32_t p : all_source_sets(kP, D, nsrc))
+        for (uint32_t n : all_source_sets(kN, D, nsrc)) sd.alphas.push_back({p, n});
+    } else {
+      if (r.n_alpha < 1 || !r.alpha) return fail(MB_EINVAL, "side request without source sets");
+      for (int j = 0; j < r.n_alpha; j++) {
+        uint32_t p = r.alpha[2 * j], n = r.alpha[2 * j + 1];
+        if ((p & ~all) || (n & ~all) || __builtin_popcount(p) != kP || __builtin_popcount(n) != kN)
+          return fail(MB_EINVAL, "side source set with wrong indices or size");
+        sd.alphas.push_back({p, n});
+      }
+    }
+    const int rc = source_coefficients(tl, r.stage + 1, sd.alphas, side_coef[i]);
+    if (rc) return rc;
+    tl->sides.push_back(std::move(sd));
+  }
+
   // ---- stages
   tl->st.resize(A);
   {
@@ -505,6 +551,11 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
       uint32_t u = qkey_u(q), d = qkey_d(q);
       for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(u & ~yu, d & ~yd)); });
     }
+    // the quark parts that side nuclei read from stage s - 1
+    for (size_t i = 0; i < tl->sides.size(); i++)
+      if (tl->sides[i].stage == s - 1)
+        for (auto &v : side_coef[i])
+          for (auto &e : v) X.insert(e.first);
     P.quark = X.sorted();
     const bool pd = P.type == PROTON && s - 1 > 0;
     sort_stage(P.quark, pd);
@@ -530,6 +581,24 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, bool counts_
       }
     }
   }
+  // side coefficients as CSR over their source sets, columns in the order of
+  // their stage
+  for (size_t i = 0; i < tl->sides.size(); i++) {
+    Side &sd = tl->sides[i];
+    const int j = sd.stage;
+    const bool dm = tl->path[j] == PROTON && j > 0;
+    sd.crow.assign(1, 0);
+    for (auto &v : side_coef[i]) {
+      std::vector<std::pair<uint32_t, int64_t>> row;
+      for (auto &e : v) row.push_back({find_stage(tl->st[j].quark, dm, e.first), e.second});
+      std::sort(row.begin(), row.end());
+      for (auto &e : row) {
+        sd.ccol.push_back(e.first);
+        sd.cval.push_back(e.second);
+      }
+      sd.crow.push_back(int64_t(sd.ccol.size()));
+    }
+  }
   {
     Stage &S0 = tl->st[0];
     if (!counts_only) {
@@ -553,7 +622,18 @@ size_t mb_term_list::image_bytes() const {
   o += al(st[0].first.size() * 4);
   if (projected) o += al(prow.size() * 8) + al(pcol.size() * 4) + al(pval.size() * 8);
   else o += al(crow.size() * 8) + al(ccol.size() * 4) + al(cval.size() * 8);
+  for (const mb::Side &sd : sides) o += al(sd.crow.size() * 8) + al(sd.ccol.size() * 4) + al(sd.cval.size() * 8);
   return o + 256;
+}
+
+int64_t mb_term_list::main_outputs() const {
+  return projected ? 1 : st.back().nspin() * int64_t(alphas.size());
+}
+
+int64_t mb_term_list::side_offset(size_t i) const {
+  int64_t o = main_outputs();
+  for (size_t j = 0; j < i; j++) o += st[sides[j].stage].nspin() * int64_t(sides[j].alphas.size());
+  return o;
 }
 
 using namespace mb;
@@ -562,7 +642,7 @@ extern "C" {
 
 int mb_build_term_list(const mb_nucleus *nuc, const mb_spin_request *req, mb_term_list **out) {
   try {
-    return build(nuc, req, false, out);
+    return build(nuc, req, 0, nullptr, false, out);
   } catch (const std::bad_alloc &) {
     return fail(MB_ENOMEM, "out of host memory");
   }
@@ -571,7 +651,16 @@ int mb_build_term_list(const mb_nucleus *nuc, const mb_spin_request *req, mb_ter
 int mb_build_term_list_counts_only(const mb_nucleus *nuc, const mb_spin_request *req,
                                    mb_term_list **out) {
   try {
-    return build(nuc, req, true, out);
+    return build(nuc, req, 0, nullptr, true, out);
+  } catch (const std::bad_alloc &) {
+    return fail(MB_ENOMEM, "out of host memory");
+  }
+}
+
+int mb_build_term_list_path(const mb_nucleus *nuc, const mb_spin_request *req, int n_side,
+                            const mb_side_request *side, mb_term_list **out) {
+  try {
+    return build(nuc, req, n_side, side, false, out);
   } catch (const std::bad_alloc &) {
     return fail(MB_ENOMEM, "out of host memory");
   }
@@ -601,13 +690,19 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *c) {
   c->device_bytes = int64_t(tl->image_bytes());
   c->projected = tl->projected ? 1 : 0;
   c->n_LM = int64_t(tl->pcol.size());
+  c->n_side = int32_t(tl->sides.size());
+  c->n_out = tl->side_offset(tl->sides.size());
   return MB_OK;
 }
 
 int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, size_t *bytes) {
   if (!tl || !bytes) return fail(MB_EINVAL, "null argument");
-  if (stage < 0 || stage >= tl->nstages) return fail(MB_EINVAL, "bad stage");
-  const Stage &S = tl->st[stage];
+  if (what == MB_EXPORT_SIDE) {
+    if (stage < 0 || size_t(stage) >= tl->sides.size()) return fail(MB_EINVAL, "no such side request");
+  } else if (stage < 0 || stage >= tl->nstages) {
+    return fail(MB_EINVAL, "bad stage");
+  }
+  const Stage &S = tl->st[what == MB_EXPORT_SIDE ? 0 : stage];
   std::vector<uint8_t> tmp;
   auto put = [&](const void *p, size_t n) {
     size_t o = tmp.size();
@@ -683,6 +778,16 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, 
     case MB_EXPORT_ALPHA:
       for (auto &a : tl->alphas) put(a.data(), 8);
       break;
+    case MB_EXPORT_SIDE: {
+      const Side &sd = tl->sides[size_t(stage)];
+      const int64_t hd[2] = {sd.stage, int64_t(sd.alphas.size())};
+      put(hd, 16);
+      for (auto &a : sd.alphas) put(a.data(), 8);
+      put(sd.crow.data(), sd.crow.size() * 8);
+      put(sd.ccol.data(), sd.ccol.size() * 8);
+      put(sd.cval.data(), sd.cval.size() * 8);
+      break;
+    }
     case MB_EXPORT_PROJ:
       if (!tl->projected) return fail(MB_EINVAL, "not a projected term list");
       put(tl->prow.data(), tl->prow.size() * 8);

@@ -28,8 +28,17 @@ class Runner:
         self.bws = torch.empty(max(nbw, 1), dtype=torch.uint8, device=dev)
         self.cws = torch.empty(max(ncw, 1), dtype=torch.uint8, device=dev)
         c = tl.counts()
-        shape = (self.batch, 1, 1) if c["projected"] else (self.batch, c["n_delta"], c["n_alpha"])
-        self.corr = torch.empty(shape, dtype=torch.complex128, device=dev)
+        # main output, then the side nuclei's outputs, each [batch][rows][columns]
+        self.out = torch.empty(self.batch * c["n_out"], dtype=torch.complex128, device=dev)
+        shape = (1, 1) if c["projected"] else (c["n_delta"], c["n_alpha"])
+        self.corr = self.out[:self.batch * shape[0] * shape[1]].view(self.batch, *shape)
+        self.side_corr = []
+        off = self.batch * shape[0] * shape[1]
+        for i in range(c["n_side"]):
+            stage, alphas, *_ = tl.side(i)
+            n = self.batch * c["n_spin"][stage] * len(alphas)
+            self.side_corr.append(self.out[off:off + n].view(self.batch, c["n_spin"][stage], len(alphas)))
+            off += n
         self.exp = torch.empty(self.batch, dtype=torch.int32, device=dev)
 
     def set_props(self, props_u, props_d, scale_exp=None):
@@ -45,7 +54,7 @@ class Runner:
         B.make_blocks(self.tl, self.p, self.blocks, self.bws, stream)
 
     def run_contract(self, stream=None):
-        B.contract_correlator(self.tl, self.p, self.blocks, self.corr, self.exp, self.cws, stream)
+        B.contract_correlator(self.tl, self.p, self.blocks, self.out, self.exp, self.cws, stream)
 
     def run(self, stream=None):
         self.run_blocks(stream)

@@ -293,3 +293,56 @@ def test_projected_correlator_matches_oracle(rel, nsrc, nP, nN, V, nl, kind):
             assert scale > 0
             assert abs(cp[b, 0, 0] - (W * R).sum()) <= tol * scale, (prec, b)
             assert abs(cp[b, 0, 0] - (W * cfull[b]).sum()) <= tol * scale, (prec, b)
+
+
+# --------------------------------------------------------------------- smaller nuclei on the path (Sec. 7)
+
+SIDE_CASES = [
+    # rel, nsrc, nP, nN, sides (stage, source sets), V, lanes
+    (False, 1, 2, 1, [(0, None), (1, None)], 8, 2),   # 3He with p and pp
+    (False, 1, 2, 2, [(2, None)], 8, 2),              # 4He NR with 3H
+    (True, 1, 1, 1, [(0, None)], 8, 1),               # p+n relativistic with n
+    (False, 2, 1, 1, [(0, None)], 8, 2),              # p+n, two sources, with n
+]
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,sides,V,nl", SIDE_CASES)
+def test_side_nuclei_match_oracle(rel, nsrc, nP, nN, sides, V, nl):
+    """Correlators of the smaller nuclei on the path, read from the shared
+    stages, match the oracle's Wick contraction of each smaller nucleus; the
+    main correlator matches the list without side nuclei."""
+    Su, Sd, w, k = _inputs(41 + nP + nN, nl, V, nsrc, np.complex128, True, with_sink=nsrc == 2)
+    tl = B.TermList(nP, nN, rel, nsrc, all_components=True, sides=sides)
+    main = B.TermList(nP, nN, rel, nsrc, all_components=True)
+    c = tl.counts()
+    _, cmain, _ = _run(main, Su, Sd, w, k, B.MB_FP64)
+    tu = torch.from_numpy(np.ascontiguousarray(Su)).to(DEV)
+    tw = None if w is None else torch.from_numpy(np.ascontiguousarray(w)).to(DEV)
+    tk = torch.from_numpy(k).to(DEV)
+    refs = []
+    for i, (stage, _) in enumerate(sides):
+        _, alphas, *_ = tl.side(i)
+        kP = sum(1 for t in c["path"][:stage + 1] if t == 0)
+        kN = stage + 1 - kP
+        dsets = tl.export(B.MB_EXPORT_SPIN, stage).reshape(-1, 2)
+        req = dict(sinkP=int(np.bitwise_or.reduce(dsets[:, 0])), sinkN=int(np.bitwise_or.reduce(dsets[:, 1])),
+                   alphas=[tuple(map(int, a)) for a in alphas])
+        per_lane = []
+        for b in range(nl):
+            ref = O.correlators(rel, nsrc, kP, kN, req, Su[b], Sd[b], w, 2.0 ** int(k[b]))
+            per_lane.append(np.array([[ref[(tuple(map(int, d)), tuple(map(int, a)))] for a in alphas]
+                                      for d in dsets]))
+        refs.append(per_lane)
+    for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)]:
+        r = Runner(tl, tu, tu, prec, tw, tk)
+        corr, ex = r.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(ex.cpu().numpy(), 3 * (nP + nN) * k)
+        got_main = corr.cpu().numpy()
+        for b in range(nl):
+            assert rel_err(got_main[b], cmain[b]) <= tol, (prec, b)
+        for i in range(len(sides)):
+            got = r.side_corr[i].cpu().numpy()
+            for b in range(nl):
+                assert np.linalg.norm(refs[i][b]) > 0
+                assert rel_err(got[b], refs[i][b]) <= tol, (prec, i, b)

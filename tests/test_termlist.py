@@ -257,8 +257,9 @@ def _replay_tables(tl, fb):
     return _final_sum(tl, _replay_stages(tl, fb))
 
 
-def _replay_stages(tl, fb):
-    """The last stage F[final quark part][sink set] from the exported tables."""
+def _replay_stages(tl, fb, upto=None):
+    """Stage `upto` (default: the last) F[quark part][spin part] from the
+    exported tables."""
     c = tl.counts()
     nxi = c["n_xi"]
     pr = {(a, b): i for i, (a, b) in enumerate(_pairs(nxi))}
@@ -273,7 +274,8 @@ def _replay_stages(tl, fb):
         for si, (p, n) in enumerate(S0):
             psi = O._bits(int(p if T0 == 0 else n))[0]
             F[qi, si] = fb[T0][psi, y]
-    for s in range(1, c["n_stages"]):
+    last = c["n_stages"] - 1 if upto is None else upto
+    for s in range(1, last + 1):
         T = c["path"][s]
         qs = tl.export(B.MB_EXPORT_QSPLIT, s).reshape(c["n_quark"][s], -1, 2)
         ss = tl.export(B.MB_EXPORT_SSPLIT, s, np.int32).reshape(c["n_spin"][s], -1, 3)
@@ -509,3 +511,102 @@ def test_projection_rejects_weights_that_are_not_finite():
     assert e.value.code == B.MB_EINVAL
     with pytest.raises(B.MBError):
         full.export(B.MB_EXPORT_PROJ, dtype=np.uint8)   # not a projected list
+
+
+# ----------------------------------------------------------------- smaller nuclei on the path (Sec. 7)
+
+def _keyed(coef_rows, Q):
+    """{alpha index: {(u mask, d mask): c}} from CSR rows over a quark list."""
+    row, col, val = coef_rows
+    return [{tuple(map(int, Q[col[e]])): int(val[e]) for e in range(row[a], row[a + 1])}
+            for a in range(len(row) - 1)]
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,sides", [
+    (2, 2, True, 1, [(2, None), (1, None)]),       # 4He relativistic with 3H and nn on its path
+    (2, 2, False, 1, [(2, None)]),                 # 4He NR with 3H
+    (2, 1, False, 1, [(0, None), (1, None)]),      # 3He with p and pp
+    (1, 1, False, 2, [(0, None)]),                 # p+n, two sources, with n
+])
+def test_side_nuclei_coefficients_match_their_own_lists(nP, nN, rel, nsrc, sides):
+    """A smaller nucleus read from a stage of the path has the coefficients
+    c_alpha(z) of its own term list (same source sets, same order), and the
+    combined list costs more than the main list alone but less than the
+    two lists built separately (Sec. 7)."""
+    tl = B.TermList(nP, nN, rel, nsrc, all_components=True, sides=sides)
+    main = B.TermList(nP, nN, rel, nsrc, all_components=True)
+    c, cm = tl.counts(), main.counts()
+    assert c["n_side"] == len(sides)
+    # the main list's coefficients and final quark parts are unchanged
+    assert np.array_equal(tl.export(B.MB_EXPORT_COEF, dtype=np.int64), main.export(B.MB_EXPORT_COEF, dtype=np.int64))
+    assert np.array_equal(tl.export(B.MB_EXPORT_QUARK, c["n_stages"] - 1), main.export(B.MB_EXPORT_QUARK, cm["n_stages"] - 1))
+    separate = cm["n_lambda"]
+    n_out = cm["n_delta"] * cm["n_alpha"]
+    for i, (stage, _) in enumerate(sides):
+        st, alphas, row, col, val = tl.side(i)
+        assert st == stage
+        kP = sum(1 for t in c["path"][:stage + 1] if t == 0)
+        kN = stage + 1 - kP
+        own = B.TermList(kP, kN, rel, nsrc, all_components=True)
+        co = own.counts()
+        assert np.array_equal(alphas, own.export(B.MB_EXPORT_ALPHA).reshape(-1, 2))
+        Qs = tl.export(B.MB_EXPORT_QUARK, stage).reshape(-1, 2)
+        Qo = own.export(B.MB_EXPORT_QUARK, co["n_stages"] - 1).reshape(-1, 2)
+        oc = own.export(B.MB_EXPORT_COEF, dtype=np.int64)
+        na = co["n_alpha"]
+        orow, ocol = oc[:na + 1], oc[na + 1:na + 1 + oc[na]]
+        oval = oc[na + 1 + oc[na]:]
+        assert _keyed((row, col, val), Qs) == _keyed((orow, ocol, oval), Qo)
+        # the side's sink sets are the spin parts of its stage, in its own list's order
+        assert np.array_equal(tl.export(B.MB_EXPORT_SPIN, stage), own.export(B.MB_EXPORT_DELTA))
+        separate += co["n_lambda"]
+        n_out += c["n_spin"][stage] * na
+    assert cm["n_lambda"] <= c["n_lambda"] <= separate
+    assert c["n_out"] == n_out
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,sides", [
+    (2, 1, False, 1, [(0, None), (1, None)]),
+    (1, 1, True, 1, [(0, None)]),
+    (1, 1, False, 2, [(0, None)]),
+])
+def test_side_nuclei_tables_reproduce_oracle(nP, nN, rel, nsrc, sides):
+    """Side correlators read from the replayed stages of the combined list
+    equal the oracle's Wick contraction of the smaller nucleus, and the main
+    correlator is unchanged."""
+    from tests.gpu_helpers import oracle_blocks_lib_layout
+    rng = np.random.default_rng(11 * nP + nN + nsrc)
+    V = 2
+    Su = rng.normal(size=(V, nsrc, 12, 12)) + 1j * rng.normal(size=(V, nsrc, 12, 12))
+    w = rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))
+    tl = B.TermList(nP, nN, rel, nsrc, all_components=True, sides=sides)
+    c = tl.counts()
+    fP, fN = O.blocks(rel, nsrc, Su, Su, w)
+    fb = oracle_blocks_lib_layout(fP, fN)
+    for i, (stage, _) in enumerate(sides):
+        _, alphas, row, col, val = tl.side(i)
+        kP = sum(1 for t in c["path"][:stage + 1] if t == 0)
+        kN = stage + 1 - kP
+        F = _replay_stages(tl, fb, stage)
+        got = np.stack([(val[row[a]:row[a + 1], None] * F[col[row[a]:row[a + 1]], :]).sum(0)
+                        for a in range(len(alphas))], 1) / (math.factorial(kP) * math.factorial(kN))
+        dsets = tl.export(B.MB_EXPORT_SPIN, stage).reshape(-1, 2)
+        req = dict(sinkP=int(np.bitwise_or.reduce(dsets[:, 0])), sinkN=int(np.bitwise_or.reduce(dsets[:, 1])),
+                   alphas=[tuple(map(int, a)) for a in alphas])
+        ref = O.correlators(rel, nsrc, kP, kN, req, Su, Su, w)
+        R = np.array([[ref[(tuple(map(int, d)), tuple(map(int, a)))] for a in alphas] for d in dsets])
+        assert np.linalg.norm(R) > 0
+        assert np.linalg.norm(got - R) <= 1e-12 * np.linalg.norm(R), i
+    main = B.TermList(nP, nN, rel, nsrc, all_components=True)
+    R = _replay_tables(main, fb)
+    assert np.linalg.norm(_replay_tables(tl, fb) - R) <= 1e-13 * np.linalg.norm(R)
+
+
+def test_side_requests_are_validated():
+    with pytest.raises(B.MBError):
+        B.TermList(2, 2, False, 1, all_components=True, sides=[(3, None)])   # the last stage is the main nucleus
+    with pytest.raises(B.MBError):
+        B.TermList(2, 2, False, 1, all_components=True, sides=[(1, [(1, 0)])])   # stage 1 is nn: no proton
+    with pytest.raises(B.MBError) as e:
+        B.TermList(2, 2, False, 1, sink_P=3, sink_N=3, alphas=[(3, 3)], proj=np.ones((1, 1)), sides=[(1, None)])
+    assert e.value.code == B.MB_EUNSUPPORTED
