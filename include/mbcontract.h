@@ -61,6 +61,8 @@ extern "C" {
 #define MB_PATH_AUTO 0         /* more numerous species first, neutrons on a tie (Sec. 7) */
 #define MB_PATH_PROTONS_FIRST 1
 #define MB_PATH_NEUTRONS_FIRST 2
+#define MB_PATH_EXPLICIT 3     /* the order given in mb_nucleus.order */
+#define MB_PATH_BEST 4         /* the order with the fewest operations (below) */
 
 #define MB_C64 0               /* complex float (re, im)   */
 #define MB_C128 1              /* complex double (re, im)  */
@@ -75,13 +77,23 @@ extern "C" {
  *   rel    1: Gamma_1 = 1, Gamma_2 = C gamma_5; 0: the nonrelativistic
  *          Gamma_1 = P_nr, Gamma_2 = C gamma_5 P_nr (Dirac representation).
  *   n_src  number of orthogonal quark sources N_s (Sec. 6), 1 or 2.
- *   path   order of the recursion (MB_PATH_*); all baryons of the first
- *          species are added before any of the second.                       */
+ *   path   order of the recursion (MB_PATH_*).  AUTO, PROTONS_FIRST and
+ *          NEUTRONS_FIRST add all baryons of one species before the other.
+ *          EXPLICIT: bit i of `order` set means that the (i+1)-th baryon added
+ *          is a proton (n_P bits among the low n_P + n_N).  BEST: of every
+ *          order (C(A, n_P) of them) the one with the fewest operations
+ *          n_lambda for this request (Sec. 7: the best path is decided case by
+ *          case); ties go to the AUTO order, then to the smaller mask.  The
+ *          search counts the required sets of every order backwards from the
+ *          final ones, without operation tables; MB_EUNSUPPORTED with side
+ *          requests.  The correlators do not depend on the order.
+ *   order  see EXPLICIT (ignored otherwise)                                   */
 typedef struct {
     int n_P, n_N;
     int rel;
     int n_src;
     int path;
+    uint32_t order;
 } mb_nucleus;
 
 /* Which components of C(delta set; alpha set) are wanted (Sec. 5, Sec. 8).

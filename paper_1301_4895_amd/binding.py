@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmbcontract.so")
 
 MB_OK, MB_EINVAL, MB_EPAULI, MB_EUNSUPPORTED, MB_ENOWORKSPACE, MB_EHIP, MB_ENOMEM = 0, -1, -2, -3, -4, -5, -6
-MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST = 0, 1, 2
+MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST, MB_PATH_EXPLICIT, MB_PATH_BEST = 0, 1, 2, 3, 4
 MB_C64, MB_C128 = 0, 1
 MB_FP64, MB_MIXED = 0, 1
 MB_MAX_STAGES = 16
@@ -42,7 +42,7 @@ class MBError(RuntimeError):
 
 class mb_nucleus(C.Structure):
     _fields_ = [("n_P", C.c_int), ("n_N", C.c_int), ("rel", C.c_int), ("n_src", C.c_int),
-                ("path", C.c_int)]
+                ("path", C.c_int), ("order", C.c_uint32)]
 
 
 class mb_spin_request(C.Structure):
@@ -128,11 +128,12 @@ class TermList:
     [n_delta][n_alpha] of the spin projection (Sec. 5), over the sink and
     source sets of the same request without it.  ``sides``: smaller nuclei
     on the path (Sec. 7), as (stage, source sets) with source sets None for
-    all of them."""
+    all of them.  ``order``: with path MB_PATH_EXPLICIT, bit i set when the
+    (i+1)-th baryon added is a proton."""
 
     def __init__(self, n_P, n_N, rel, n_src=1, *, all_components=False, sink_P=0, sink_N=0,
-                 alphas=(), path=MB_PATH_AUTO, counts_only=False, proj=None, sides=()):
-        nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path)
+                 alphas=(), path=MB_PATH_AUTO, order=0, counts_only=False, proj=None, sides=()):
+        nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path, order)
         arr = np.ascontiguousarray(np.asarray(alphas, np.uint32).reshape(-1))
         self._alpha_keep = arr
         w = None if proj is None else np.ascontiguousarray(np.asarray(proj, np.float64).reshape(-1))

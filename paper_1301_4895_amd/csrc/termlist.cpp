@@ -359,17 +359,81 @@ static std::vector<uint32_t> all_source_sets(int n, int D, int nsrc) {
   return v;
 }
 
+// Operations of every step for the recursion order `path`, counted from the
+// final quark parts backwards (the required sets of each stage are the
+// sub-tuples of the next one's), without operation tables.
+static int64_t path_operations(const std::vector<uint64_t> &U, const int *path, int A, uint32_t SP, uint32_t SN) {
+  int kP[MB_MAX_STAGES], kN[MB_MAX_STAGES];
+  for (int s = 0, p = 0, n = 0; s < A; s++) {
+    (path[s] == PROTON ? p : n)++;
+    kP[s] = p;
+    kN[s] = n;
+  }
+  std::vector<uint64_t> cur = U;
+  int64_t total = 0;
+  for (int s = A - 1; s >= 1; s--) {
+    const int T = path[s];
+    const int ku = 2 * kP[s] + kN[s], kd = kP[s] + 2 * kN[s];
+    const int64_t Sq = T == PROTON ? int64_t(binom(ku, 2)) * kd : int64_t(ku) * binom(kd, 2);
+    const int64_t nspin = int64_t(binom(__builtin_popcount(SP), kP[s])) * binom(__builtin_popcount(SN), kN[s]);
+    total += nspin * int64_t(cur.size()) * (T == PROTON ? kP[s] : kN[s]) * Sq;
+    KeySet X(cur.size() * 4 + 16);
+    for (uint64_t q : cur) {
+      const uint32_t u = qkey_u(q), d = qkey_d(q);
+      for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(u & ~yu, d & ~yd)); });
+    }
+    cur = X.sorted();
+  }
+  return total;
+}
+
 static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, const mb_side_request *side,
                  bool counts_only, mb_term_list **out) {
   if (!nuc || !req || !out) return fail(MB_EINVAL, "null argument");
   if (n_side < 0 || (n_side > 0 && !side)) return fail(MB_EINVAL, "bad side requests");
+  if (nuc->path == MB_PATH_BEST) {
+    // the final required quark parts do not depend on the order (only signs
+    // of L do): take them from the AUTO order, count every order, then build
+    // the best one
+    if (n_side > 0) return fail(MB_EUNSUPPORTED, "order search with side requests");
+    mb_nucleus n2 = *nuc;
+    n2.path = MB_PATH_AUTO;
+    mb_term_list *probe = nullptr;
+    int rc = build(&n2, req, 0, nullptr, true, &probe);
+    if (rc) return rc;
+    std::unique_ptr<mb_term_list> pg(probe);
+    const int A = probe->A;
+    uint32_t auto_mask = 0;
+    for (int i = 0; i < A; i++)
+      if (probe->path[i] == PROTON) auto_mask |= 1u << i;
+    int path[MB_MAX_STAGES];
+    auto ops = [&](uint32_t m) {
+      for (int i = 0; i < A; i++) path[i] = (m >> i & 1) ? PROTON : NEUTRON;
+      return path_operations(probe->st[A - 1].quark, path, A, probe->SP, probe->SN);
+    };
+    uint32_t best = auto_mask;
+    int64_t best_ops = ops(auto_mask);
+    for (uint32_t m = 0; m < (1u << A); m++) {
+      if (__builtin_popcount(m) != nuc->n_P || m == auto_mask) continue;
+      const int64_t o = ops(m);
+      if (o < best_ops) {
+        best_ops = o;
+        best = m;
+      }
+    }
+    n2.path = MB_PATH_EXPLICIT;
+    n2.order = best;
+    rc = build(&n2, req, 0, nullptr, counts_only, out);
+    if (rc == MB_OK) (*out)->nuc.path = MB_PATH_BEST;
+    return rc;
+  }
   *out = nullptr;
   const int nP = nuc->n_P, nN = nuc->n_N;
   if (nP < 0 || nN < 0 || nP + nN < 1) return fail(MB_EINVAL, "need at least one baryon");
   if (nP + nN > MB_MAX_STAGES) return fail(MB_EUNSUPPORTED, "more than 16 baryons");
   if (nuc->rel != 0 && nuc->rel != 1) return fail(MB_EINVAL, "rel must be 0 or 1");
   if (nuc->n_src != 1 && nuc->n_src != 2) return fail(MB_EUNSUPPORTED, "n_src must be 1 or 2");
-  if (nuc->path < 0 || nuc->path > 2) return fail(MB_EINVAL, "bad path");
+  if (nuc->path < 0 || nuc->path > MB_PATH_EXPLICIT) return fail(MB_EINVAL, "bad path");
   const int D = nuc->rel ? 4 : 2, nsrc = nuc->n_src;
   const int npsi = D * nsrc, nxi = 3 * D * nsrc;
   const int nu = 2 * nP + nN, nd = nP + 2 * nN;
@@ -395,11 +459,15 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
               : (nN >= nP ? NEUTRON : PROTON);
   if (first == PROTON && nP == 0) first = NEUTRON;
   if (first == NEUTRON && nN == 0) first = PROTON;
-  {
+  if (nuc->path == MB_PATH_EXPLICIT) {
+    if ((A < 32 && (nuc->order >> A) != 0) || __builtin_popcount(nuc->order) != nP)
+      return fail(MB_EINVAL, "order must mark n_P of the first n_P + n_N baryons as protons");
+    for (int i = 0; i < A; i++) tl->path[i] = (nuc->order >> i & 1) ? PROTON : NEUTRON;
+  } else {
     int nf = first == PROTON ? nP : nN;
     for (int i = 0; i < A; i++) tl->path[i] = i < nf ? first : 1 - first;
-    tl->nstages = A;
   }
+  tl->nstages = A;
 
   // spin request
   const uint32_t all = (1u << npsi) - 1;

@@ -346,3 +346,33 @@ def test_side_nuclei_match_oracle(rel, nsrc, nP, nN, sides, V, nl):
             for b in range(nl):
                 assert np.linalg.norm(refs[i][b]) > 0
                 assert rel_err(got[b], refs[i][b]) <= tol, (prec, i, b)
+
+
+# --------------------------------------------------------------------- recursion orders (Sec. 7)
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins,order,V,nl", [
+    (False, 1, 2, 1, None, 0b101, 8, 2),              # 3He as P N P
+    (False, 1, 2, 2, (0, 1, 0, 1), 0b1010, 27, 2),    # 4He NR as N P N P
+    (True, 1, 1, 2, (0, 0, 1), 0b010, 8, 1),          # 3H relativistic as N P N
+    (False, 2, 2, 2, (0, 2, 0, 2), 0b0110, 8, 1),     # 4He NR, two sources, as N P P N
+])
+def test_interleaved_order_matches_oracle(rel, nsrc, nP, nN, spins, order, V, nl):
+    """A recursion that alternates the species (every step kind reached from
+    stages of mixed content) gives the oracle's correlators and those of the
+    default order, in both precision modes."""
+    Su, Sd, w, k = _inputs(51 + order, nl, V, nsrc, np.complex128, True, with_sink=nsrc == 2)
+    ref_tl = _tl(rel, nsrc, nP, nN, spins)
+    if spins is None:
+        tl = B.TermList(nP, nN, rel, nsrc, all_components=True, path=B.MB_PATH_EXPLICIT, order=order)
+    else:
+        tl = B.TermList.spin_state(nP, nN, rel, nsrc, spins, path=B.MB_PATH_EXPLICIT, order=order)
+    assert tl.counts()["path"] == [0 if (order >> i) & 1 else 1 for i in range(nP + nN)]
+    _, cref, _ = _run(ref_tl, Su, Sd, w, k, B.MB_FP64)
+    for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-6)]:
+        _, corr, ex = _run(tl, Su, Sd, w, k, prec)
+        assert np.array_equal(ex, 3 * (nP + nN) * k)
+        for b in range(nl):
+            assert rel_err(corr[b], cref[b]) <= tol, (prec, b)
+            if prec == B.MB_FP64:
+                ref = _oracle_corr(tl, rel, nsrc, nP, nN, Su[b], Sd[b], w, k[b])
+                assert rel_err(corr[b], ref) <= 1e-12, b

@@ -610,3 +610,90 @@ def test_side_requests_are_validated():
     with pytest.raises(B.MBError) as e:
         B.TermList(2, 2, False, 1, sink_P=3, sink_N=3, alphas=[(3, 3)], proj=np.ones((1, 1)), sides=[(1, None)])
     assert e.value.code == B.MB_EUNSUPPORTED
+
+
+# ----------------------------------------------------------------- recursion orders (Sec. 7)
+
+def _masks(A, nP):
+    return [m for m in range(1 << A) if bin(m).count("1") == nP]
+
+
+def test_explicit_orders_of_3he():
+    """3He (2,1) with all components: adding the protons first (PPN) costs
+    6048 operations, the mirror of Table 2's (1,2) row; neutron first (NPP)
+    15480.  PNP costs the same as NPP: required sets depend only on the
+    number of baryons of each species in a stage, so both orders have the
+    same stages and steps of equal size (one proton and one neutron, then a
+    proton).  The order search picks PPN."""
+    n = {}
+    for m in _masks(3, 2):
+        tl = B.TermList(2, 1, False, 1, all_components=True, path=B.MB_PATH_EXPLICIT, order=m, counts_only=True)
+        c = tl.counts()
+        assert c["path"] == [0 if (m >> i) & 1 else 1 for i in range(3)]
+        n[m] = c["n_lambda"]
+    assert n[0b011] == 6048 and n[0b110] == 15480 == n[0b101]
+    best = B.TermList(2, 1, False, 1, all_components=True, path=B.MB_PATH_BEST, counts_only=True).counts()
+    assert best["path"] == [0, 0, 1] and best["n_lambda"] == 6048
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,spins", [(2, 2, True, 1, None), (2, 2, False, 1, (0, 1, 0, 1)),
+                                                 (1, 2, True, 1, (0, 0, 1)), (2, 3, False, 2, None),
+                                                 (1, 3, False, 2, None)])
+def test_order_search_finds_the_fewest_operations(nP, nN, rel, nsrc, spins):
+    """The searched order's count equals the minimum over every order built
+    explicitly (full builds count their operation tables independently of
+    the search's backward count)."""
+    kw = dict(all_components=True) if spins is None else dict(
+        sink_P=sum(1 << s for s in spins[:nP]), sink_N=sum(1 << s for s in spins[nP:]),
+        alphas=[(sum(1 << s for s in spins[:nP]), sum(1 << s for s in spins[nP:]))])
+    counts = {}
+    for m in _masks(nP + nN, nP):
+        counts[m] = B.TermList(nP, nN, rel, nsrc, path=B.MB_PATH_EXPLICIT, order=m, counts_only=True,
+                               **kw).counts()["n_lambda"]
+    best = B.TermList(nP, nN, rel, nsrc, path=B.MB_PATH_BEST, counts_only=True, **kw).counts()
+    m_best = sum(1 << i for i, t in enumerate(best["path"]) if t == 0)
+    assert best["n_lambda"] == counts[m_best] == min(counts.values())
+    auto = B.TermList(nP, nN, rel, nsrc, counts_only=True, **kw).counts()
+    assert best["n_lambda"] <= auto["n_lambda"]
+
+
+@pytest.mark.parametrize("nP,nN,rel,nsrc,spins,order", [
+    (2, 1, False, 1, None, 0b101),              # 3He as P N P
+    (2, 1, False, 1, None, 0b110),              # 3He as N P P
+    (2, 2, False, 1, (0, 1, 0, 1), 0b1010),     # 4He as N P N P
+    (1, 1, True, 1, None, 0b01),                # p+n relativistic, proton first
+    (1, 2, False, 2, None, 0b010),              # 3H, two sources, as N P N
+])
+def test_interleaved_orders_reproduce_oracle(nP, nN, rel, nsrc, spins, order):
+    """Tables built for an interleaved order, replayed on oracle blocks, give
+    the oracle's correlators: the result does not depend on the order."""
+    from tests.gpu_helpers import oracle_blocks_lib_layout
+    rng = np.random.default_rng(order + 7 * nsrc)
+    V = 2
+    Su = rng.normal(size=(V, nsrc, 12, 12)) + 1j * rng.normal(size=(V, nsrc, 12, 12))
+    w = rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))
+    if spins is None:
+        tl = B.TermList(nP, nN, rel, nsrc, all_components=True, path=B.MB_PATH_EXPLICIT, order=order)
+    else:
+        tl = B.TermList.spin_state(nP, nN, rel, nsrc, spins, path=B.MB_PATH_EXPLICIT, order=order)
+    assert tl.counts()["path"] == [0 if (order >> i) & 1 else 1 for i in range(nP + nN)]
+    fP, fN = O.blocks(rel, nsrc, Su, Su, w)
+    got = _replay_tables(tl, oracle_blocks_lib_layout(fP, fN))
+    dsets = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    asets = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+    req = dict(sinkP=int(np.bitwise_or.reduce(dsets[:, 0])), sinkN=int(np.bitwise_or.reduce(dsets[:, 1])),
+               alphas=[tuple(map(int, a)) for a in asets])
+    ref = O.correlators(rel, nsrc, nP, nN, req, Su, Su, w)
+    R = np.array([[ref[(tuple(map(int, d)), tuple(map(int, a)))] for a in asets] for d in dsets])
+    assert np.linalg.norm(R) > 0
+    assert np.linalg.norm(got - R) <= 1e-12 * np.linalg.norm(R)
+
+
+def test_orders_are_validated():
+    for order in (0b111, 0b001, 0b1011):   # wrong proton count, or a baryon beyond A
+        with pytest.raises(B.MBError) as e:
+            B.TermList(2, 1, False, 1, all_components=True, path=B.MB_PATH_EXPLICIT, order=order)
+        assert e.value.code == B.MB_EINVAL
+    with pytest.raises(B.MBError) as e:
+        B.TermList(2, 2, False, 1, all_components=True, path=B.MB_PATH_BEST, sides=[(1, None)])
+    assert e.value.code == B.MB_EUNSUPPORTED
