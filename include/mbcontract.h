@@ -179,6 +179,17 @@ int mb_build_term_list_path(const mb_nucleus *nuc, const mb_spin_request *req, i
 
 void mb_term_list_free(mb_term_list *tl);
 
+/* Term lists are built once per nucleus and request, independently of any
+ * gauge configuration (Sec. 3, 7).  mb_term_list_save writes a host term
+ * list (not its device image or launch tuning) to the file `path` in a
+ * versioned binary format of this library, native byte order; MB_EINVAL if
+ * the file cannot be written.  mb_term_list_load reads it back into a new
+ * list, owned by the caller (upload it before contracting); MB_EINVAL for a
+ * missing, truncated or foreign file, MB_EUNSUPPORTED for another format
+ * version.  A loaded list exports and contracts exactly as the saved one.   */
+int mb_term_list_save(const mb_term_list *tl, const char *path);
+int mb_term_list_load(const char *path, mb_term_list **out);
+
 #define MB_MAX_STAGES 16
 #define MB_MAX_BATCH 65535     /* lanes per call */
 
@@ -202,7 +213,8 @@ void mb_term_list_free(mb_term_list *tl);
  *                   projected); n_L then counts the entries of c on the
  *                   kept quark parts
  *   n_side          side requests (smaller nuclei on the path)
- *   n_out           complex outputs per lane: main output and side outputs */
+ *   n_out           complex outputs per lane: main output and side outputs
+ *   rel, n_src      the operators and sources of the nucleus             */
 typedef struct {
     int n_stages;
     int path[MB_MAX_STAGES];
@@ -220,6 +232,7 @@ typedef struct {
     int64_t n_LM;
     int32_t n_side;
     int64_t n_out;
+    int32_t rel, n_src;
 } mb_counts;
 
 int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);

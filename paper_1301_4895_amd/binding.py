@@ -27,6 +27,7 @@ MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUN
 
 EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_build_term_list_path", "mb_term_list_free",
+    "mb_term_list_save", "mb_term_list_load",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
     "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune",
     "mb_batch_plan", "mb_batch_create", "mb_batch_launch", "mb_batch_kernel_count", "mb_batch_free",
@@ -62,7 +63,7 @@ class mb_counts(C.Structure):
                 ("n_L", C.c_int64), ("n_U", C.c_int64), ("n_delta", C.c_int32),
                 ("n_alpha", C.c_int32), ("n_psi", C.c_int32), ("n_xi", C.c_int32),
                 ("device_bytes", C.c_int64), ("projected", C.c_int32), ("n_LM", C.c_int64),
-                ("n_side", C.c_int32), ("n_out", C.c_int64)]
+                ("n_side", C.c_int32), ("n_out", C.c_int64), ("rel", C.c_int32), ("n_src", C.c_int32)]
 
 
 class mb_problem(C.Structure):
@@ -94,6 +95,8 @@ def lib():
         L.mb_build_term_list_path.argtypes = [C.POINTER(mb_nucleus), C.POINTER(mb_spin_request), C.c_int,
                                               C.POINTER(mb_side_request), C.POINTER(P)]
         L.mb_term_list_free.argtypes = [P]
+        L.mb_term_list_save.argtypes = [P, C.c_char_p]
+        L.mb_term_list_load.argtypes = [C.c_char_p, C.POINTER(P)]
         L.mb_term_list_free.restype = None
         L.mb_term_list_counts.argtypes = [P, C.POINTER(mb_counts)]
         L.mb_term_list_export.argtypes = [P, C.c_int, C.c_int, P, C.POINTER(C.c_size_t)]
@@ -158,6 +161,23 @@ class TermList:
         self.nucleus = dict(n_P=n_P, n_N=n_N, rel=bool(rel), n_src=n_src)
         self._dev = None
 
+    def save(self, path):
+        """Writes the host term list to a file (mb_term_list_save)."""
+        _check(lib().mb_term_list_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        """A term list read back from a file written by ``save``."""
+        h = C.c_void_p()
+        _check(lib().mb_term_list_load(os.fsencode(path), C.byref(h)))
+        self = cls.__new__(cls)
+        self.h = h
+        self._dev = None
+        c = self.counts()
+        nP = sum(1 for t in c["path"] if t == 0)
+        self.nucleus = dict(n_P=nP, n_N=c["n_stages"] - nP, rel=bool(c["rel"]), n_src=c["n_src"])
+        return self
+
     @classmethod
     def spin_state(cls, n_P, n_N, rel, n_src, spins, **kw):
         """Single spin component (Sec. 8): indices listed protons first."""
@@ -185,7 +205,7 @@ class TermList:
                     n_quark=list(c.n_quark[:n]), n_spin=list(c.n_spin[:n]), n_L=c.n_L, n_U=c.n_U,
                     n_delta=c.n_delta, n_alpha=c.n_alpha, n_psi=c.n_psi, n_xi=c.n_xi,
                     device_bytes=c.device_bytes, projected=bool(c.projected), n_LM=c.n_LM,
-                    n_side=c.n_side, n_out=c.n_out)
+                    n_side=c.n_side, n_out=c.n_out, rel=c.rel, n_src=c.n_src)
 
     def side(self, i):
         """Side request i: (stage, source sets [n][2], CSR row starts, quark

@@ -14,6 +14,7 @@
 //     eq. antis_product_2 is the product of the per-group signs.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -760,6 +761,8 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *c) {
   c->n_LM = int64_t(tl->pcol.size());
   c->n_side = int32_t(tl->sides.size());
   c->n_out = tl->side_offset(tl->sides.size());
+  c->rel = tl->nuc.rel;
+  c->n_src = tl->nsrc;
   return MB_OK;
 }
 
@@ -876,5 +879,248 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, 
 }
 
 const char *mb_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Saving and loading term lists: a magic word and format version, then every
+// field of the host list in a fixed order; vectors as a 64-bit length
+// followed by their elements.
+namespace {
+
+constexpr uint64_t kFileMagic = 0x3153494c4d524554ull;   // "TERMLIS1"
+constexpr uint32_t kFileVersion = 1;
+
+struct Writer {
+  FILE *f;
+  bool ok = true;
+  void raw(const void *p, size_t n) {
+    if (ok && n) ok = std::fwrite(p, 1, n, f) == n;
+  }
+  template <typename T> void val(const T &v) { raw(&v, sizeof v); }
+  void val(const bool &v) {
+    const uint8_t b = v ? 1 : 0;
+    raw(&b, 1);
+  }
+  template <typename T> void vec(const std::vector<T> &v) {
+    val(uint64_t(v.size()));
+    raw(v.data(), v.size() * sizeof(T));
+  }
+};
+
+struct Reader {
+  FILE *f;
+  bool ok = true;
+  void raw(void *p, size_t n) {
+    if (ok && n) ok = std::fread(p, 1, n, f) == n;
+  }
+  template <typename T> void val(T &v) { raw(&v, sizeof v); }
+  void val(bool &v) {
+    uint8_t b = 0;
+    raw(&b, 1);
+    if (b > 1) ok = false;
+    v = b == 1;
+  }
+  template <typename T> void vec(std::vector<T> &v) {
+    uint64_t n = 0;
+    val(n);
+    // a length beyond what is left in the file marks a corrupt file
+    const long here = std::ftell(f);
+    std::fseek(f, 0, SEEK_END);
+    const long end = std::ftell(f);
+    std::fseek(f, here, SEEK_SET);
+    if (!ok || here < 0 || end < here || n > uint64_t(end - here) / sizeof(T)) {
+      ok = false;
+      return;
+    }
+    v.resize(size_t(n));
+    raw(v.data(), v.size() * sizeof(T));
+  }
+};
+
+template <typename IO, typename TL, typename STAGE, typename SIDE>
+void fields(IO &io, TL &tl, std::vector<STAGE> &st, std::vector<SIDE> &sides) {
+  io.val(tl.nuc);
+  io.val(tl.D);
+  io.val(tl.nsrc);
+  io.val(tl.npsi);
+  io.val(tl.nxi);
+  io.val(tl.A);
+  io.val(tl.nstages);
+  io.val(tl.path);
+  io.val(tl.SP);
+  io.val(tl.SN);
+  io.vec(tl.alphas);
+  io.vec(tl.crow);
+  io.vec(tl.ccol);
+  io.vec(tl.cval);
+  io.val(tl.nL);
+  io.val(tl.nU);
+  io.val(tl.projected);
+  io.vec(tl.prow);
+  io.vec(tl.pcol);
+  io.vec(tl.pval);
+  io.val(tl.counts_only);
+  for (auto &S : st) {
+    io.val(S.type);
+    io.val(S.kP);
+    io.val(S.kN);
+    io.val(S.ku);
+    io.val(S.kd);
+    io.val(S.nPsets);
+    io.val(S.nNsets);
+    io.vec(S.quark);
+    io.val(S.Sq);
+    io.vec(S.qsplit);
+    io.vec(S.first);
+    io.val(S.n_lambda);
+  }
+  for (auto &sd : sides) {
+    io.val(sd.stage);
+    io.vec(sd.alphas);
+    io.vec(sd.crow);
+    io.vec(sd.ccol);
+    io.vec(sd.cval);
+  }
+}
+
+// Structural checks of a loaded list: every size follows from the nucleus,
+// the path and the sink base sets as in a built list, and every index the
+// kernels follow (split tables, gather indices, coefficient lists) stays
+// inside the table it points into.
+bool valid_loaded(const mb_term_list &t) {
+  const mb_nucleus &n = t.nuc;
+  if (n.n_P < 0 || n.n_N < 0 || n.n_P + n.n_N < 1 || n.n_P + n.n_N > MB_MAX_STAGES) return false;
+  if ((n.rel != 0 && n.rel != 1) || (n.n_src != 1 && n.n_src != 2)) return false;
+  const int D = n.rel ? 4 : 2, A = n.n_P + n.n_N;
+  if (t.D != D || t.nsrc != n.n_src || t.npsi != D * n.n_src || t.nxi != 3 * D * n.n_src) return false;
+  if (t.A != A || t.nstages != A || int(t.st.size()) != A) return false;
+  const uint32_t allpsi = (1u << t.npsi) - 1, allxi = (1u << t.nxi) - 1;
+  if ((t.SP & ~allpsi) || (t.SN & ~allpsi)) return false;
+  int kP = 0, kN = 0;
+  for (int s = 0; s < A; s++) {
+    const Stage &S = t.st[size_t(s)];
+    if (t.path[s] != PROTON && t.path[s] != NEUTRON) return false;
+    (t.path[s] == PROTON ? kP : kN)++;
+    if (S.type != t.path[s] || S.kP != kP || S.kN != kN || S.ku != 2 * kP + kN || S.kd != kP + 2 * kN) return false;
+    if (S.nPsets != binom(__builtin_popcount(t.SP), kP) || S.nNsets != binom(__builtin_popcount(t.SN), kN)) return false;
+    if (S.nPsets < 1 || S.nNsets < 1) return false;
+    for (uint64_t q : S.quark)
+      if ((qkey_u(q) & ~allxi) || (qkey_d(q) & ~allxi) || __builtin_popcount(qkey_u(q)) != S.ku ||
+          __builtin_popcount(qkey_d(q)) != S.kd)
+        return false;
+    // quark parts strictly increasing in the stage's order (lookups bisect)
+    const bool dm = S.type == PROTON && s > 0;
+    for (size_t i = 1; i < S.quark.size(); i++)
+      if (order_key(S.quark[i - 1], dm) >= order_key(S.quark[i], dm)) return false;
+    if (s == 0) {
+      if (!t.counts_only && S.first.size() != S.quark.size()) return false;
+      for (size_t i = 0; i < S.first.size(); i++)
+        if (S.first[i] != block_qidx(S.type, qkey_u(S.quark[i]), qkey_d(S.quark[i]), t.nxi)) return false;
+      continue;
+    }
+    const Stage &P = t.st[size_t(s) - 1];
+    const bool pdm = P.type == PROTON && s - 1 > 0;
+    const int64_t Sq = S.type == PROTON ? int64_t(binom(S.ku, 2)) * S.kd : int64_t(S.ku) * binom(S.kd, 2);
+    if (S.Sq != Sq || S.n_lambda != S.nreq() * (S.type == PROTON ? kP : kN) * Sq) return false;
+    if (S.qsplit.size() != (t.counts_only ? 0 : S.quark.size() * size_t(S.Sq) * 2)) return false;
+    // every split entry is the one the builder derives from the quark parts
+    bool same = true;
+    for (size_t qi = 0; same && qi < S.quark.size(); qi++) {
+      const uint32_t u = qkey_u(S.quark[qi]), d = qkey_d(S.quark[qi]);
+      size_t o = qi * size_t(S.Sq) * 2;
+      for_quark_splits(S.type, u, d, [&](uint32_t yu, uint32_t yd) {
+        if (!same || S.qsplit.empty()) return;
+        const uint64_t xk = qkey(u & ~yu, d & ~yd);
+        const uint32_t xi = find_stage(P.quark, pdm, xk);
+        const int sg = split_sign(u & ~yu, yu) * split_sign(d & ~yd, yd);
+        const uint32_t y = block_qidx(S.type, yu, yd, t.nxi) | (sg < 0 ? 0x80000000u : 0u);
+        if (xi >= P.quark.size() || P.quark[xi] != xk || S.qsplit[o] != xi || S.qsplit[o + 1] != y) same = false;
+        o += 2;
+      });
+    }
+    if (!same) return false;
+  }
+  if (kP != n.n_P || kN != n.n_N) return false;
+  auto csr_ok = [](const std::vector<int64_t> &row, size_t nrows, const std::vector<int64_t> &col, size_t nval,
+                   size_t ncols) {
+    if (row.size() != nrows + 1 || row[0] != 0 || uint64_t(row.back()) != col.size() || nval != col.size())
+      return false;
+    for (size_t i = 0; i < nrows; i++)
+      if (row[i + 1] < row[i]) return false;
+    for (int64_t c : col)
+      if (c < 0 || uint64_t(c) >= ncols) return false;
+    return true;
+  };
+  const size_t nfinal = t.st.back().quark.size();
+  for (auto &a : t.alphas)
+    if ((a[0] & ~allpsi) || (a[1] & ~allpsi) || __builtin_popcount(a[0]) != n.n_P || __builtin_popcount(a[1]) != n.n_N)
+      return false;
+  if (!csr_ok(t.crow, t.alphas.size(), t.ccol, t.cval.size(), nfinal)) return false;
+  if (t.projected && !csr_ok(t.prow, size_t(t.st.back().nspin()), t.pcol, t.pval.size(), nfinal)) return false;
+  if (!t.projected && (!t.prow.empty() || !t.pcol.empty() || !t.pval.empty())) return false;
+  if (t.projected && !t.sides.empty()) return false;
+  for (const Side &sd : t.sides) {
+    if (sd.stage < 0 || sd.stage >= A - 1) return false;
+    if (!csr_ok(sd.crow, sd.alphas.size(), sd.ccol, sd.cval.size(), t.st[size_t(sd.stage)].quark.size())) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mb_term_list_save(const mb_term_list *tl, const char *path) {
+  if (!tl || !path) return fail(MB_EINVAL, "null argument");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(MB_EINVAL, std::string("cannot open ") + path + " for writing");
+  Writer w{f};
+  w.val(kFileMagic);
+  w.val(kFileVersion);
+  w.val(uint64_t(tl->st.size()));
+  w.val(uint64_t(tl->sides.size()));
+  // the field walk takes non-const references; the writer only reads them
+  mb_term_list &t = const_cast<mb_term_list &>(*tl);
+  fields(w, t, t.st, t.sides);
+  const bool ok = w.ok && std::fclose(f) == 0;
+  if (!ok) return fail(MB_EINVAL, std::string("write to ") + path + " failed");
+  set_error("");
+  return MB_OK;
+}
+
+int mb_term_list_load(const char *path, mb_term_list **out) {
+  if (!path || !out) return fail(MB_EINVAL, "null argument");
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(MB_EINVAL, std::string("cannot open ") + path);
+  std::unique_ptr<FILE, int (*)(FILE *)> fg(f, std::fclose);
+  try {
+    Reader r{f};
+    uint64_t magic = 0, nst = 0, nside = 0;
+    uint32_t version = 0;
+    r.val(magic);
+    if (!r.ok || magic != kFileMagic) return fail(MB_EINVAL, std::string(path) + " is not a term list file");
+    r.val(version);
+    if (!r.ok || version != kFileVersion) return fail(MB_EUNSUPPORTED, "term list file of another format version");
+    r.val(nst);
+    r.val(nside);
+    if (!r.ok || nst < 1 || nst > MB_MAX_STAGES || nside > MB_MAX_STAGES)
+      return fail(MB_EINVAL, std::string(path) + " is corrupt");
+    std::unique_ptr<mb_term_list> tl(new mb_term_list());
+    tl->st.resize(size_t(nst));
+    tl->sides.resize(size_t(nside));
+    fields(r, *tl, tl->st, tl->sides);
+    char extra;
+    if (!r.ok || std::fread(&extra, 1, 1, f) != 0 || tl->nstages != int(nst) || tl->A != int(nst))
+      return fail(MB_EINVAL, std::string(path) + " is truncated or corrupt");
+    if (!valid_loaded(*tl)) return fail(MB_EINVAL, std::string(path) + " is corrupt");
+    *out = tl.release();
+    set_error("");
+    return MB_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MB_ENOMEM, "out of host memory");
+  }
+}
 
 }  // extern "C"

@@ -376,3 +376,19 @@ def test_interleaved_order_matches_oracle(rel, nsrc, nP, nN, spins, order, V, nl
             if prec == B.MB_FP64:
                 ref = _oracle_corr(tl, rel, nsrc, nP, nN, Su[b], Sd[b], w, k[b])
                 assert rel_err(corr[b], ref) <= 1e-12, b
+
+
+# --------------------------------------------------------------------- saved term lists
+
+def test_loaded_term_list_contracts_identically(tmp_path):
+    """A term list written to a file and read back gives bit-identical
+    correlators to the one built in memory, in both precision modes."""
+    Su, Sd, w, k = _inputs(61, 3, 8, 1, np.complex128, True, with_sink=False)
+    tl = B.TermList(2, 1, False, 1, all_components=True, sides=[(1, None)])
+    f = tmp_path / "list.mbt"
+    tl.save(f)
+    back = B.TermList.load(f)
+    for prec in (B.MB_FP64, B.MB_MIXED):
+        _, a, ea = _run(tl, Su, Sd, w, k, prec)
+        _, b, eb = _run(back, Su, Sd, w, k, prec)
+        assert np.array_equal(a, b) and np.array_equal(ea, eb), prec

@@ -697,3 +697,85 @@ def test_orders_are_validated():
     with pytest.raises(B.MBError) as e:
         B.TermList(2, 2, False, 1, all_components=True, path=B.MB_PATH_BEST, sides=[(1, None)])
     assert e.value.code == B.MB_EUNSUPPORTED
+
+
+# ----------------------------------------------------------------- saving and loading
+
+def _all_exports(tl):
+    c = tl.counts()
+    out = {"counts": c}
+    for s in range(c["n_stages"]):
+        out[("quark", s)] = tl.export(B.MB_EXPORT_QUARK, s).tobytes()
+        out[("spin", s)] = tl.export(B.MB_EXPORT_SPIN, s).tobytes()
+        if s >= 1:
+            out[("ssplit", s)] = tl.export(B.MB_EXPORT_SSPLIT, s, np.int32).tobytes()
+            if c["device_bytes"]:
+                out[("qsplit", s)] = tl.export(B.MB_EXPORT_QSPLIT, s).tobytes()
+    for what in (B.MB_EXPORT_COEF, B.MB_EXPORT_DELTA, B.MB_EXPORT_ALPHA):
+        out[what] = tl.export(what, dtype=np.uint8).tobytes()
+    if c["projected"]:
+        out["proj"] = tl.export(B.MB_EXPORT_PROJ, dtype=np.uint8).tobytes()
+    for i in range(c["n_side"]):
+        out[("side", i)] = tl.export(B.MB_EXPORT_SIDE, i, np.uint8).tobytes()
+    return out
+
+
+@pytest.mark.parametrize("make", [
+    lambda: B.TermList(2, 2, True, 1, all_components=True),
+    lambda: B.TermList(2, 1, False, 1, all_components=True, sides=[(0, None), (1, None)]),
+    lambda: B.TermList(1, 1, False, 1, all_components=True, proj=np.arange(16.0).reshape(4, 4) - 7.5),
+    lambda: B.TermList.spin_state(2, 2, False, 1, (0, 1, 0, 1), path=B.MB_PATH_EXPLICIT, order=0b1010),
+    lambda: B.TermList.spin_state(4, 4, False, 2, (0, 1, 2, 3, 0, 1, 2, 3), counts_only=True),
+])
+def test_saved_term_list_loads_identically(make, tmp_path):
+    """A saved and loaded term list has the same counts and exports (every
+    table, coefficient list, projected list and side list) as the built one."""
+    tl = make()
+    f = tmp_path / "list.mbt"
+    tl.save(f)
+    back = B.TermList.load(f)
+    assert _all_exports(back) == _all_exports(tl)
+    assert back.nucleus == tl.nucleus
+
+
+def test_loading_rejects_foreign_and_damaged_files(tmp_path):
+    tl = B.TermList(2, 1, False, 1, all_components=True, sides=[(1, None)])
+    f = tmp_path / "list.mbt"
+    tl.save(f)
+    raw = f.read_bytes()
+    with pytest.raises(B.MBError) as e:
+        B.TermList.load(tmp_path / "missing.mbt")
+    assert e.value.code == B.MB_EINVAL
+    bad = tmp_path / "bad.mbt"
+    for cut in (0, 7, 12, 40, len(raw) // 2, len(raw) - 1):   # truncated
+        bad.write_bytes(raw[:cut])
+        with pytest.raises(B.MBError) as e:
+            B.TermList.load(bad)
+        assert e.value.code == B.MB_EINVAL, cut
+    bad.write_bytes(raw + b"\0")                               # trailing bytes
+    with pytest.raises(B.MBError):
+        B.TermList.load(bad)
+    bad.write_bytes(b"X" + raw[1:])                            # not a term list file
+    with pytest.raises(B.MBError) as e:
+        B.TermList.load(bad)
+    assert e.value.code == B.MB_EINVAL
+    v = bytearray(raw)
+    v[8] ^= 0x7                                                # another format version
+    bad.write_bytes(bytes(v))
+    with pytest.raises(B.MBError) as e:
+        B.TermList.load(bad)
+    assert e.value.code == B.MB_EUNSUPPORTED
+    # damaged bytes anywhere: the load either fails cleanly or gives a list
+    # that passed the structural checks (every index inside its table)
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        v = bytearray(raw)
+        pos = int(rng.integers(28, len(raw)))
+        v[pos] ^= int(rng.integers(1, 256))
+        bad.write_bytes(bytes(v))
+        try:
+            t2 = B.TermList.load(bad)
+        except B.MBError as err:
+            assert err.code == B.MB_EINVAL
+            continue
+        _all_exports(t2)
