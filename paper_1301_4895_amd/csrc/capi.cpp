@@ -304,6 +304,23 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
   const char *img = static_cast<const char *>(tl->dev);
 
+  // Stage j is stored in the paired layout when the step that reads it is
+  // the direct kernel adding a proton with 64-lane tiles and an even
+  // passthrough group (so that every thread reads both spin parts of a pair)
+  // and the stages are float; stages read by a side nucleus or by the final
+  // sum stay plain.
+  auto paired = [&](int j) {
+    if (!mixed || j + 1 >= tl->nstages) return false;
+    const Stage &C = tl->st[j + 1];
+    if (C.type != PROTON || C.tune_kernel != 0 || C.tune_group > 1 || C.tune_tile != 64) return false;
+    const int npass = C.nNsets;
+    const int pg = C.tune_pg ? C.tune_pg : npass % 3 == 0 ? 3 : npass % 2 == 0 ? 2 : 1;
+    if (npass % 2 || pg % 2) return false;
+    for (const mb::Side &sd : tl->sides)
+      if (sd.stage == j) return false;
+    return true;
+  };
+
   for (int step = first_step; step <= last_step; step++) {
     if (step == 0) {
       // the first baryon's block restricted to the required components
@@ -318,6 +335,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.ns = int(S0.nspin());
       a.npsi = tl->npsi;
       psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+      a.paired_out = paired(0);
       if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
     } else if (step < tl->nstages) {
       const Stage &S = tl->st[step], &Pv = tl->st[step - 1];
@@ -339,6 +357,8 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.tile = S.tune_tile;
       a.unroll = S.tune_unroll;
       a.group = S.tune_group;
+      a.paired_in = paired(step - 1);
+      a.paired_out = paired(step);
       a.npsi = tl->npsi;
       psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
@@ -365,6 +385,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         b.bsplit = nxi > 9 ? 9 : nxi;
         b.div_magic = uint32_t(((uint64_t(1) << 32) + uint64_t(nxi) - 1) / uint64_t(nxi));
         for (int i = 0; i < 8; i++) b.psi_of_pos[i] = a.psi_of_pos[i];
+        b.paired_out = a.paired_out;
         HIP_CHECK(launch_stage_lds(b, mixed, s));
       } else if (a.nq_out > 0) {
         HIP_CHECK(launch_stage(a, mixed, s));

@@ -20,6 +20,8 @@
 // compile time.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace mb {
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void stage0_kernel(Stage0Args a) {
   C2 o;
   o.x = T(v.x);
   o.y = T(v.y);
-  F[q * a.ns * a.Bp + lane_off(b, a.ns) + sig * 16] = o;
+  F[q * a.ns * a.Bp + spin_off(b, a.ns, sig, a.paired_out)] = o;
 }
 
 hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s) {
@@ -155,7 +157,7 @@ __device__ __forceinline__ TileOut xcd_map() {
   return {g / nout, g % nout};
 }
 
-template <typename TS, int M, int K, int PG, int TILE, int U, bool AP>
+template <typename TS, int M, int K, int PG, int TILE, int U, bool AP, bool PKI>
 __device__ __forceinline__ void stage_body(const StageArgs &a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
@@ -189,8 +191,9 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
 #pragma unroll
   for (int d = 0; d < M; d++) yoff[d] = uint32_t(a.psi_of_pos[d]) * 16 * uint32_t(sizeof(double2));
   const uint32_t x_lane = uint32_t(lane_off(b, ns_in)) * uint32_t(sizeof(CS));
+  // paired input: the pair (2j, 2j+1) of spin parts of this lane, 16 bytes
+  const uint32_t x_lane_pk = uint32_t((b >> 4) * ns_in * 16 + (b & 15) * 2) * uint32_t(sizeof(CS));
   const uint32_t y_lane = uint32_t(lane_off(b, a.npsi)) * uint32_t(sizeof(double2));
-  const int64_t out_lane = lane_off(b, ns_out);
   const int64_t xstride = int64_t(ns_in) * Bp * int64_t(sizeof(CS));
   const int64_t ystride = int64_t(a.npsi) * Bp * int64_t(sizeof(double2));
 
@@ -228,10 +231,21 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
 #pragma unroll
         for (int d = 0; d < M; d++) fy[u][d] = ld(reinterpret_cast<const double2 *>(yrow + yoff[d]), y_lane);
 #pragma unroll
-        for (int rr = 0; rr < NIN; rr++)
+        for (int rr = 0; rr < NIN; rr++) {
+          if constexpr (PKI) {
+            // passthrough parts 2j and 2j+1 of row rr are neighbours: one load
 #pragma unroll
-          for (int g = 0; g < PG; g++)
-            xin[u][g][rr] = ld(reinterpret_cast<const CS *>(xrow + roff[rr]), x_lane + g * GSTEP);
+            for (int j = 0; j < PG / 2; j++) {
+              const float4 v = ld(reinterpret_cast<const float4 *>(xrow + roff[rr]), x_lane_pk + j * 2 * ROW);
+              xin[u][2 * j][rr] = make_float2(v.x, v.y);
+              xin[u][2 * j + 1][rr] = make_float2(v.z, v.w);
+            }
+          } else {
+#pragma unroll
+            for (int g = 0; g < PG; g++)
+              xin[u][g][rr] = ld(reinterpret_cast<const CS *>(xrow + roff[rr]), x_lane + g * GSTEP);
+          }
+        }
       } else {
         // per-lane row bases: one 64-bit pointer per r (and per d), the
         // passthrough parts at immediate offsets from it
@@ -303,7 +317,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
       CS v;
       v.x = TS(acc[g][o].x);
       v.y = TS(acc[g][o].y);
-      Fout[q * ns_out * Bp + out_lane + sig_out(o, pass0 + g) * 16] = v;
+      Fout[q * ns_out * Bp + spin_off(b, ns_out, sig_out(o, pass0 + g), a.paired_out)] = v;
     }
 }
 
@@ -320,10 +334,14 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
 // stage), which keeps four times more previous-stage rows in L2.  Which tile
 // is faster depends on the step; the autotuner decides.  The spin layout of
 // the step (added species proton or neutron) selects one of two bodies.
-template <typename TS, int M, int K, int PG, int TILE, int U>
+template <typename TS, int M, int K, int PG, int TILE, int U, bool PKI>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
-  if (a.act_is_P) stage_body<TS, M, K, PG, TILE, U, true>(a);
-  else stage_body<TS, M, K, PG, TILE, U, false>(a);
+  if constexpr (PKI) {
+    stage_body<TS, M, K, PG, TILE, U, true, true>(a);   // launched only for a proton step
+  } else {
+    if (a.act_is_P) stage_body<TS, M, K, PG, TILE, U, true, false>(a);
+    else stage_body<TS, M, K, PG, TILE, U, false, false>(a);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -401,7 +419,6 @@ __global__ __launch_bounds__(LDS_THREADS) void stage_lds_kernel(StageLdsArgs a) 
   const CS *Fin = static_cast<const CS *>(a.Fin);
   const double2 *fb = static_cast<const double2 *>(a.fblk);
   const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
-  const int64_t out_lane = lane_off(b, ns_out);
   const int64_t ftile = tile * a.npsi * 16;
   const int64_t xstride = int64_t(ns_in) * Bp;
 
@@ -511,7 +528,7 @@ __global__ __launch_bounds__(LDS_THREADS) void stage_lds_kernel(StageLdsArgs a) 
       CS o;
       o.x = TS(acc[g][r].x);
       o.y = TS(acc[g][r].y);
-      Fout[q * ns_out * Bp + out_lane + sig_out(r, pass0 + g) * 16] = o;
+      Fout[q * ns_out * Bp + spin_off(b, ns_out, sig_out(r, pass0 + g), a.paired_out)] = o;
     }
 }
 
@@ -584,7 +601,6 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
 #pragma unroll
   for (int d = 0; d < M; d++) f_off[d] = uint32_t(lane_off(b, a.npsi) + a.psi_of_pos[d] * 16);
   const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
-  const int64_t out_lane = lane_off(b, ns_out);
   const int64_t xstride = int64_t(ns_in) * Bp, ystride = int64_t(a.npsi) * Bp;
 
   double2 acc[G][PG][NOUT];
@@ -661,7 +677,7 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
         CS v;
         v.x = TS(acc[g][p][o].x);
         v.y = TS(acc[g][p][o].y);
-        Fout[(q0 + g) * ns_out * Bp + out_lane + sig_out(o, pass0 + p) * 16] = v;
+        Fout[(q0 + g) * ns_out * Bp + spin_off(b, ns_out, sig_out(o, pass0 + p), a.paired_out)] = v;
       }
   }
 }
@@ -681,7 +697,18 @@ static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
   if (!grid_x_fits(n8 * (a.npass / PG), 64)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / TILE));
-  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U>), grid, dim3(64), a.lds_bytes, s, a);
+  if (a.paired_in) {
+    // paired input: float stages, 64-lane tiles, even passthrough groups of
+    // a proton step with an even passthrough count
+    if constexpr (std::is_same<T, float>::value && TILE == 64 && PG % 2 == 0) {
+      if (!a.act_is_P || a.npass % 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, true>), grid, dim3(64), a.lds_bytes, s, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, false>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
@@ -699,6 +726,7 @@ static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
 template <typename T, int M, int K, int PG>
 static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
   if constexpr (PG <= 3) {
+    if ((a.group == 2 || a.group == 4) && a.paired_in) return hipErrorInvalidValue;   // plain input only
     if (a.group == 2) return launch_stage_group<T, M, K, PG, 2>(a, s);
     if (a.group == 4) return launch_stage_group<T, M, K, PG, 4>(a, s);
   }

@@ -45,6 +45,16 @@ hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int 
 // one operand (its spin parts, its baryon indices) are adjacent in memory.
 __host__ __device__ inline int64_t lane_off(int64_t b, int n) { return (b >> 4) * n * 16 + (b & 15); }
 
+// Element offset of spin part sigma of lane b inside one quark part of a
+// stage with n spin parts.  Plain layout: [lane / 16][sigma][lane % 16].
+// Paired layout (float stages whose next step reads neighbouring spin parts
+// together): [lane / 16][sigma / 2][lane % 16][sigma % 2], so that a lane's
+// spin parts 2j and 2j+1 are one 16-byte load.
+__host__ __device__ inline int64_t spin_off(int64_t b, int n, int sigma, bool paired) {
+  return paired ? (b >> 4) * n * 16 + (sigma >> 1) * 32 + (b & 15) * 2 + (sigma & 1)
+                : (b >> 4) * n * 16 + sigma * 16 + (b & 15);
+}
+
 // A dispatch covers fewer than 2^32 work-items per dimension (the grid size
 // of the dispatch packet is 32-bit); larger launches are refused, never
 // truncated.
@@ -58,6 +68,7 @@ struct Stage0Args {
   int64_t nq, Bp;
   int nyq, ns, npsi;
   int psi_of_pos[8];
+  int paired_out;            // stage 0 stored in the paired layout
 };
 hipError_t launch_stage0(const Stage0Args &a, bool mixed, hipStream_t s);
 
@@ -78,6 +89,8 @@ struct StageArgs {
   int group;                 // outputs per wavefront of the grouped kernel: 1 (off), 2, 4
   int npsi;                  // baryon indices of the block layout
   int psi_of_pos[8];
+  int paired_in, paired_out; // stage layouts (spin_off); paired input only for the
+                             // direct kernel adding a proton, 64-lane tiles, even pg, float stages
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);
 
@@ -100,6 +113,7 @@ struct StageLdsArgs {
   int nxi, npair, npsi, bsplit;
   uint32_t div_magic;        // ceil(2^32 / nxi): exact division of multiples of nxi
   int psi_of_pos[8];
+  int paired_out;
 };
 hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s);
 // LDS bytes the staged kernel uses for a term list with nxi quark indices,
