@@ -298,6 +298,10 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
  *                       64 lanes, where neighbouring outputs share the block
  *                       rows they read at the same split position (applies
  *                       with passthrough groups up to 3)
+ *   MB_TUNE_PAIRED      1 (default): the float stage this step reads is stored
+ *                       with neighbouring spin parts of a lane together
+ *                       when every thread of the step takes both (one
+ *                       16-byte load instead of two); 0: plain layout
  *   MB_TUNE_KERNEL      0 (default): every thread gathers its block entries
  *                       from global memory; 1: the block rows of one single
  *                       quark index at a time are staged in LDS per
@@ -310,6 +314,7 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
 #define MB_TUNE_KERNEL 4
 #define MB_TUNE_UNROLL 5
 #define MB_TUNE_GROUP 6
+#define MB_TUNE_PAIRED 7
 int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
 
 /* Copies the operation tables to device memory `dev` (caller-owned, at least

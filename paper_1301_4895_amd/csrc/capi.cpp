@@ -201,6 +201,9 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
     } else if (what == MB_TUNE_UNROLL) {
       if (value < 0 || value > 2) return fail(MB_EINVAL, "unroll must be 0, 1 or 2");
       S.tune_unroll = value;
+    } else if (what == MB_TUNE_PAIRED) {
+      if (value != 0 && value != 1) return fail(MB_EINVAL, "paired must be 0 or 1");
+      S.tune_paired = value;
     } else if (what == MB_TUNE_KERNEL) {
       if (value != 0 && value != 1) return fail(MB_EINVAL, "kernel must be 0 or 1");
       S.tune_kernel = value;
@@ -304,21 +307,30 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
   const char *img = static_cast<const char *>(tl->dev);
 
-  // Stage j is stored in the paired layout when the step that reads it is
-  // the direct kernel adding a proton with 64-lane tiles and an even
-  // passthrough group (so that every thread reads both spin parts of a pair)
-  // and the stages are float; stages read by a side nucleus or by the final
-  // sum stay plain.
+  // Float stage j is stored in the paired layout (neighbouring spin parts of
+  // a lane together, one 16-byte load) when every thread of the step that
+  // reads it takes both parts of each pair: 1, the direct kernel of a proton
+  // step with 64-lane tiles, an even passthrough count and group (pairs of
+  // passthrough parts); 2, the direct kernel with 64-lane tiles or the
+  // grouped kernel, with an even number of input sets that are neighbours in
+  // the stage order (a neutron step, or one passthrough part).  Stages read
+  // by a side nucleus or by the final sum stay plain.  Returns the mode.
   auto paired = [&](int j) {
-    if (!mixed || j + 1 >= tl->nstages) return false;
-    const Stage &C = tl->st[j + 1];
-    if (C.type != PROTON || C.tune_kernel != 0 || C.tune_group > 1 || C.tune_tile != 64) return false;
-    const int npass = C.nNsets;
-    const int pg = C.tune_pg ? C.tune_pg : npass % 3 == 0 ? 3 : npass % 2 == 0 ? 2 : 1;
-    if (npass % 2 || pg % 2) return false;
+    if (!mixed || j + 1 >= tl->nstages) return 0;
     for (const mb::Side &sd : tl->sides)
-      if (sd.stage == j) return false;
-    return true;
+      if (sd.stage == j) return 0;
+    const Stage &C = tl->st[j + 1];
+    if (C.tune_kernel != 0 || !C.tune_paired) return 0;
+    const bool AP = C.type == PROTON;
+    const int npass = AP ? C.nNsets : C.nPsets;
+    const int pg = C.tune_pg ? C.tune_pg : npass % 3 == 0 ? 3 : npass % 2 == 0 ? 2 : 1;
+    const bool grouped = (C.tune_group == 2 || C.tune_group == 4) && pg <= 3;
+    const bool direct64 = !grouped && C.tune_tile == 64;
+    const int M = __builtin_popcount(AP ? tl->SP : tl->SN);
+    const int nin = binom(M, AP ? tl->st[j].kP : tl->st[j].kN);
+    if (direct64 && AP && npass % 2 == 0 && pg % 2 == 0) return 1;
+    if ((direct64 || grouped) && nin % 2 == 0 && (!AP || npass == 1)) return 2;
+    return 0;
   };
 
   for (int step = first_step; step <= last_step; step++) {
@@ -335,7 +347,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.ns = int(S0.nspin());
       a.npsi = tl->npsi;
       psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
-      a.paired_out = paired(0);
+      a.paired_out = paired(0) != 0;
       if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
     } else if (step < tl->nstages) {
       const Stage &S = tl->st[step], &Pv = tl->st[step - 1];
@@ -358,7 +370,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
       a.unroll = S.tune_unroll;
       a.group = S.tune_group;
       a.paired_in = paired(step - 1);
-      a.paired_out = paired(step);
+      a.paired_out = paired(step) != 0;
       a.npsi = tl->npsi;
       psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
       if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");

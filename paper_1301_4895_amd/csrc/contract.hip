@@ -157,7 +157,11 @@ __device__ __forceinline__ TileOut xcd_map() {
   return {g / nout, g % nout};
 }
 
-template <typename TS, int M, int K, int PG, int TILE, int U, bool AP, bool PKI>
+// PKI: input layout.  0 plain; 1 paired, the pairs along the passthrough
+// parts (a proton step, even passthrough count and group); 2 paired, the
+// pairs along the input spin sets of the added species (neighbours in the
+// stage order: a neutron step, or a proton step with one passthrough part).
+template <typename TS, int M, int K, int PG, int TILE, int U, bool AP, int PKI>
 __device__ __forceinline__ void stage_body(const StageArgs &a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
@@ -232,13 +236,23 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
         for (int d = 0; d < M; d++) fy[u][d] = ld(reinterpret_cast<const double2 *>(yrow + yoff[d]), y_lane);
 #pragma unroll
         for (int rr = 0; rr < NIN; rr++) {
-          if constexpr (PKI) {
+          if constexpr (PKI == 1) {
             // passthrough parts 2j and 2j+1 of row rr are neighbours: one load
 #pragma unroll
             for (int j = 0; j < PG / 2; j++) {
               const float4 v = ld(reinterpret_cast<const float4 *>(xrow + roff[rr]), x_lane_pk + j * 2 * ROW);
               xin[u][2 * j][rr] = make_float2(v.x, v.y);
               xin[u][2 * j + 1][rr] = make_float2(v.z, v.w);
+            }
+          } else if constexpr (PKI == 2) {
+            // input sets rr and rr + 1 of one passthrough part are neighbours
+            if (rr % 2 == 0) {
+#pragma unroll
+              for (int g = 0; g < PG; g++) {
+                const float4 v = ld(reinterpret_cast<const float4 *>(xrow + roff[rr]), x_lane_pk + g * GSTEP);
+                xin[u][g][rr] = make_float2(v.x, v.y);
+                xin[u][g][rr + 1] = make_float2(v.z, v.w);
+              }
             }
           } else {
 #pragma unroll
@@ -334,13 +348,13 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
 // stage), which keeps four times more previous-stage rows in L2.  Which tile
 // is faster depends on the step; the autotuner decides.  The spin layout of
 // the step (added species proton or neutron) selects one of two bodies.
-template <typename TS, int M, int K, int PG, int TILE, int U, bool PKI>
+template <typename TS, int M, int K, int PG, int TILE, int U, int PKI>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
-  if constexpr (PKI) {
-    stage_body<TS, M, K, PG, TILE, U, true, true>(a);   // launched only for a proton step
+  if constexpr (PKI == 1) {
+    stage_body<TS, M, K, PG, TILE, U, true, 1>(a);   // launched only for a proton step
   } else {
-    if (a.act_is_P) stage_body<TS, M, K, PG, TILE, U, true, false>(a);
-    else stage_body<TS, M, K, PG, TILE, U, false, false>(a);
+    if (a.act_is_P) stage_body<TS, M, K, PG, TILE, U, true, PKI>(a);
+    else stage_body<TS, M, K, PG, TILE, U, false, PKI>(a);
   }
 }
 
@@ -576,7 +590,7 @@ hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s) {
 // differs, and every other distinct row only when it occurs; each output
 // still loads its own previous-stage operands.  Comparisons are on
 // wave-uniform values, so every branch is uniform.
-template <typename TS, int M, int K, int PG, int G>
+template <typename TS, int M, int K, int PG, int G, bool PKI>
 __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
   using CS = typename c2<TS>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
@@ -601,6 +615,8 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
 #pragma unroll
   for (int d = 0; d < M; d++) f_off[d] = uint32_t(lane_off(b, a.npsi) + a.psi_of_pos[d] * 16);
   const uint32_t in_lane = uint32_t(lane_off(b, ns_in));
+  // paired input (pairs along the input sets): element of the pair (2i, 2i+1)
+  const uint32_t in_lane_pk = uint32_t((b >> 4) * ns_in * 16 + (b & 15) * 2);
   const int64_t xstride = int64_t(ns_in) * Bp, ystride = int64_t(a.npsi) * Bp;
 
   double2 acc[G][PG][NOUT];
@@ -641,8 +657,18 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
 #pragma unroll
       for (int p = 0; p < PG; p++)
 #pragma unroll
-        for (int rr = 0; rr < NIN; rr++)
-          xin[g][p][rr] = ld(xrow, (in_lane + uint32_t(sig_in(rr, pass0 + p) * 16)) * uint32_t(sizeof(CS)));
+        for (int rr = 0; rr < NIN; rr++) {
+          if constexpr (PKI) {
+            if (rr % 2 == 0) {
+              const float4 v = ld(reinterpret_cast<const float4 *>(xrow),
+                                  (in_lane_pk + uint32_t(sig_in(rr, pass0 + p) * 16)) * uint32_t(sizeof(CS)));
+              xin[g][p][rr] = make_float2(v.x, v.y);
+              xin[g][p][rr + 1] = make_float2(v.z, v.w);
+            }
+          } else {
+            xin[g][p][rr] = ld(xrow, (in_lane + uint32_t(sig_in(rr, pass0 + p) * 16)) * uint32_t(sizeof(CS)));
+          }
+        }
     }
     double2 fya[M], fyb[M];
     load_y(ya, fya);
@@ -688,7 +714,18 @@ static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (ngrp + 7) / 8 * 8;
   if (!grid_x_fits(n8 * (a.npass / PG), 64)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / 64));
-  hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G>), grid, dim3(64), a.lds_bytes, s, a);
+  if (a.paired_in == 2) {
+    // pairs along the input sets (see launch_stage_mkptu)
+    if constexpr (std::is_same<T, float>::value && binom_c(M, K) % 2 == 0) {
+      if (a.act_is_P && a.npass != 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G, true>), grid, dim3(64), a.lds_bytes, s, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  if (a.paired_in) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G, false>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
@@ -697,18 +734,30 @@ static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
   const int64_t n8 = (a.nq_out + 7) / 8 * 8;
   if (!grid_x_fits(n8 * (a.npass / PG), 64)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(n8 * (a.npass / PG)), unsigned(a.Bp / TILE));
-  if (a.paired_in) {
-    // paired input: float stages, 64-lane tiles, even passthrough groups of
-    // a proton step with an even passthrough count
-    if constexpr (std::is_same<T, float>::value && TILE == 64 && PG % 2 == 0) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  if (a.paired_in == 1) {
+    // pairs along the passthrough parts: float stages, 64-lane tiles, even
+    // passthrough groups of a proton step with an even passthrough count
+    if constexpr (F32 && TILE == 64 && PG % 2 == 0) {
       if (!a.act_is_P || a.npass % 2) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, true>), grid, dim3(64), a.lds_bytes, s, a);
+      hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 1>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, false>), grid, dim3(64), a.lds_bytes, s, a);
+  if (a.paired_in == 2) {
+    // pairs along the input sets: an even number of them, neighbours in the
+    // stage order (a neutron step, or one passthrough part)
+    if constexpr (F32 && TILE == 64 && binom_c(M, K) % 2 == 0) {
+      if (a.act_is_P && a.npass != 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 2>), grid, dim3(64), a.lds_bytes, s, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 0>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
@@ -726,7 +775,6 @@ static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
 template <typename T, int M, int K, int PG>
 static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
   if constexpr (PG <= 3) {
-    if ((a.group == 2 || a.group == 4) && a.paired_in) return hipErrorInvalidValue;   // plain input only
     if (a.group == 2) return launch_stage_group<T, M, K, PG, 2>(a, s);
     if (a.group == 4) return launch_stage_group<T, M, K, PG, 4>(a, s);
   }

@@ -37,6 +37,7 @@ struct Stage {
   int tune_kernel = 0;                            // 0 direct gather, 1 blocks staged in LDS
   int tune_unroll = 0;                            // splits in flight per wavefront (0 automatic)
   int tune_group = 1;                             // outputs per wavefront (grouped kernel when > 1)
+  int tune_paired = 1;                            // input stage in the paired layout when possible
   int64_t nspin() const { return int64_t(nPsets) * nNsets; }
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };

@@ -89,8 +89,9 @@ struct StageArgs {
   int group;                 // outputs per wavefront of the grouped kernel: 1 (off), 2, 4
   int npsi;                  // baryon indices of the block layout
   int psi_of_pos[8];
-  int paired_in, paired_out; // stage layouts (spin_off); paired input only for the
-                             // direct kernel adding a proton, 64-lane tiles, even pg, float stages
+  int paired_in;             // input layout: 0 plain, 1 pairs along the passthrough parts,
+                             // 2 pairs along the input sets (float stages, 64-lane waves)
+  int paired_out;            // output stored in the paired layout (spin_off)
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);
 

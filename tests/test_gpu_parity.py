@@ -397,29 +397,34 @@ def test_loaded_term_list_contracts_identically(tmp_path):
 # --------------------------------------------------------------------- paired stage layout
 
 @pytest.mark.parametrize("rel,nsrc,nP,nN,spins,V,nl", [
-    (True, 1, 2, 2, None, 8, 70),                    # 4He relativistic: steps 2 and 3 read paired stages
-    (False, 2, 2, 2, (0, 2, 0, 2), 8, 64),          # 4He NR, two sources: no even passthrough count
+    (True, 1, 2, 2, None, 8, 70),                          # 4He relativistic: pairs of passthrough parts
+    (False, 2, 2, 2, (0, 2, 0, 2), 8, 64),                # pairs of input sets (neutron steps, one passthrough)
+    (False, 2, 4, 4, (0, 1, 2, 3, 0, 1, 2, 3), 8, 66),    # 8Be: every step kind
 ])
 def test_paired_stage_layout_is_bit_identical(rel, nsrc, nP, nN, spins, V, nl):
     """Float stages stored with neighbouring spin parts paired per lane (read
-    by the direct proton step with an even passthrough group) give exactly
-    the correlators of the plain layout: every output keeps its sum order."""
+    with one 16-byte load by the direct kernel with 64-lane tiles or the
+    grouped kernel) give exactly the correlators of the plain layout with
+    the same kernels: every output keeps its sum order."""
     Su, Sd, w, k = _inputs(71, nl, V, nsrc, np.complex64, True, with_sink=nsrc == 2)
     tl = _tl(rel, nsrc, nP, nN, spins)
     nst = tl.counts()["n_stages"]
-    res = {}
-    for pg in (3, 2, 6):
-        for s in range(1, nst):
-            tl.tune(s, B.MB_TUNE_KERNEL, 0)
-            tl.tune(s, B.MB_TUNE_GROUP, 1)
-            tl.tune(s, B.MB_TUNE_LANE_TILE, 64)
-            tl.tune(s, B.MB_TUNE_LDS_BYTES, 0)
-            tl.tune(s, B.MB_TUNE_UNROLL, 0)
-            try:
-                tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
-            except B.MBError:
-                tl.tune(s, B.MB_TUNE_PASS_GROUP, 1)
-        res[pg] = _run(tl, Su, Sd, w, k, B.MB_MIXED)[1]
-    assert np.array_equal(res[3], res[2]) and np.array_equal(res[3], res[6])
     _, ref, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
-    assert max(rel_err(res[6][b], ref[b]) for b in range(nl)) <= 1e-6
+    # (pass group, outputs per wave), 64-lane tiles
+    for pg, group in [(3, 1), (2, 1), (6, 1), (1, 1), (1, 2), (1, 4)]:
+        res = []
+        for paired in (0, 1):
+            for s in range(1, nst):
+                tl.tune(s, B.MB_TUNE_KERNEL, 0)
+                tl.tune(s, B.MB_TUNE_GROUP, group)
+                tl.tune(s, B.MB_TUNE_LANE_TILE, 64)
+                tl.tune(s, B.MB_TUNE_LDS_BYTES, 0)
+                tl.tune(s, B.MB_TUNE_UNROLL, 0)
+                tl.tune(s, B.MB_TUNE_PAIRED, paired)
+                try:
+                    tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
+                except B.MBError:
+                    tl.tune(s, B.MB_TUNE_PASS_GROUP, 1)
+            res.append(_run(tl, Su, Sd, w, k, B.MB_MIXED)[1])
+        assert np.array_equal(res[0], res[1]), (pg, group)
+        assert max(rel_err(res[1][b], ref[b]) for b in range(nl)) <= 1e-6, (pg, group)

@@ -369,14 +369,14 @@ def test_launch_tuning_validation():
     ok = [(B.MB_TUNE_PASS_GROUP, 0), (B.MB_TUNE_LANE_TILE, 16), (B.MB_TUNE_LANE_TILE, 64),
           (B.MB_TUNE_LDS_BYTES, 0), (B.MB_TUNE_LDS_BYTES, 65536), (B.MB_TUNE_KERNEL, 1), (B.MB_TUNE_KERNEL, 0),
           (B.MB_TUNE_UNROLL, 0), (B.MB_TUNE_UNROLL, 2), (B.MB_TUNE_GROUP, 4), (B.MB_TUNE_GROUP, 2),
-          (B.MB_TUNE_GROUP, 1)]
+          (B.MB_TUNE_GROUP, 1), (B.MB_TUNE_PAIRED, 0), (B.MB_TUNE_PAIRED, 1)]
     for what, v in ok:
         tl.tune(3, what, v)
     for g in (1, 2, 3, 6):
         tl.tune(3, B.MB_TUNE_PASS_GROUP, g)
     bad = [(B.MB_TUNE_PASS_GROUP, 4), (B.MB_TUNE_PASS_GROUP, 5), (B.MB_TUNE_LANE_TILE, 32),
            (B.MB_TUNE_LDS_BYTES, 65537), (B.MB_TUNE_KERNEL, 2), (B.MB_TUNE_UNROLL, 3), (B.MB_TUNE_GROUP, 3),
-           (B.MB_TUNE_GROUP, 8),
+           (B.MB_TUNE_GROUP, 8), (B.MB_TUNE_PAIRED, 2),
            (99, 0)]
     for what, v in bad:
         with pytest.raises(B.MBError):
