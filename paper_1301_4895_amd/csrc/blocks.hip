@@ -31,17 +31,21 @@ __device__ inline double2 scaled(double2 v, double scale) { return make_double2(
 // A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.  A complex product
 // is three real MFMAs (below).
 //
-// The workgroup's eight waves take two roles.  Waves 4-7 (builders) stage
-// the propagators of a group of sites in LDS and build the operands of that
-// group there (the diquark on the vector units); waves 0-3 multiply the
-// previous group on the matrix cores, each owning a quarter of the 16x16
-// output tiles.  Operands and staged propagators are double-buffered, so one
-// barrier per group separates the roles, and every SIMD holds one wave of
-// each: its vector and matrix units work at the same time.
+// The workgroup's waves take two roles.  Four builder waves stage the
+// propagators of a group of sites in LDS and build the operands of that
+// group there (the diquark on the vector units); NMW waves (four, or two for
+// the two or three output tiles of nonrelativistic operators with one
+// source) multiply the previous group on the matrix cores, each owning an
+// equal share of the 16x16 output tiles.  Operands and staged propagators
+// are double-buffered, so one barrier per group separates the roles, and a
+// SIMD holds waves of both roles: its vector and matrix units work at the
+// same time.
 typedef double mb_d4 __attribute__((ext_vector_type(4)));
 
-template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
-__global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
+// NMW: multiplying waves (the builders are always four waves, 256 threads);
+// fewer than four when there are fewer output tiles than four.
+template <typename TIN, int NXI, int NPSI, int NROW, bool SYM, int NMW>
+__global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int NPAIR = SYM ? NXI * (NXI + 1) / 2 : NXI * NXI;
   constexpr int M = NPSI * NXI;
   constexpr int MT = (M + 15) / 16, NT = (NPAIR + 15) / 16;
@@ -49,7 +53,8 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int NS = 4;                // sites per group
   constexpr int KG = 3 * NS;           // k = 3 * site + colour, multiple of 4
   constexpr int NTILE = MT * NT;
-  constexpr int TPW = (NTILE + 3) / 4;  // tiles per multiplying wave
+  constexpr int TPW = (NTILE + NMW - 1) / NMW;  // tiles per multiplying wave
+  constexpr int NT_ALL = 64 * (NMW + 4);        // threads of the workgroup
   constexpr int D = NROW / 3;
   constexpr int NB = SYM ? 1 : 2;      // buffers of the q1 and d slots
 
@@ -65,9 +70,9 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   __shared__ unsigned char px2[NP], px3[NP];  // pair index -> (xi2, xi3)
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const bool builder = wave >= 4;
-  const int bt = tid & 255;            // thread index within its role
-  for (int p = tid; p < NP; p += 512) {
+  const bool builder = wave >= NMW;
+  const int bt = (tid - 64 * NMW) & 255;   // thread index within its role (builders: 0..255)
+  for (int p = tid; p < NP; p += NT_ALL) {
     int x2 = 0, x3 = 0;
     if (p < NPAIR) {
       if (SYM) {
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
         double oa[TPW][3], ob[TPW][3];
 #pragma unroll
         for (int j = 0; j < TPW; j++) {
-          const int t = min(wave + 4 * j, NTILE - 1);
+          const int t = min(wave + NMW * j, NTILE - 1);
           const int mt = t / NT, nt = t % NT;
           const int am = mt * 16 + (lane & 15), bn = nt * 16 + (lane & 15);
           const double2 av = Ac[buf][k][am], bv = Bc[buf][k][bn];
@@ -284,7 +289,7 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   double2 *out = reinterpret_cast<double2 *>(a.partial) + ((ln * a.nchunk + chunk) * NPSI) * int64_t(NXI) * NPAIR;
 #pragma unroll
   for (int j = 0; j < TPW; j++) {
-    const int t = wave + 4 * j;
+    const int t = wave + NMW * j;
     if (t < NTILE) {
       const int mt = t / NT, nt = t % NT;
       const int n = nt * 16 + (lane & 15);
@@ -299,10 +304,10 @@ __global__ __launch_bounds__(512) void blocks_mfma_kernel(BlocksArgs a) {
   }
 }
 
-template <typename TIN, int NXI, int NPSI, int NROW, bool SYM>
+template <typename TIN, int NXI, int NPSI, int NROW, bool SYM, int NMW = 4>
 static hipError_t launch_bm(const BlocksArgs &a, hipStream_t s) {
   dim3 grid(a.nchunk, unsigned(a.B));
-  hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM>), grid, dim3(512), 0, s, a);
+  hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM, NMW>), grid, dim3(64 * (NMW + 4)), 0, s, a);
   return hipGetLastError();
 }
 
@@ -310,8 +315,10 @@ template <typename TIN>
 static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
   if (a.D == 4 && a.nsrc == 1)
     return sym ? launch_bm<TIN, 12, 4, 12, true>(a, s) : launch_bm<TIN, 12, 4, 12, false>(a, s);
+  // NR, one source: two output tiles (symmetric pairs) or three, so two
+  // multiplying waves; the smaller workgroups fit more of them per CU
   if (a.D == 2 && a.nsrc == 1)
-    return sym ? launch_bm<TIN, 6, 2, 6, true>(a, s) : launch_bm<TIN, 6, 2, 6, false>(a, s);
+    return sym ? launch_bm<TIN, 6, 2, 6, true, 2>(a, s) : launch_bm<TIN, 6, 2, 6, false, 2>(a, s);
   if (a.D == 2 && a.nsrc == 2)
     return sym ? launch_bm<TIN, 12, 4, 6, true>(a, s) : launch_bm<TIN, 12, 4, 6, false>(a, s);
   return hipErrorInvalidValue;
