@@ -779,3 +779,16 @@ def test_loading_rejects_foreign_and_damaged_files(tmp_path):
             assert err.code == B.MB_EINVAL
             continue
         _all_exports(t2)
+
+
+def test_order_search_uses_the_projected_support():
+    """With a projection the search counts the orders on the pruned final
+    quark parts: its count is the minimum over every projected order."""
+    full = B.TermList(2, 1, False, 1, all_components=True)
+    c = full.counts()
+    W = sparse_weights((c["n_delta"], c["n_alpha"]), 3, 0.3)
+    counts = {m: B.TermList(2, 1, False, 1, all_components=True, proj=W, path=B.MB_PATH_EXPLICIT, order=m,
+                            counts_only=True).counts()["n_lambda"] for m in _masks(3, 2)}
+    best = B.TermList(2, 1, False, 1, all_components=True, proj=W, path=B.MB_PATH_BEST, counts_only=True).counts()
+    assert best["projected"] and best["n_lambda"] == min(counts.values())
+    assert best["n_lambda"] <= c["n_lambda"]
