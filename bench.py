@@ -165,12 +165,20 @@ def run_workload(name, args):
         tuning[prec_name] = None
         if not args.no_autotune:
             from paper_1301_4895_amd import autotune
-            best = autotune.tune(tl, r, key=f"{name}|{prec_name}|{chunk}", cache=args.tune_cache,
-                                 log=log)
-            tuning[prec_name] = {str(k): {"kernel": "lds-staged" if v[0] else "direct", "pass_group": v[1],
-                                          "lds_bytes": v[2], "lane_tile": v[3], "unroll": v[4],
-                                          "outputs_per_wave": v[5], "ms": round(v[6], 3)}
-                                 for k, v in best.items()}
+            key = f"{name}|{prec_name}|{chunk}"
+            best = None if args.retune else autotune.committed(key)
+            source = "committed (paper_1301_4895_amd/tuned.json)"
+            if best is not None:
+                autotune.apply(tl, best)
+                log(f"[bench] {name} {prec_name}: committed launch settings")
+            else:
+                best = autotune.tune(tl, r, key=key, cache=args.tune_cache, log=log)
+                source = "autotuned in this run"
+            tuning[prec_name] = {"source": source, "steps": {
+                str(k): {"kernel": "lds-staged" if v[0] else "direct", "pass_group": v[1],
+                         "lds_bytes": v[2], "lane_tile": v[3], "unroll": v[4],
+                         "outputs_per_wave": v[5], "ms_when_tuned": round(v[6], 3)}
+                for k, v in best.items()}}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
         ev = {}
 
@@ -382,7 +390,9 @@ def main():
                     help="lanes per launch (default: every lane of the workload in one launch; batch items of at most 256 lanes for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="library default launch settings")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune every step in this run instead of using the committed settings")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned launch settings (read/write)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")

@@ -35,10 +35,12 @@
  * stream (NULL = default stream); device faults surface at the caller's next
  * synchronisation.
  *
- * Errors.  Every call returns MB_OK (0) or a negative MB_E* code; arguments
- * are validated on the host before anything is launched, and nothing is
- * launched when a call fails.  mb_last_error() gives a message for the last
- * failure of the calling thread.
+ * Errors.  Every call returns MB_OK (0) or a negative MB_E* code; arguments,
+ * and the existence of a kernel for every launch of the call, are validated
+ * on the host before anything is launched, and nothing is launched when a
+ * call fails validation (MB_EHIP from the runtime during the launches can
+ * leave earlier launches of the call queued).  mb_last_error() gives a
+ * message for the last failure of the calling thread.
  */
 #ifndef MBCONTRACT_H
 #define MBCONTRACT_H
@@ -391,17 +393,41 @@ int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
  *             the main nucleus' 3*A*scale_exp[b])
  *   exp_out   device, int32 [B] or NULL: 3*A*scale_exp[b], so that the
  *             correlator of the unscaled propagators is corr_out * 2^-exp_out
+ *   err_out   device, double [B][n_out][2] or NULL: for every output of
+ *             corr_out (same order, main then side outputs), an a-posteriori
+ *             estimate of how far the MB_MIXED result lies from the MB_FP64
+ *             result for the same blocks, in the units of corr_out:
+ *               [0]  sigma: standard deviation of that difference when the
+ *                    rounding errors of the float stage storage are taken as
+ *                    independent (each stored real rounded to nearest, error
+ *                    uniform on half an ulp each side), propagated through
+ *                    every step of eq. recr_F and the sum of eq. C_final;
+ *               [1]  bound: the same propagation with absolute values, a
+ *                    bound to first order in u = 2^-24 (it ignores u^2 terms
+ *                    and the double-precision rounding common to both paths).
+ *             The propagation runs extra kernels over two error stages (one
+ *             float pair per component) and needs mb_workspace_query_err
+ *             more workspace bytes after contract_ws_bytes.  MB_FP64 writes
+ *             zeros (no extra workspace).  The correlators themselves do not
+ *             change.
  * The term list must be uploaded.                                           */
 int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p,
                            const void *blocks, size_t blocks_bytes, double *corr_out,
-                           int32_t *exp_out, void *ws, size_t ws_bytes, void *stream);
+                           int32_t *exp_out, double *err_out, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Additional contraction workspace (bytes, after contract_ws_bytes) that
+ * mb_contract_correlator needs with err_out != NULL: two error stages of
+ * 8 bytes per component and lane, plus per-sink-set estimates of a projected
+ * list; 0 for MB_FP64.                                                     */
+int mb_workspace_query_err(const mb_term_list *tl, const mb_problem *p, size_t *err_ws_bytes);
 
 /* One part of mb_contract_correlator, for timing the parts separately:
  * step 0 copies the first baryon's block into stage 0, step s in 1..A-1 is
  * recursion step s (eq. recr_F), step A is the final sum (corr_out, exp_out
  * as above; ignored for the other steps).  Running steps 0..A in order on
- * one stream is exactly mb_contract_correlator; the workspace carries the
- * stages between the calls.                                                 */
+ * one stream is exactly mb_contract_correlator with err_out = NULL; the
+ * workspace carries the stages between the calls.                           */
 int mb_contract_step(const mb_term_list *tl, const mb_problem *p, const void *blocks,
                      size_t blocks_bytes, int step, double *corr_out, int32_t *exp_out, void *ws,
                      size_t ws_bytes, void *stream);

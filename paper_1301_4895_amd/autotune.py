@@ -8,6 +8,11 @@ reserved per workgroup (which caps resident workgroups, hence operands in
 flight per L2) -- on the caller's own buffers, keeps the fastest, and records
 the choice in a JSON cache keyed by workload, precision, lanes and device.
 Results of the method do not depend on the settings.
+
+The choices the benchmark times are kept in ``tuned.json`` beside this file
+(read only: ``committed`` and ``apply``), so that the timed launch settings
+are the ones the full-size parity tests run; ``tune`` writes only to a cache
+file the caller names.
 """
 from __future__ import annotations
 
@@ -20,6 +25,7 @@ import torch
 from . import binding as B
 
 LDS_CANDIDATES = (0, 16384)
+COMMITTED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 TILES = (64, 16)
 
 
@@ -45,6 +51,32 @@ def _apply(tl, s, kernel, pg, lds, tile, unroll, group):
     tl.tune(s, B.MB_TUNE_GROUP, group)
 
 
+def _device_arch():
+    if torch.cuda.is_available():
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return "gfx950"
+
+
+def full_key(key):
+    return f"{key}|{_device_arch()}|{CACHE_VERSION}"
+
+
+def committed(key):
+    """The committed launch settings of a workload key ("c3|mixed|768"), or
+    None: {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group, ms)}."""
+    if not os.path.exists(COMMITTED):
+        return None
+    table = json.load(open(COMMITTED))
+    v = table.get(full_key(key))
+    return None if v is None else {int(s): tuple(x) for s, x in v.items()}
+
+
+def apply(tl, best):
+    """Sets every step's launch settings from a {step: settings} table."""
+    for s, v in best.items():
+        _apply(tl, s, *v[:6])
+
+
 def _time_step(tl, runner, step, reps, stream):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     ev[0].record(stream)
@@ -61,16 +93,14 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
     """Tunes every step on ``runner``'s buffers.
     Returns {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group, ms)}."""
     c = tl.counts()
-    dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
-    full_key = f"{key}|{dev}|{CACHE_VERSION}" if key else None
-    if cache and full_key and os.path.exists(cache):
+    fkey = full_key(key) if key else None
+    if cache and fkey and os.path.exists(cache):
         table = json.load(open(cache))
-        if full_key not in table and log:
-            log(f"[autotune] {full_key} not in {cache}: tuning")
-        if full_key in table:
-            best = {int(s): tuple(v) for s, v in table[full_key].items()}
-            for s, v in best.items():
-                _apply(tl, s, *v[:-1])
+        if fkey not in table and log:
+            log(f"[autotune] {fkey} not in {cache}: tuning")
+        if fkey in table:
+            best = {int(s): tuple(v) for s, v in table[fkey].items()}
+            apply(tl, best)
             return best
     stream = torch.cuda.current_stream()
     # bring every stage to a valid state once
@@ -101,9 +131,9 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
             log(f"[autotune] step {s}: " + ", ".join(
                 f"{'lds' if k else 'dir'}/pg{g}/lds{l}/t{t}/u{u}/g{gr}={m:.2f}ms"
                 for m, k, g, l, t, u, gr in sorted(results)[:4]))
-    if cache and full_key:
+    if cache and fkey:
         table = json.load(open(cache)) if os.path.exists(cache) else {}
-        table[full_key] = {str(s): list(v) for s, v in best.items()}
+        table[fkey] = {str(s): list(v) for s, v in best.items()}
         json.dump(table, open(cache, "w"), indent=1)
     return best
 

@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_build_term_list_path", "mb_term_list_free",
     "mb_term_list_save", "mb_term_list_load",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
-    "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune",
+    "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune", "mb_workspace_query_err",
     "mb_batch_plan", "mb_batch_create", "mb_batch_launch", "mb_batch_kernel_count", "mb_batch_free",
     "mb_last_error",
 ]
@@ -105,8 +105,9 @@ def lib():
         L.mb_workspace_query.argtypes = [P, C.POINTER(mb_problem), C.POINTER(C.c_size_t),
                                          C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.mb_make_blocks.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, C.c_size_t, P]
-        L.mb_contract_correlator.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, P, P,
+        L.mb_contract_correlator.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, P, P, P,
                                              C.c_size_t, P]
+        L.mb_workspace_query_err.argtypes = [P, C.POINTER(mb_problem), C.POINTER(C.c_size_t)]
         L.mb_contract_step.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, C.c_int, P, P, P,
                                        C.c_size_t, P]
         L.mb_term_list_tune.argtypes = [P, C.c_int, C.c_int, C.c_int]
@@ -261,6 +262,13 @@ def workspace_query(tl: TermList, p: mb_problem):
     return a.value, b.value, c.value
 
 
+def workspace_query_err(tl: TermList, p: mb_problem):
+    """Extra contraction workspace bytes for error estimates."""
+    a = C.c_size_t()
+    _check(lib().mb_workspace_query_err(tl.h, C.byref(p), C.byref(a)))
+    return a.value
+
+
 def make_blocks(tl: TermList, p: mb_problem, blocks, ws, stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
@@ -268,12 +276,15 @@ def make_blocks(tl: TermList, p: mb_problem, blocks, ws, stream=None):
                                 C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))
 
 
-def contract_correlator(tl: TermList, p: mb_problem, blocks, corr, exp_out, ws, stream=None):
+def contract_correlator(tl: TermList, p: mb_problem, blocks, corr, exp_out, ws, stream=None, err=None):
+    """err: optional float64 device tensor [batch][n_out][2] for the error
+    estimates (then ws must hold workspace_query_err more bytes)."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     _check(lib().mb_contract_correlator(
         tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()), blocks.numel() * blocks.element_size(),
         C.c_void_p(corr.data_ptr()), C.c_void_p(exp_out.data_ptr()) if exp_out is not None else None,
+        C.c_void_p(err.data_ptr()) if err is not None else None,
         C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))
 
 

@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -37,12 +38,13 @@ def _compile(src, obj, kind):
 
 def build_library(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
-    for name, kind in [("termlist.cpp", "host"), ("capi.cpp", "hipapi"), ("batch.cpp", "hipapi"), ("blocks.hip", "hip"),
-                       ("contract.hip", "hip")]:
-        obj = os.path.join(BUILD_DIR, name + ".o")
-        _compile(os.path.join(CSRC, name), obj, kind)
-        objs.append(obj)
+    units = [("termlist.cpp", "host"), ("capi.cpp", "hipapi"), ("batch.cpp", "hipapi"), ("blocks.hip", "hip"),
+             ("contract.hip", "hip"), ("errest.hip", "hip")]
+    objs = [os.path.join(BUILD_DIR, name + ".o") for name, _ in units]
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(units), os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(_compile, os.path.join(CSRC, name), obj, kind) for (name, kind), obj in zip(units, objs)]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

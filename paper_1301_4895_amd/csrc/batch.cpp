@@ -143,7 +143,7 @@ int mb_batch_create(const mb_batch_item *items, int n_items, int n_branches, mb_
     rc = mb_make_blocks(it.tl, &it.prob, it.blocks, it.blocks_bytes, it.blocks_ws, it.blocks_ws_bytes, s);
     if (rc == MB_OK)
       rc = mb_contract_correlator(it.tl, &it.prob, it.blocks, it.blocks_bytes, it.corr_out, it.exp_out,
-                                  it.contract_ws, it.contract_ws_bytes, s);
+                                  nullptr, it.contract_ws, it.contract_ws_bytes, s);
   }
   for (int k = 0; k < n_branches && rc == MB_OK; k++) {
     he = hipEventRecord(c.join[k], c.br[k]);

@@ -78,6 +78,25 @@ void stage_buffer_sizes(const mb_term_list *tl, const mb_problem *p, size_t *eve
   *odd = al256(o);
 }
 
+// The error-estimate area of a mixed contraction: two error stages (float2
+// (E, S) per component, plain layout) and, for a projected list, the
+// per-sink-set estimates.
+void err_stage_sizes(const mb_term_list *tl, const mb_problem *p, size_t *even, size_t *odd) {
+  size_t e = 0, o = 0;
+  for (int s = 0; s < tl->nstages; s++) {
+    size_t n = size_t(tl->st[s].nreq()) * size_t(lanes_padded(p->batch)) * 8;
+    if (s % 2 == 0) e = std::max(e, n);
+    else o = std::max(o, n);
+  }
+  *even = al256(e);
+  *odd = al256(o);
+}
+size_t err_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+  size_t e, o;
+  err_stage_sizes(tl, p, &e, &o);
+  return e + o + proj_bytes_of(tl, p);
+}
+
 void psi_positions(uint32_t base, int *out) {
   int k = 0;
   for (int i = 0; i < 32 && k < 8; i++)
@@ -283,7 +302,7 @@ int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks, si
 }
 
 static int contract_steps(const mb_term_list *tl, const mb_problem *p, const void *blocks,
-                          size_t blocks_bytes, double *corr_out, int32_t *exp_out, void *ws,
+                          size_t blocks_bytes, double *corr_out, int32_t *exp_out, double *err_out, void *ws,
                           size_t ws_bytes, void *stream, int first_step, int last_step) {
   int rc = check_problem(tl, p);
   if (rc) return rc;
@@ -296,16 +315,29 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
   size_t ev, od;
   stage_buffer_sizes(tl, p, &ev, &od);
-  if (ws_bytes < ev + od + proj_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t main_ws = ev + od + proj_bytes_of(tl, p);
+  if (ws_bytes < main_ws) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
   const bool mixed = p->precision == MB_MIXED;
+  // error estimates of the float stages (mixed path only; the FP64 path
+  // reports 0): two error stages and the projected partials after the stages
+  const bool err_stages = err_out && mixed;
+  if (err_out && (first_step != 0 || last_step != tl->nstages))
+    return fail(MB_EINVAL, "error estimates need the whole contraction");
+  if (err_stages && ws_bytes < main_ws + err_bytes_of(tl, p))
+    return fail(MB_ENOWORKSPACE, "contraction workspace too small for the error estimates");
+  hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t Bp = lanes_padded(p->batch);
   const int nxi = tl->nxi;
   const int nyq = nxi * (nxi - 1) / 2 * nxi;
   const char *blk = static_cast<const char *>(blocks);
   const void *fblk[2] = {blk, blk + size_t(tl->npsi) * nyq * Bp * 16};  // proton, neutron
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
+  size_t eev = 0, eod = 0;
+  err_stage_sizes(tl, p, &eev, &eod);
+  char *ebuf[2] = {static_cast<char *>(ws) + main_ws, static_cast<char *>(ws) + main_ws + eev};
+  double *eproj = reinterpret_cast<double *>(static_cast<char *>(ws) + main_ws + eev + eod);
   const char *img = static_cast<const char *>(tl->dev);
+  const int32_t *lane_exp = reinterpret_cast<const int32_t *>(blk + blocks_entry_bytes(tl, p));
 
   // Float stage j is stored in the paired layout (neighbouring spin parts of
   // a lane together, one 16-byte load) when every thread of the step that
@@ -332,136 +364,219 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
     if ((direct64 || grouped) && nin % 2 == 0 && (!AP || npass == 1)) return 2;
     return 0;
   };
+  // a launcher's refusal in the validation pass: no kernel for this shape
+  auto launch_rc = [&](hipError_t e, const char *what) {
+    if (e == hipSuccess) return MB_OK;
+    if (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration)
+      return fail(MB_EUNSUPPORTED, std::string(what) + ": no kernel for this step's shape and launch settings");
+    return fail(MB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  auto final_args = [&](const void *F, size_t o_row, size_t o_col, size_t o_val, double *out, int n_delta,
+                        int n_alpha, int A, double inv_fact) {
+    FinalArgs a{};
+    a.F = F;
+    a.crow = reinterpret_cast<const int64_t *>(img + o_row);
+    a.ccol = reinterpret_cast<const int32_t *>(img + o_col);
+    a.cval = reinterpret_cast<const double *>(img + o_val);
+    a.corr = out;
+    a.scale_exp = p->scale_exp;
+    a.B = p->batch;
+    a.Bp = Bp;
+    a.n_delta = n_delta;
+    a.n_alpha = n_alpha;
+    a.A = A;
+    a.lane_exp = lane_exp;
+    a.inv_fact = inv_fact;
+    return a;
+  };
+  auto err_final = [&](const FinalArgs &f, const void *E, double *out, int diag) {
+    ErrFinalArgs a{};
+    a.E = E;
+    a.crow = f.crow;
+    a.ccol = f.ccol;
+    a.cval = f.cval;
+    a.err = out;
+    a.lane_exp = lane_exp;
+    a.B = f.B;
+    a.Bp = Bp;
+    a.n_delta = f.n_delta;
+    a.n_alpha = f.n_alpha;
+    a.A = f.A;
+    a.inv_fact = f.inv_fact;
+    a.diag = diag;
+    return launch_err_final(a, s);
+  };
 
-  for (int step = first_step; step <= last_step; step++) {
-    if (step == 0) {
-      // the first baryon's block restricted to the required components
-      const Stage &S0 = tl->st[0];
-      Stage0Args a{};
-      a.fblk = fblk[S0.type];
-      a.Fout = buf[0];
-      a.first = reinterpret_cast<const uint32_t *>(img + tl->off_first);
-      a.nq = int64_t(S0.quark.size());
-      a.Bp = Bp;
-      a.nyq = nyq;
-      a.ns = int(S0.nspin());
-      a.npsi = tl->npsi;
-      psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
-      a.paired_out = paired(0) != 0;
-      if (a.nq * a.ns > 0) HIP_CHECK(launch_stage0(a, mixed, s));
-    } else if (step < tl->nstages) {
-      const Stage &S = tl->st[step], &Pv = tl->st[step - 1];
-      StageArgs a{};
-      a.Fin = buf[(step - 1) % 2];
-      a.Fout = buf[step % 2];
-      a.fblk = fblk[S.type];
-      a.qsplit = reinterpret_cast<const uint32_t *>(img + tl->off_qsplit[step]);
-      a.nq_out = int64_t(S.quark.size());
-      a.Bp = Bp;
-      a.Sq = S.Sq;
-      a.nyq = nyq;
-      a.act_is_P = S.type == PROTON;
-      a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
-      a.K = S.type == PROTON ? Pv.kP : Pv.kN;
-      a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
-      a.pg = S.tune_pg;
-      a.lds_bytes = S.tune_lds;
-      a.tile = S.tune_tile;
-      a.unroll = S.tune_unroll;
-      a.group = S.tune_group;
-      a.paired_in = paired(step - 1);
-      a.paired_out = paired(step) != 0;
-      a.npsi = tl->npsi;
-      psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
-      if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
-      if (a.nq_out > 0 && S.tune_kernel == 1) {
-        StageLdsArgs b{};
-        b.Fin = a.Fin;
-        b.Fout = a.Fout;
-        b.fblk = a.fblk;
-        b.qsplit = a.qsplit;
-        b.masks = reinterpret_cast<const uint32_t *>(img + tl->off_masks[step]);
-        b.nq_out = a.nq_out;
-        b.Bp = Bp;
-        b.Sq = S.Sq;
-        b.pp = S.Sq / (S.type == PROTON ? S.kd : S.ku);
-        b.npass = a.npass;
-        b.pg = (S.tune_pg >= 1 && S.tune_pg <= 3) ? S.tune_pg : (a.npass % 3 == 0 ? 3 : a.npass % 2 == 0 ? 2 : 1);
-        b.npg = a.npass / b.pg;
-        b.act_is_P = a.act_is_P;
-        b.M = a.M;
-        b.K = a.K;
-        b.nxi = nxi;
-        b.npair = nxi * (nxi - 1) / 2;
-        b.npsi = tl->npsi;
-        b.bsplit = nxi > 9 ? 9 : nxi;
-        b.div_magic = uint32_t(((uint64_t(1) << 32) + uint64_t(nxi) - 1) / uint64_t(nxi));
-        for (int i = 0; i < 8; i++) b.psi_of_pos[i] = a.psi_of_pos[i];
-        b.paired_out = a.paired_out;
-        HIP_CHECK(launch_stage_lds(b, mixed, s));
-      } else if (a.nq_out > 0) {
-        HIP_CHECK(launch_stage(a, mixed, s));
+  // Pass 0 validates every launch (nothing runs); pass 1 launches.
+  for (int pass = 0; pass < 2; pass++) {
+    const bool dry = pass == 0;
+    for (int step = first_step; step <= last_step; step++) {
+      if (step == 0) {
+        // the first baryon's block restricted to the required components
+        const Stage &S0 = tl->st[0];
+        Stage0Args a{};
+        a.fblk = fblk[S0.type];
+        a.Fout = buf[0];
+        a.first = reinterpret_cast<const uint32_t *>(img + tl->off_first);
+        a.nq = int64_t(S0.quark.size());
+        a.Bp = Bp;
+        a.nyq = nyq;
+        a.ns = int(S0.nspin());
+        a.npsi = tl->npsi;
+        psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+        a.paired_out = paired(0) != 0;
+        if (!dry && a.nq * a.ns > 0) {
+          HIP_CHECK(launch_stage0(a, mixed, s));
+          if (err_stages) {
+            ErrStageArgs e{};
+            e.Eout = ebuf[0];
+            e.F = buf[0];
+            e.nq_out = a.nq;
+            e.Bp = Bp;
+            e.ns_out = a.ns;
+            e.paired_F = a.paired_out;
+            HIP_CHECK(launch_err_stage0(e, s));
+          }
+        }
+      } else if (step < tl->nstages) {
+        const Stage &S = tl->st[step], &Pv = tl->st[step - 1];
+        StageArgs a{};
+        a.Fin = buf[(step - 1) % 2];
+        a.Fout = buf[step % 2];
+        a.fblk = fblk[S.type];
+        a.qsplit = reinterpret_cast<const uint32_t *>(img + tl->off_qsplit[step]);
+        a.nq_out = int64_t(S.quark.size());
+        a.Bp = Bp;
+        a.Sq = S.Sq;
+        a.nyq = nyq;
+        a.act_is_P = S.type == PROTON;
+        a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
+        a.K = S.type == PROTON ? Pv.kP : Pv.kN;
+        a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
+        a.pg = S.tune_pg;
+        a.lds_bytes = S.tune_lds;
+        a.tile = S.tune_tile;
+        a.unroll = S.tune_unroll;
+        a.group = S.tune_group;
+        a.paired_in = paired(step - 1);
+        a.paired_out = paired(step) != 0;
+        a.npsi = tl->npsi;
+        a.dry = dry;
+        psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+        if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
+        if (a.nq_out > 0 && S.tune_kernel == 1) {
+          StageLdsArgs b{};
+          b.Fin = a.Fin;
+          b.Fout = a.Fout;
+          b.fblk = a.fblk;
+          b.qsplit = a.qsplit;
+          b.masks = reinterpret_cast<const uint32_t *>(img + tl->off_masks[step]);
+          b.nq_out = a.nq_out;
+          b.Bp = Bp;
+          b.Sq = S.Sq;
+          b.pp = S.Sq / (S.type == PROTON ? S.kd : S.ku);
+          b.npass = a.npass;
+          b.pg = (S.tune_pg >= 1 && S.tune_pg <= 3) ? S.tune_pg : (a.npass % 3 == 0 ? 3 : a.npass % 2 == 0 ? 2 : 1);
+          b.npg = a.npass / b.pg;
+          b.act_is_P = a.act_is_P;
+          b.M = a.M;
+          b.K = a.K;
+          b.nxi = nxi;
+          b.npair = nxi * (nxi - 1) / 2;
+          b.npsi = tl->npsi;
+          b.bsplit = nxi > 9 ? 9 : nxi;
+          b.div_magic = uint32_t(((uint64_t(1) << 32) + uint64_t(nxi) - 1) / uint64_t(nxi));
+          for (int i = 0; i < 8; i++) b.psi_of_pos[i] = a.psi_of_pos[i];
+          b.paired_out = a.paired_out;
+          b.dry = dry;
+          if ((rc = launch_rc(launch_stage_lds(b, mixed, s), "recursion step (LDS-staged kernel)"))) return rc;
+        } else if (a.nq_out > 0) {
+          if ((rc = launch_rc(launch_stage(a, mixed, s), "recursion step"))) return rc;
+        }
+        if (err_stages && a.nq_out > 0) {
+          if (dry) {
+            if (!grid_x_fits(a.nq_out * a.npass, 64))
+              return fail(MB_EUNSUPPORTED, "error estimate: grid too large for this step");
+          } else {
+            ErrStageArgs e{};
+            e.Ein = ebuf[(step - 1) % 2];
+            e.Eout = ebuf[step % 2];
+            e.F = a.Fout;
+            e.fblk = a.fblk;
+            e.qsplit = a.qsplit;
+            e.nq_out = a.nq_out;
+            e.Bp = Bp;
+            e.Sq = a.Sq;
+            e.npass = a.npass;
+            e.ns_out = int(S.nspin());
+            e.act_is_P = a.act_is_P;
+            e.M = a.M;
+            e.K = a.K;
+            e.npsi = tl->npsi;
+            for (int i = 0; i < 8; i++) e.psi_of_pos[i] = a.psi_of_pos[i];
+            e.paired_F = a.paired_out;
+            HIP_CHECK(launch_err_stage(e, s));
+          }
+        }
+      } else if (!dry) {
+        const Stage &SN = tl->st[tl->nstages - 1];
+        const int last = tl->nstages - 1;
+        FinalArgs a = final_args(buf[last % 2], tl->off_crow, tl->off_ccol, tl->off_cval, corr_out,
+                                 int(SN.nspin()), int(tl->alphas.size()), tl->A,
+                                 1.0 / (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N))));
+        a.exp_out = exp_out;
+        if (tl->projected) {
+          // row delta of the list pairs with sink set delta only; the sums per
+          // delta go to the workspace and are then added in delta order
+          a.diag = 1;
+          a.corr = reinterpret_cast<double *>(buf[1] + od);
+          HIP_CHECK(launch_final(a, mixed, s));
+          HIP_CHECK(launch_project(a.corr, corr_out, p->batch, a.n_delta, s));
+          if (err_stages) {
+            HIP_CHECK(err_final(a, ebuf[last % 2], eproj, 1));
+            HIP_CHECK(launch_err_project(eproj, err_out, p->batch, a.n_delta, s));
+          }
+        } else {
+          HIP_CHECK(launch_final(a, mixed, s));
+          if (err_stages) HIP_CHECK(err_final(a, ebuf[last % 2], err_out, 0));
+        }
+        if (err_out && !err_stages) HIP_CHECK(launch_zero(err_out, 2 * p->batch * tl->main_outputs(), s));
       }
-    } else {
-      const Stage &SN = tl->st[tl->nstages - 1];
-      FinalArgs a{};
-      a.F = buf[(tl->nstages - 1) % 2];
-      a.crow = reinterpret_cast<const int64_t *>(img + tl->off_crow);
-      a.ccol = reinterpret_cast<const int32_t *>(img + tl->off_ccol);
-      a.cval = reinterpret_cast<const double *>(img + tl->off_cval);
-      a.corr = corr_out;
-      a.exp_out = exp_out;
-      a.scale_exp = p->scale_exp;
-      a.B = p->batch;
-      a.Bp = Bp;
-      a.n_delta = int(SN.nspin());
-      a.n_alpha = int(tl->alphas.size());
-      a.A = tl->A;
-      a.lane_exp = reinterpret_cast<const int32_t *>(blk + blocks_entry_bytes(tl, p));
-      a.inv_fact = 1.0 / (double(factorial(tl->nuc.n_P)) * double(factorial(tl->nuc.n_N)));
-      if (tl->projected) {
-        // row delta of the list pairs with sink set delta only; the sums per
-        // delta go to the workspace and are then added in delta order
-        a.diag = 1;
-        a.corr = reinterpret_cast<double *>(buf[1] + od);
+      // side nuclei read from the stage just formed (before a later step
+      // overwrites its buffer): C_i = sum_z F(delta; z) c_i(alpha; z) / (k_P! k_N!)
+      for (size_t i = 0; !dry && step < tl->nstages && i < tl->sides.size(); i++) {
+        const mb::Side &sd = tl->sides[i];
+        if (sd.stage != step) continue;
+        const Stage &S = tl->st[step];
+        FinalArgs a = final_args(buf[step % 2], sd.off_crow, sd.off_ccol, sd.off_cval,
+                                 corr_out + 2 * p->batch * tl->side_offset(i), int(S.nspin()),
+                                 int(sd.alphas.size()), step + 1,
+                                 1.0 / (double(factorial(S.kP)) * double(factorial(S.kN))));
         HIP_CHECK(launch_final(a, mixed, s));
-        HIP_CHECK(launch_project(a.corr, corr_out, p->batch, a.n_delta, s));
-      } else {
-        HIP_CHECK(launch_final(a, mixed, s));
+        if (err_out) {
+          double *eo = err_out + 2 * p->batch * tl->side_offset(i);
+          if (err_stages) HIP_CHECK(err_final(a, ebuf[step % 2], eo, 0));
+          else HIP_CHECK(launch_zero(eo, 2 * p->batch * int64_t(S.nspin()) * int64_t(sd.alphas.size()), s));
+        }
       }
-    }
-    // side nuclei read from the stage just formed (before a later step
-    // overwrites its buffer): C_i = sum_z F(delta; z) c_i(alpha; z) / (k_P! k_N!)
-    for (size_t i = 0; step < tl->nstages && i < tl->sides.size(); i++) {
-      const mb::Side &sd = tl->sides[i];
-      if (sd.stage != step) continue;
-      const Stage &S = tl->st[step];
-      FinalArgs a{};
-      a.F = buf[step % 2];
-      a.crow = reinterpret_cast<const int64_t *>(img + sd.off_crow);
-      a.ccol = reinterpret_cast<const int32_t *>(img + sd.off_ccol);
-      a.cval = reinterpret_cast<const double *>(img + sd.off_cval);
-      a.corr = corr_out + 2 * p->batch * tl->side_offset(i);
-      a.exp_out = nullptr;
-      a.scale_exp = p->scale_exp;
-      a.B = p->batch;
-      a.Bp = Bp;
-      a.n_delta = int(S.nspin());
-      a.n_alpha = int(sd.alphas.size());
-      a.A = step + 1;
-      a.lane_exp = reinterpret_cast<const int32_t *>(blk + blocks_entry_bytes(tl, p));
-      a.inv_fact = 1.0 / (double(factorial(S.kP)) * double(factorial(S.kN)));
-      HIP_CHECK(launch_final(a, mixed, s));
     }
   }
   return MB_OK;
 }
 
+int mb_workspace_query_err(const mb_term_list *tl, const mb_problem *p, size_t *err_ws_bytes) {
+  int rc = check_problem(tl, p);
+  if (rc) return rc;
+  if (!err_ws_bytes) return fail(MB_EINVAL, "null argument");
+  *err_ws_bytes = p->precision == MB_MIXED ? err_bytes_of(tl, p) : 0;
+  return MB_OK;
+}
+
 int mb_contract_correlator(const mb_term_list *tl, const mb_problem *p, const void *blocks,
-                           size_t blocks_bytes, double *corr_out, int32_t *exp_out, void *ws,
+                           size_t blocks_bytes, double *corr_out, int32_t *exp_out, double *err_out, void *ws,
                            size_t ws_bytes, void *stream) {
   if (!tl) return fail(MB_EINVAL, "null argument");
-  return contract_steps(tl, p, blocks, blocks_bytes, corr_out, exp_out, ws, ws_bytes, stream, 0,
+  return contract_steps(tl, p, blocks, blocks_bytes, corr_out, exp_out, err_out, ws, ws_bytes, stream, 0,
                         tl->nstages);
 }
 
@@ -470,7 +585,7 @@ int mb_contract_step(const mb_term_list *tl, const mb_problem *p, const void *bl
                      size_t ws_bytes, void *stream) {
   if (!tl) return fail(MB_EINVAL, "null argument");
   if (step < 0 || step > tl->nstages) return fail(MB_EINVAL, "step out of range");
-  return contract_steps(tl, p, blocks, blocks_bytes, corr_out, exp_out, ws, ws_bytes, stream, step,
+  return contract_steps(tl, p, blocks, blocks_bytes, corr_out, exp_out, nullptr, ws, ws_bytes, stream, step,
                         step);
 }
 

@@ -552,6 +552,7 @@ static hipError_t launch_stage_lds_mkp(const StageLdsArgs &a, hipStream_t s) {
   const int64_t nwg = ((nslot + LDS_SLOTS - 1) / LDS_SLOTS + 7) / 8 * 8;
   if (!grid_x_fits(nwg, LDS_THREADS)) return hipErrorInvalidConfiguration;
   dim3 grid(unsigned(nwg), unsigned(a.Bp / 16));
+  if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
   hipLaunchKernelGGL((stage_lds_kernel<T, M, K, PG>), grid, dim3(LDS_THREADS), stage_lds_bytes(a.nxi, M, a.pp), s,
                      a);
   return hipGetLastError();
@@ -718,6 +719,7 @@ static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
     // pairs along the input sets (see launch_stage_mkptu)
     if constexpr (std::is_same<T, float>::value && binom_c(M, K) % 2 == 0) {
       if (a.act_is_P && a.npass != 1) return hipErrorInvalidValue;
+      if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
       hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G, true>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
@@ -725,6 +727,7 @@ static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
     }
   }
   if (a.paired_in) return hipErrorInvalidValue;
+  if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
   hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G, false>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
@@ -740,6 +743,7 @@ static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
     // passthrough groups of a proton step with an even passthrough count
     if constexpr (F32 && TILE == 64 && PG % 2 == 0) {
       if (!a.act_is_P || a.npass % 2) return hipErrorInvalidValue;
+      if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
       hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 1>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
@@ -751,12 +755,14 @@ static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
     // stage order (a neutron step, or one passthrough part)
     if constexpr (F32 && TILE == 64 && binom_c(M, K) % 2 == 0) {
       if (a.act_is_P && a.npass != 1) return hipErrorInvalidValue;
+      if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
       hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 2>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
     }
   }
+  if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
   hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 0>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }

@@ -92,6 +92,7 @@ struct StageArgs {
   int paired_in;             // input layout: 0 plain, 1 pairs along the passthrough parts,
                              // 2 pairs along the input sets (float stages, 64-lane waves)
   int paired_out;            // output stored in the paired layout (spin_off)
+  int dry;                   // validate only: return what the launch would, launch nothing
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);
 
@@ -115,6 +116,7 @@ struct StageLdsArgs {
   uint32_t div_magic;        // ceil(2^32 / nxi): exact division of multiples of nxi
   int psi_of_pos[8];
   int paired_out;
+  int dry;                   // validate only (as in StageArgs)
 };
 hipError_t launch_stage_lds(const StageLdsArgs &a, bool mixed, hipStream_t s);
 // LDS bytes the staged kernel uses for a term list with nxi quark indices,
@@ -141,5 +143,43 @@ struct FinalArgs {
 hipError_t launch_final(const FinalArgs &a, bool mixed, hipStream_t s);
 // Projected correlator: out[b] = sum over delta (in order) of part[b][delta].
 hipError_t launch_project(const double *part, double *out, int64_t B, int n_delta, hipStream_t s);
+
+// Rounding-error estimate of the float stages (implemented in errest.hip):
+// per stage component a float2 (E, S), E a first-order bound and S a
+// standard deviation of the difference between the stored float value and
+// the FP64 path's value, in the plain stage layout.
+struct ErrStageArgs {
+  const void *Ein;           // error stage s-1 (unused at stage 0)
+  void *Eout;                // error stage s
+  const void *F;             // float stage s as stored by step s
+  const void *fblk;          // block of the added species
+  const uint32_t *qsplit;    // [nq_out][Sq][2]
+  int64_t nq_out, Bp;
+  int Sq, npass, ns_out;
+  int act_is_P, M, K, npsi;
+  int psi_of_pos[8];
+  int paired_F;              // stage s stored in the paired layout
+};
+hipError_t launch_err_stage0(const ErrStageArgs &a, hipStream_t s);
+hipError_t launch_err_stage(const ErrStageArgs &a, hipStream_t s);
+
+// err[b][delta][alpha] = (S_C, E_C) from the final error stage and |c|.
+struct ErrFinalArgs {
+  const void *E;
+  const int64_t *crow;
+  const int32_t *ccol;
+  const double *cval;
+  double *err;
+  const int32_t *lane_exp;
+  int64_t B, Bp;
+  int n_delta, n_alpha, A;
+  double inv_fact;
+  int diag;
+};
+hipError_t launch_err_final(const ErrFinalArgs &a, hipStream_t s);
+// Projected correlator: out[b] = (sqrt(sum S^2), sum E) over the sink sets.
+hipError_t launch_err_project(const double *part, double *out, int64_t B, int n_delta, hipStream_t s);
+// p[0..n) = 0 (a kernel, so that the call can be captured in a graph).
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 }  // namespace mb

@@ -14,7 +14,8 @@ class Runner:
     scale_exp: int32 [batch] or None.  Buffers are allocated once here;
     ``run`` only launches."""
 
-    def __init__(self, tl: B.TermList, props_u, props_d, precision, sink_w=None, scale_exp=None):
+    def __init__(self, tl: B.TermList, props_u, props_d, precision, sink_w=None, scale_exp=None,
+                 err_estimate=False):
         self.tl = tl
         if tl._dev is None:
             tl.upload(props_u.device)
@@ -23,6 +24,8 @@ class Runner:
         self.p = B.problem(self.batch, self.V, props_u, props_d, precision,
                            None if sink_w is None else torch.view_as_real(sink_w), scale_exp)
         nb, nbw, ncw = B.workspace_query(tl, self.p)
+        if err_estimate:
+            ncw += B.workspace_query_err(tl, self.p)
         dev = props_u.device
         self.blocks = torch.empty(nb, dtype=torch.uint8, device=dev)
         self.bws = torch.empty(max(nbw, 1), dtype=torch.uint8, device=dev)
@@ -40,6 +43,11 @@ class Runner:
             self.side_corr.append(self.out[off:off + n].view(self.batch, c["n_spin"][stage], len(alphas)))
             off += n
         self.exp = torch.empty(self.batch, dtype=torch.int32, device=dev)
+        # error estimates (sigma, bound) of every output, as corr and side_corr
+        self.err_all = (torch.empty((self.batch * c["n_out"], 2), dtype=torch.float64, device=dev)
+                        if err_estimate else None)
+        self.err = None if self.err_all is None else self.err_all[:self.batch * shape[0] * shape[1]].view(
+            self.batch, *shape, 2)
 
     def set_props(self, props_u, props_d, scale_exp=None):
         """Points the problem at other propagators of the same shape."""
@@ -54,7 +62,7 @@ class Runner:
         B.make_blocks(self.tl, self.p, self.blocks, self.bws, stream)
 
     def run_contract(self, stream=None):
-        B.contract_correlator(self.tl, self.p, self.blocks, self.out, self.exp, self.cws, stream)
+        B.contract_correlator(self.tl, self.p, self.blocks, self.out, self.exp, self.cws, stream, self.err_all)
 
     def run(self, stream=None):
         self.run_blocks(stream)

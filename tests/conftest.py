@@ -28,3 +28,18 @@ def _oracle_built():
     if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
         O.build()
     yield
+
+
+@pytest.fixture(autouse=True)
+def _release_device_memory():
+    """Frees the device memory a test leaves behind (a failing full-size test
+    would otherwise hold its buffers while the next one allocates)."""
+    yield
+    import gc
+    gc.collect()
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.empty_cache()
+    except ImportError:
+        pass

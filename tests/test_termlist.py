@@ -235,7 +235,7 @@ def test_device_calls_validate_before_launch():
     a, b, w = B.workspace_query(tl, p)
     assert L.mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), a - 1, C.c_void_p(1), b, None) == B.MB_ENOWORKSPACE
     # not uploaded
-    assert L.mb_contract_correlator(tl.h, C.byref(p), C.c_void_p(1), a, C.c_void_p(1), None,
+    assert L.mb_contract_correlator(tl.h, C.byref(p), C.c_void_p(1), a, C.c_void_p(1), None, None,
                                     C.c_void_p(1), w, None) == B.MB_EINVAL
     tc = lib_termlist(False, 1, 1, 1, None, counts_only=True)
     assert L.mb_workspace_query(tc.h, C.byref(p), None, None, None) == B.MB_EINVAL
