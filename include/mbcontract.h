@@ -381,6 +381,23 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
 int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
                    size_t blocks_bytes, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): exactly
+ * mb_make_blocks -- same kernels, same chunking, bit-identical blocks --
+ * with the site-chunk partial sums in a fixed device array of
+ * MB_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends, instead of a workspace argument.  The caller
+ * still passes the propagators and the blocks buffer.  Sizes beyond the
+ * array (mb_workspace_query's blocks_ws_bytes above
+ * MB_NOALLOC_SCRATCH_BYTES) fail with MB_ENOWORKSPACE before anything is
+ * launched.  No allocating call is made.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams without
+ * ordering, other host threads) race and must be serialised by the caller.
+ * Nothing in the array needs to start at zero.                             */
+#define MB_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mb_make_blocks_noalloc(const mb_term_list *tl, const mb_problem *p, void *blocks,
+                           size_t blocks_bytes, void *stream);
+
 /* Correlators from blocks: the recursion of eq. recr_F over the operation
  * lists, then C(delta; alpha) = sum_z F_-(delta; z) L(alpha; z) / (n_P! n_N!)
  * (eq. C_final with the sum over sorted index sets), the final sum in double.

@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_build_term_list_path", "mb_term_list_free",
     "mb_term_list_save", "mb_term_list_load",
     "mb_term_list_counts", "mb_term_list_export", "mb_term_list_upload", "mb_workspace_query",
-    "mb_make_blocks", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune", "mb_workspace_query_err",
+    "mb_make_blocks", "mb_make_blocks_noalloc", "mb_contract_correlator", "mb_contract_step", "mb_term_list_tune", "mb_workspace_query_err",
     "mb_batch_plan", "mb_batch_create", "mb_batch_launch", "mb_batch_kernel_count", "mb_batch_free",
     "mb_last_error",
 ]
@@ -105,6 +105,7 @@ def lib():
         L.mb_workspace_query.argtypes = [P, C.POINTER(mb_problem), C.POINTER(C.c_size_t),
                                          C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.mb_make_blocks.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, C.c_size_t, P]
+        L.mb_make_blocks_noalloc.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P]
         L.mb_contract_correlator.argtypes = [P, C.POINTER(mb_problem), P, C.c_size_t, P, P, P, P,
                                              C.c_size_t, P]
         L.mb_workspace_query_err.argtypes = [P, C.POINTER(mb_problem), C.POINTER(C.c_size_t)]
@@ -274,6 +275,17 @@ def make_blocks(tl: TermList, p: mb_problem, blocks, ws, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     _check(lib().mb_make_blocks(tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()), blocks.numel() * blocks.element_size(),
                                 C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), C.c_void_p(s)))
+
+
+MB_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def make_blocks_noalloc(tl: TermList, p: mb_problem, blocks, stream=None):
+    """mb_make_blocks with the partial sums in the library's fixed scratch."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib().mb_make_blocks_noalloc(tl.h, C.byref(p), C.c_void_p(blocks.data_ptr()),
+                                        blocks.numel() * blocks.element_size(), C.c_void_p(s)))
 
 
 def contract_correlator(tl: TermList, p: mb_problem, blocks, corr, exp_out, ws, stream=None, err=None):

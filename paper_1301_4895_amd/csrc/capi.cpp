@@ -106,6 +106,66 @@ void psi_positions(uint32_t base, int *out) {
 
 }  // namespace
 
+namespace mb {
+
+size_t blocks_workspace_bytes(const mb_term_list *tl, const mb_problem *p) { return blocks_ws_of(tl, p); }
+int check_blocks_problem(const mb_term_list *tl, const mb_problem *p) { return check_problem(tl, p); }
+
+// The launches of mb_make_blocks with the site-chunk partial sums in `ws`
+// (the caller's workspace, or the no-allocation entry point's scratch).
+int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, size_t blocks_bytes, void *ws,
+                     size_t ws_bytes, void *stream) {
+  int rc = check_problem(tl, p);
+  if (rc) return rc;
+  if (!p->prop_u || !p->prop_d || !blocks || !ws) return fail(MB_EINVAL, "null device buffer");
+  if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
+  if (ws_bytes < blocks_ws_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool sym = p->prop_u == p->prop_d;
+  const bool mixed = p->precision == MB_MIXED;
+  BlocksArgs a{};
+  a.prop_u = p->prop_u;
+  a.prop_d = p->prop_d;
+  a.sink_w = p->sink_w;
+  a.scale_exp = p->scale_exp;
+  a.B = p->batch;
+  a.V = p->V;
+  a.nsrc = tl->nsrc;
+  a.D = tl->D;
+  a.nchunk = nchunks_for(p->batch, p->V);
+  a.sites_per_chunk = (p->V + a.nchunk - 1) / a.nchunk;
+  a.in_c128 = p->in_dtype == MB_C128;
+  const size_t half = blocks_ws_of(tl, p) / (sym ? 1 : 2);
+  double *partP = static_cast<double *>(ws);
+  double *partN = sym ? partP : reinterpret_cast<double *>(static_cast<char *>(ws) + half);
+  a.prop_q1 = p->prop_u;
+  a.partial = partP;
+  HIP_CHECK(launch_blocks_partial(a, mixed, sym, s));
+  if (!sym) {
+    a.prop_q1 = p->prop_d;
+    a.partial = partN;
+    HIP_CHECK(launch_blocks_partial(a, mixed, sym, s));
+  }
+  FinishArgs f{};
+  f.partP = partP;
+  f.partN = partN;
+  f.blocks = blocks;
+  f.B = p->batch;
+  f.Bp = lanes_padded(p->batch);
+  f.nsrc = tl->nsrc;
+  f.D = tl->D;
+  f.nchunk = a.nchunk;
+  f.sym = sym;
+  HIP_CHECK(launch_blocks_finish(f, mixed, s));
+  const int nyq = tl->nxi * (tl->nxi - 1) / 2 * tl->nxi;
+  HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
+                                                                     blocks_entry_bytes(tl, p)),
+                                f.Bp, tl->npsi, 2 * nyq, s));
+  return MB_OK;
+}
+
+}  // namespace mb
+
 extern "C" {
 
 int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream) {
@@ -252,53 +312,7 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p, size_t *bloc
 
 int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks, size_t blocks_bytes,
                    void *ws, size_t ws_bytes, void *stream) {
-  int rc = check_problem(tl, p);
-  if (rc) return rc;
-  if (!p->prop_u || !p->prop_d || !blocks || !ws) return fail(MB_EINVAL, "null device buffer");
-  if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
-  if (ws_bytes < blocks_ws_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks workspace too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool sym = p->prop_u == p->prop_d;
-  const bool mixed = p->precision == MB_MIXED;
-  BlocksArgs a{};
-  a.prop_u = p->prop_u;
-  a.prop_d = p->prop_d;
-  a.sink_w = p->sink_w;
-  a.scale_exp = p->scale_exp;
-  a.B = p->batch;
-  a.V = p->V;
-  a.nsrc = tl->nsrc;
-  a.D = tl->D;
-  a.nchunk = nchunks_for(p->batch, p->V);
-  a.sites_per_chunk = (p->V + a.nchunk - 1) / a.nchunk;
-  a.in_c128 = p->in_dtype == MB_C128;
-  const size_t half = blocks_ws_of(tl, p) / (sym ? 1 : 2);
-  double *partP = static_cast<double *>(ws);
-  double *partN = sym ? partP : reinterpret_cast<double *>(static_cast<char *>(ws) + half);
-  a.prop_q1 = p->prop_u;
-  a.partial = partP;
-  HIP_CHECK(launch_blocks_partial(a, mixed, sym, s));
-  if (!sym) {
-    a.prop_q1 = p->prop_d;
-    a.partial = partN;
-    HIP_CHECK(launch_blocks_partial(a, mixed, sym, s));
-  }
-  FinishArgs f{};
-  f.partP = partP;
-  f.partN = partN;
-  f.blocks = blocks;
-  f.B = p->batch;
-  f.Bp = lanes_padded(p->batch);
-  f.nsrc = tl->nsrc;
-  f.D = tl->D;
-  f.nchunk = a.nchunk;
-  f.sym = sym;
-  HIP_CHECK(launch_blocks_finish(f, mixed, s));
-  const int nyq = tl->nxi * (tl->nxi - 1) / 2 * tl->nxi;
-  HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
-                                                                     blocks_entry_bytes(tl, p)),
-                                f.Bp, tl->npsi, 2 * nyq, s));
-  return MB_OK;
+  return mb::make_blocks_with(tl, p, blocks, blocks_bytes, ws, ws_bytes, stream);
 }
 
 static int contract_steps(const mb_term_list *tl, const mb_problem *p, const void *blocks,

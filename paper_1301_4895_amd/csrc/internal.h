@@ -93,4 +93,10 @@ int subset_rank(uint32_t posmask, int m);
 // the positions of the bits of `sub` within base set `base`, as a mask
 uint32_t to_positions(uint32_t sub, uint32_t base);
 uint32_t from_positions(uint32_t pos, uint32_t base);
+// Blocks (capi.cpp): the launches of mb_make_blocks with the site-chunk
+// partial sums in ws, and the size of that workspace.
+int check_blocks_problem(const mb_term_list *tl, const mb_problem *p);
+size_t blocks_workspace_bytes(const mb_term_list *tl, const mb_problem *p);
+int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, size_t blocks_bytes, void *ws,
+                     size_t ws_bytes, void *stream);
 }  // namespace mb

@@ -241,6 +241,18 @@ def test_device_calls_validate_before_launch():
     assert L.mb_workspace_query(tc.h, C.byref(p), None, None, None) == B.MB_EINVAL
 
 
+def test_noalloc_blocks_refuse_problems_beyond_the_scratch():
+    """mb_make_blocks_noalloc checks the partial-sum size against its fixed
+    scratch before anything touches the device."""
+    import ctypes as C
+    tl = lib_termlist(True, 1, 1, 1, None)
+    L = B.lib()
+    p = B.mb_problem(2048, 64 ** 3, B.MB_C64, B.MB_MIXED, 1, 1, None, None)
+    assert B.workspace_query(tl, p)[1] > B.MB_NOALLOC_SCRATCH_BYTES
+    assert L.mb_make_blocks_noalloc(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, None) == B.MB_ENOWORKSPACE
+    assert b"fixed scratch" in L.mb_last_error()
+
+
 def test_library_exports_every_declared_symbol():
     import os
     hdr = open(os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "mbcontract.h")).read()
