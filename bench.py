@@ -104,7 +104,7 @@ def kernel_hash():
     """Hash of the recursion-step sources: the measured traffic of a step is
     only reported while these are unchanged."""
     h = hashlib.sha256()
-    for f in ("contract.hip", "kernels.h"):
+    for f in ("contract.hip", "contract_impl.h", "contract_f32.hip", "contract_f64.hip", "kernels.h"):
         h.update(open(os.path.join(ROOT, "paper_1301_4895_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -170,6 +170,7 @@ def run_workload(name, args):
             source = "committed (paper_1301_4895_amd/tuned.json)"
             if best is not None:
                 autotune.apply(tl, best)
+                r.ensure_workspace()
                 log(f"[bench] {name} {prec_name}: committed launch settings")
             else:
                 best = autotune.tune(tl, r, key=key, cache=args.tune_cache, log=log)
@@ -177,7 +178,7 @@ def run_workload(name, args):
             tuning[prec_name] = {"source": source, "steps": {
                 str(k): {"kernel": "lds-staged" if v[0] else "direct", "pass_group": v[1],
                          "lds_bytes": v[2], "lane_tile": v[3], "unroll": v[4],
-                         "outputs_per_wave": v[5], "ms_when_tuned": round(v[6], 3)}
+                         "outputs_per_wave": v[5], "two_phase": v[6], "ms_when_tuned": round(v[7], 3)}
                 for k, v in best.items()}}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
         ev = {}

@@ -304,6 +304,17 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
  *                       with neighbouring spin parts of a lane together
  *                       when every thread of the step takes both (one
  *                       16-byte load instead of two); 0: plain layout
+ *   MB_TUNE_TWO_PHASE   0 (default) or 1 (direct kernel only): the step runs
+ *                       in two parts.  Part A computes, for every output and
+ *                       every single-flavour index c of it (d of a proton,
+ *                       u of a neutron), the sum over the splits whose added
+ *                       baryon takes c -- all of them read previous-stage
+ *                       parts with the same single-flavour set, and part A
+ *                       runs those work items together, so that the parts
+ *                       they read stay in L2 -- and writes it as a partial;
+ *                       part B adds the partials of every output.  The
+ *                       contraction workspace then holds the partials of
+ *                       the largest such step (query it after tuning).
  *   MB_TUNE_KERNEL      0 (default): every thread gathers its block entries
  *                       from global memory; 1: the block rows of one single
  *                       quark index at a time are staged in LDS per
@@ -317,6 +328,7 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
 #define MB_TUNE_UNROLL 5
 #define MB_TUNE_GROUP 6
 #define MB_TUNE_PAIRED 7
+#define MB_TUNE_TWO_PHASE 8
 int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
 
 /* Copies the operation tables to device memory `dev` (caller-owned, at least
@@ -357,7 +369,9 @@ typedef struct {
  *   blocks_bytes     output of mb_make_blocks / input of the contraction
  *   blocks_ws_bytes  workspace of mb_make_blocks (site-chunk partial sums)
  *   contract_ws_bytes workspace of mb_contract_correlator (two stages of F;
- *                    for a projected term list also the per-sink-set sums) */
+ *                    for a projected term list also the per-sink-set sums;
+ *                    with MB_TUNE_TWO_PHASE the partials of the largest
+ *                    two-phase step, so the size depends on the tuning)   */
 int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
                        size_t *blocks_bytes, size_t *blocks_ws_bytes,
                        size_t *contract_ws_bytes);

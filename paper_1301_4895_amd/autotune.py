@@ -29,26 +29,29 @@ COMMITTED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json
 TILES = (64, 16)
 
 
-CACHE_VERSION = "v4"
+CACHE_VERSION = "v5"
 
 
-def _candidates(npass):
-    """(kernel, pass group, LDS bytes, lane tile, splits in flight, outputs per wavefront)."""
+def _candidates(npass, nsingle):
+    """(kernel, pass group, LDS bytes, lane tile, splits in flight, outputs per
+    wavefront, two-phase)."""
     pgs = [pg for pg in (1, 2, 3, 6) if npass % pg == 0]
-    direct = [(0, pg, 0, t, u, 1) for pg in pgs for t in TILES for u in (1, 2)]
-    capped = [(0, pg, lds, t, 0, 1) for pg in pgs for t in TILES for lds in LDS_CANDIDATES if lds]
-    grouped = [(0, pg, 0, 64, 0, gr) for pg in pgs if pg <= 3 for gr in (2, 4)]
-    staged = [(1, pg, 0, 16, 0, 1) for pg in (1, 2, 3) if npass % pg == 0]
-    return direct + capped + grouped + staged
+    direct = [(0, pg, 0, t, u, 1, 0) for pg in pgs for t in TILES for u in (1, 2)]
+    capped = [(0, pg, lds, t, 0, 1, 0) for pg in pgs for t in TILES for lds in LDS_CANDIDATES if lds]
+    grouped = [(0, pg, 0, 64, 0, gr, 0) for pg in pgs if pg <= 3 for gr in (2, 4)]
+    staged = [(1, pg, 0, 16, 0, 1, 0) for pg in (1, 2, 3) if npass % pg == 0]
+    two = [(0, pg, 0, t, u, 1, 1) for pg in pgs for t in TILES for u in (1, 2)] if nsingle > 1 else []
+    return direct + capped + grouped + staged + two
 
 
-def _apply(tl, s, kernel, pg, lds, tile, unroll, group):
+def _apply(tl, s, kernel, pg, lds, tile, unroll, group, two_phase=0):
     tl.tune(s, B.MB_TUNE_KERNEL, kernel)
     tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
     tl.tune(s, B.MB_TUNE_LDS_BYTES, lds)
     tl.tune(s, B.MB_TUNE_LANE_TILE, tile)
     tl.tune(s, B.MB_TUNE_UNROLL, unroll)
     tl.tune(s, B.MB_TUNE_GROUP, group)
+    tl.tune(s, B.MB_TUNE_TWO_PHASE, two_phase)
 
 
 def _device_arch():
@@ -63,7 +66,8 @@ def full_key(key):
 
 def committed(key):
     """The committed launch settings of a workload key ("c3|mixed|768"), or
-    None: {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group, ms)}."""
+    None: {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group,
+    two_phase, ms)}."""
     if not os.path.exists(COMMITTED):
         return None
     table = json.load(open(COMMITTED))
@@ -74,7 +78,7 @@ def committed(key):
 def apply(tl, best):
     """Sets every step's launch settings from a {step: settings} table."""
     for s, v in best.items():
-        _apply(tl, s, *v[:6])
+        _apply(tl, s, *v[:7])
 
 
 def _time_step(tl, runner, step, reps, stream):
@@ -91,7 +95,7 @@ def _time_step(tl, runner, step, reps, stream):
 def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = None, reps: int = 2,
          log=None):
     """Tunes every step on ``runner``'s buffers.
-    Returns {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group, ms)}."""
+    Returns {step: (kernel, pass_group, lds_bytes, lane_tile, unroll, group, two_phase, ms)}."""
     c = tl.counts()
     fkey = full_key(key) if key else None
     if cache and fkey and os.path.exists(cache):
@@ -103,6 +107,23 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
             apply(tl, best)
             return best
     stream = torch.cuda.current_stream()
+    # two-phase candidates only where their partials fit in the free device
+    # memory (with a margin); the workspace for the largest of them is
+    # allocated once (a reallocation would drop the stages the timed steps read)
+    lanes = (runner.batch + 63) // 64 * 64
+    elem = 8 if runner.p.precision == B.MB_MIXED else 16
+    free = torch.cuda.mem_get_info()[0] - (8 << 30)
+    two_ok = {}
+    for s in range(1, c["n_stages"]):
+        kP = sum(1 for t in c["path"][:s + 1] if t == 0)
+        kN = s + 1 - kP
+        nsingle = (kP + 2 * kN) if c["path"][s] == 0 else (2 * kP + kN)
+        two_ok[s] = nsingle > 1 and nsingle * c["n_req"][s] * lanes * elem <= free
+    for s in range(1, c["n_stages"]):
+        tl.tune(s, B.MB_TUNE_TWO_PHASE, int(two_ok[s]))
+    runner.ensure_workspace()
+    for s in range(1, c["n_stages"]):
+        tl.tune(s, B.MB_TUNE_TWO_PHASE, 0)
     # bring every stage to a valid state once
     runner.run_blocks()
     for s in range(c["n_stages"] + 1):
@@ -120,17 +141,20 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
         kN = s + 1 - kP
         other = 1 - added
         npass = math.comb(_base(tl, other), kN if other == 1 else kP)
+        nsingle = (kP + 2 * kN) if added == 0 else (2 * kP + kN)
         results = []
-        for cand in _candidates(npass):
+        for cand in _candidates(npass, nsingle if two_ok[s] else 1):
             _apply(tl, s, *cand)
+            runner.ensure_workspace()
             results.append((_time_step(tl, runner, s, reps, stream),) + cand)
         ms, *cand = min(results)
         _apply(tl, s, *cand)
+        runner.ensure_workspace()
         best[s] = tuple(cand) + (ms,)
         if log:
             log(f"[autotune] step {s}: " + ", ".join(
-                f"{'lds' if k else 'dir'}/pg{g}/lds{l}/t{t}/u{u}/g{gr}={m:.2f}ms"
-                for m, k, g, l, t, u, gr in sorted(results)[:4]))
+                f"{'lds' if k else 'dir'}/pg{g}/lds{l}/t{t}/u{u}/g{gr}{'/2ph' if tp else ''}={m:.2f}ms"
+                for m, k, g, l, t, u, gr, tp in sorted(results)[:4]))
     if cache and fkey:
         table = json.load(open(cache)) if os.path.exists(cache) else {}
         table[fkey] = {str(s): list(v) for s, v in best.items()}

@@ -23,6 +23,7 @@ MB_MAX_STAGES = 16
 MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUNE_UNROLL, MB_TUNE_GROUP = \
     1, 2, 3, 4, 5, 6
 MB_TUNE_PAIRED = 7
+MB_TUNE_TWO_PHASE = 8
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
  MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ, MB_EXPORT_SIDE) = range(1, 10)
 

@@ -78,6 +78,18 @@ void stage_buffer_sizes(const mb_term_list *tl, const mb_problem *p, size_t *eve
   *odd = al256(o);
 }
 
+// Partials of the two-phase steps (one set at a time): nsingle partial
+// stages of the step's output, in the stage type.
+size_t h_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+  size_t h = 0;
+  for (int s = 1; s < tl->nstages; s++) {
+    const Stage &S = tl->st[s];
+    if (!S.tune_two_phase || S.tune_kernel != 0) continue;
+    h = std::max(h, size_t(S.nsingle()) * size_t(S.nreq()) * size_t(lanes_padded(p->batch)) * elem_bytes(p));
+  }
+  return al256(h);
+}
+
 // The error-estimate area of a mixed contraction: two error stages (float2
 // (E, S) per component, plain layout) and, for a projected list, the
 // per-sink-set estimates.
@@ -189,7 +201,9 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
   size_t o = 0;
   tl->off_qsplit.assign(tl->nstages, 0);
   tl->off_masks.assign(tl->nstages, 0);
+  tl->off_items.assign(tl->nstages, 0);
   std::vector<std::vector<uint32_t>> masks(tl->nstages);   // kept alive until the copies finish
+  std::vector<std::vector<uint32_t>> items(tl->nstages);
   for (int st = 1; st < tl->nstages; st++) {
     tl->off_qsplit[st] = o;
     const auto &v = tl->st[st].qsplit;
@@ -204,6 +218,33 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
     }
     if (!m.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, m.data(), m.size() * 4, hipMemcpyHostToDevice, s));
     o += al256(m.size() * 4);
+    // two-phase items (q, j): the j-th group of pair splits of output q reads
+    // previous-stage parts whose single-flavour set is the output's minus its
+    // j-th single index.  Ordered by that set, so that the items reading one
+    // group of previous-stage parts run together; then by the output's
+    // pair-flavour set, so that neighbouring items read the same rows at
+    // every split position; then by the single index.
+    tl->off_items[st] = o;
+    const Stage &S = tl->st[st];
+    const int ns1 = S.nsingle();
+    std::vector<std::array<uint32_t, 4>> keyed;
+    keyed.reserve(S.quark.size() * ns1);
+    for (size_t q = 0; q < S.quark.size(); q++) {
+      const uint32_t single = S.type == PROTON ? qkey_d(S.quark[q]) : qkey_u(S.quark[q]);
+      const uint32_t pairset = S.type == PROTON ? qkey_u(S.quark[q]) : qkey_d(S.quark[q]);
+      uint32_t rest = single;
+      for (int j = 0; j < ns1; j++) {
+        const uint32_t c = rest & (~rest + 1u);   // j-th smallest single index
+        rest &= rest - 1u;
+        keyed.push_back({single & ~c, pairset, c, uint32_t(q * ns1 + j)});
+      }
+    }
+    std::sort(keyed.begin(), keyed.end());
+    auto &it = items[st];
+    it.resize(keyed.size());
+    for (size_t i = 0; i < keyed.size(); i++) it[i] = keyed[i][3];
+    if (!it.empty()) UPLOAD_CHECK(hipMemcpyAsync(base + o, it.data(), it.size() * 4, hipMemcpyHostToDevice, s));
+    o += al256(it.size() * 4);
   }
   tl->off_first = o;
   {
@@ -280,6 +321,9 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
     } else if (what == MB_TUNE_UNROLL) {
       if (value < 0 || value > 2) return fail(MB_EINVAL, "unroll must be 0, 1 or 2");
       S.tune_unroll = value;
+    } else if (what == MB_TUNE_TWO_PHASE) {
+      if (value != 0 && value != 1) return fail(MB_EINVAL, "two-phase must be 0 or 1");
+      S.tune_two_phase = value;
     } else if (what == MB_TUNE_PAIRED) {
       if (value != 0 && value != 1) return fail(MB_EINVAL, "paired must be 0 or 1");
       S.tune_paired = value;
@@ -305,7 +349,7 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p, size_t *bloc
   if (contract_ws_bytes) {
     size_t e, o;
     stage_buffer_sizes(tl, p, &e, &o);
-    *contract_ws_bytes = e + o + proj_bytes_of(tl, p);
+    *contract_ws_bytes = e + o + proj_bytes_of(tl, p) + h_bytes_of(tl, p);
   }
   return MB_OK;
 }
@@ -329,7 +373,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
   size_t ev, od;
   stage_buffer_sizes(tl, p, &ev, &od);
-  const size_t main_ws = ev + od + proj_bytes_of(tl, p);
+  const size_t main_ws = ev + od + proj_bytes_of(tl, p) + h_bytes_of(tl, p);
   if (ws_bytes < main_ws) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
   const bool mixed = p->precision == MB_MIXED;
   // error estimates of the float stages (mixed path only; the FP64 path
@@ -346,6 +390,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   const char *blk = static_cast<const char *>(blocks);
   const void *fblk[2] = {blk, blk + size_t(tl->npsi) * nyq * Bp * 16};  // proton, neutron
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
+  char *hbuf = static_cast<char *>(ws) + ev + od + proj_bytes_of(tl, p);   // two-phase partials
   size_t eev = 0, eod = 0;
   err_stage_sizes(tl, p, &eev, &eod);
   char *ebuf[2] = {static_cast<char *>(ws) + main_ws, static_cast<char *>(ws) + main_ws + eev};
@@ -476,6 +521,16 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         a.paired_out = paired(step) != 0;
         a.npsi = tl->npsi;
         a.dry = dry;
+        const bool two_phase = S.tune_two_phase && S.tune_kernel == 0;
+        if (two_phase) {
+          a.two_phase = 1;
+          a.items = reinterpret_cast<const uint32_t *>(img + tl->off_items[step]);
+          a.nsingle = S.nsingle();
+          a.n_items = a.nq_out * a.nsingle;
+          a.pp = S.Sq / a.nsingle;
+          a.H = hbuf;
+          a.hstride = S.nreq() * Bp;
+        }
         psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
         if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
         if (a.nq_out > 0 && S.tune_kernel == 1) {
@@ -506,6 +561,18 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
           if ((rc = launch_rc(launch_stage_lds(b, mixed, s), "recursion step (LDS-staged kernel)"))) return rc;
         } else if (a.nq_out > 0) {
           if ((rc = launch_rc(launch_stage(a, mixed, s), "recursion step"))) return rc;
+          if (two_phase && !dry) {
+            StageSumArgs b{};
+            b.H = hbuf;
+            b.Fout = a.Fout;
+            b.nq = a.nq_out;
+            b.Bp = Bp;
+            b.hstride = a.hstride;
+            b.ns = int(S.nspin());
+            b.nsingle = a.nsingle;
+            b.paired_out = a.paired_out;
+            HIP_CHECK(launch_stage_sum(b, mixed, s));
+          }
         }
         if (err_stages && a.nq_out > 0) {
           if (dry) {
@@ -529,6 +596,11 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
             e.npsi = tl->npsi;
             for (int i = 0; i < 8; i++) e.psi_of_pos[i] = a.psi_of_pos[i];
             e.paired_F = a.paired_out;
+            if (two_phase) {
+              e.H = hbuf;
+              e.nh = a.nsingle;
+              e.hstride = a.hstride;
+            }
             HIP_CHECK(launch_err_stage(e, s));
           }
         }

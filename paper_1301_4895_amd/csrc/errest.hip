@@ -102,12 +102,19 @@ __global__ __launch_bounds__(64) void err_stage_kernel(ErrStageArgs a) {
     }
   }
   const float2 *F = static_cast<const float2 *>(a.F);
+  const float2 *H = static_cast<const float2 *>(a.H);
   float2 *Eout = static_cast<float2 *>(a.Eout);
 #pragma unroll
   for (int o = 0; o < NOUT; o++) {
     const double m = mag(F[q * ns_out * a.Bp + spin_off(b, ns_out, sig_out(o), a.paired_F)]);
-    const double ee = e[o] + U_F32 * m;
-    const double vv = v[o] + U_F32 * U_F32 * m * m / 3.0;
+    double ee = e[o] + U_F32 * m;
+    double vv = v[o] + U_F32 * U_F32 * m * m / 3.0;
+    // a two-phase step also rounded its partials to float before adding them
+    for (int j = 0; j < a.nh; j++) {
+      const double mh = mag(H[j * a.hstride + q * ns_out * a.Bp + lane_off(b, ns_out) + sig_out(o) * 16]);
+      ee += U_F32 * mh;
+      vv += U_F32 * U_F32 * mh * mh / 3.0;
+    }
     Eout[q * ns_out * a.Bp + lane_off(b, ns_out) + sig_out(o) * 16] = make_float2(float(ee), float(sqrt(vv)));
   }
 }

@@ -38,7 +38,12 @@ struct Stage {
   int tune_unroll = 0;                            // splits in flight per wavefront (0 automatic)
   int tune_group = 1;                             // outputs per wavefront (grouped kernel when > 1)
   int tune_paired = 1;                            // input stage in the paired layout when possible
+  int tune_two_phase = 0;                         // 1: partial sums per single index, then their sum
   int64_t nspin() const { return int64_t(nPsets) * nNsets; }
+  // quark indices of the added baryon's single flavour in an output quark
+  // part (d for a proton step, u for a neutron step): the splits of an
+  // output come in that many groups of Sq / nsingle() pair splits
+  int nsingle() const { return type == PROTON ? kd : ku; }
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };
 
@@ -78,6 +83,8 @@ struct mb_term_list {
   size_t dev_bytes = 0;
   std::vector<size_t> off_qsplit;  // per stage (s >= 1)
   std::vector<size_t> off_masks;   // per stage (s >= 1): (u mask, d mask) of every quark part
+  std::vector<size_t> off_items;   // per stage (s >= 1): two-phase items q * nsingle + j, ordered by
+                                   // the single-flavour set of the previous-stage part they read
   size_t off_first = 0, off_crow = 0, off_ccol = 0, off_cval = 0;
   size_t image_bytes() const;
 };

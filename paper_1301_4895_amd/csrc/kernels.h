@@ -93,8 +93,30 @@ struct StageArgs {
                              // 2 pairs along the input sets (float stages, 64-lane waves)
   int paired_out;            // output stored in the paired layout (spin_off)
   int dry;                   // validate only: return what the launch would, launch nothing
+  // Two-phase step, part A (two_phase = 1, direct kernel): work item
+  // items[i] = q * nsingle + j takes the j-th group of pp pair splits of
+  // output q (those with the j-th single index of q) and writes its partial
+  // sum to H + j * hstride in the plain layout; part B (launch_stage_sum)
+  // adds the nsingle partials of every output.  Items are ordered by the
+  // previous-stage parts they read, so that those stay in L2.
+  int two_phase;
+  const uint32_t *items;
+  int64_t n_items;
+  int pp, nsingle;
+  void *H;
+  int64_t hstride;           // elements (of the stage type) between partials
 };
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s);
+
+// Part B of a two-phase step: F[q][sigma] = sum_j H_j[q][sigma] (in double,
+// j ascending), written in the stage's layout.
+struct StageSumArgs {
+  const void *H;
+  void *Fout;
+  int64_t nq, Bp, hstride;
+  int ns, nsingle, paired_out;
+};
+hipError_t launch_stage_sum(const StageSumArgs &a, bool mixed, hipStream_t s);
 
 // The same step with the block of the added species staged in LDS.  Splits
 // of an output are ordered by the single index of the added baryon, then by
@@ -159,6 +181,9 @@ struct ErrStageArgs {
   int act_is_P, M, K, npsi;
   int psi_of_pos[8];
   int paired_F;              // stage s stored in the paired layout
+  const void *H;             // two-phase step: its float partials (or null)
+  int nh;                    // number of partials
+  int64_t hstride;           // elements between partials
 };
 hipError_t launch_err_stage0(const ErrStageArgs &a, hipStream_t s);
 hipError_t launch_err_stage(const ErrStageArgs &a, hipStream_t s);

@@ -687,7 +687,8 @@ size_t mb_term_list::image_bytes() const {
   if (counts_only) return 0;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t o = 0;
-  for (int s = 1; s < nstages; s++) o += al(st[s].qsplit.size() * 4) + al(st[s].quark.size() * 8);
+  for (int s = 1; s < nstages; s++)
+    o += al(st[s].qsplit.size() * 4) + al(st[s].quark.size() * 8) + al(st[s].quark.size() * st[s].nsingle() * 4);
   o += al(st[0].first.size() * 4);
   if (projected) o += al(prow.size() * 8) + al(pcol.size() * 4) + al(pval.size() * 8);
   else o += al(crow.size() * 8) + al(ccol.size() * 4) + al(cval.size() * 8);

@@ -23,9 +23,8 @@ class Runner:
         self.keep = (props_u, props_d, sink_w, scale_exp)
         self.p = B.problem(self.batch, self.V, props_u, props_d, precision,
                            None if sink_w is None else torch.view_as_real(sink_w), scale_exp)
-        nb, nbw, ncw = B.workspace_query(tl, self.p)
-        if err_estimate:
-            ncw += B.workspace_query_err(tl, self.p)
+        self.err_estimate = err_estimate
+        nb, nbw, ncw = self._sizes()
         dev = props_u.device
         self.blocks = torch.empty(nb, dtype=torch.uint8, device=dev)
         self.bws = torch.empty(max(nbw, 1), dtype=torch.uint8, device=dev)
@@ -49,6 +48,21 @@ class Runner:
         self.err = None if self.err_all is None else self.err_all[:self.batch * shape[0] * shape[1]].view(
             self.batch, *shape, 2)
 
+    def _sizes(self):
+        nb, nbw, ncw = B.workspace_query(self.tl, self.p)
+        if self.err_estimate:
+            ncw += B.workspace_query_err(self.tl, self.p)
+        return nb, nbw, ncw
+
+    def ensure_workspace(self):
+        """Grows the contraction workspace when the term list's launch tuning
+        needs more (two-phase steps keep their partials there)."""
+        ncw = self._sizes()[2]
+        if ncw > self.cws.numel():
+            self.cws = None
+            torch.cuda.empty_cache()
+            self.cws = torch.empty(ncw, dtype=torch.uint8, device=self.blocks.device)
+
     def set_props(self, props_u, props_d, scale_exp=None):
         """Points the problem at other propagators of the same shape."""
         sink_w = self.keep[2]
@@ -62,6 +76,7 @@ class Runner:
         B.make_blocks(self.tl, self.p, self.blocks, self.bws, stream)
 
     def run_contract(self, stream=None):
+        self.ensure_workspace()
         B.contract_correlator(self.tl, self.p, self.blocks, self.out, self.exp, self.cws, stream, self.err_all)
 
     def run(self, stream=None):

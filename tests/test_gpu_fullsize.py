@@ -85,6 +85,7 @@ def bench_runner(name, tl, props, prec, sink, k):
         best = autotune.tune(tl, r, key=None)
     else:
         autotune.apply(tl, best)
+    r.ensure_workspace()
     return r, best
 
 

@@ -218,14 +218,19 @@ def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V
     # float, which the per-lane block exponents keep out of the float stages
     assert np.all(np.isfinite(ref))
     nst = tl.counts()["n_stages"]
-    for kern, pg, tile, lds, unroll, group in [
-            (0, 1, 16, 0, 1, 1), (0, 2, 64, 16384, 0, 1), (0, 3, 16, 0, 2, 1), (0, 3, 64, 0, 1, 1),
-            (0, 6, 64, 0, 2, 1), (0, 6, 16, 0, 1, 1), (0, 1, 64, 0, 2, 1), (0, 1, 64, 0, 0, 2), (0, 2, 64, 0, 0, 4),
-            (0, 3, 64, 0, 0, 4), (1, 1, 16, 0, 0, 1), (1, 2, 16, 0, 0, 1), (1, 3, 16, 0, 0, 1)]:
+    for kern, pg, tile, lds, unroll, group, two in [
+            (0, 1, 16, 0, 1, 1, 0), (0, 2, 64, 16384, 0, 1, 0), (0, 3, 16, 0, 2, 1, 0), (0, 3, 64, 0, 1, 1, 0),
+            (0, 6, 64, 0, 2, 1, 0), (0, 6, 16, 0, 1, 1, 0), (0, 1, 64, 0, 2, 1, 0), (0, 1, 64, 0, 0, 2, 0),
+            (0, 2, 64, 0, 0, 4, 0), (0, 3, 64, 0, 0, 4, 0), (1, 1, 16, 0, 0, 1, 0), (1, 2, 16, 0, 0, 1, 0),
+            (1, 3, 16, 0, 0, 1, 0),
+            # two-phase steps (partials per single index, then their sum)
+            (0, 6, 64, 0, 2, 1, 1), (0, 3, 16, 0, 1, 1, 1), (0, 1, 64, 0, 1, 1, 1), (0, 2, 64, 0, 0, 1, 1),
+            (0, 1, 16, 0, 2, 1, 1)]:
         for s in range(1, nst):
             tl.tune(s, B.MB_TUNE_KERNEL, kern)
             tl.tune(s, B.MB_TUNE_UNROLL, unroll)
             tl.tune(s, B.MB_TUNE_GROUP, group)
+            tl.tune(s, B.MB_TUNE_TWO_PHASE, two)
             try:
                 tl.tune(s, B.MB_TUNE_PASS_GROUP, pg)
             except B.MBError:
@@ -237,7 +242,7 @@ def test_launch_tuning_keeps_results(precision, tol, rel, nsrc, nP, nN, spins, V
         else:
             _, got, _ = _run(tl, Su, Sd, w, k, precision)
             sig = None
-        assert_close(got, ref, tol, (kern, pg, tile, lds, unroll, group), sigma=sig)
+        assert_close(got, ref, tol, (kern, pg, tile, lds, unroll, group, two), sigma=sig)
 
 
 @pytest.mark.parametrize("nl", [150, 500, 520])
@@ -430,13 +435,14 @@ def test_paired_stage_layout_is_bit_identical(rel, nsrc, nP, nN, spins, V, nl):
     tl = _tl(rel, nsrc, nP, nN, spins)
     nst = tl.counts()["n_stages"]
     _, ref, _ = _run(tl, Su, Sd, w, k, B.MB_FP64)
-    # (pass group, outputs per wave), 64-lane tiles
-    for pg, group in [(3, 1), (2, 1), (6, 1), (1, 1), (1, 2), (1, 4)]:
+    # (pass group, outputs per wave, two-phase), 64-lane tiles
+    for pg, group, two in [(3, 1, 0), (2, 1, 0), (6, 1, 0), (1, 1, 0), (1, 2, 0), (1, 4, 0), (6, 1, 1), (1, 1, 1)]:
         res = []
         for paired in (0, 1):
             for s in range(1, nst):
                 tl.tune(s, B.MB_TUNE_KERNEL, 0)
                 tl.tune(s, B.MB_TUNE_GROUP, group)
+                tl.tune(s, B.MB_TUNE_TWO_PHASE, two)
                 tl.tune(s, B.MB_TUNE_LANE_TILE, 64)
                 tl.tune(s, B.MB_TUNE_LDS_BYTES, 0)
                 tl.tune(s, B.MB_TUNE_UNROLL, 0)
@@ -447,14 +453,15 @@ def test_paired_stage_layout_is_bit_identical(rel, nsrc, nP, nN, spins, V, nl):
                     tl.tune(s, B.MB_TUNE_PASS_GROUP, 1)
             got, sig = _mixed(tl, Su, Sd, w, k)
             res.append(got)
-        assert np.array_equal(res[0], res[1]), (pg, group)
-        assert_close(res[1], ref, 1e-6, (pg, group), sigma=sig)
+        assert np.array_equal(res[0], res[1]), (pg, group, two)
+        assert_close(res[1], ref, 1e-6, (pg, group, two), sigma=sig)
 
 
 # --------------------------------------------------------------------- error estimates (err_out)
 
+@pytest.mark.parametrize("two_phase", [0, 1])
 @pytest.mark.parametrize("rel,nsrc,nP,nN,spins,V,nl,dtype", MIXED_CASES)
-def test_error_estimate_covers_the_mixed_deviation(rel, nsrc, nP, nN, spins, V, nl, dtype):
+def test_error_estimate_covers_the_mixed_deviation(rel, nsrc, nP, nN, spins, V, nl, dtype, two_phase):
     """err_out of the mixed path against the measured deviation of the mixed
     correlators from the FP64 ones (eq. C_final outputs): every component
     lies within its first-order bound and within 6 estimated standard
@@ -463,6 +470,8 @@ def test_error_estimate_covers_the_mixed_deviation(rel, nsrc, nP, nN, spins, V, 
     one.  The FP64 path reports zeros."""
     Su, Sd, w, k = _inputs(9, nl, V, nsrc, dtype, True, with_sink=nsrc == 2)
     tl = _tl(rel, nsrc, nP, nN, spins)
+    for s in range(1, tl.counts()["n_stages"]):
+        tl.tune(s, B.MB_TUNE_TWO_PHASE, two_phase)   # partials rounded to float too
     tu = torch.from_numpy(np.ascontiguousarray(Su)).to(DEV)
     tw = None if w is None else torch.from_numpy(np.ascontiguousarray(w)).to(DEV)
     tk = torch.from_numpy(k).to(DEV)
