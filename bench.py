@@ -8,7 +8,7 @@ plain FP64 path timed on the same inputs, the relative error between them,
 per-kernel times from HIP events on the launch stream, the roofline of the
 dominant kernel and the oracle timed on a bounded sample on the host.
 
-  python bench.py [--config c3|c4|c2|c1] [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--config all|c3+c4|c1|c2|c3|c4|c5] [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
 
@@ -107,6 +107,39 @@ def kernel_hash():
     for f in ("contract.hip", "contract_impl.h", "contract_f32.hip", "contract_f64.hip", "kernels.h"):
         h.update(open(os.path.join(ROOT, "paper_1301_4895_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def error_report(mixed, fp64, sigma=None):
+    """Mixed against FP64, per lane (leading axis of each array in the lists):
+    the relative Frobenius norm over the lane's components, the largest
+    relative error of its components of at least 1e-3 of its largest, and,
+    with the library's error estimates (sigma per component), how the
+    measured deviation compares with them."""
+    import numpy as np
+    per_lane, comp = [], []
+    ratio, dev_over_sig = [], 0.0
+    for i, (a, b) in enumerate(zip(mixed, fp64)):
+        a2, b2 = a.reshape(a.shape[0], -1), b.reshape(b.shape[0], -1)
+        d = np.abs(a2 - b2)
+        per_lane.append(np.linalg.norm(d, axis=1) / np.linalg.norm(b2, axis=1))
+        ref = np.abs(b2)
+        big = ref >= 1e-3 * ref.max(axis=1, keepdims=True)
+        comp.append(np.where(big, d / np.where(big, ref, 1.0), 0.0).max(axis=1))
+        if sigma is not None:
+            sg = sigma[i].reshape(sigma[i].shape[0], -1)
+            ratio.append(np.linalg.norm(sg, axis=1) / np.maximum(np.linalg.norm(d, axis=1), 1e-300))
+            dev_over_sig = max(dev_over_sig, float((d / np.maximum(sg, 1e-300)).max()))
+    per_lane, comp = np.concatenate(per_lane), np.concatenate(comp)
+    out = dict(median=float(np.median(per_lane)), p99=float(np.quantile(per_lane, 0.99)), max=float(per_lane.max()),
+               componentwise_max=float(comp.max()), componentwise_median=float(np.median(comp)),
+               componentwise_threshold="components >= 1e-3 of the lane's largest")
+    if sigma is not None:
+        ratio = np.concatenate(ratio)
+        out["error_estimate"] = dict(
+            sigma_over_deviation_per_lane=dict(min=float(ratio.min()), median=float(np.median(ratio)),
+                                               max=float(ratio.max())),
+            max_component_deviation_in_sigmas=dev_over_sig)
+    return out
 
 
 def run_workload(name, args):
@@ -232,14 +265,31 @@ def run_workload(name, args):
     err = None
     err_stats = None
     if "mixed" in outs and "fp64" in outs:
-        a, b = outs["mixed"], outs["fp64"]
-        num = np.linalg.norm((a - b).reshape(lanes, -1), axis=1)
-        den = np.linalg.norm(b.reshape(lanes, -1), axis=1)
-        per_lane = num / den
-        err = float(np.max(per_lane))
-        err_stats = dict(median=float(np.median(per_lane)), p99=float(np.quantile(per_lane, 0.99)), max=err)
+        # one untimed mixed pass with the library's error estimates (err_out),
+        # in the timed launch settings; its correlators must be the timed ones
+        sig = torch.empty((lanes,) + tuple(outs["mixed"].shape[1:]), dtype=torch.float64)
+        same = True
+        if tuning.get("mixed") is not None:
+            from paper_1301_4895_amd import autotune
+            autotune.apply(tl, {int(k): (0 if v["kernel"] == "direct" else 1, v["pass_group"], v["lds_bytes"],
+                                         v["lane_tile"], v["unroll"], v["outputs_per_wave"], v["two_phase"], 0.0)
+                                for k, v in tuning["mixed"]["steps"].items()})
+        re = Runner(tl, props[:chunk], props[:chunk], B.MB_MIXED, sink, kexp[:chunk], err_estimate=True)
+        for c in range(nchunk):
+            sl = slice(c * chunk, (c + 1) * chunk)
+            re.set_props(props[sl], props[sl], kexp[sl])
+            corr, _ = re.run()
+            torch.cuda.synchronize()
+            same = same and bool(np.array_equal(corr.cpu().numpy(), outs["mixed"][sl]))
+            sig[sl] = re.err[..., 0].cpu()
+        del re
+        torch.cuda.empty_cache()
+        err_stats = error_report([outs["mixed"]], [outs["fp64"]], [sig.numpy()])
+        err_stats["error_estimate"]["correlators_identical_to_timed_run"] = same
+        err = err_stats["max"]
         log(f"[bench] rel err mixed vs fp64 over {lanes} lanes: median {err_stats['median']:.2e} "
-            f"p99 {err_stats['p99']:.2e} max {err:.3e}")
+            f"p99 {err_stats['p99']:.2e} max {err:.3e}; componentwise max {err_stats['componentwise_max']:.2e}; "
+            f"estimate/deviation {err_stats['error_estimate']['sigma_over_deviation_per_lane']}")
 
     main_name = "mixed" if "mixed" in results else "fp64"
     res = results[main_name]
@@ -256,10 +306,21 @@ def run_workload(name, args):
         key = f"{name}:{main_name}:{dom}"
         if t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {}):
             traffic = t["bytes_per_launch"][key]
-    roofline = dict(bound="alu", kernel=f"recursion {dom} ({'proton' if counts['path'][s] == 0 else 'neutron'} added)",
+    alu_frac = achieved / VALU_PEAK_TFLOPS
+    # measured HBM traffic (FETCH_SIZE x calibration + WRITE_SIZE; FETCH_SIZE
+    # counts every L2 request to the memory fabric, MALL hits included) over
+    # the launch time, against the HBM peak
+    hbm_frac = None if traffic is None else traffic / (res["kernel_avg_ms"][dom] / 1e3) / 1e9 / HBM_PEAK_GBS
+    bound = "hbm" if hbm_frac is not None and hbm_frac > alu_frac else "alu"
+    roofline = dict(bound=bound, kernel=f"recursion {dom} ({'proton' if counts['path'][s] == 0 else 'neutron'} added)",
                     achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=traffic,
+                    frac=round(alu_frac, 4), traffic=traffic,
+                    hbm_frac=None if hbm_frac is None else round(hbm_frac, 4),
                     flops_per_launch=flops, launch_ms=round(res["kernel_avg_ms"][dom], 4))
+    if bound == "hbm":
+        roofline.update(achieved=round(traffic / (res["kernel_avg_ms"][dom] / 1e3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(hbm_frac, 4), alu_frac=round(alu_frac, 4),
+                        alu_achieved_tflops=round(achieved, 3))
     roofline["blocks"] = blocks_roofline(cfg, counts, chunk, res["kernel_avg_ms"]["blocks"])
 
     return dict(name=name, cfg=cfg, lanes=lanes, V=V, counts=counts, chunk=chunk, results=results,
@@ -284,11 +345,14 @@ def run_mix(args):
     for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
+        sources = None
         if not args.no_autotune:
-            tune_nuclei(groups, prec, c5_chunk, cache=args.tune_cache, key="c5", log=log)
+            tuned = tune_nuclei(groups, prec, c5_chunk, cache=args.tune_cache, key="c5", log=log,
+                                committed_first=not args.retune)
+            sources = sorted({src for _, src in tuned.values()})
         br = BatchRunner(groups, prec, n_branches=4, chunk=c5_chunk)
         times = br.tune_branches(log=log) if not args.no_autotune else None
-        tuning[prec_name] = dict(branches=br.n_branches, graph_ms_by_branches=times)
+        tuning[prec_name] = dict(branches=br.n_branches, graph_ms_by_branches=times, launch_settings=sources)
         for _ in range(args.warmup):
             br.launch()
         torch.cuda.synchronize()
@@ -310,12 +374,10 @@ def run_mix(args):
         torch.cuda.empty_cache()
     err = err_stats = None
     if len(outs) == 2:
-        per_lane = np.concatenate([
-            np.linalg.norm((a - b).reshape(a.shape[0], -1), axis=1) / np.linalg.norm(b.reshape(b.shape[0], -1), axis=1)
-            for a, b in zip(outs["mixed"], outs["fp64"])])
-        err = float(per_lane.max())
-        err_stats = dict(median=float(np.median(per_lane)), p99=float(np.quantile(per_lane, 0.99)), max=err)
-        log(f"[bench] mix rel err mixed vs fp64: median {err_stats['median']:.2e} max {err:.3e}")
+        err_stats = error_report(outs["mixed"], outs["fp64"])
+        err = err_stats["max"]
+        log(f"[bench] mix rel err mixed vs fp64: median {err_stats['median']:.2e} max {err:.3e}, "
+            f"componentwise max {err_stats['componentwise_max']:.2e}")
     main_name = "mixed" if "mixed" in results else "fp64"
     cfg = dict(workload=f"uneven batch: {len(probs)} problems drawn by seed {MIX_SEED} from "
                         f"{', '.join(m['name'] for m in MIX_TYPES)}; L in {{16,24,32}}, T in {{32,64,96}}; "
@@ -327,22 +389,35 @@ def run_mix(args):
 
 def blocks_roofline(cfg, counts, chunk, ms):
     """The blocks call (site sums on FP64 MFMA, finish, lane exponents) against
-    its binding roof: dense contraction flops (rows psi x xi1, symmetric
-    diquark pairs, 3 colours, 8 flops per complex FMA) over the FP64 matrix
-    peak, or the propagator entries it must read over the HBM peak."""
+    its binding roof.  Algorithmic flops per site, symmetric diquark (u = d):
+    the contraction 3 colours x (rows psi x xi1) x (xi2 <= xi3 pairs) and
+    the diquark 3 colours x pairs x (2 eps terms x the nonzero C gamma_5
+    entries: 4 relativistic, 2 nonrelativistic) complex FMAs, 8 flops each
+    (104 832 per site for 4He relativistic, 97 344 for 8Be with two sources,
+    8 064 for nonrelativistic one-source nuclei).  Bytes: the propagator
+    entries the blocks need, (3 D)^2 per source and site (the rows and
+    columns of the active spins), each read once.  The bound is the roof
+    with the longer ideal time; both fractions are reported."""
     V = cfg["L"] ** 3
     npsi, nxi = counts["n_psi"], counts["n_xi"]
     D = 4 if cfg["rel"] else 2
-    flops = chunk * V * 8.0 * 3 * npsi * nxi * nxi * (nxi + 1) / 2
+    npair = nxi * (nxi + 1) // 2
+    ncg5 = 4 if cfg["rel"] else 2
+    per_site = 8.0 * 3 * npair * (npsi * nxi + 2 * ncg5)
+    flops = chunk * V * per_site
     nbytes = chunk * V * cfg["nsrc"] * (3 * D) ** 2 * (16 if cfg["c128"] else 8)
     t_mfma, t_hbm = flops / (MFMA_F64_PEAK_TFLOPS * 1e12), nbytes / (HBM_PEAK_GBS * 1e9)
+    tflops = flops / (ms / 1e3) / 1e12
+    gbs = nbytes / (ms / 1e3) / 1e9
+    out = dict(flops_per_site=per_site, bytes_per_site=nbytes / (chunk * V), launch_ms=round(ms, 4),
+               mfma_frac=round(tflops / MFMA_F64_PEAK_TFLOPS, 4), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+               ideal_ms_mfma=round(t_mfma * 1e3, 4), ideal_ms_hbm=round(t_hbm * 1e3, 4))
     if t_mfma >= t_hbm:
-        achieved = flops / (ms / 1e3) / 1e12
-        return dict(bound="mfma", achieved=round(achieved, 3), peak=MFMA_F64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / MFMA_F64_PEAK_TFLOPS, 4), launch_ms=round(ms, 4))
-    achieved = nbytes / (ms / 1e3) / 1e9
-    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), launch_ms=round(ms, 4))
+        out.update(bound="mfma", achieved=round(tflops, 3), peak=MFMA_F64_PEAK_TFLOPS, unit="TFLOP/s",
+                   frac=out["mfma_frac"])
+    else:
+        out.update(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=out["hbm_frac"])
+    return out
 
 
 def summary(w):
@@ -362,6 +437,7 @@ def summary(w):
         "roofline": w["roofline"],
         "term_list_build_s": round(w["t_list"], 2),
         "autotune": w["tuning"],
+        "kernels_per_graph": res.get("kernels_per_graph"),
     }
 
 
@@ -385,8 +461,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c3+c4", choices=sorted(CONFIGS) + ["c3+c4", "c5"],
-                    help="workload; c3+c4 times 4He relativistic (the reported value) and 8Be NR")
+    ap.add_argument("--config", default="all", choices=sorted(CONFIGS) + ["all", "c3+c4", "c5"],
+                    help="workload; all (default) times 4He relativistic (the reported value), 8Be NR, the "
+                         "uneven batch and 4He NR; c3+c4 only the first two")
     ap.add_argument("--chunk", type=int, default=0,
                     help="lanes per launch (default: every lane of the workload in one launch; batch items of at most 256 lanes for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -405,8 +482,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    names = ["c3", "c4"] if args.config == "c3+c4" else [args.config]
-    ws = [run_mix(args) if n == "c5" else run_workload(n, args) for n in names]
+    names = {"all": ["c3", "c4", "c5", "c2"], "c3+c4": ["c3", "c4"]}.get(args.config, [args.config])
+    ws = []
+    for n in names:
+        ws.append(run_mix(args) if n == "c5" else run_workload(n, args))
+        import torch
+        torch.cuda.empty_cache()
     first = summary(ws[0])
     cpu = None
     if not args.no_cpu_baseline and names[0] != "c5":
@@ -436,8 +517,8 @@ def main():
     line["cpu_baseline"] = cpu
     for k in ("term_list_build_s", "autotune"):
         line[k] = first[k]
-    if len(ws) > 1:
-        line["second_workload"] = summary(ws[1])
+    for key, w in zip(("second_workload", "third_workload", "fourth_workload"), ws[1:]):
+        line[key] = summary(w)
     print(json.dumps(line), flush=True)
 
 
@@ -449,12 +530,14 @@ def cpu_baseline(cfg, name):
 
     from oracle import oracle as O
     from synth import props as SP
-    threads = min(16, os.cpu_count() or 1)   # the host share of one GPU
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = min(16, avail)   # the host share of one GPU
     O.set_threads(threads)
+    host = dict(cpu_count=os.cpu_count(), available_to_process=avail, threads_used=threads)
     V = cfg["L"] ** 3
     D = 4 if cfg["rel"] else 2
     if cfg["nP"] + cfg["nN"] > 4:
-        return {"value": None, "unit": "timeslices/s", "cores": threads, "kind": "oracle",
+        return {"value": None, "unit": "timeslices/s", "cores": threads, "host": host, "kind": "oracle",
                 "sample": "infeasible: the oracle's permutation sum has n_u! n_d! = (12!)^2 terms per "
                           "component for 8Be"}
     nsite = V
@@ -482,12 +565,32 @@ def cpu_baseline(cfg, name):
     # the permutation sums cost about the same per L entry for every pair
     nl_total = len(dsets) * sum(nL.values())
     per_ts = t_blocks_sample * V / nsite + t_pairs * nl_total / nl_sample
-    return {"value": 1.0 / per_ts, "unit": "timeslices/s", "cores": threads, "kind": "oracle",
+    # the same oracle on one thread, on a smaller sample: blocks on 1/16 of
+    # the sites and 2 of the pairs, scaled the same way
+    O.set_threads(1)
+    ns1 = max(1, V // 16)
+    t = time.time()
+    fP1, fN1 = O.blocks(cfg["rel"], cfg["nsrc"], S[:ns1], S[:ns1], None, 2.0)
+    t_b1 = time.time() - t
+    t = time.time()
+    nl1 = 0
+    for d, a in sample_pairs[:2]:
+        um, dm, cf = O.L_for_alpha(cfg["rel"], cfg["nsrc"], cfg["nP"], cfg["nN"], a)
+        O.corr_from_L(types, O._bits(d[0]) + O._bits(d[1]), fP1, fN1, um, dm, cf)
+        nl1 += len(um)
+    t_p1 = time.time() - t
+    O.set_threads(threads)
+    per_ts1 = t_b1 * V / ns1 + t_p1 * nl_total / nl1
+    return {"value": 1.0 / per_ts, "unit": "timeslices/s", "cores": threads, "host": host, "kind": "oracle",
             "sample": (f"one timeslice: oracle blocks on {nsite} of {V} sites ({t_blocks_sample:.1f}s), "
                        f"scaled by {V / nsite:.2f}; oracle correlator for {len(sample_pairs)} of "
                        f"{len(dsets)}x{len(req['alphas'])} component pairs ({nl_sample} L entries, "
                        f"{t_pairs:.1f}s), scaled by the {nl_total} L entries of all pairs"),
-            "seconds_measured": round(t_blocks_sample + t_pairs, 2)}
+            "seconds_measured": round(t_blocks_sample + t_pairs, 2),
+            "single_thread": {"value": 1.0 / per_ts1, "unit": "timeslices/s", "cores": 1,
+                              "sample": (f"oracle blocks on {ns1} of {V} sites ({t_b1:.1f}s), correlator for 2 "
+                                         f"component pairs ({nl1} L entries, {t_p1:.1f}s), scaled as above"),
+                              "seconds_measured": round(t_b1 + t_p1, 2)}}
 
 
 if __name__ == "__main__":

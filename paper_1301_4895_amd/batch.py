@@ -112,9 +112,12 @@ class BatchRunner:
         return times
 
 
-def tune_nuclei(groups, precision, chunk=256, cache=None, key=None, log=None):
-    """Autotunes the recursion launches of every distinct term list once, on
-    the largest of its groups (the settings do not depend on the volume)."""
+def tune_nuclei(groups, precision, chunk=256, cache=None, key=None, log=None, committed_first=True):
+    """Launch settings of every distinct term list: the committed ones for
+    this key (paper_1301_4895_amd/tuned.json) when present and
+    committed_first, else the autotuner on the largest of its groups (the
+    settings do not depend on the volume).  Returns {id(tl): (settings,
+    source)}."""
     from . import autotune
     from .runner import Runner
     best = {}
@@ -123,10 +126,15 @@ def tune_nuclei(groups, precision, chunk=256, cache=None, key=None, log=None):
         if id(tl) in best:
             continue
         n = min(chunk, g["props"].shape[0])
+        k = None if key is None else f"{key}|{g['name']}|{precision}|{n}"
+        fixed = autotune.committed(k) if (committed_first and k) else None
+        if fixed is not None:
+            autotune.apply(tl, fixed)
+            best[id(tl)] = (fixed, "committed")
+            continue
         r = Runner(tl, g["props"][:n], g["props"][:n], precision, g.get("sink_w"),
                    None if g.get("scale_exp") is None else g["scale_exp"][:n])
-        k = None if key is None else f"{key}|{g['name']}|{precision}|{n}"
-        best[id(tl)] = autotune.tune(tl, r, key=k, cache=cache, log=log)
+        best[id(tl)] = (autotune.tune(tl, r, key=k, cache=cache, log=log), "autotuned")
         del r
         torch.cuda.empty_cache()
     return best

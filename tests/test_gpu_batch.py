@@ -169,10 +169,15 @@ def test_batch_rejects_shared_buffers_across_branches():
 
 
 def test_full_uneven_batch():
+    """In the launch settings the benchmark times (the committed table, keyed
+    like bench.py's C5 run)."""
+    from paper_1301_4895_amd.batch import tune_nuclei
     groups, tls, probs = mix_groups(torch.device(DEV))
     assert sum(g["props"].shape[0] for g in groups) == sum(T for _, _, T in probs)
     res = {}
     for prec in (B.MB_MIXED, B.MB_FP64):
+        tuned = tune_nuclei(groups, prec, 256, key="c5")
+        print(prec, {src for _, src in tuned.values()}, flush=True)
         br = BatchRunner(groups, prec, n_branches=4, chunk=256)
         br.launch()
         torch.cuda.synchronize()
