@@ -104,7 +104,8 @@ def kernel_hash():
     """Hash of the recursion-step sources: the measured traffic of a step is
     only reported while these are unchanged."""
     h = hashlib.sha256()
-    for f in ("contract.hip", "contract_impl.h", "contract_f32.hip", "contract_f64.hip", "kernels.h"):
+    for f in ("contract.hip", "contract_impl.h", "contract_f32.hip", "contract_f64.hip", "contract_f32_m6.hip",
+              "contract_f64_m6.hip", "kernels.h"):
         h.update(open(os.path.join(ROOT, "paper_1301_4895_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

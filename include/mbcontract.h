@@ -78,7 +78,9 @@ extern "C" {
 /* A nucleus of n_P protons and n_N neutrons (Sec. 7).
  *   rel    1: Gamma_1 = 1, Gamma_2 = C gamma_5; 0: the nonrelativistic
  *          Gamma_1 = P_nr, Gamma_2 = C gamma_5 P_nr (Dirac representation).
- *   n_src  number of orthogonal quark sources N_s (Sec. 6), 1 or 2.
+ *   n_src  number of orthogonal quark sources N_s (Sec. 6): 1 or 2, and 3
+ *          with nonrelativistic operators (18 quark indices per flavour);
+ *          MB_EUNSUPPORTED otherwise.
  *   path   order of the recursion (MB_PATH_*).  AUTO, PROTONS_FIRST and
  *          NEUTRONS_FIRST add all baryons of one species before the other.
  *          EXPLICIT: bit i of `order` set means that the (i+1)-th baryon added
@@ -100,10 +102,10 @@ typedef struct {
 
 /* Which components of C(delta set; alpha set) are wanted (Sec. 5, Sec. 8).
  *   all_components != 0: every sink set over the D*N_s baryon indices and,
- *          with one source, every source set; with two sources the source
- *          sets that put min(n, D) baryons of a species on source 0 and the
- *          rest on source 1 (the convention of Tables 1-3).  The other
- *          fields are ignored.
+ *          with one source, every source set; with several sources the
+ *          source sets that put min(n, D) baryons of a species on source 0,
+ *          min(rest, D) on source 1 and the rest on source 2 (the
+ *          convention of Tables 1-3).  The other fields are ignored.
  *   otherwise: sink_P, sink_N are bit masks of the sink baryon indices; the
  *          output rows are every n_P-subset of sink_P times every
  *          n_N-subset of sink_N.  alpha[2*i], alpha[2*i+1] are the proton
@@ -319,7 +321,11 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
  *                       from global memory; 1: the block rows of one single
  *                       quark index at a time are staged in LDS per
  *                       workgroup of 16 lanes x 16 outputs (lane tile and
- *                       LDS bytes are then fixed)
+ *                       LDS bytes are then fixed; up to 12 quark indices)
+ * Steps whose species has more than four sink indices (three sources) run
+ * the direct kernel with one passthrough part per thread and no output
+ * grouping: other kernel, passthrough-group or grouping settings there make
+ * the contraction return MB_EUNSUPPORTED before any launch.
  * Returns MB_EINVAL for an unknown item, step or value.                      */
 #define MB_TUNE_PASS_GROUP 1
 #define MB_TUNE_LDS_BYTES 2

@@ -281,7 +281,7 @@ def all_components_request(nP, nN, D, nsrc):
     """'All independent spinor components' (Tables 1-3): every sink set over
     the D*N_s baryon indices; at the source, with one source every set, with
     several sources the sets that put min(n, D) baryons of a species on
-    source 0 (any spins) and the rest on source 1."""
+    source 0 (any spins), min(rest, D) on source 1, and so on."""
     nb = D * nsrc
     sinkP = (1 << nb) - 1
     sinkN = (1 << nb) - 1
@@ -289,15 +289,12 @@ def all_components_request(nP, nN, D, nsrc):
     def src_sets(n):
         if nsrc == 1:
             return [_mask(c) for c in itertools.combinations(range(nb), n)]
-        n0 = min(n, D)
-        n1 = n - n0
-        on0 = [nsrc * a + 0 for a in range(D)]
-        on1 = [nsrc * a + 1 for a in range(D)]
-        sets = []
-        for c0 in itertools.combinations(on0, n0):
-            for c1 in itertools.combinations(on1, n1):
-                sets.append(_mask(c0 + c1))
-        return sets
+        counts, left = [], n
+        for s in range(nsrc):
+            counts.append(min(left, D))
+            left -= counts[-1]
+        per_source = [itertools.combinations([nsrc * a + s for a in range(D)], counts[s]) for s in range(nsrc)]
+        return sorted(_mask(sum(cs, ())) for cs in itertools.product(*[list(p) for p in per_source]))
 
     alphas = [(p, n) for p in src_sets(nP) for n in src_sets(nN)]
     return dict(sinkP=sinkP, sinkN=sinkN, alphas=alphas)

@@ -146,7 +146,12 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
         for cand in _candidates(npass, nsingle if two_ok[s] else 1):
             _apply(tl, s, *cand)
             runner.ensure_workspace()
-            results.append((_time_step(tl, runner, s, reps, stream),) + cand)
+            try:
+                results.append((_time_step(tl, runner, s, reps, stream),) + cand)
+            except B.MBError as e:
+                # no kernel for this setting and step (refused before any launch)
+                if e.code != B.MB_EUNSUPPORTED:
+                    raise
         ms, *cand = min(results)
         _apply(tl, s, *cand)
         runner.ensure_workspace()

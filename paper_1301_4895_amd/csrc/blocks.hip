@@ -311,6 +311,131 @@ static hipError_t launch_bm(const BlocksArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The same site sums on the vector units, for shapes without a matrix-core
+// instantiation (nonrelativistic operators with three sources: 18 quark
+// indices, 6 baryon indices).  A workgroup owns one lane, one chunk of sites
+// and a range of output entries (psi, xi1, pair) of the partial layout; for
+// every site it stages the propagator rows in LDS (in double), forms the
+// diquark of every pair and colour there, and every thread adds the three
+// colour products of its entries.
+constexpr int GEN_THREADS = 256, GEN_EPT = 8;   // entries per thread
+constexpr int GEN_MAXROW = 6, GEN_MAXXI = 18;
+
+template <typename TIN, bool SYM>
+__global__ __launch_bounds__(GEN_THREADS) void blocks_generic_kernel(BlocksArgs a) {
+  __shared__ double2 su[GEN_MAXROW * GEN_MAXXI], sd[GEN_MAXROW * GEN_MAXXI], s1[GEN_MAXROW * GEN_MAXXI];
+  __shared__ double2 dq[3 * GEN_MAXXI * GEN_MAXXI];
+  __shared__ double2 wsh[8];
+  const int tid = threadIdx.x;
+  const int nsrc = a.nsrc, D = a.D, nrow = 3 * D, nxi = 3 * D * nsrc, npsi = D * nsrc;
+  const int npair = SYM ? nxi * (nxi + 1) / 2 : nxi * nxi;
+  const int64_t nent = int64_t(npsi) * nxi * npair;
+  const int64_t ln = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int64_t e0 = int64_t(blockIdx.z) * GEN_THREADS * GEN_EPT;
+  const int64_t x0 = int64_t(chunk) * a.sites_per_chunk;
+  const int64_t x1 = min(a.V, x0 + a.sites_per_chunk);
+  const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[ln]) : 1.0;
+  const bool same1 = a.prop_q1 == a.prop_u;
+  const double2 *s1_f = (SYM || same1) ? su : s1;
+  const double2 *sd_f = SYM ? su : sd;
+
+  // the entries of this thread: (psi, xi1, pair) and their A-operand rows
+  int e_xi1[GEN_EPT], e_pair[GEN_EPT], e_row0[GEN_EPT], e_sk[GEN_EPT];
+  bool e_ok[GEN_EPT];
+  double2 acc[GEN_EPT];
+#pragma unroll
+  for (int j = 0; j < GEN_EPT; j++) {
+    const int64_t e = e0 + tid + int64_t(j) * GEN_THREADS;
+    e_ok[j] = e < nent;
+    const int64_t ee = e_ok[j] ? e : 0;
+    const int pair = int(ee % npair);
+    const int rest = int(ee / npair);
+    const int xi1 = rest % nxi, psi = rest / nxi;
+    e_xi1[j] = xi1;
+    e_pair[j] = pair;
+    e_row0[j] = 3 * (psi / nsrc);   // row (alpha, colour 0) of the q1 propagator
+    e_sk[j] = psi % nsrc;           // sink function
+    acc[j] = make_double2(0.0, 0.0);
+  }
+  auto ld = [&](const void *base, int64_t x, int r, int xi) {
+    const int s = xi % nsrc, kap = xi / nsrc;
+    const int64_t off = (((ln * a.V + x) * nsrc + s) * 12 + r) * 12 + kap;
+    const TIN v = static_cast<const TIN *>(base)[off];
+    return make_double2(double(v.x) * scale, double(v.y) * scale);
+  };
+  for (int64_t x = x0; x < x1; x++) {
+    __syncthreads();   // the previous site's operands are no longer read
+    for (int i = tid; i < nrow * nxi; i += GEN_THREADS) {
+      const int r = i / nxi, xi = i % nxi;
+      su[i] = ld(a.prop_u, x, r, xi);
+      if (!SYM) {
+        sd[i] = ld(a.prop_d, x, r, xi);
+        if (!same1) s1[i] = ld(a.prop_q1, x, r, xi);
+      }
+    }
+    if (tid < nsrc)
+      wsh[tid] = a.sink_w ? reinterpret_cast<const double2 *>(a.sink_w)[int64_t(tid) * a.V + x] : make_double2(1.0, 0.0);
+    __syncthreads();
+    // diquark D_a[pair] = sum eps_abc (C g5)_{g d} S_u[(g, b), xi2] S_d[(d, c), xi3]
+    // ((C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1)
+    for (int i = tid; i < 3 * npair; i += GEN_THREADS) {
+      const int ac = i / npair, p = i % npair;
+      int x2, x3;
+      if (SYM) {
+        x3 = 0;
+        while ((x3 + 1) * (x3 + 2) / 2 <= p) x3++;
+        x2 = p - x3 * (x3 + 1) / 2;
+      } else {
+        x2 = p / nxi;
+        x3 = p % nxi;
+      }
+      const int bb = (ac + 1) % 3, cc = (ac + 2) % 3;
+      double re = 0.0, im = 0.0;
+      for (int gs = 0; gs < D; gs++) {
+        const double sg = (gs & 1) ? 1.0 : -1.0;
+        const int gd = gs ^ 1;
+        const double2 l0 = su[(3 * gs + bb) * nxi + x2], r0 = sd_f[(3 * gd + cc) * nxi + x3];
+        const double2 l1 = su[(3 * gs + cc) * nxi + x2], r1 = sd_f[(3 * gd + bb) * nxi + x3];
+        re += sg * ((l0.x * r0.x - l0.y * r0.y) - (l1.x * r1.x - l1.y * r1.y));
+        im += sg * ((l0.x * r0.y + l0.y * r0.x) - (l1.x * r1.y + l1.y * r1.x));
+      }
+      dq[i] = make_double2(re, im);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < GEN_EPT; j++) {
+      if (!e_ok[j]) continue;
+      const double2 w = wsh[e_sk[j]];
+#pragma unroll
+      for (int ac = 0; ac < 3; ac++) {
+        const double2 v = s1_f[(e_row0[j] + ac) * nxi + e_xi1[j]];
+        const double2 A = make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+        const double2 B = dq[ac * npair + e_pair[j]];
+        acc[j].x = fma(A.x, B.x, fma(-A.y, B.y, acc[j].x));
+        acc[j].y = fma(A.x, B.y, fma(A.y, B.x, acc[j].y));
+      }
+    }
+  }
+  double2 *out = reinterpret_cast<double2 *>(a.partial) + (ln * a.nchunk + chunk) * nent;
+#pragma unroll
+  for (int j = 0; j < GEN_EPT; j++)
+    if (e_ok[j]) out[e0 + tid + int64_t(j) * GEN_THREADS] = acc[j];
+}
+
+template <typename TIN, bool SYM>
+static hipError_t launch_generic(const BlocksArgs &a, hipStream_t s) {
+  const int nxi = 3 * a.D * a.nsrc, npsi = a.D * a.nsrc;
+  if (3 * a.D > GEN_MAXROW || nxi > GEN_MAXXI || a.nsrc > 8) return hipErrorInvalidValue;
+  const int npair = SYM ? nxi * (nxi + 1) / 2 : nxi * nxi;
+  const int64_t nent = int64_t(npsi) * nxi * npair;
+  const unsigned gz = unsigned((nent + GEN_THREADS * GEN_EPT - 1) / (GEN_THREADS * GEN_EPT));
+  hipLaunchKernelGGL((blocks_generic_kernel<TIN, SYM>), dim3(a.nchunk, unsigned(a.B), gz), dim3(GEN_THREADS), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
 template <typename TIN>
 static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
   if (a.D == 4 && a.nsrc == 1)
@@ -321,6 +446,8 @@ static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
     return sym ? launch_bm<TIN, 6, 2, 6, true, 2>(a, s) : launch_bm<TIN, 6, 2, 6, false, 2>(a, s);
   if (a.D == 2 && a.nsrc == 2)
     return sym ? launch_bm<TIN, 12, 4, 6, true>(a, s) : launch_bm<TIN, 12, 4, 6, false>(a, s);
+  // nonrelativistic operators with three sources: the vector-unit sums
+  if (a.D == 2 && a.nsrc == 3) return sym ? launch_generic<TIN, true>(a, s) : launch_generic<TIN, false>(a, s);
   return hipErrorInvalidValue;
 }
 

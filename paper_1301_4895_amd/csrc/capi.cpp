@@ -38,7 +38,7 @@ int check_problem(const mb_term_list *tl, const mb_problem *p) {
   if (p->in_dtype != MB_C64 && p->in_dtype != MB_C128) return fail(MB_EINVAL, "bad in_dtype");
   if (p->precision != MB_FP64 && p->precision != MB_MIXED) return fail(MB_EINVAL, "bad precision");
   if (tl->counts_only) return fail(MB_EINVAL, "counts-only term list");
-  if (tl->nxi > 12) return fail(MB_EUNSUPPORTED, "blocks support at most 12 quark indices");
+  if (tl->nxi > 18) return fail(MB_EUNSUPPORTED, "blocks support at most 18 quark indices");
   return MB_OK;
 }
 
@@ -414,10 +414,12 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
     if (C.tune_kernel != 0 || !C.tune_paired) return 0;
     const bool AP = C.type == PROTON;
     const int npass = AP ? C.nNsets : C.nPsets;
-    const int pg = C.tune_pg ? C.tune_pg : npass % 3 == 0 ? 3 : npass % 2 == 0 ? 2 : 1;
-    const bool grouped = (C.tune_group == 2 || C.tune_group == 4) && pg <= 3;
-    const bool direct64 = !grouped && C.tune_tile == 64;
     const int M = __builtin_popcount(AP ? tl->SP : tl->SN);
+    // steps with more than four sink indices per species run one
+    // passthrough part per thread in the direct kernel
+    const int pg = M > 4 ? 1 : C.tune_pg ? C.tune_pg : npass % 3 == 0 ? 3 : npass % 2 == 0 ? 2 : 1;
+    const bool grouped = M <= 4 && (C.tune_group == 2 || C.tune_group == 4) && pg <= 3;
+    const bool direct64 = !grouped && C.tune_tile == 64;
     const int nin = binom(M, AP ? tl->st[j].kP : tl->st[j].kN);
     if (direct64 && AP && npass % 2 == 0 && pg % 2 == 0) return 1;
     if ((direct64 || grouped) && nin % 2 == 0 && (!AP || npass == 1)) return 2;
@@ -532,8 +534,11 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
           a.hstride = S.nreq() * Bp;
         }
         psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
-        if (a.M > 4) return fail(MB_EUNSUPPORTED, "more than 4 sink indices per species");
+        if (a.M > 6) return fail(MB_EUNSUPPORTED, "more than 6 sink indices per species");
         if (a.nq_out > 0 && S.tune_kernel == 1) {
+          // the LDS-staged kernel holds one range of at most 36 pair rows:
+          // n_xi <= 12 (one source relativistic, up to two nonrelativistic)
+          if (nxi > 12) return fail(MB_EUNSUPPORTED, "LDS-staged step kernel: more than 12 quark indices");
           StageLdsArgs b{};
           b.Fin = a.Fin;
           b.Fout = a.Fout;

@@ -800,23 +800,37 @@ static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
 // passthrough count, else 2, else 1
 template <typename T, int M, int K>
 static hipError_t launch_stage_mk(const StageArgs &a, hipStream_t s) {
-  if (a.pg == 1) return launch_stage_mkp<T, M, K, 1>(a, s);
-  if (a.pg == 2) return launch_stage_mkp<T, M, K, 2>(a, s);
-  if (a.pg == 3) return launch_stage_mkp<T, M, K, 3>(a, s);
-  if (a.pg == 6) return launch_stage_mkp<T, M, K, 6>(a, s);
-  if (a.npass % 3 == 0) return launch_stage_mkp<T, M, K, 3>(a, s);
-  if (a.npass % 2 == 0) return launch_stage_mkp<T, M, K, 2>(a, s);
-  return launch_stage_mkp<T, M, K, 1>(a, s);
+  if constexpr (M > 4) {
+    // more than four sink indices per species (three sources): one
+    // passthrough part per thread and the direct kernel (the wedge alone
+    // holds up to C(6,3) = 20 outputs per thread)
+    if (a.pg > 1 || a.group > 1) return hipErrorInvalidValue;
+    return a.tile == 16 ? launch_stage_mkpt<T, M, K, 1, 16>(a, s) : launch_stage_mkpt<T, M, K, 1, 64>(a, s);
+  } else {
+    if (a.pg == 1) return launch_stage_mkp<T, M, K, 1>(a, s);
+    if (a.pg == 2) return launch_stage_mkp<T, M, K, 2>(a, s);
+    if (a.pg == 3) return launch_stage_mkp<T, M, K, 3>(a, s);
+    if (a.pg == 6) return launch_stage_mkp<T, M, K, 6>(a, s);
+    if (a.npass % 3 == 0) return launch_stage_mkp<T, M, K, 3>(a, s);
+    if (a.npass % 2 == 0) return launch_stage_mkp<T, M, K, 2>(a, s);
+    return launch_stage_mkp<T, M, K, 1>(a, s);
+  }
 }
 
-template <typename T>
+// Instantiates the step kernels of the base-set sizes lo <= M <= hi only
+// (the translation units split the instantiations by M).
+template <typename T, int LO, int HI>
 hipError_t launch_stage_t(const StageArgs &a, hipStream_t s) {
 #define MB_CASE(m, k) \
-  if (a.M == m && a.K == k) return launch_stage_mk<T, m, k>(a, s);
+  if constexpr (LO <= m && m <= HI) { \
+    if (a.M == m && a.K == k) return launch_stage_mk<T, m, k>(a, s); \
+  }
   MB_CASE(1, 0)
   MB_CASE(2, 0) MB_CASE(2, 1)
   MB_CASE(3, 0) MB_CASE(3, 1) MB_CASE(3, 2)
   MB_CASE(4, 0) MB_CASE(4, 1) MB_CASE(4, 2) MB_CASE(4, 3)
+  MB_CASE(5, 0) MB_CASE(5, 1) MB_CASE(5, 2) MB_CASE(5, 3) MB_CASE(5, 4)
+  MB_CASE(6, 0) MB_CASE(6, 1) MB_CASE(6, 2) MB_CASE(6, 3) MB_CASE(6, 4) MB_CASE(6, 5)
 #undef MB_CASE
   return hipErrorInvalidValue;
 }

@@ -184,6 +184,8 @@ hipError_t launch_err_stage(const ErrStageArgs &a, hipStream_t s) {
   MB_CASE(2, 0) MB_CASE(2, 1)
   MB_CASE(3, 0) MB_CASE(3, 1) MB_CASE(3, 2)
   MB_CASE(4, 0) MB_CASE(4, 1) MB_CASE(4, 2) MB_CASE(4, 3)
+  MB_CASE(5, 0) MB_CASE(5, 1) MB_CASE(5, 2) MB_CASE(5, 3) MB_CASE(5, 4)
+  MB_CASE(6, 0) MB_CASE(6, 1) MB_CASE(6, 2) MB_CASE(6, 3) MB_CASE(6, 4) MB_CASE(6, 5)
 #undef MB_CASE
   return hipErrorInvalidValue;
 }

@@ -333,30 +333,37 @@ static int source_coefficients(const mb_term_list *tl, int n, const std::vector<
 }
 
 // Source sets of `n` baryons of one species with all spins: every n-subset
-// of the D*N_s indices with one source; with two sources, min(n, D) on
-// source 0 and the rest on source 1 (the convention of Tables 1-3).
+// of the D*N_s indices with one source; with several sources, min(n, D) on
+// source 0, min(rest, D) on source 1 and so on, any spins on each (the
+// convention of Tables 1-3 for two sources, continued source by source).
 static std::vector<uint32_t> all_source_sets(int n, int D, int nsrc) {
   const uint32_t all = (1u << (D * nsrc)) - 1;
   std::vector<uint32_t> v;
   if (nsrc == 1) {
     for (uint32_t m = 0; m <= all; m++)
       if (__builtin_popcount(m) == n) v.push_back(m);
-  } else {
-    int n0 = std::min(n, D), n1 = n - n0;
-    for (uint32_t m0 = 0; m0 < (1u << D); m0++) {
-      if (__builtin_popcount(m0) != n0) continue;
-      for (uint32_t m1 = 0; m1 < (1u << D); m1++) {
-        if (__builtin_popcount(m1) != n1) continue;
-        uint32_t m = 0;
-        for (int a = 0; a < D; a++) {
-          if (m0 >> a & 1) m |= 1u << (nsrc * a + 0);
-          if (m1 >> a & 1) m |= 1u << (nsrc * a + 1);
-        }
-        v.push_back(m);
-      }
-    }
-    std::sort(v.begin(), v.end());
+    return v;
   }
+  // counts per source, then every choice of spins on each source
+  int cnt[8] = {};
+  for (int s = 0, left = n; s < nsrc; s++) {
+    cnt[s] = std::min(left, D);
+    left -= cnt[s];
+  }
+  v.push_back(0);
+  for (int s = 0; s < nsrc; s++) {
+    std::vector<uint32_t> next;
+    for (uint32_t base : v)
+      for (uint32_t ms = 0; ms < (1u << D); ms++) {
+        if (__builtin_popcount(ms) != cnt[s]) continue;
+        uint32_t m = base;
+        for (int a = 0; a < D; a++)
+          if (ms >> a & 1) m |= 1u << (nsrc * a + s);
+        next.push_back(m);
+      }
+    v.swap(next);
+  }
+  std::sort(v.begin(), v.end());
   return v;
 }
 
@@ -433,7 +440,9 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   if (nP < 0 || nN < 0 || nP + nN < 1) return fail(MB_EINVAL, "need at least one baryon");
   if (nP + nN > MB_MAX_STAGES) return fail(MB_EUNSUPPORTED, "more than 16 baryons");
   if (nuc->rel != 0 && nuc->rel != 1) return fail(MB_EINVAL, "rel must be 0 or 1");
-  if (nuc->n_src != 1 && nuc->n_src != 2) return fail(MB_EUNSUPPORTED, "n_src must be 1 or 2");
+  if (nuc->n_src < 1 || nuc->n_src > 3) return fail(MB_EUNSUPPORTED, "n_src must be 1, 2 or 3");
+  // quark index sets are 24-bit fields of the packed keys: 3 D N_s <= 24
+  if (nuc->n_src == 3 && nuc->rel) return fail(MB_EUNSUPPORTED, "three sources need nonrelativistic operators");
   if (nuc->path < 0 || nuc->path > MB_PATH_EXPLICIT) return fail(MB_EINVAL, "bad path");
   const int D = nuc->rel ? 4 : 2, nsrc = nuc->n_src;
   const int npsi = D * nsrc, nxi = 3 * D * nsrc;
@@ -992,7 +1001,7 @@ void fields(IO &io, TL &tl, std::vector<STAGE> &st, std::vector<SIDE> &sides) {
 bool valid_loaded(const mb_term_list &t) {
   const mb_nucleus &n = t.nuc;
   if (n.n_P < 0 || n.n_N < 0 || n.n_P + n.n_N < 1 || n.n_P + n.n_N > MB_MAX_STAGES) return false;
-  if ((n.rel != 0 && n.rel != 1) || (n.n_src != 1 && n.n_src != 2)) return false;
+  if ((n.rel != 0 && n.rel != 1) || n.n_src < 1 || n.n_src > 3 || (n.n_src == 3 && n.rel)) return false;
   const int D = n.rel ? 4 : 2, A = n.n_P + n.n_N;
   if (t.D != D || t.nsrc != n.n_src || t.npsi != D * n.n_src || t.nxi != 3 * D * n.n_src) return false;
   if (t.A != A || t.nstages != A || int(t.st.size()) != A) return false;

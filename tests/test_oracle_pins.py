@@ -158,6 +158,9 @@ def test_proton_uca_equals_closed_form_and_literal_wick(rel):
     (False, 2, [0, 1], [2, 1], [0, 2], 1),
     (True, 1, [0, 1], [2, 0], [3, 1], 1),      # relativistic p+n
     (True, 1, [1, 1], [1, 2], [0, 3], 1),
+    (False, 3, [0, 1], [0, 5], [2, 5], 1),     # p+n, three sources (Sec. 6, eq. G_tilde)
+    (False, 3, [1, 1], [1, 2], [1, 5], 2),     # nn from sources 1 and 2
+    (False, 3, [0, 0], [3, 2], [0, 5], 1),     # pp from sources 0 and 2
 ])
 def test_uca_equals_literal_wick(rel, nsrc, types, psis, chis, V):
     Su, Sd = rand_props(V, nsrc), rand_props(V, nsrc)
@@ -388,6 +391,48 @@ def test_two_source_factorisation():
     c0 = _uca_corr(False, 1, [0, 1], [0, 1], [0, 1], Su[:, :1], Sd[:, :1], w[:1])
     c1 = _uca_corr(False, 1, [0, 1], [0, 1], [0, 1], Su[:, 1:], Sd[:, 1:], w[1:])
     assert abs(got) > 0 and abs(got - c0 * c1) <= 1e-11 * abs(got)
+
+
+def test_three_source_factorisation():
+    """Three sources on three disjoint regions (Sec. 6): every baryon's quarks
+    come from the source of its region, so the correlator is the product of
+    one-source correlators of the regions.  Baryon index psi = 3 alpha + s."""
+    V = 3   # one site per region
+    Su, Sd = rand_props(V, 3), rand_props(V, 3)
+    w = np.zeros((3, V), np.complex128)
+    for s in range(3):
+        for S in (Su, Sd):
+            S[[x for x in range(V) if x != s], s] = 0
+        w[s, s] = RNG.normal() + 1j * RNG.normal()
+    one = lambda S, s: S[:, s:s + 1]
+    # three neutrons, one per source: psi = chi = {0, 4, 2} -> (alpha 0, s 0), (1, 1), (0, 2)
+    got = _uca_corr(False, 3, [1, 1, 1], [0, 2, 4], [0, 2, 4], Su, Sd, w)
+    ref = 1.0
+    for s, alpha in [(0, 0), (2, 0), (1, 1)]:
+        ref *= _uca_corr(False, 1, [1], [alpha], [alpha], one(Su, s), one(Sd, s), w[s:s + 1])
+    assert abs(got) > 0 and abs(got - ref) <= 1e-11 * abs(got)
+    # p (source 0, spin 1) + n (source 1, spin 0) + n (source 2, spin 1):
+    # psi = chi sets P {3}, N {1, 5}
+    got = _uca_corr(False, 3, [0, 1, 1], [3, 1, 5], [3, 1, 5], Su, Sd, w)
+    ref = (_uca_corr(False, 1, [0], [1], [1], one(Su, 0), one(Sd, 0), w[0:1])
+           * _uca_corr(False, 1, [1], [0], [0], one(Su, 1), one(Sd, 1), w[1:2])
+           * _uca_corr(False, 1, [1], [1], [1], one(Su, 2), one(Sd, 2), w[2:3]))
+    assert abs(got) > 0 and abs(got - ref) <= 1e-11 * abs(got)
+
+
+def test_three_source_request_and_bounds():
+    """All components with three sources: min(n, D) baryons on source 0,
+    then on source 1, the rest on source 2 (any spins on each).  The
+    required sets of every stage stay within the bound P of Sec. 6 (with
+    2 N_s baryon indices and 6 N_s quark indices per flavour)."""
+    req = O.all_components_request(0, 5, 2, 3)
+    # 2 on source 0 (both spins), 2 on source 1, 1 on source 2 (either spin)
+    assert req["alphas"] == [(0, 0b011111), (0, 0b111011)]
+    tl = O.term_list(False, 3, 0, 3, O.spin_state_request(0, 3, (0, 2, 4)))
+    kn = 0
+    for s, r in enumerate(tl["req"]):
+        kn += 1
+        assert 0 < len(r) <= O.bound_P(2, 3, 0, kn)
 
 
 def test_rescale_exponent():

@@ -94,6 +94,8 @@ CASES = [
     (True, 1, 0, 3, (0, 1, 3)), (True, 1, 1, 0, None), (False, 1, 0, 1, None),
     (False, 2, 1, 1, None), (False, 2, 1, 2, None), (False, 2, 2, 2, (0, 2, 0, 2)),
     (False, 2, 0, 3, (0, 2, 3)), (False, 2, 1, 2, (2, 0, 2)), (False, 2, 2, 2, None),
+    (False, 3, 1, 1, None), (False, 3, 1, 2, None), (False, 3, 0, 3, (0, 2, 4)), (False, 3, 1, 2, (0, 1, 5)),
+    (False, 3, 2, 2, (0, 4, 1, 5)),
 ]
 
 
@@ -182,6 +184,25 @@ def test_headline_term_lists():
         assert n == O.bound_P(2, 2, kP, s + 1 - kP)
 
 
+def test_three_source_five_neutrons():
+    """Five neutrons on three sources (two, two and one per source, Sec. 6):
+    one source set, and every stage's required components stay within the
+    bound P of Sec. 6 with D N_s = 6 baryon and 3 D N_s = 18 quark indices
+    per flavour."""
+    tl = lib_termlist(False, 3, 0, 5, (0, 3, 1, 4, 2))
+    c = tl.counts()
+    assert c["n_xi"] == 18 and c["n_alpha"] == 1 and c["n_delta"] == 1 and c["path"] == [1] * 5
+    req = O.spin_state_request(0, 5, (0, 1, 2, 3, 4))
+    um, dm, cf = O.L_for_alpha(False, 3, 0, 5, req["alphas"][0])
+    assert c["n_U"] == len(cf) and c["n_L"] == len(cf)
+    coef = tl.export(B.MB_EXPORT_COEF, dtype=np.int64)
+    Qf = tl.export(B.MB_EXPORT_QUARK, c["n_stages"] - 1).reshape(-1, 2)
+    got = {(int(Qf[q, 0]), int(Qf[q, 1])): int(v) for q, v in zip(coef[2:2 + coef[1]], coef[2 + coef[1]:])}
+    assert got == {(int(u), int(d)): int(v) for u, d, v in zip(um, dm, cf)}
+    for s, n in enumerate(c["n_req"]):
+        assert 0 < n <= O.bound_P(2, 3, 0, s + 1)
+
+
 def test_path_rule():
     # Sec. 7: the more numerous species first; neutrons first on a tie
     assert lib_termlist(False, 1, 2, 1, None).counts()["path"] == [0, 0, 1]
@@ -201,8 +222,14 @@ def test_error_codes():
         B.TermList(0, 5, True, 1, all_components=True)
     assert e.value.code == B.MB_EPAULI
     with pytest.raises(B.MBError) as e:
-        B.TermList(1, 1, False, 3, all_components=True)
+        B.TermList(1, 1, False, 4, all_components=True)   # at most three sources
     assert e.value.code == B.MB_EUNSUPPORTED
+    with pytest.raises(B.MBError) as e:
+        B.TermList(1, 1, True, 3, all_components=True)    # 36 quark indices per flavour
+    assert e.value.code == B.MB_EUNSUPPORTED
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 7, False, 3, all_components=True)   # 7 neutrons, 6 spin indices
+    assert e.value.code == B.MB_EPAULI
     with pytest.raises(B.MBError) as e:
         B.TermList(1, 1, False, 1, sink_P=1, sink_N=1, alphas=[(3, 1)])  # wrong popcount
     assert e.value.code == B.MB_EINVAL
@@ -317,7 +344,8 @@ def _final_sum(tl, F):
 
 @pytest.mark.parametrize("rel,nsrc,nP,nN,spins", [
     (False, 1, 1, 1, None), (False, 1, 2, 1, None), (True, 1, 1, 2, (0, 0, 1)), (False, 1, 2, 2, (0, 1, 0, 1)),
-    (False, 2, 1, 1, None), (False, 2, 2, 2, (0, 2, 0, 2)), (True, 1, 0, 2, None), (False, 1, 1, 0, None)])
+    (False, 2, 1, 1, None), (False, 2, 2, 2, (0, 2, 0, 2)), (True, 1, 0, 2, None), (False, 1, 1, 0, None),
+    (False, 3, 1, 1, None), (False, 3, 0, 3, (0, 2, 4)), (False, 3, 1, 2, (0, 1, 5))])
 def test_factorised_tables_reproduce_oracle_correlators(rel, nsrc, nP, nN, spins):
     """The library's tables, replayed on oracle blocks, give the oracle's
     correlators (checks table semantics, signs and normalisation on the CPU)."""
