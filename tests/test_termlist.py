@@ -184,12 +184,47 @@ def test_headline_term_lists():
         assert n == O.bound_P(2, 2, kP, s + 1 - kP)
 
 
+def _ops_of_outputs(tl, stage, qi, si):
+    """Operations of the outputs (spin part si[j], quark part qi[j]) of a
+    step, from the factorised export, as sorted (z key, x key, y key, sign)
+    rows (the keys of test_term_list_bit_exact_against_oracle)."""
+    c = tl.counts()
+    nxi = c["n_xi"]
+    pr = _pairs(nxi)
+    npair = len(pr)
+    Q = tl.export(B.MB_EXPORT_QUARK, stage).reshape(-1, 2)
+    S = tl.export(B.MB_EXPORT_SPIN, stage).reshape(-1, 2)
+    Qp = tl.export(B.MB_EXPORT_QUARK, stage - 1).reshape(-1, 2)
+    Sp = tl.export(B.MB_EXPORT_SPIN, stage - 1).reshape(-1, 2)
+    qs = tl.export(B.MB_EXPORT_QSPLIT, stage).reshape(len(Q), -1, 2)
+    ss = tl.export(B.MB_EXPORT_SSPLIT, stage, np.int32).reshape(len(S), -1, 3)
+    added = c["path"][stage]
+    rows = []
+    for q, sp in zip(qi, si):
+        for (x, yw) in qs[q]:
+            y = int(yw) & 0x7FFFFFFF
+            qsg = -1 if int(yw) >> 31 else 1
+            if added == 0:
+                a, b = pr[y // nxi]
+                yu, yd = (1 << a) | (1 << b), 1 << (y % nxi)
+            else:
+                a, b = pr[y % npair]
+                yu, yd = 1 << (y // npair), (1 << a) | (1 << b)
+            for sin, psi, sg in ss[sp]:
+                rows.append((S[sp][0], S[sp][1], Q[q][0], Q[q][1], Sp[sin][0], Sp[sin][1], Qp[x][0], Qp[x][1],
+                             1 << int(psi), yu, yd, qsg * int(sg)))
+    r = np.array(rows, np.int64)
+    return r[np.lexsort(r.T[::-1])]
+
+
 def test_three_source_five_neutrons():
-    """Five neutrons on three sources (two, two and one per source, Sec. 6):
-    one source set, and every stage's required components stay within the
-    bound P of Sec. 6 with D N_s = 6 baryon and 3 D N_s = 18 quark indices
-    per flavour."""
-    tl = lib_termlist(False, 3, 0, 5, (0, 3, 1, 4, 2))
+    """Five neutrons on three sources (two, two and one per source, Sec. 6),
+    beyond the two-source Pauli limit, against the oracle: L bit-exact, the
+    required components of every stage bit-exact, and the operations of 48
+    sampled outputs of every step bit-exact (the whole list, ~2e9
+    operations, is beyond the plain enumeration).  The required sets stay
+    within the bound P of Sec. 6 (D N_s = 6 baryon and 18 quark indices)."""
+    tl = lib_termlist(False, 3, 0, 5, (0, 1, 2, 3, 4))
     c = tl.counts()
     assert c["n_xi"] == 18 and c["n_alpha"] == 1 and c["n_delta"] == 1 and c["path"] == [1] * 5
     req = O.spin_state_request(0, 5, (0, 1, 2, 3, 4))
@@ -199,8 +234,29 @@ def test_three_source_five_neutrons():
     Qf = tl.export(B.MB_EXPORT_QUARK, c["n_stages"] - 1).reshape(-1, 2)
     got = {(int(Qf[q, 0]), int(Qf[q, 1])): int(v) for q, v in zip(coef[2:2 + coef[1]], coef[2 + coef[1]:])}
     assert got == {(int(u), int(d)): int(v) for u, d, v in zip(um, dm, cf)}
-    for s, n in enumerate(c["n_req"]):
-        assert 0 < n <= O.bound_P(2, 3, 0, s + 1)
+    final = np.array([(0, 31, u, d) for u, d in zip(um, dm)], np.uint32)
+    final = final[np.lexsort(final.T[::-1])]
+    reqs = [final if kn == 5 else O.req_stage(final, (0, kn, kn, 2 * kn)) for kn in range(1, 6)]
+    for s in range(c["n_stages"]):
+        assert 0 < c["n_req"][s] <= O.bound_P(2, 3, 0, s + 1)
+        S = tl.export(B.MB_EXPORT_SPIN, s).reshape(-1, 2)
+        Q = tl.export(B.MB_EXPORT_QUARK, s).reshape(-1, 2)
+        lib_keys = np.sort(_key(np.repeat(S, len(Q), 0), np.tile(Q, (len(S), 1))))
+        assert np.array_equal(lib_keys, np.sort(_key(reqs[s][:, :2], reqs[s][:, 2:]))), s
+    rng = np.random.default_rng(5)
+    for s in range(1, c["n_stages"]):
+        nq, ns = c["n_quark"][s], c["n_spin"][s]
+        qi = rng.integers(0, nq, 48)
+        si = rng.integers(0, ns, 48)
+        lib_ops = _ops_of_outputs(tl, s, qi, si)
+        S = tl.export(B.MB_EXPORT_SPIN, s).reshape(-1, 2)
+        Q = tl.export(B.MB_EXPORT_QUARK, s).reshape(-1, 2)
+        zs = np.array([(S[b][0], S[b][1], Q[a][0], Q[a][1]) for a, b in zip(qi, si)], np.uint32)
+        ops = O.lambda_stage(zs, O.NEUTRON, reqs[s - 1], rows=True)
+        z, x = zs[ops[:, 0]].astype(np.int64), reqs[s - 1][ops[:, 1]].astype(np.int64)
+        ora = np.concatenate([z, x, ops[:, 2:]], 1)
+        ora = ora[np.lexsort(ora.T[::-1])]
+        assert lib_ops.shape == ora.shape and np.array_equal(lib_ops, ora), s
 
 
 def test_path_rule():
