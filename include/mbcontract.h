@@ -12,7 +12,8 @@
  *   mb_make_blocks          the baryon blocks f_P, f_N of Sec. 2 (with the
  *                           several-source form of Sec. 6) from quark
  *                           propagators in device memory, antisymmetrised in
- *                           their same-flavour quark indices (Sec. 4).
+ *                           their same-flavour quark indices (Sec. 4), and
+ *                           for a system with a Lambda its block f_L.
  *   mb_contract_correlator  the recursion F_-^(n+1) = F_-^(n) . f (eq. recr_F)
  *                           over the operation lists and the final contraction
  *                           with L (eq. C_final, eq. C_final_moresource).
@@ -22,8 +23,9 @@
  * over 3*D*N_s values with D = 4 (relativistic) or 2.  Baryon index
  * psi (sink) or chi (source) = N_s*alpha + s, D*N_s values; at the sink s
  * selects the sink function.  Within a correlator the baryons are ordered
- * protons first, each species in ascending index, identically at sink and
- * source; the result is C(delta set; alpha set) of eq. C_final with the
+ * protons first, then neutrons, then the Lambda, each species in ascending
+ * index, identically at sink and source; the result is C(delta set; alpha
+ * set) of eq. C_final with the
  * normalisation that makes it equal the Wick contraction of Sec. 2 (no
  * overall Grassmann sign).
  *
@@ -75,7 +77,8 @@ extern "C" {
                                   blocks stored in double, every product and sum
                                   formed in double                                */
 
-/* A nucleus of n_P protons and n_N neutrons (Sec. 7).
+/* A nucleus of n_P protons and n_N neutrons (Sec. 7), and optionally one
+ * Lambda hyperon.
  *   rel    1: Gamma_1 = 1, Gamma_2 = C gamma_5; 0: the nonrelativistic
  *          Gamma_1 = P_nr, Gamma_2 = C gamma_5 P_nr (Dirac representation).
  *   n_src  number of orthogonal quark sources N_s (Sec. 6): 1 or 2, and 3
@@ -91,13 +94,24 @@ extern "C" {
  *          search counts the required sets of every order backwards from the
  *          final ones, without operation tables; MB_EUNSUPPORTED with side
  *          requests.  The correlators do not depend on the order.
- *   order  see EXPLICIT (ignored otherwise)                                   */
+ *   order  see EXPLICIT (ignored otherwise)
+ *   n_Lambda  0, or 1 for a system with one Lambda: the baryon form of Sec. 1
+ *          (eq. C_baryons) with (q1, q2, q3) = (s, u, d) and the nucleons'
+ *          Gamma_1, Gamma_2, a third quark flavour s whose propagator is
+ *          mb_problem.prop_s.  The Lambda is added after the nucleons (the
+ *          last step of the path; its operations split one u, one d and the
+ *          s index off every final component).  Supported with up to 12
+ *          quark indices per flavour (relativistic with one source,
+ *          nonrelativistic with one or two) and without side requests,
+ *          projection or MB_PATH_BEST; n_P + n_N may be 0 (a single Lambda).
+ *          MB_EUNSUPPORTED otherwise.                                        */
 typedef struct {
     int n_P, n_N;
     int rel;
     int n_src;
     int path;
     uint32_t order;
+    int n_Lambda;
 } mb_nucleus;
 
 /* Which components of C(delta set; alpha set) are wanted (Sec. 5, Sec. 8).
@@ -112,6 +126,11 @@ typedef struct {
  *          and neutron source index sets (bit masks, popcounts n_P and n_N)
  *          of output column i, 0 <= i < n_alpha.  A single spin component
  *          (Sec. 8) has sink_P = alpha[0], sink_N = alpha[1], n_alpha = 1.
+ *   sink_L, alpha_L  with a Lambda: the Lambda's sink base set (rows: every
+ *          proton set, then neutron set, then Lambda index of it, Lambda
+ *          fastest) and alpha_L[i] its one-bit source set of column i; with
+ *          all_components every index at the sink and, at the source, each
+ *          of source 0's.  Ignored without a Lambda.
  *   proj   NULL: every (sink set, source set) component is an output.
  *          Otherwise the projection of Sec. 5: real weights
  *          proj[delta * n_alpha + alpha] over the sink sets (in the order
@@ -131,6 +150,8 @@ typedef struct {
     int n_alpha;
     const uint32_t *alpha;
     const double *proj;
+    uint32_t sink_L;
+    const uint32_t *alpha_L;
 } mb_spin_request;
 
 /* A smaller nucleus on the recursion path (Sec. 7): the nucleus of the
@@ -204,8 +225,9 @@ int mb_term_list_load(const char *path, mb_term_list **out);
  *                   count the paper's tables report)
  *   n_lambda_step   operations of step s (entry 0 is 0)
  *   n_req           |required components| of stage s
- *   n_quark         distinct (u set, d set) parts of stage s
- *   n_spin          distinct (proton set, neutron set) parts of stage s
+ *   n_quark         distinct (u set, d set[, s set]) parts of stage s
+ *   n_spin          distinct (proton set, neutron set[, Lambda set]) parts
+ *                   of stage s
  *   n_L             nonzero entries of L over all requested source sets
  *   n_U             distinct quark parts with a nonzero L (final stage)
  *   n_delta, n_alpha  sink sets / source sets of the request (the output
@@ -218,7 +240,9 @@ int mb_term_list_load(const char *path, mb_term_list **out);
  *                   kept quark parts
  *   n_side          side requests (smaller nuclei on the path)
  *   n_out           complex outputs per lane: main output and side outputs
- *   rel, n_src      the operators and sources of the nucleus             */
+ *   rel, n_src      the operators and sources of the nucleus
+ *   n_Lambda        0 or 1 (the last stage then adds the Lambda: path entry
+ *                   MB_LAMBDA)                                             */
 typedef struct {
     int n_stages;
     int path[MB_MAX_STAGES];
@@ -237,7 +261,12 @@ typedef struct {
     int32_t n_side;
     int64_t n_out;
     int32_t rel, n_src;
+    int32_t n_Lambda;
 } mb_counts;
+
+#define MB_PROTON 0    /* species numbers of mb_counts.path */
+#define MB_NEUTRON 1
+#define MB_LAMBDA 2
 
 int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
 
@@ -270,9 +299,17 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
  *                    stage, int64 n_alpha, then uint32 [n_alpha][2] source
  *                    sets, then the coefficients as for MB_EXPORT_COEF with
  *                    quark part indices of that stage
+ *   MB_EXPORT_QUARK_S  uint32 [n_quark]: the s mask of each quark part (0
+ *                    before the Lambda's stage)
+ *   MB_EXPORT_SPIN_L uint32 [n_spin]: the Lambda mask of each spin part (0
+ *                    before the Lambda's stage)
+ *   MB_EXPORT_DELTA_L, MB_EXPORT_ALPHA_L  uint32 [n_delta] / [n_alpha]: the
+ *                    Lambda's sink / source set of each row / column
  * The block quark index of a proton split with u pair (a<b) and d index c is
  * (b*(b-1)/2 + a)*n_xi + c; of a neutron split with u index c and d pair
- * (a<b) it is c*(n_xi*(n_xi-1)/2) + b*(b-1)/2 + a.                          */
+ * (a<b) it is c*(n_xi*(n_xi-1)/2) + b*(b-1)/2 + a; of the Lambda with s
+ * index e, u index c and d index f it is (e*n_xi + c)*n_xi + f.  A Lambda
+ * step's splits are ordered by the u index, then the d index.              */
 #define MB_EXPORT_QUARK 1
 #define MB_EXPORT_SPIN 2
 #define MB_EXPORT_QSPLIT 3
@@ -282,6 +319,10 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *out);
 #define MB_EXPORT_ALPHA 7
 #define MB_EXPORT_PROJ 8
 #define MB_EXPORT_SIDE 9
+#define MB_EXPORT_QUARK_S 10
+#define MB_EXPORT_SPIN_L 11
+#define MB_EXPORT_DELTA_L 12
+#define MB_EXPORT_ALPHA_L 13
 int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
                         size_t *bytes);
 
@@ -359,7 +400,10 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
  *   sink_w     device, complex double [n_src][V]: sink function s' at site
  *              x (Sec. 2, 6); NULL means s(x) = 1 for every sink function.
  *   scale_exp  device, int32 [B]: the propagators of lane b are read
- *              multiplied by 2^scale_exp[b] (exact); NULL means 0.          */
+ *              multiplied by 2^scale_exp[b] (exact); NULL means 0.
+ *   prop_s     device, the strange propagator in the layout of prop_u, for
+ *              a term list with a Lambda (MB_EINVAL if NULL there); ignored
+ *              otherwise.  It may equal prop_u or prop_d.                   */
 typedef struct {
     int64_t batch;
     int64_t V;
@@ -369,6 +413,7 @@ typedef struct {
     const void *prop_d;
     const double *sink_w;
     const int32_t *scale_exp;
+    const void *prop_s;
 } mb_problem;
 
 /* Device buffer sizes for one batch:
@@ -390,9 +435,12 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
  * normalisation in the two same-flavour slots (Sec. 4), for every lane.
  * The sum over sites runs in double precision and the blocks are stored in
  * double in both precision modes.
+ * With a Lambda also f_L of (q1, q2, q3) = (s, u, d), which has no two
+ * slots of one flavour and is stored as it is.
  * Output layout (complex double in both precision modes): proton block
  * [block quark index][lane / 16][psi][lane % 16] followed by the neutron
- * block, lanes padded to a multiple of 64, then int32 e[lane] (padded
+ * block (and the Lambda block, n_xi^3 block quark indices), lanes padded to
+ * a multiple of 64, then int32 e[lane] (padded
  * lanes included): the blocks of a lane are stored multiplied by 2^-e[lane]
  * (exact), e chosen so that their largest real or imaginary part lies in
  * [1/2, 1) (e = 0 for an all-zero lane).  Products of many blocks then stay

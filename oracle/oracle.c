@@ -195,6 +195,65 @@ void orc_blocks(int rel, int nsrc, int npsi, int nxi, int V, const cplx *Su,
 #undef SP
 }
 
+/* The Lambda block: the same baryon form (Sec. 1, eq. C_baryons) with
+ * (q1, q2, q3) = (s, u, d), Gamma_1 and Gamma_2 as for the nucleons:
+ *   fL(psi; xi1, xi2, xi3) = sum_x w_{s'}(x) eps_abc (Gamma_1)_{alpha beta}
+ *        (Gamma_2)_{gamma delta} S_s[(beta,a), xi1] S_u[(gamma,b), xi2]
+ *        S_d[(delta,c), xi3].
+ * Same layout and conventions as orc_blocks.                              */
+void orc_blocks_lambda(int rel, int nsrc, int npsi, int nxi, int V, const cplx *Su,
+                       const cplx *Sd, const cplx *Ss, const cplx *sinkw, double scale,
+                       cplx *fL)
+{
+    cplx G1[16], G2[16];
+    orc_gamma(rel, G1, G2);
+    long nout = (long)npsi * nxi * nxi * nxi;
+    memset(fL, 0, nout * sizeof(cplx));
+#define SP(S, x, row, xi) \
+    (scale * (S)[(((long)(x) * nsrc + (xi) % nsrc) * 12 + (row)) * 12 + (xi) / nsrc])
+#pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int psi = 0; psi < npsi; psi++) {
+        for (int x1 = 0; x1 < nxi; x1++) {
+            int alpha = psi / nsrc, sk = psi % nsrc;
+            for (int x2 = 0; x2 < nxi; x2++)
+                for (int x3 = 0; x3 < nxi; x3++) {
+                    cplx acc = 0;
+                    for (int x = 0; x < V; x++) {
+                        cplx w = sinkw ? sinkw[(long)sk * V + x] : 1.0;
+                        for (int a = 0; a < 3; a++)
+                            for (int b = 0; b < 3; b++)
+                                for (int c = 0; c < 3; c++) {
+                                    int e = eps3(a, b, c);
+                                    if (!e) continue;
+                                    for (int be = 0; be < 4; be++) {
+                                        cplx g1 = G1[4 * alpha + be];
+                                        if (g1 == 0) continue;
+                                        for (int ga = 0; ga < 4; ga++)
+                                            for (int de = 0; de < 4; de++) {
+                                                cplx g2 = G2[4 * ga + de];
+                                                if (g2 == 0) continue;
+                                                acc += w * (double)e * g1 * g2 * SP(Ss, x, 3 * be + a, x1) *
+                                                       SP(Su, x, 3 * ga + b, x2) * SP(Sd, x, 3 * de + c, x3);
+                                            }
+                                    }
+                                }
+                    }
+                    fL[(((long)psi * nxi + x1) * nxi + x2) * nxi + x3] = acc;
+                }
+        }
+    }
+#undef SP
+}
+
+/* Flavour of quark slot j of a baryon of type t (0 = u, 1 = d, 2 = s):
+ * proton (u,u,d), neutron (d,u,d), Lambda (s,u,d).                        */
+static int slot_flavour(int t, int j)
+{
+    if (j == 1) return 0;
+    if (j == 2) return 1;
+    return t == 0 ? 0 : t == 1 ? 1 : 2;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Small open-addressing hash map: 4 x uint32 key -> int64 value.          */
 
@@ -277,6 +336,14 @@ static int key_cmp(const void *a, const void *b)
     return 0;
 }
 
+static int key3_cmp(const void *a, const void *b)
+{
+    const uint32_t *x = a, *y = b;
+    for (int i = 0; i < 3; i++)
+        if (x[i] != y[i]) return x[i] < y[i] ? -1 : 1;
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The tensor L of the unified contraction algorithm (eq. tensor_L), built
  * the way Sec. 2 describes it: by running over every combination of nonzero
@@ -285,20 +352,21 @@ static int key_cmp(const void *a, const void *b)
  * sorted index sets:
  *   L(alpha; z) = sum over assignments eta of the indices of z to the quark
  *                 slots of  sgn(eta) * prod_k G^{B_k}(alpha_k; eta slots of k),
- * where sgn(eta) is the parity of the u sequence times that of the d
- * sequence (slots in baryon order, within a baryon in operator order:
- * proton (u,u,d), neutron (d,u,d)); assignments that repeat an index of one
- * flavour cancel and are skipped.
- * types[k] = 0 proton / 1 neutron, chis[k] the source index of baryon k.
- * Output: keys (u mask, d mask) ascending and their integer values; returns
- * the number of nonzero entries (at most max are written).                */
+ * where sgn(eta) is the product of the parities of the u, d and s
+ * sequences (slots in baryon order, within a baryon in operator order:
+ * proton (u,u,d), neutron (d,u,d), Lambda (s,u,d)); assignments that repeat
+ * an index of one flavour cancel and are skipped.
+ * types[k] = 0 proton / 1 neutron / 2 Lambda, chis[k] the source index of
+ * baryon k.  Output: keys (u mask, d mask, s mask) ascending and their
+ * integer values (smask may be NULL without Lambdas); returns the number of
+ * nonzero entries (at most max are written).                              */
 
 typedef struct {
     int nb, types[16];
     int nent[16];
     int *xi[16];
     cplx *val[16];
-    int useq[64], dseq[64];
+    int seq[3][64];   /* index sequence of each flavour, slots in order */
     hmap *acc;
 } uca_state;
 
@@ -311,43 +379,37 @@ static int parity(const int *s, int n)
     return (inv & 1) ? -1 : 1;
 }
 
-static void uca_rec(uca_state *st, int k, int nu, int nd, uint32_t um,
-                    uint32_t dm, cplx prod)
+/* n[f], m[f]: length and index set of flavour f's sequence so far */
+static void uca_rec(uca_state *st, int k, const int *n, const uint32_t *m, cplx prod)
 {
     if (k == st->nb) {
         double re = creal(prod), im = cimag(prod);
         long long iv = (long long)(re < 0 ? re - 0.5 : re + 0.5);
         (void)im;
-        uint32_t key[4] = {um, dm, 0, 0};
-        hm_add(st->acc, key, iv * parity(st->useq, nu) * parity(st->dseq, nd));
+        uint32_t key[4] = {m[0], m[1], m[2], 0};
+        hm_add(st->acc, key, iv * parity(st->seq[0], n[0]) * parity(st->seq[1], n[1]) *
+                                 parity(st->seq[2], n[2]));
         return;
     }
     for (int e = 0; e < st->nent[k]; e++) {
         const int *x = st->xi[k] + 3 * e;
-        int q[3] = {x[0], x[1], x[2]};
-        /* slot flavours: proton (u,u,d), neutron (d,u,d) */
-        int isu[3] = {st->types[k] == 0, 1, 0};
-        uint32_t u2 = um, d2 = dm;
-        int nu2 = nu, nd2 = nd, ok = 1;
+        int n2[3] = {n[0], n[1], n[2]};
+        uint32_t m2[3] = {m[0], m[1], m[2]};
+        int ok = 1;
         for (int j = 0; j < 3 && ok; j++) {
-            uint32_t bit = 1u << q[j];
-            if (isu[j]) {
-                if (u2 & bit) ok = 0;
-                u2 |= bit;
-                st->useq[nu2++] = q[j];
-            } else {
-                if (d2 & bit) ok = 0;
-                d2 |= bit;
-                st->dseq[nd2++] = q[j];
-            }
+            int f = slot_flavour(st->types[k], j);
+            uint32_t bit = 1u << x[j];
+            if (m2[f] & bit) ok = 0;
+            m2[f] |= bit;
+            st->seq[f][n2[f]++] = x[j];
         }
         if (!ok) continue; /* a repeated index of one flavour: the term cancels */
-        uca_rec(st, k + 1, nu2, nd2, u2, d2, prod * st->val[k][e]);
+        uca_rec(st, k + 1, n2, m2, prod * st->val[k][e]);
     }
 }
 
 long orc_L_uca(int rel, int nsrc, int nb, const int *types, const int *chis,
-               uint32_t *umask, uint32_t *dmask, long long *coef, long max)
+               uint32_t *umask, uint32_t *dmask, uint32_t *smask, long long *coef, long max)
 {
     uca_state st;
     memset(&st, 0, sizeof st);
@@ -362,24 +424,26 @@ long orc_L_uca(int rel, int nsrc, int nb, const int *types, const int *chis,
     hmap acc;
     hm_init(&acc, 1 << 12);
     st.acc = &acc;
-    uca_rec(&st, 0, 0, 0, 0, 0, 1.0);
-    /* collect nonzero values, sorted by (u mask, d mask) */
+    const int n0[3] = {0, 0, 0};
+    const uint32_t m0[3] = {0, 0, 0};
+    uca_rec(&st, 0, n0, m0, 1.0);
+    /* collect nonzero values, sorted by (u mask, d mask, s mask) */
     long n = 0;
-    uint32_t *tmp = malloc(sizeof(uint32_t) * 4 * (acc.n + 1));
+    uint32_t *tmp = malloc(sizeof(uint32_t) * 5 * (acc.n + 1));
     for (long i = 0; i < acc.cap; i++)
         if (acc.used[i] && acc.v[i] != 0) {
-            tmp[4 * n] = acc.k[4 * i];
-            tmp[4 * n + 1] = acc.k[4 * i + 1];
+            memcpy(tmp + 5 * n, acc.k + 4 * i, 12);
             long long v = acc.v[i];
-            tmp[4 * n + 2] = (uint32_t)(v & 0xffffffffu);
-            tmp[4 * n + 3] = (uint32_t)((unsigned long long)v >> 32);
+            tmp[5 * n + 3] = (uint32_t)(v & 0xffffffffu);
+            tmp[5 * n + 4] = (uint32_t)((unsigned long long)v >> 32);
             n++;
         }
-    qsort(tmp, n, 16, key_cmp);
+    qsort(tmp, n, 20, key3_cmp);
     for (long i = 0; i < n && i < max; i++) {
-        umask[i] = tmp[4 * i];
-        dmask[i] = tmp[4 * i + 1];
-        coef[i] = (long long)(((unsigned long long)tmp[4 * i + 3] << 32) | tmp[4 * i + 2]);
+        umask[i] = tmp[5 * i];
+        dmask[i] = tmp[5 * i + 1];
+        if (smask) smask[i] = tmp[5 * i + 2];
+        coef[i] = (long long)(((unsigned long long)tmp[5 * i + 4] << 32) | tmp[5 * i + 3]);
     }
     free(tmp);
     hm_free(&acc);
@@ -395,11 +459,12 @@ long orc_L_uca(int rel, int nsrc, int nb, const int *types, const int *chis,
  * Only index tuples with distinct indices per flavour contribute, and for
  * each sorted set z the sum over the orderings of z is
  *   C = sum_z L(alpha; z) * W(delta; z),
- *   W(delta; z) = sum_{pi_u, pi_d} sgn(pi_u) sgn(pi_d)
+ *   W(delta; z) = sum_{pi_u, pi_d, pi_s} sgn(pi_u) sgn(pi_d) sgn(pi_s)
  *                 prod_k f_{B_k}(delta_k; the slots of k filled from z
- *                                permuted by pi_u, pi_d),
+ *                                permuted by pi_u, pi_d, pi_s),
  * with the same slot order as in orc_L_uca.  Blocks are the full
- * (unsymmetrised) f of orc_blocks.                                       */
+ * (unsymmetrised) f of orc_blocks and orc_blocks_lambda (fL and smask may
+ * be NULL without Lambdas).                                              */
 
 static int nperms(int n, int *perm, int *sgn, long max)
 {
@@ -434,47 +499,53 @@ static long factl(int n)
 }
 
 void orc_corr(int nb, const int *types, const int *psis, int npsi, int nxi,
-              const cplx *fP, const cplx *fN, long nz, const uint32_t *umask,
-              const uint32_t *dmask, const long long *coef, cplx *out)
+              const cplx *fP, const cplx *fN, const cplx *fL, long nz, const uint32_t *umask,
+              const uint32_t *dmask, const uint32_t *smask, const long long *coef, cplx *out)
 {
-    /* slot bookkeeping: for every baryon slot, its flavour and its position
-     * in the flavour's slot sequence */
-    int uslot_b[64], uslot_j[64], dslot_b[64], dslot_j[64], nu = 0, nd = 0;
-    for (int k = 0; k < nb; k++) {
-        int isu[3] = {types[k] == 0, 1, 0};
+    /* slot bookkeeping: for every flavour, the (baryon, slot) of each
+     * position of its slot sequence */
+    int sb[3][64], sj[3][64], nf[3] = {0, 0, 0};
+    for (int k = 0; k < nb; k++)
         for (int j = 0; j < 3; j++) {
-            if (isu[j]) { uslot_b[nu] = k; uslot_j[nu] = j; nu++; }
-            else        { dslot_b[nd] = k; dslot_j[nd] = j; nd++; }
+            int f = slot_flavour(types[k], j);
+            sb[f][nf[f]] = k;
+            sj[f][nf[f]] = j;
+            nf[f]++;
         }
+    long fct[3];
+    int *pm[3], *ps[3];
+    for (int f = 0; f < 3; f++) {
+        fct[f] = factl(nf[f]);
+        pm[f] = malloc(sizeof(int) * (nf[f] ? nf[f] : 1) * fct[f]);
+        ps[f] = malloc(sizeof(int) * fct[f]);
+        nperms(nf[f], pm[f], ps[f], fct[f]);
     }
-    long fu = factl(nu), fd = factl(nd);
-    int *pu = malloc(sizeof(int) * nu * fu), *su = malloc(sizeof(int) * fu);
-    int *pd = malloc(sizeof(int) * nd * fd), *sd = malloc(sizeof(int) * fd);
-    nperms(nu, pu, su, fu);
-    nperms(nd, pd, sd, fd);
     /* W(delta; z) for every z (independent, one thread each), then the sum
      * over z in order */
     cplx *Wz = malloc(sizeof(cplx) * (nz > 0 ? nz : 1));
 #pragma omp parallel for schedule(dynamic)
     for (long iz = 0; iz < nz; iz++) {
-        int ul[32], dl[32], a = 0, b = 0;
-        for (int i = 0; i < 32; i++) {
-            if (umask[iz] >> i & 1) ul[a++] = i;
-            if (dmask[iz] >> i & 1) dl[b++] = i;
-        }
+        int lst[3][32], cnt[3] = {0, 0, 0};
+        const uint32_t m[3] = {umask[iz], dmask[iz], smask ? smask[iz] : 0u};
+        for (int f = 0; f < 3; f++)
+            for (int i = 0; i < 32; i++)
+                if (m[f] >> i & 1) lst[f][cnt[f]++] = i;
         cplx W = 0;
-        for (long p = 0; p < fu; p++) {
-            int slot[16][3];
-            for (int j = 0; j < nu; j++) slot[uslot_b[j]][uslot_j[j]] = ul[pu[p * nu + j]];
-            for (long q = 0; q < fd; q++) {
-                for (int j = 0; j < nd; j++) slot[dslot_b[j]][dslot_j[j]] = dl[pd[q * nd + j]];
-                cplx prod = su[p] * sd[q];
-                for (int k = 0; k < nb; k++) {
-                    const cplx *f = types[k] == 0 ? fP : fN;
-                    long o = (((long)psis[k] * nxi + slot[k][0]) * nxi + slot[k][1]) * nxi + slot[k][2];
-                    prod *= f[o];
+        int slot[16][3];
+        for (long p = 0; p < fct[0]; p++) {
+            for (int j = 0; j < nf[0]; j++) slot[sb[0][j]][sj[0][j]] = lst[0][pm[0][p * nf[0] + j]];
+            for (long q = 0; q < fct[1]; q++) {
+                for (int j = 0; j < nf[1]; j++) slot[sb[1][j]][sj[1][j]] = lst[1][pm[1][q * nf[1] + j]];
+                for (long r = 0; r < fct[2]; r++) {
+                    for (int j = 0; j < nf[2]; j++) slot[sb[2][j]][sj[2][j]] = lst[2][pm[2][r * nf[2] + j]];
+                    cplx prod = ps[0][p] * ps[1][q] * ps[2][r];
+                    for (int k = 0; k < nb; k++) {
+                        const cplx *f = types[k] == 0 ? fP : types[k] == 1 ? fN : fL;
+                        long o = (((long)psis[k] * nxi + slot[k][0]) * nxi + slot[k][1]) * nxi + slot[k][2];
+                        prod *= f[o];
+                    }
+                    W += prod;
                 }
-                W += prod;
             }
         }
         Wz[iz] = W;
@@ -484,7 +555,10 @@ void orc_corr(int nb, const int *types, const int *psis, int npsi, int nxi,
     free(Wz);
     (void)npsi;
     *out = total;
-    free(pu); free(su); free(pd); free(sd);
+    for (int f = 0; f < 3; f++) {
+        free(pm[f]);
+        free(ps[f]);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -542,7 +616,7 @@ void orc_proton_closed(int rel, int V, const cplx *Su, const cplx *Sd,
  * baryons on a handful of sites.                                          */
 void orc_wick_literal(int rel, int nsrc, int nb, const int *types,
                       const int *psis, const int *chis, int V, const cplx *Su,
-                      const cplx *Sd, const cplx *sinkw, double scale, cplx *out)
+                      const cplx *Sd, const cplx *Ss, const cplx *sinkw, double scale, cplx *out)
 {
     cplx G1[16], G2[16];
     orc_gamma(rel, G1, G2);
@@ -568,20 +642,22 @@ void orc_wick_literal(int rel, int nsrc, int nb, const int *types,
         soc[k] = malloc(sizeof(cplx) * cap);
         nso[k] = orc_g_nonzero(rel, nsrc, chis[k], sox[k], soc[k], cap);
     }
-    /* flavour slot lists */
-    int uslot[64], dslot[64], nu = 0, nd = 0; /* slot id = 3*k + j */
-    for (int k = 0; k < nb; k++) {
-        int isu[3] = {types[k] == 0, 1, 0};
+    /* flavour slot lists (slot id = 3*k + j) and their permutations */
+    int fslot[3][64], nf[3] = {0, 0, 0};
+    for (int k = 0; k < nb; k++)
         for (int j = 0; j < 3; j++) {
-            if (isu[j]) uslot[nu++] = 3 * k + j;
-            else dslot[nd++] = 3 * k + j;
+            int f = slot_flavour(types[k], j);
+            fslot[f][nf[f]++] = 3 * k + j;
         }
+    const cplx *Sf[3] = {Su, Sd, Ss};
+    long fct[3];
+    int *pm[3], *ps[3];
+    for (int f = 0; f < 3; f++) {
+        fct[f] = factl(nf[f]);
+        pm[f] = malloc(sizeof(int) * (nf[f] ? nf[f] : 1) * fct[f]);
+        ps[f] = malloc(sizeof(int) * fct[f]);
+        nperms(nf[f], pm[f], ps[f], fct[f]);
     }
-    long fu = factl(nu), fd = factl(nd);
-    int *pu = malloc(sizeof(int) * nu * fu), *su = malloc(sizeof(int) * fu);
-    int *pd = malloc(sizeof(int) * nd * fd), *sd = malloc(sizeof(int) * fd);
-    nperms(nu, pu, su, fu);
-    nperms(nd, pd, sd, fd);
 
     cplx tot = 0;
     long npos = 1;
@@ -613,25 +689,23 @@ void orc_wick_literal(int rel, int nsrc, int nb, const int *types,
                     cso *= soc[k][iso[k]];
                     for (int j = 0; j < 3; j++) col[3 * k + j] = sox[k][3 * iso[k] + j];
                 }
+                /* every flavour-preserving pairing: sink slot fslot[f][j]
+                 * takes the source slot fslot[f][perm(j)] */
                 cplx acc = 0;
-                for (long p = 0; p < fu; p++) {
-                    cplx pr = su[p];
-                    for (int j = 0; j < nu; j++) {
-                        int sl = uslot[j], tl = uslot[pu[p * nu + j]];
-                        int xi = col[tl];
-                        pr *= scale * Su[(((long)xs[sl / 3] * nsrc + xi % nsrc) * 12 + row[sl]) * 12 + xi / nsrc];
-                    }
-                    if (pr == 0) continue;
-                    for (long q = 0; q < fd; q++) {
-                        cplx pq = pr * sd[q];
-                        for (int j = 0; j < nd; j++) {
-                            int sl = dslot[j], tl = dslot[pd[q * nd + j]];
-                            int xi = col[tl];
-                            pq *= scale * Sd[(((long)xs[sl / 3] * nsrc + xi % nsrc) * 12 + row[sl]) * 12 + xi / nsrc];
+                for (long p = 0; p < fct[0]; p++)
+                    for (long q = 0; q < fct[1]; q++)
+                        for (long r = 0; r < fct[2]; r++) {
+                            const long pick[3] = {p, q, r};
+                            cplx pr = ps[0][p] * ps[1][q] * ps[2][r];
+                            for (int f = 0; f < 3 && pr != 0; f++)
+                                for (int j = 0; j < nf[f]; j++) {
+                                    int sl = fslot[f][j], tl = fslot[f][pm[f][pick[f] * nf[f] + j]];
+                                    int xi = col[tl];
+                                    pr *= scale * Sf[f][(((long)xs[sl / 3] * nsrc + xi % nsrc) * 12 + row[sl]) * 12 +
+                                                        xi / nsrc];
+                                }
+                            acc += pr;
                         }
-                        acc += pq;
-                    }
-                }
                 tot += cso * acc;
                 int k = 0;
                 while (k < nb && ++iso[k] == nso[k]) iso[k++] = 0;
@@ -646,7 +720,50 @@ void orc_wick_literal(int rel, int nsrc, int nb, const int *types,
     for (int k = 0; k < nb; k++) {
         free(skr[k]); free(skc[k]); free(sox[k]); free(soc[k]);
     }
-    free(pu); free(su); free(pd); free(sd);
+    for (int f = 0; f < 3; f++) {
+        free(pm[f]);
+        free(ps[f]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-Lambda two-point function by direct Wick contraction: the s, u and
+ * d quarks of the Lambda (slots (s,u,d)) each contract with their own
+ * source quark, so there is only the direct term:
+ *   C = sum_x w(x) eps_abc eps_a'b'c' G1_{delta beta} G2_{gamma eps}
+ *       G1_{alpha beta'} G2_{gamma' eps'} S_s[(beta,a),(beta',a')]
+ *       S_u[(gamma,b),(gamma',b')] S_d[(eps,c),(eps',c')].
+ * One source only.                                                        */
+void orc_lambda_closed(int rel, int V, const cplx *Su, const cplx *Sd, const cplx *Ss,
+                       const cplx *sinkw, double scale, int delta, int alpha, cplx *out)
+{
+    cplx G1[16], G2[16];
+    orc_gamma(rel, G1, G2);
+    cplx tot = 0;
+    for (int x = 0; x < V; x++) {
+        const cplx *u = Su + (long)x * 144, *d = Sd + (long)x * 144, *st = Ss + (long)x * 144;
+        cplx w = sinkw ? sinkw[x] : 1.0;
+        for (int a = 0; a < 3; a++) for (int b = 0; b < 3; b++) for (int c = 0; c < 3; c++) {
+            int e1 = eps3(a, b, c);
+            if (!e1) continue;
+            for (int a2 = 0; a2 < 3; a2++) for (int b2 = 0; b2 < 3; b2++) for (int c2 = 0; c2 < 3; c2++) {
+                int e2 = eps3(a2, b2, c2);
+                if (!e2) continue;
+                for (int be = 0; be < 4; be++) for (int ga = 0; ga < 4; ga++) for (int ep = 0; ep < 4; ep++) {
+                    cplx s1 = G1[4 * delta + be] * G2[4 * ga + ep];
+                    if (s1 == 0) continue;
+                    for (int be2 = 0; be2 < 4; be2++) for (int ga2 = 0; ga2 < 4; ga2++) for (int ep2 = 0; ep2 < 4; ep2++) {
+                        cplx s2 = G1[4 * alpha + be2] * G2[4 * ga2 + ep2];
+                        if (s2 == 0) continue;
+                        tot += w * (double)(e1 * e2) * s1 * s2 * scale * scale * scale *
+                               st[12 * (3 * be + a) + 3 * be2 + a2] * u[12 * (3 * ga + b) + 3 * ga2 + b2] *
+                               d[12 * (3 * ep + c) + 3 * ep2 + c2];
+                    }
+                }
+            }
+        }
+    }
+    *out = tot;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -15,8 +15,11 @@ Conventions (the paper leaves them open; see the readings in the design notes):
   * nonrelativistic operators keep spins 0, 1 only (Dirac representation,
     Sec. 7), so quark indices run over 3*D*N_s values and baryon indices over
     D*N_s values, with D = 4 (relativistic) or 2;
-  * baryon order inside a correlator: protons, then neutrons, each group in
-    ascending spin index; the same order at sink and source;
+  * baryon order inside a correlator: protons, then neutrons, then the
+    Lambda, each group in ascending spin index; the same order at sink and
+    source;
+  * the Lambda operator is the baryon form of Sec. 1 (eq. C_baryons) with
+    (q1, q2, q3) = (s, u, d) and the nucleons' Gamma_1, Gamma_2;
   * propagators S[x][s][row][kappa] complex128, row the sink spin-colour,
     kappa the source spin-colour of source s.
 """
@@ -34,7 +37,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
 _lib = None
 
-PROTON, NEUTRON = 0, 1
+PROTON, NEUTRON, LAMBDA = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -134,6 +137,23 @@ def blocks(rel, nsrc, Su, Sd, sinkw=None, scale=1.0, D=None):
     return fP, fN
 
 
+def blocks_lambda(rel, nsrc, Su, Sd, Ss, sinkw=None, scale=1.0, D=None):
+    """Full Lambda block fL[psi][xi_s][xi_u][xi_d]: the baryon form of
+    Sec. 1 with (q1, q2, q3) = (s, u, d), same conventions as blocks()."""
+    D = D or (4 if rel else 2)
+    Su, Sd, Ss = (np.ascontiguousarray(S, np.complex128) for S in (Su, Sd, Ss))
+    V = Su.shape[0]
+    assert Su.shape == (V, nsrc, 12, 12) and Sd.shape == Su.shape and Ss.shape == Su.shape
+    npsi, nxi = D * nsrc, 3 * D * nsrc
+    fL = np.zeros((npsi, nxi, nxi, nxi), np.complex128)
+    if sinkw is not None:
+        sinkw = np.ascontiguousarray(sinkw, np.complex128)
+        assert sinkw.shape == (nsrc, V)
+    lib().orc_blocks_lambda(int(rel), nsrc, npsi, nxi, V, _p(Su), _p(Sd), _p(Ss),
+                            _p(sinkw) if sinkw is not None else None, C.c_double(scale), _p(fL))
+    return fL
+
+
 def antisym_blocks(fP, fN):
     """Antisymmetrised blocks (Sec. 4: all permutations of the same-flavour
     slots, without normalisation) as dictionaries keyed by
@@ -154,27 +174,33 @@ def antisym_blocks(fP, fN):
 # --------------------------------------------------------------------------
 # The tensor L (Sec. 2 eq. tensor_L)
 
-def L_uca(rel, nsrc, types, chis):
+def L_uca(rel, nsrc, types, chis, with_s=False):
     """L(alpha; z) on sorted index sets, by explicit permutations (Sec. 2).
 
-    types/chis: per baryon in order.  Returns (umask, dmask, coef) arrays of
-    the nonzero entries, ascending in (umask, dmask)."""
+    types/chis: per baryon in order (LAMBDA for a Lambda).  Returns (umask,
+    dmask, coef) arrays of the nonzero entries, or (umask, dmask, smask,
+    coef) with with_s, ascending in (umask, dmask, smask)."""
     t, c = _ints(types), _ints(chis)
     nb = len(t)
     cap = 1 << 22
     um = np.zeros(cap, np.uint32)
     dm = np.zeros(cap, np.uint32)
+    sm = np.zeros(cap, np.uint32)
     cf = np.zeros(cap, np.int64)
-    n = lib().orc_L_uca(int(rel), nsrc, nb, _p(t), _p(c), _p(um), _p(dm), _p(cf), C.c_long(cap))
+    n = lib().orc_L_uca(int(rel), nsrc, nb, _p(t), _p(c), _p(um), _p(dm), _p(sm), _p(cf), C.c_long(cap))
     assert n <= cap
+    if with_s:
+        return um[:n].copy(), dm[:n].copy(), sm[:n].copy(), cf[:n].copy()
+    assert not sm[:n].any()
     return um[:n].copy(), dm[:n].copy(), cf[:n].copy()
 
 
 # --------------------------------------------------------------------------
 # Correlator (Sec. 2 eq. f_L_contr) and independent closed forms
 
-def corr_from_L(types, psis, fP, fN, um, dm, coef):
-    """C = sum_z L(alpha; z) W(delta; z) with the permutation sum W."""
+def corr_from_L(types, psis, fP, fN, um, dm, coef, fL=None, sm=None):
+    """C = sum_z L(alpha; z) W(delta; z) with the permutation sum W (fL and
+    the s masks sm for a system with a Lambda)."""
     t, ps = _ints(types), _ints(psis)
     out = np.zeros(1, np.complex128)
     um = np.ascontiguousarray(um, np.uint32)
@@ -182,8 +208,12 @@ def corr_from_L(types, psis, fP, fN, um, dm, coef):
     coef = np.ascontiguousarray(coef, np.int64)
     fP = np.ascontiguousarray(fP)
     fN = np.ascontiguousarray(fN)
+    assert (LAMBDA in list(t)) == (fL is not None)
+    fL = None if fL is None else np.ascontiguousarray(fL)
+    sm = None if sm is None else np.ascontiguousarray(sm, np.uint32)
     lib().orc_corr(len(t), _p(t), _p(ps), fP.shape[0], fP.shape[1], _p(fP), _p(fN),
-                   C.c_long(len(um)), _p(um), _p(dm), _p(coef), _p(out))
+                   _p(fL) if fL is not None else None, C.c_long(len(um)), _p(um), _p(dm),
+                   _p(sm) if sm is not None else None, _p(coef), _p(out))
     return complex(out[0])
 
 
@@ -200,16 +230,33 @@ def proton_closed(rel, Su, Sd, sinkw=None, scale=1.0, delta=0, alpha=0):
     return complex(out[0])
 
 
-def wick_literal(rel, nsrc, types, psis, chis, Su, Sd, sinkw=None, scale=1.0):
-    """Literal Wick contraction of <prod B prod Bbar> (tiny systems only)."""
+def wick_literal(rel, nsrc, types, psis, chis, Su, Sd, sinkw=None, scale=1.0, Ss=None):
+    """Literal Wick contraction of <prod B prod Bbar> (tiny systems only);
+    Ss is the strange propagator of a system with a Lambda."""
     Su = np.ascontiguousarray(Su, np.complex128)
     Sd = np.ascontiguousarray(Sd, np.complex128)
+    Ss = None if Ss is None else np.ascontiguousarray(Ss, np.complex128)
     V = Su.shape[0]
     t, ps, ch = _ints(types), _ints(psis), _ints(chis)
+    assert (LAMBDA in list(t)) == (Ss is not None)
     out = np.zeros(1, np.complex128)
     w = None if sinkw is None else np.ascontiguousarray(sinkw, np.complex128)
     lib().orc_wick_literal(int(rel), nsrc, len(t), _p(t), _p(ps), _p(ch), V, _p(Su), _p(Sd),
-                           _p(w) if w is not None else None, C.c_double(scale), _p(out))
+                           _p(Ss) if Ss is not None else None, _p(w) if w is not None else None,
+                           C.c_double(scale), _p(out))
+    return complex(out[0])
+
+
+def lambda_closed(rel, Su, Sd, Ss, sinkw=None, scale=1.0, delta=0, alpha=0):
+    """Single Lambda two-point function by direct Wick contraction (the s,
+    u and d quarks each meet their own source quark: one term)."""
+    Su, Sd, Ss = (np.ascontiguousarray(S, np.complex128) for S in (Su, Sd, Ss))
+    V = Su.shape[0]
+    assert Su.shape[1] == 1
+    out = np.zeros(1, np.complex128)
+    w = None if sinkw is None else np.ascontiguousarray(sinkw, np.complex128).reshape(-1)
+    lib().orc_lambda_closed(int(rel), V, _p(Su), _p(Sd), _p(Ss), _p(w) if w is not None else None,
+                            C.c_double(scale), delta, alpha, _p(out))
     return complex(out[0])
 
 
@@ -377,6 +424,124 @@ def correlators(rel, nsrc, nP, nN, req, Su, Sd, sinkw=None, scale=1.0, tl=None):
         for d in delta_sets(nP, nN, req):
             psis = _bits(d[0]) + _bits(d[1])
             out[(d, a)] = corr_from_L(types, psis, fP, fN, um, dm, cf)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Systems with one Lambda (the baryon form of Sec. 1 with (s, u, d) slots),
+# added after the nucleons: the generalisation of Sec. 3-4 to a third quark
+# flavour and a third baryon species.
+
+def _src_sets(n, D, nsrc):
+    """The source sets of all_components_request for n baryons of one
+    species."""
+    nb = D * nsrc
+    if nsrc == 1:
+        return [_mask(c) for c in itertools.combinations(range(nb), n)]
+    counts, left = [], n
+    for s in range(nsrc):
+        counts.append(min(left, D))
+        left -= counts[-1]
+    per_source = [itertools.combinations([nsrc * a + s for a in range(D)], counts[s]) for s in range(nsrc)]
+    return sorted(_mask(sum(cs, ())) for cs in itertools.product(*[list(p) for p in per_source]))
+
+
+def hyperon_request_all(nP, nN, D, nsrc):
+    """All components of a system of nP protons, nN neutrons and one Lambda:
+    every sink set, and the source sets of all_components_request per
+    species (the Lambda on source 0)."""
+    full = (1 << (D * nsrc)) - 1
+    alphas = [(p, n, l) for p in _src_sets(nP, D, nsrc) for n in _src_sets(nN, D, nsrc)
+              for l in _src_sets(1, D, nsrc)]
+    return dict(sinkP=full if nP else 0, sinkN=full if nN else 0, sinkL=full, alphas=alphas)
+
+
+def hyperon_request_spin(nP, nN, spins):
+    """One spin component: protons, neutrons, then the Lambda's index."""
+    pm, nm, lm = _mask(spins[:nP]), _mask(spins[nP:nP + nN]), _mask(spins[nP + nN:nP + nN + 1])
+    assert bin(pm).count("1") == nP and bin(nm).count("1") == nN and bin(lm).count("1") == 1
+    return dict(sinkP=pm, sinkN=nm, sinkL=lm, alphas=[(pm, nm, lm)])
+
+
+def hyperon_delta_sets(nP, nN, req):
+    """Sink sets (P set, N set, Lambda index), proton rank major, then the
+    neutron rank, then the Lambda's."""
+    ps = [_mask(c) for c in itertools.combinations(_bits(req["sinkP"]), nP)]
+    ns = [_mask(c) for c in itertools.combinations(_bits(req["sinkN"]), nN)]
+    ls = [1 << b for b in _bits(req["sinkL"])]
+    return [(p, n, l) for p in ps for n in ns for l in ls]
+
+
+def hyperon_L(rel, nsrc, nP, nN, alpha):
+    """L(alpha; z) on sorted (u, d, s) sets of the system (Sec. 2)."""
+    types = [PROTON] * nP + [NEUTRON] * nN + [LAMBDA]
+    chis = _bits(alpha[0]) + _bits(alpha[1]) + _bits(alpha[2])
+    return L_uca(rel, nsrc, types, chis, with_s=True)
+
+
+def _sgn_group(x, y):
+    """sgn(x|y) of Sec. 3 for one group: -1 to the number of pairs i in x,
+    j in y with i > j."""
+    return -1 if sum(bin(x >> (j + 1)).count("1") for j in _bits(y)) % 2 else 1
+
+
+def hyperon_term_list(rel, nsrc, nP, nN, req, with_ops=False):
+    """term_list for nP protons, nN neutrons and one Lambda added last:
+    components are (P set, N set, Lambda set, u, d, s); the stages before
+    the Lambda hold nucleon components only (4-tuples as in term_list).
+    The Lambda step's operations split every final component z into x (a
+    nucleon component) and y = (the Lambda's spin, one u, one d, the s
+    index) with sign sgn(x_u|y_u) sgn(x_d|y_d)."""
+    D = 4 if rel else 2
+    Ls, U = {}, set()
+    for a in req["alphas"]:
+        um, dm, sm, cf = hyperon_L(rel, nsrc, nP, nN, a)
+        Ls[a] = {(int(u), int(d), int(x)): int(c) for u, d, x, c in zip(um, dm, sm, cf)}
+        U.update(Ls[a].keys())
+    U = sorted(U)
+    dsets = hyperon_delta_sets(nP, nN, req)
+    final = np.array([(p, n, l, u, d, x) for (p, n, l) in dsets for (u, d, x) in U], np.uint32).reshape(-1, 6)
+    final = final[np.lexsort(final.T[::-1])]
+    seq = path(nP, nN) if nP + nN else []
+    shapes, kp, kn = [], 0, 0
+    for t in seq:
+        kp += t == PROTON
+        kn += t == NEUTRON
+        shapes.append((kp, kn, 2 * kp + kn, kp + 2 * kn))
+    nuc_final = np.unique(final[:, [0, 1, 3, 4]], axis=0) if seq else None
+    reqs = [req_stage(nuc_final, sh) for sh in shapes] + [final]
+    ops = []
+    for i in range(1, len(seq)):
+        ops.append(lambda_stage(reqs[i], seq[i], reqs[i - 1], rows=with_ops))
+    if seq:
+        xs = reqs[-2]
+        xindex = {tuple(map(int, r)): i for i, r in enumerate(xs)}
+        rows = []
+        for iz, (p, n, l, u, d, x) in enumerate(final.tolist()):
+            for yu in _bits(u):
+                for yd in _bits(d):
+                    xk = (p, n, u & ~(1 << yu), d & ~(1 << yd))
+                    sg = _sgn_group(xk[2], 1 << yu) * _sgn_group(xk[3], 1 << yd)
+                    rows.append((iz, xindex[xk], l, 1 << yu, 1 << yd, x, sg))
+        ops.append(np.array(rows, np.int64).reshape(-1, 7) if with_ops else len(rows))
+    n_ops = sum(len(o) if with_ops else o for o in ops)
+    return dict(L=Ls, U=U, dsets=dsets, path=seq + [LAMBDA], shapes=shapes, req=reqs, ops=ops,
+                n_lambda=int(n_ops), D=D)
+
+
+def hyperon_correlators(rel, nsrc, nP, nN, req, Su, Sd, Ss, sinkw=None, scale=1.0):
+    """C[delta set, alpha set] of the system by eq. f_L_contr with the blocks
+    by their definition, keyed by (delta, alpha) triples."""
+    D = 4 if rel else 2
+    fP, fN = blocks(rel, nsrc, Su, Sd, sinkw, scale, D=D)
+    fL = blocks_lambda(rel, nsrc, Su, Sd, Ss, sinkw, scale, D=D)
+    types = [PROTON] * nP + [NEUTRON] * nN + [LAMBDA]
+    out = {}
+    for a in req["alphas"]:
+        um, dm, sm, cf = hyperon_L(rel, nsrc, nP, nN, a)
+        for d in hyperon_delta_sets(nP, nN, req):
+            psis = _bits(d[0]) + _bits(d[1]) + _bits(d[2])
+            out[(d, a)] = corr_from_L(types, psis, fP, fN, um, dm, cf, fL=fL, sm=sm)
     return out
 
 

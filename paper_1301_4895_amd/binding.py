@@ -25,7 +25,9 @@ MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUN
 MB_TUNE_PAIRED = 7
 MB_TUNE_TWO_PHASE = 8
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
- MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ, MB_EXPORT_SIDE) = range(1, 10)
+ MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ, MB_EXPORT_SIDE, MB_EXPORT_QUARK_S, MB_EXPORT_SPIN_L,
+ MB_EXPORT_DELTA_L, MB_EXPORT_ALPHA_L) = range(1, 14)
+MB_PROTON, MB_NEUTRON, MB_LAMBDA = 0, 1, 2
 
 EXPORTED_SYMBOLS = [
     "mb_build_term_list", "mb_build_term_list_counts_only", "mb_build_term_list_path", "mb_term_list_free",
@@ -45,12 +47,13 @@ class MBError(RuntimeError):
 
 class mb_nucleus(C.Structure):
     _fields_ = [("n_P", C.c_int), ("n_N", C.c_int), ("rel", C.c_int), ("n_src", C.c_int),
-                ("path", C.c_int), ("order", C.c_uint32)]
+                ("path", C.c_int), ("order", C.c_uint32), ("n_Lambda", C.c_int)]
 
 
 class mb_spin_request(C.Structure):
     _fields_ = [("all_components", C.c_int), ("sink_P", C.c_uint32), ("sink_N", C.c_uint32),
-                ("n_alpha", C.c_int), ("alpha", C.POINTER(C.c_uint32)), ("proj", C.POINTER(C.c_double))]
+                ("n_alpha", C.c_int), ("alpha", C.POINTER(C.c_uint32)), ("proj", C.POINTER(C.c_double)),
+                ("sink_L", C.c_uint32), ("alpha_L", C.POINTER(C.c_uint32))]
 
 
 class mb_side_request(C.Structure):
@@ -65,13 +68,14 @@ class mb_counts(C.Structure):
                 ("n_L", C.c_int64), ("n_U", C.c_int64), ("n_delta", C.c_int32),
                 ("n_alpha", C.c_int32), ("n_psi", C.c_int32), ("n_xi", C.c_int32),
                 ("device_bytes", C.c_int64), ("projected", C.c_int32), ("n_LM", C.c_int64),
-                ("n_side", C.c_int32), ("n_out", C.c_int64), ("rel", C.c_int32), ("n_src", C.c_int32)]
+                ("n_side", C.c_int32), ("n_out", C.c_int64), ("rel", C.c_int32), ("n_src", C.c_int32),
+                ("n_Lambda", C.c_int32)]
 
 
 class mb_problem(C.Structure):
     _fields_ = [("batch", C.c_int64), ("V", C.c_int64), ("in_dtype", C.c_int),
                 ("precision", C.c_int), ("prop_u", C.c_void_p), ("prop_d", C.c_void_p),
-                ("sink_w", C.c_void_p), ("scale_exp", C.c_void_p)]
+                ("sink_w", C.c_void_p), ("scale_exp", C.c_void_p), ("prop_s", C.c_void_p)]
 
 
 class mb_batch_item(C.Structure):
@@ -136,17 +140,24 @@ class TermList:
     source sets of the same request without it.  ``sides``: smaller nuclei
     on the path (Sec. 7), as (stage, source sets) with source sets None for
     all of them.  ``order``: with path MB_PATH_EXPLICIT, bit i set when the
-    (i+1)-th baryon added is a proton."""
+    (i+1)-th baryon added is a proton.  ``n_Lambda`` = 1 adds one Lambda
+    (after the nucleons); then ``alphas`` are (proton set, neutron set,
+    Lambda set) triples and ``sink_L`` is the Lambda's sink base set."""
 
     def __init__(self, n_P, n_N, rel, n_src=1, *, all_components=False, sink_P=0, sink_N=0,
-                 alphas=(), path=MB_PATH_AUTO, order=0, counts_only=False, proj=None, sides=()):
-        nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path, order)
-        arr = np.ascontiguousarray(np.asarray(alphas, np.uint32).reshape(-1))
-        self._alpha_keep = arr
+                 alphas=(), path=MB_PATH_AUTO, order=0, counts_only=False, proj=None, sides=(),
+                 n_Lambda=0, sink_L=0):
+        nuc = mb_nucleus(n_P, n_N, int(rel), n_src, path, order, n_Lambda)
+        width = 3 if n_Lambda else 2
+        al = np.asarray(alphas, np.uint32).reshape(-1, width)
+        arr = np.ascontiguousarray(al[:, :2].reshape(-1))
+        arrL = np.ascontiguousarray(al[:, 2]) if n_Lambda else np.zeros(0, np.uint32)
+        self._alpha_keep = (arr, arrL)
         w = None if proj is None else np.ascontiguousarray(np.asarray(proj, np.float64).reshape(-1))
         req = mb_spin_request(int(all_components), sink_P, sink_N, len(arr) // 2,
                               arr.ctypes.data_as(C.POINTER(C.c_uint32)) if len(arr) else None,
-                              w.ctypes.data_as(C.POINTER(C.c_double)) if w is not None else None)
+                              w.ctypes.data_as(C.POINTER(C.c_double)) if w is not None else None,
+                              sink_L, arrL.ctypes.data_as(C.POINTER(C.c_uint32)) if len(arrL) else None)
         h = C.c_void_p()
         if sides:
             if counts_only:
@@ -162,7 +173,7 @@ class TermList:
             fn = lib().mb_build_term_list_counts_only if counts_only else lib().mb_build_term_list
             _check(fn(C.byref(nuc), C.byref(req), C.byref(h)))
         self.h = h
-        self.nucleus = dict(n_P=n_P, n_N=n_N, rel=bool(rel), n_src=n_src)
+        self.nucleus = dict(n_P=n_P, n_N=n_N, rel=bool(rel), n_src=n_src, n_Lambda=n_Lambda)
         self._dev = None
 
     def save(self, path):
@@ -179,14 +190,19 @@ class TermList:
         self._dev = None
         c = self.counts()
         nP = sum(1 for t in c["path"] if t == 0)
-        self.nucleus = dict(n_P=nP, n_N=c["n_stages"] - nP, rel=bool(c["rel"]), n_src=c["n_src"])
+        self.nucleus = dict(n_P=nP, n_N=c["n_stages"] - nP, rel=bool(c["rel"]), n_src=c["n_src"], n_Lambda=0)
         return self
 
     @classmethod
-    def spin_state(cls, n_P, n_N, rel, n_src, spins, **kw):
-        """Single spin component (Sec. 8): indices listed protons first."""
+    def spin_state(cls, n_P, n_N, rel, n_src, spins, n_Lambda=0, **kw):
+        """Single spin component (Sec. 8): indices listed protons first,
+        then neutrons, then the Lambda's."""
         pm = sum(1 << s for s in spins[:n_P])
         nm = sum(1 << s for s in spins[n_P:n_P + n_N])
+        if n_Lambda:
+            lm = 1 << spins[n_P + n_N]
+            return cls(n_P, n_N, rel, n_src, sink_P=pm, sink_N=nm, sink_L=lm, alphas=[(pm, nm, lm)],
+                       n_Lambda=1, **kw)
         return cls(n_P, n_N, rel, n_src, sink_P=pm, sink_N=nm, alphas=[(pm, nm)], **kw)
 
     def close(self):
@@ -209,7 +225,7 @@ class TermList:
                     n_quark=list(c.n_quark[:n]), n_spin=list(c.n_spin[:n]), n_L=c.n_L, n_U=c.n_U,
                     n_delta=c.n_delta, n_alpha=c.n_alpha, n_psi=c.n_psi, n_xi=c.n_xi,
                     device_bytes=c.device_bytes, projected=bool(c.projected), n_LM=c.n_LM,
-                    n_side=c.n_side, n_out=c.n_out, rel=c.rel, n_src=c.n_src)
+                    n_side=c.n_side, n_out=c.n_out, rel=c.rel, n_src=c.n_src, n_Lambda=c.n_Lambda)
 
     def side(self, i):
         """Side request i: (stage, source sets [n][2], CSR row starts, quark
@@ -249,13 +265,15 @@ class TermList:
         return self
 
 
-def problem(batch, V, props_u, props_d, precision, sink_w=None, scale_exp=None):
-    """mb_problem for torch device tensors (props complex64 / complex128)."""
+def problem(batch, V, props_u, props_d, precision, sink_w=None, scale_exp=None, props_s=None):
+    """mb_problem for torch device tensors (props complex64 / complex128;
+    props_s the strange propagator of a system with a Lambda)."""
     import torch
     in_dtype = MB_C128 if props_u.dtype == torch.complex128 else MB_C64
     return mb_problem(batch, V, in_dtype, precision, props_u.data_ptr(), props_d.data_ptr(),
                       sink_w.data_ptr() if sink_w is not None else None,
-                      scale_exp.data_ptr() if scale_exp is not None else None)
+                      scale_exp.data_ptr() if scale_exp is not None else None,
+                      props_s.data_ptr() if props_s is not None else None)
 
 
 def workspace_query(tl: TermList, p: mb_problem):

@@ -517,6 +517,38 @@ __global__ __launch_bounds__(256) void blocks_finish_kernel(FinishArgs a, int nx
   out[(int64_t(species) * nyq + yq) * npsi * a.Bp + lane_off(b, npsi) + psi * 16] = o;
 }
 
+// The Lambda block: f_L(psi; e, c, f) with (s, u, d) indices (e, c, f) is
+// the partial entry (psi, xi1 = e, pair = c*n_xi + f) summed over the site
+// chunks; its block quark index (e*n_xi + c)*n_xi + f is the partial's
+// offset inside the psi row, so that a thread's chunk sums are one strided
+// walk.  Stored in double from block row row0 on.
+__global__ __launch_bounds__(256) void blocks_finish_lambda_kernel(FinishArgs a, int nxi, int npsi, int64_t row0) {
+  const int64_t b = blockIdx.x;
+  const int64_t nyl = int64_t(nxi) * nxi * nxi;
+  const int64_t comp = blockIdx.y * int64_t(blockDim.x) + threadIdx.x;   // over npsi * nyl
+  if (comp >= npsi * nyl) return;
+  const int psi = int(comp / nyl);
+  const int64_t y = comp % nyl;
+  double2 v = make_double2(0.0, 0.0);
+  if (b < a.B) {
+    const double2 *part = reinterpret_cast<const double2 *>(a.partP);
+    const int64_t stride = npsi * nyl;
+    for (int ch = 0; ch < a.nchunk; ch++) {
+      const double2 x = part[(b * a.nchunk + ch) * stride + comp];
+      v.x += x.x;
+      v.y += x.y;
+    }
+  }
+  static_cast<double2 *>(a.blocks)[(row0 + y) * npsi * a.Bp + lane_off(b, npsi) + psi * 16] = v;
+}
+
+hipError_t launch_blocks_finish_lambda(const FinishArgs &a, int nxi, int npsi, int64_t row0, hipStream_t s) {
+  const int64_t n = int64_t(npsi) * nxi * nxi * nxi;
+  hipLaunchKernelGGL(blocks_finish_lambda_kernel, dim3(unsigned(a.Bp), unsigned((n + 255) / 256)), dim3(256), 0, s,
+                     a, nxi, npsi, row0);
+  return hipGetLastError();
+}
+
 // Per-lane exponent: e_b with 2^(e_b - 1) <= max |Re|, |Im| over the lane's
 // block entries (both species) < 2^e_b, and the entries multiplied by
 // 2^-e_b (exact), so that products of many blocks stay near 1 whatever the

@@ -47,19 +47,33 @@ size_t elem_bytes(const mb_problem *p) { return p->precision == MB_MIXED ? 8 : 1
 // Blocks are stored in double in both precision modes (they are small and
 // every block entry enters every component).
 // followed by the per-lane block exponents (int32, padded lanes)
-size_t blocks_entry_bytes(const mb_term_list *tl, const mb_problem *p) {
+// Block quark indices of both nucleon blocks, then of the Lambda's (n_xi^3).
+int64_t block_rows(const mb_term_list *tl) {
   const int64_t nyq = int64_t(tl->nxi) * (tl->nxi - 1) / 2 * tl->nxi;
-  return size_t(2 * tl->npsi * nyq) * size_t(lanes_padded(p->batch)) * 16;
+  return 2 * nyq + (tl->nLam ? int64_t(tl->nxi) * tl->nxi * tl->nxi : 0);
+}
+size_t blocks_entry_bytes(const mb_term_list *tl, const mb_problem *p) {
+  return size_t(tl->npsi * block_rows(tl)) * size_t(lanes_padded(p->batch)) * 16;
+}
+
+// The sink base set of a species.
+uint32_t base_of(const mb_term_list *tl, int type) {
+  return type == PROTON ? tl->SP : type == NEUTRON ? tl->SN : tl->SL;
 }
 size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
   return blocks_entry_bytes(tl, p) + al256(size_t(lanes_padded(p->batch)) * 4);
 }
 
+// Site-chunk partial sums: one set per nucleon block (one with u = d), then
+// the Lambda's (all ordered (u, d) pairs) in the same space after the
+// nucleon blocks are finished.
 size_t blocks_ws_of(const mb_term_list *tl, const mb_problem *p) {
   const bool sym = p->prop_u == p->prop_d;
-  const int npair = sym ? tl->nxi * (tl->nxi + 1) / 2 : tl->nxi * tl->nxi;
-  const size_t per = size_t(nchunks_for(p->batch, p->V)) * tl->npsi * tl->nxi * npair * 16;
-  return al256(per * size_t(p->batch)) * (sym ? 1 : 2);
+  auto part = [&](int npair) {
+    return al256(size_t(nchunks_for(p->batch, p->V)) * tl->npsi * tl->nxi * npair * 16 * size_t(p->batch));
+  };
+  const size_t nuc = part(sym ? tl->nxi * (tl->nxi + 1) / 2 : tl->nxi * tl->nxi) * (sym ? 1 : 2);
+  return tl->nLam ? std::max(nuc, part(tl->nxi * tl->nxi)) : nuc;
 }
 
 // Per-sink-set sums of a projected final sum: complex double [Bp][n_delta].
@@ -130,6 +144,7 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   int rc = check_problem(tl, p);
   if (rc) return rc;
   if (!p->prop_u || !p->prop_d || !blocks || !ws) return fail(MB_EINVAL, "null device buffer");
+  if (tl->nLam && !p->prop_s) return fail(MB_EINVAL, "null strange propagator for a term list with a Lambda");
   if (blocks_bytes < blocks_bytes_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks buffer too small");
   if (ws_bytes < blocks_ws_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -147,7 +162,9 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   a.nchunk = nchunks_for(p->batch, p->V);
   a.sites_per_chunk = (p->V + a.nchunk - 1) / a.nchunk;
   a.in_c128 = p->in_dtype == MB_C128;
-  const size_t half = blocks_ws_of(tl, p) / (sym ? 1 : 2);
+  const int npair_n = sym ? tl->nxi * (tl->nxi + 1) / 2 : tl->nxi * tl->nxi;
+  const size_t half =
+      al256(size_t(a.nchunk) * tl->npsi * tl->nxi * npair_n * 16 * size_t(p->batch));
   double *partP = static_cast<double *>(ws);
   double *partN = sym ? partP : reinterpret_cast<double *>(static_cast<char *>(ws) + half);
   a.prop_q1 = p->prop_u;
@@ -170,9 +187,18 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   f.sym = sym;
   HIP_CHECK(launch_blocks_finish(f, mixed, s));
   const int nyq = tl->nxi * (tl->nxi - 1) / 2 * tl->nxi;
+  if (tl->nLam) {
+    // the Lambda (s, u, d): every ordered (u, d) pair, no antisymmetrisation;
+    // its partials reuse the workspace (the finish above has read it)
+    a.prop_q1 = p->prop_s;
+    a.partial = partP;
+    HIP_CHECK(launch_blocks_partial(a, mixed, false, s));
+    f.partP = partP;
+    HIP_CHECK(launch_blocks_finish_lambda(f, tl->nxi, tl->npsi, int64_t(2) * nyq, s));
+  }
   HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
                                                                      blocks_entry_bytes(tl, p)),
-                                f.Bp, tl->npsi, 2 * nyq, s));
+                                f.Bp, tl->npsi, int(block_rows(tl)), s));
   return MB_OK;
 }
 
@@ -305,7 +331,7 @@ int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
   for (int s = 1; s < tl->nstages; s++) {
     if (step != -1 && s != step) continue;
     Stage &S = tl->st[s];
-    const int npass = S.type == PROTON ? S.nNsets : S.nPsets;
+    const int npass = S.npass();
     if (what == MB_TUNE_PASS_GROUP) {
       if (value < 0 || value > 6 || value == 4 || value == 5 || (value > 0 && npass % value != 0)) {
         if (step != -1) return fail(MB_EINVAL, "passthrough group must divide the passthrough count");
@@ -388,7 +414,8 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   const int nxi = tl->nxi;
   const int nyq = nxi * (nxi - 1) / 2 * nxi;
   const char *blk = static_cast<const char *>(blocks);
-  const void *fblk[2] = {blk, blk + size_t(tl->npsi) * nyq * Bp * 16};  // proton, neutron
+  // proton, neutron, Lambda
+  const void *fblk[3] = {blk, blk + size_t(tl->npsi) * nyq * Bp * 16, blk + size_t(tl->npsi) * 2 * nyq * Bp * 16};
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
   char *hbuf = static_cast<char *>(ws) + ev + od + proj_bytes_of(tl, p);   // two-phase partials
   size_t eev = 0, eod = 0;
@@ -413,14 +440,14 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
     const Stage &C = tl->st[j + 1];
     if (C.tune_kernel != 0 || !C.tune_paired) return 0;
     const bool AP = C.type == PROTON;
-    const int npass = AP ? C.nNsets : C.nPsets;
-    const int M = __builtin_popcount(AP ? tl->SP : tl->SN);
+    const int npass = C.npass();
+    const int M = __builtin_popcount(base_of(tl, C.type));
     // steps with more than four sink indices per species run one
     // passthrough part per thread in the direct kernel
     const int pg = M > 4 ? 1 : C.tune_pg ? C.tune_pg : npass % 3 == 0 ? 3 : npass % 2 == 0 ? 2 : 1;
     const bool grouped = M <= 4 && (C.tune_group == 2 || C.tune_group == 4) && pg <= 3;
     const bool direct64 = !grouped && C.tune_tile == 64;
-    const int nin = binom(M, AP ? tl->st[j].kP : tl->st[j].kN);
+    const int nin = binom(M, AP ? tl->st[j].kP : C.type == NEUTRON ? tl->st[j].kN : tl->st[j].kL);
     if (direct64 && AP && npass % 2 == 0 && pg % 2 == 0) return 1;
     if ((direct64 || grouped) && nin % 2 == 0 && (!AP || npass == 1)) return 2;
     return 0;
@@ -484,7 +511,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         a.nyq = nyq;
         a.ns = int(S0.nspin());
         a.npsi = tl->npsi;
-        psi_positions(S0.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+        psi_positions(base_of(tl, S0.type), a.psi_of_pos);
         a.paired_out = paired(0) != 0;
         if (!dry && a.nq * a.ns > 0) {
           HIP_CHECK(launch_stage0(a, mixed, s));
@@ -510,10 +537,12 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         a.Bp = Bp;
         a.Sq = S.Sq;
         a.nyq = nyq;
+        // the active species' spin index is the major one for a proton
+        // step, the minor one for a neutron or Lambda step
         a.act_is_P = S.type == PROTON;
-        a.M = __builtin_popcount(S.type == PROTON ? tl->SP : tl->SN);
-        a.K = S.type == PROTON ? Pv.kP : Pv.kN;
-        a.npass = S.type == PROTON ? S.nNsets : S.nPsets;
+        a.M = __builtin_popcount(base_of(tl, S.type));
+        a.K = S.type == PROTON ? Pv.kP : S.type == NEUTRON ? Pv.kN : Pv.kL;
+        a.npass = S.npass();
         a.pg = S.tune_pg;
         a.lds_bytes = S.tune_lds;
         a.tile = S.tune_tile;
@@ -523,6 +552,10 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         a.paired_out = paired(step) != 0;
         a.npsi = tl->npsi;
         a.dry = dry;
+        // the LDS-staged kernel and the two-phase step follow the pair and
+        // single-index structure of nucleon splits
+        if (S.type == LAMBDA && (S.tune_kernel == 1 || S.tune_two_phase))
+          return fail(MB_EUNSUPPORTED, "a Lambda step runs the direct or grouped kernel in one phase");
         const bool two_phase = S.tune_two_phase && S.tune_kernel == 0;
         if (two_phase) {
           a.two_phase = 1;
@@ -533,7 +566,7 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
           a.H = hbuf;
           a.hstride = S.nreq() * Bp;
         }
-        psi_positions(S.type == PROTON ? tl->SP : tl->SN, a.psi_of_pos);
+        psi_positions(base_of(tl, S.type), a.psi_of_pos);
         if (a.M > 6) return fail(MB_EUNSUPPORTED, "more than 6 sink indices per species");
         if (a.nq_out > 0 && S.tune_kernel == 1) {
           // the LDS-staged kernel holds one range of at most 36 pair rows:

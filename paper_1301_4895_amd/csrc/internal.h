@@ -16,18 +16,26 @@ namespace mb {
 inline uint64_t qkey(uint32_t u, uint32_t d) { return (uint64_t(u) << 32) | d; }
 inline uint32_t qkey_u(uint64_t k) { return uint32_t(k >> 32); }
 inline uint32_t qkey_d(uint64_t k) { return uint32_t(k); }
+// In a system with a Lambda (at most 12 quark indices per flavour) the s
+// index set of the Lambda's stage sits above the u set: u field = u | s << 16.
+constexpr int S_SHIFT = 16;
+inline uint32_t ufield_u(uint32_t f) { return f & ((1u << S_SHIFT) - 1u); }
+inline uint32_t ufield_s(uint32_t f) { return f >> S_SHIFT; }
 
-enum { PROTON = 0, NEUTRON = 1 };
+enum { PROTON = 0, NEUTRON = 1, LAMBDA = 2 };
 
 // One stage of the recursion: the components holding the first s+1 baryons
 // of the path.  Required components are (spin part) x (quark part); the spin
 // parts are every kP-subset of the sink proton base set times every
-// kN-subset of the neutron base set, ordered (proton rank, neutron rank)
-// with subsets ranked by mask value.
+// kN-subset of the neutron base set (times, at the Lambda's stage, every
+// index of the Lambda's sink base set), ordered (proton rank, neutron rank,
+// Lambda rank) with subsets ranked by mask value.
 struct Stage {
   int type = 0;                  // species of the baryon added to reach this stage
   int kP = 0, kN = 0, ku = 0, kd = 0;
+  int kL = 0;                    // 1 at the Lambda's stage
   int nPsets = 0, nNsets = 0;    // C(|SP|, kP), C(|SN|, kN)
+  int nLsets = 1;                // C(|SL|, kL)
   std::vector<uint64_t> quark;   // sorted quark parts
   int Sq = 0;                    // quark splits per output quark part (s >= 1)
   std::vector<uint32_t> qsplit;  // [nq][Sq][2]: x index, y block index | sign<<31
@@ -39,11 +47,14 @@ struct Stage {
   int tune_group = 1;                             // outputs per wavefront (grouped kernel when > 1)
   int tune_paired = 1;                            // input stage in the paired layout when possible
   int tune_two_phase = 0;                         // 1: partial sums per single index, then their sum
-  int64_t nspin() const { return int64_t(nPsets) * nNsets; }
+  int64_t nspin() const { return int64_t(nPsets) * nNsets * nLsets; }
   // quark indices of the added baryon's single flavour in an output quark
   // part (d for a proton step, u for a neutron step): the splits of an
-  // output come in that many groups of Sq / nsingle() pair splits
-  int nsingle() const { return type == PROTON ? kd : ku; }
+  // output come in that many groups of Sq / nsingle() pair splits (a
+  // Lambda step, which has no pair, counts as one group)
+  int nsingle() const { return type == PROTON ? kd : type == NEUTRON ? ku : 1; }
+  // spin parts of the other species that a step passes through
+  int npass() const { return type == PROTON ? nNsets : type == NEUTRON ? nPsets : nPsets * nNsets; }
   int64_t nreq() const { return nspin() * int64_t(quark.size()); }
 };
 
@@ -64,6 +75,9 @@ struct mb_term_list {
   int path[MB_MAX_STAGES] = {};
   uint32_t SP = 0, SN = 0;                      // sink base sets
   std::vector<std::array<uint32_t, 2>> alphas;   // requested source sets
+  int nLam = 0;                                  // 1: one Lambda, added last
+  uint32_t SL = 0;                               // the Lambda's sink base set
+  std::vector<uint32_t> alphaL;                  // the Lambda's source set per column
   std::vector<mb::Stage> st;
   // final coefficients c_alpha(q) = L(alpha; q) on sorted sets, CSR over alpha
   std::vector<int64_t> crow, ccol, cval;

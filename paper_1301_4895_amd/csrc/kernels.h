@@ -33,9 +33,12 @@ struct FinishArgs {
   int nsrc, D, nchunk, sym;
 };
 hipError_t launch_blocks_finish(const FinishArgs &a, bool mixed, hipStream_t s);
+// The Lambda block from the partials in a.partP (all ordered (u, d) pairs):
+// chunk sum in double, stored from block row row0 on.
+hipError_t launch_blocks_finish_lambda(const FinishArgs &a, int nxi, int npsi, int64_t row0, hipStream_t s);
 
 // Per-lane block exponents (see blocks_scale_kernel): blocks scaled in place
-// by 2^-lane_exp[b]; nyq2 = 2 * block quark indices (both species).
+// by 2^-lane_exp[b]; nyq2 = block quark indices of all species together.
 hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s);
 
 // Lane-blocked layouts (lanes grouped in tiles of 16, Bp = padded lanes):

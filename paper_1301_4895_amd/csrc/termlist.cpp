@@ -99,6 +99,13 @@ static inline uint32_t block_qidx(int type, uint32_t yu, uint32_t yd, int nxi) {
   return uint32_t(c) * uint32_t(nxi * (nxi - 1) / 2) + pair_rank(a, b);
 }
 
+// Block quark index of a Lambda block component: s index e, u index c, d
+// index f (one-bit masks) -> (e*n_xi + c)*n_xi + f.
+static inline uint32_t lambda_qidx(uint32_t ys, uint32_t yu, uint32_t yd, int nxi) {
+  return (uint32_t(__builtin_ctz(ys)) * uint32_t(nxi) + uint32_t(__builtin_ctz(yu))) * uint32_t(nxi) +
+         uint32_t(__builtin_ctz(yd));
+}
+
 // ---------------------------------------------------------------------------
 // Gamma matrices restricted to the active spins (Sec. 7).  On the spins that
 // enter (all four relativistically, the upper two nonrelativistically in the
@@ -156,6 +163,27 @@ static std::vector<GEnt> g_antisym(int type, int nsrc, int npsi, int nxi, uint32
             e.d = (1u << a) | (1u << b);
           }
           out.push_back(e);
+        }
+  }
+  return out;
+}
+
+// Nonzero entries of G of the Lambda, slots (s, u, d): no two slots share a
+// flavour, so nothing is antisymmetrised.
+struct GEntL {
+  int chi;
+  uint32_t s, u, d;
+  int64_t c;
+};
+static std::vector<GEntL> g_lambda(int nsrc, int npsi, int nxi, uint32_t allowed) {
+  std::vector<GEntL> out;
+  for (int chi = 0; chi < npsi; chi++) {
+    if (!(allowed >> chi & 1)) continue;
+    for (int a = 0; a < nxi; a++)
+      for (int b = 0; b < nxi; b++)
+        for (int c = 0; c < nxi; c++) {
+          const int v = g_value(chi, a, b, c, nsrc);
+          if (v) out.push_back({chi, 1u << a, 1u << b, 1u << c, v});
         }
   }
   return out;
@@ -267,6 +295,14 @@ static inline void for_quark_splits(int type, uint32_t u, uint32_t d, F &&f) {
   }
 }
 
+// The quark splits of a Lambda step: the Lambda takes one u index (slowest)
+// and one d index of the output; its s index is the output's whole s set.
+template <class F>
+static inline void for_lambda_splits(uint32_t uf, uint32_t d, F &&f) {
+  for (uint32_t tu = ufield_u(uf); tu; tu &= tu - 1)
+    for (uint32_t td = d; td; td &= td - 1) f(tu & (~tu + 1), td & (~td + 1));
+}
+
 // c_alpha(q) = L^(n)(alpha; q) / (k_P! k_N!) on sorted sets for the nucleus
 // of the first n baryons of the path (k_P protons, k_N neutrons), for every
 // source set alpha in `alphas` (eq. recr_L).  The recursion antisymmetrises
@@ -330,6 +366,37 @@ static int source_coefficients(const mb_term_list *tl, int n, const std::vector<
     per_alpha[it->second].push_back({qkey(u, d), kv.second / norm});
   }
   return MB_OK;
+}
+
+// Extends the nucleon coefficients by the Lambda (eq. recr_L with G of the
+// Lambda as the last factor): for column i, with nucleon source sets
+// nalphas[nidx[i]] and Lambda source index chi_i,
+//   c_i(U, D, s) = sum over nucleon parts (U', D') and Lambda entries
+//                  g = (s, u, d) with U = U' + u, D = D' + d of
+//                  sgn(U'|u) sgn(D'|d) c_nuc(U', D') g,
+// keyed qkey(U | s << S_SHIFT, D).  One Lambda: its spin split and the
+// normalisation (1!) are trivial.
+static void lambda_coefficients(const mb_term_list *tl, const std::vector<std::vector<std::pair<uint64_t, int64_t>>> &nuc,
+                                const std::vector<int> &nidx,
+                                std::vector<std::vector<std::pair<uint64_t, int64_t>>> &per_alpha) {
+  uint32_t allow = 0;
+  for (uint32_t l : tl->alphaL) allow |= l;
+  const std::vector<GEntL> g = g_lambda(tl->nsrc, tl->npsi, tl->nxi, allow);
+  per_alpha.assign(tl->alphaL.size(), {});
+  for (size_t i = 0; i < tl->alphaL.size(); i++) {
+    const int chi = __builtin_ctz(tl->alphaL[i]);
+    std::unordered_map<uint64_t, int64_t> m;
+    for (const auto &e : nuc[size_t(nidx[i])]) {
+      const uint32_t u = qkey_u(e.first), d = qkey_d(e.first);
+      for (const GEntL &ge : g) {
+        if (ge.chi != chi || (u & ge.u) || (d & ge.d)) continue;
+        const int sg = split_sign(u, ge.u) * split_sign(d, ge.d);
+        m[qkey((u | ge.u) | (ge.s << S_SHIFT), d | ge.d)] += sg * e.second * ge.c;
+      }
+    }
+    for (auto &kv : m)
+      if (kv.second != 0) per_alpha[i].push_back(kv);
+  }
 }
 
 // Source sets of `n` baryons of one species with all spins: every n-subset
@@ -399,6 +466,9 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
                  bool counts_only, mb_term_list **out) {
   if (!nuc || !req || !out) return fail(MB_EINVAL, "null argument");
   if (n_side < 0 || (n_side > 0 && !side)) return fail(MB_EINVAL, "bad side requests");
+  if (nuc->n_Lambda < 0 || nuc->n_Lambda > 1) return fail(MB_EUNSUPPORTED, "at most one Lambda");
+  if (nuc->n_Lambda && (nuc->path == MB_PATH_BEST || n_side > 0 || req->proj))
+    return fail(MB_EUNSUPPORTED, "a Lambda with MB_PATH_BEST, side requests or a projection");
   if (nuc->path == MB_PATH_BEST) {
     // the final required quark parts do not depend on the order (only signs
     // of L do): take them from the AUTO order, count every order, then build
@@ -436,9 +506,9 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
     return rc;
   }
   *out = nullptr;
-  const int nP = nuc->n_P, nN = nuc->n_N;
-  if (nP < 0 || nN < 0 || nP + nN < 1) return fail(MB_EINVAL, "need at least one baryon");
-  if (nP + nN > MB_MAX_STAGES) return fail(MB_EUNSUPPORTED, "more than 16 baryons");
+  const int nP = nuc->n_P, nN = nuc->n_N, nLam = nuc->n_Lambda, An = nP + nN;
+  if (nP < 0 || nN < 0 || An + nLam < 1) return fail(MB_EINVAL, "need at least one baryon");
+  if (An + nLam > MB_MAX_STAGES) return fail(MB_EUNSUPPORTED, "more than 16 baryons");
   if (nuc->rel != 0 && nuc->rel != 1) return fail(MB_EINVAL, "rel must be 0 or 1");
   if (nuc->n_src < 1 || nuc->n_src > 3) return fail(MB_EUNSUPPORTED, "n_src must be 1, 2 or 3");
   // quark index sets are 24-bit fields of the packed keys: 3 D N_s <= 24
@@ -446,10 +516,12 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   if (nuc->path < 0 || nuc->path > MB_PATH_EXPLICIT) return fail(MB_EINVAL, "bad path");
   const int D = nuc->rel ? 4 : 2, nsrc = nuc->n_src;
   const int npsi = D * nsrc, nxi = 3 * D * nsrc;
-  const int nu = 2 * nP + nN, nd = nP + 2 * nN;
+  const int nu = 2 * nP + nN + nLam, nd = nP + 2 * nN + nLam;
   if (nP > npsi || nN > npsi)
     return fail(MB_EPAULI, "more baryons of one species than baryon indices");
   if (nu > nxi || nd > nxi) return fail(MB_EPAULI, "more quarks of one flavour than quark indices");
+  // the s set of the Lambda's stage is packed above the u set (bit S_SHIFT)
+  if (nLam && nxi > S_SHIFT - 4) return fail(MB_EUNSUPPORTED, "a Lambda needs at most 12 quark indices per flavour");
 
   mb_term_list *tl = new (std::nothrow) mb_term_list();
   if (!tl) return fail(MB_ENOMEM, "out of host memory");
@@ -459,7 +531,8 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   tl->nsrc = nsrc;
   tl->npsi = npsi;
   tl->nxi = nxi;
-  tl->A = nP + nN;
+  tl->A = An + nLam;
+  tl->nLam = nLam;
   tl->counts_only = counts_only;
   const int A = tl->A;
 
@@ -470,13 +543,14 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   if (first == PROTON && nP == 0) first = NEUTRON;
   if (first == NEUTRON && nN == 0) first = PROTON;
   if (nuc->path == MB_PATH_EXPLICIT) {
-    if ((A < 32 && (nuc->order >> A) != 0) || __builtin_popcount(nuc->order) != nP)
+    if ((An < 32 && (nuc->order >> An) != 0) || __builtin_popcount(nuc->order) != nP)
       return fail(MB_EINVAL, "order must mark n_P of the first n_P + n_N baryons as protons");
-    for (int i = 0; i < A; i++) tl->path[i] = (nuc->order >> i & 1) ? PROTON : NEUTRON;
+    for (int i = 0; i < An; i++) tl->path[i] = (nuc->order >> i & 1) ? PROTON : NEUTRON;
   } else {
     int nf = first == PROTON ? nP : nN;
-    for (int i = 0; i < A; i++) tl->path[i] = i < nf ? first : 1 - first;
+    for (int i = 0; i < An; i++) tl->path[i] = i < nf ? first : 1 - first;
   }
+  if (nLam) tl->path[A - 1] = LAMBDA;   // the Lambda after the nucleons
   tl->nstages = A;
 
   // spin request
@@ -484,8 +558,14 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   if (req->all_components) {
     tl->SP = nP ? all : 0;
     tl->SN = nN ? all : 0;
+    tl->SL = nLam ? all : 0;
+    const std::vector<uint32_t> lsets = nLam ? all_source_sets(1, D, nsrc) : std::vector<uint32_t>{0u};
     for (uint32_t p : all_source_sets(nP, D, nsrc))
-      for (uint32_t n : all_source_sets(nN, D, nsrc)) tl->alphas.push_back({p, n});
+      for (uint32_t n : all_source_sets(nN, D, nsrc))
+        for (uint32_t l : lsets) {
+          tl->alphas.push_back({p, n});
+          if (nLam) tl->alphaL.push_back(l);
+        }
   } else {
     if ((req->sink_P & ~all) || (req->sink_N & ~all))
       return fail(MB_EINVAL, "sink set has indices beyond D*N_s");
@@ -500,15 +580,44 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
         return fail(MB_EINVAL, "source set with wrong indices or size");
       tl->alphas.push_back({p, n});
     }
+    if (nLam) {
+      if ((req->sink_L & ~all) || !req->sink_L) return fail(MB_EINVAL, "Lambda sink set empty or beyond D*N_s");
+      if (!req->alpha_L) return fail(MB_EINVAL, "no Lambda source sets");
+      tl->SL = req->sink_L;
+      for (int i = 0; i < req->n_alpha; i++) {
+        const uint32_t l = req->alpha_L[i];
+        if ((l & ~all) || __builtin_popcount(l) != 1) return fail(MB_EINVAL, "Lambda source set must be one index");
+        tl->alphaL.push_back(l);
+      }
+    }
   }
   if (nP == 0) tl->SP = 0;
   if (nN == 0) tl->SN = 0;
 
   // ---- L by the recursion L^(n+1) = L^(n) . G (eq. recr_L); c_alpha per source set
   std::vector<std::vector<std::pair<uint64_t, int64_t>>> per_alpha;
-  {
+  if (!nLam) {
     const int rc = source_coefficients(tl, A, tl->alphas, per_alpha);
     if (rc) return rc;
+  } else {
+    // the nucleons' coefficients for their distinct source sets, then the
+    // Lambda as the last factor
+    std::vector<std::array<uint32_t, 2>> nal;
+    std::vector<int> nidx;
+    for (auto &a : tl->alphas) {
+      size_t j = 0;
+      while (j < nal.size() && nal[j] != a) j++;
+      if (j == nal.size()) nal.push_back(a);
+      nidx.push_back(int(j));
+    }
+    std::vector<std::vector<std::pair<uint64_t, int64_t>>> nucc;
+    if (An > 0) {
+      const int rc = source_coefficients(tl, An, nal, nucc);
+      if (rc) return rc;
+    } else {
+      nucc.assign(nal.size(), {{qkey(0, 0), 1}});
+    }
+    lambda_coefficients(tl, nucc, nidx, per_alpha);
   }
 
   const bool last_d_major = tl->path[A - 1] == PROTON && A > 1;
@@ -607,17 +716,19 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   // ---- stages
   tl->st.resize(A);
   {
-    int kp = 0, kn = 0;
+    int kp = 0, kn = 0, kl = 0;
     for (int s = 0; s < A; s++) {
       Stage &S = tl->st[s];
       S.type = tl->path[s];
-      (S.type == PROTON ? kp : kn)++;
+      (S.type == PROTON ? kp : S.type == NEUTRON ? kn : kl)++;
       S.kP = kp;
       S.kN = kn;
-      S.ku = 2 * kp + kn;
-      S.kd = kp + 2 * kn;
+      S.kL = kl;
+      S.ku = 2 * kp + kn + kl;
+      S.kd = kp + 2 * kn + kl;
       S.nPsets = binom(__builtin_popcount(tl->SP), kp);
       S.nNsets = binom(__builtin_popcount(tl->SN), kn);
+      S.nLsets = binom(__builtin_popcount(tl->SL), kl);
     }
   }
   tl->st[A - 1].quark = U;
@@ -627,7 +738,10 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
     KeySet X(S.quark.size() * 4 + 16);
     for (uint64_t q : S.quark) {
       uint32_t u = qkey_u(q), d = qkey_d(q);
-      for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(u & ~yu, d & ~yd)); });
+      if (T == LAMBDA)
+        for_lambda_splits(u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(ufield_u(u) & ~yu, d & ~yd)); });
+      else
+        for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) { X.insert(qkey(u & ~yu, d & ~yd)); });
     }
     // the quark parts that side nuclei read from stage s - 1
     for (size_t i = 0; i < tl->sides.size(); i++)
@@ -637,8 +751,8 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
     P.quark = X.sorted();
     const bool pd = P.type == PROTON && s - 1 > 0;
     sort_stage(P.quark, pd);
-    S.Sq = T == PROTON ? binom(S.ku, 2) * S.kd : S.ku * binom(S.kd, 2);
-    const int kT = T == PROTON ? S.kP : S.kN;
+    S.Sq = T == PROTON ? binom(S.ku, 2) * S.kd : T == NEUTRON ? S.ku * binom(S.kd, 2) : S.ku * S.kd;
+    const int kT = T == PROTON ? S.kP : T == NEUTRON ? S.kN : S.kL;
     S.n_lambda = S.nreq() * kT * S.Sq;
     if (!counts_only) {
       try {
@@ -649,6 +763,17 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
       size_t o = 0;
       for (uint64_t q : S.quark) {
         uint32_t u = qkey_u(q), d = qkey_d(q);
+        if (T == LAMBDA) {
+          const uint32_t uu = ufield_u(u), ys = ufield_s(u);
+          for_lambda_splits(u, d, [&](uint32_t yu, uint32_t yd) {
+            uint32_t xu = uu & ~yu, xd = d & ~yd;
+            uint32_t xi = find_stage(P.quark, pd, qkey(xu, xd));
+            int sg = split_sign(xu, yu) * split_sign(xd, yd);
+            S.qsplit[o++] = xi;
+            S.qsplit[o++] = lambda_qidx(ys, yu, yd, nxi) | (sg < 0 ? 0x80000000u : 0u);
+          });
+          continue;
+        }
         for_quark_splits(T, u, d, [&](uint32_t yu, uint32_t yd) {
           uint32_t xu = u & ~yu, xd = d & ~yd;
           uint32_t xi = find_stage(P.quark, pd, qkey(xu, xd));
@@ -681,8 +806,11 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
     Stage &S0 = tl->st[0];
     if (!counts_only) {
       S0.first.resize(S0.quark.size());
-      for (size_t i = 0; i < S0.quark.size(); i++)
-        S0.first[i] = block_qidx(S0.type, qkey_u(S0.quark[i]), qkey_d(S0.quark[i]), nxi);
+      for (size_t i = 0; i < S0.quark.size(); i++) {
+        const uint32_t u = qkey_u(S0.quark[i]), d = qkey_d(S0.quark[i]);
+        S0.first[i] = S0.type == LAMBDA ? lambda_qidx(ufield_s(u), ufield_u(u), d, nxi)
+                                        : block_qidx(S0.type, u, d, nxi);
+      }
     }
   }
   *out = guard.release();
@@ -773,6 +901,7 @@ int mb_term_list_counts(const mb_term_list *tl, mb_counts *c) {
   c->n_out = tl->side_offset(tl->sides.size());
   c->rel = tl->nuc.rel;
   c->n_src = tl->nsrc;
+  c->n_Lambda = tl->nLam;
   return MB_OK;
 }
 
@@ -793,22 +922,33 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, 
   switch (what) {
     case MB_EXPORT_QUARK:
       for (uint64_t q : S.quark) {
-        uint32_t v[2] = {qkey_u(q), qkey_d(q)};
+        uint32_t v[2] = {tl->nLam ? ufield_u(qkey_u(q)) : qkey_u(q), qkey_d(q)};
         put(v, 8);
       }
       break;
-    case MB_EXPORT_SPIN: {
-      int mP = __builtin_popcount(tl->SP), mN = __builtin_popcount(tl->SN);
-      std::vector<uint32_t> ps, ns;
+    case MB_EXPORT_QUARK_S:
+      for (uint64_t q : S.quark) {
+        const uint32_t v = tl->nLam ? ufield_s(qkey_u(q)) : 0u;
+        put(&v, 4);
+      }
+      break;
+    case MB_EXPORT_SPIN:
+    case MB_EXPORT_SPIN_L: {
+      int mP = __builtin_popcount(tl->SP), mN = __builtin_popcount(tl->SN), mL = __builtin_popcount(tl->SL);
+      std::vector<uint32_t> ps, ns, ls;
       for (uint32_t m = 0; m < (1u << mP); m++)
         if (__builtin_popcount(m) == S.kP) ps.push_back(from_positions(m, tl->SP));
       for (uint32_t m = 0; m < (1u << mN); m++)
         if (__builtin_popcount(m) == S.kN) ns.push_back(from_positions(m, tl->SN));
+      for (uint32_t m = 0; m < (1u << mL); m++)
+        if (__builtin_popcount(m) == S.kL) ls.push_back(from_positions(m, tl->SL));
       for (uint32_t p : ps)
-        for (uint32_t n : ns) {
-          uint32_t v[2] = {p, n};
-          put(v, 8);
-        }
+        for (uint32_t n : ns)
+          for (uint32_t l : ls) {
+            uint32_t v[2] = {p, n};
+            if (what == MB_EXPORT_SPIN) put(v, 8);
+            else put(&l, 4);
+          }
       break;
     }
     case MB_EXPORT_QSPLIT:
@@ -819,6 +959,16 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, 
       if (stage < 1) return fail(MB_EINVAL, "no split table for stage 0");
       const Stage &Pv = tl->st[stage - 1];
       const int T = S.type;
+      if (T == LAMBDA) {
+        // one split per output: the Lambda takes its index, the nucleon
+        // spin part passes through (sign +1)
+        for (int rpn = 0; rpn < S.nPsets * S.nNsets; rpn++)
+          for (uint32_t t = tl->SL; t; t &= t - 1) {
+            int32_t v[3] = {rpn, __builtin_ctz(t), 1};
+            put(v, 12);
+          }
+        break;
+      }
       int mP = __builtin_popcount(tl->SP), mN = __builtin_popcount(tl->SN);
       for (int rp = 0; rp < S.nPsets; rp++)
         for (int rn = 0; rn < S.nNsets; rn++) {
@@ -858,6 +1008,19 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf, 
     }
     case MB_EXPORT_ALPHA:
       for (auto &a : tl->alphas) put(a.data(), 8);
+      break;
+    case MB_EXPORT_DELTA_L: {
+      size_t n = 0;
+      mb_term_list_export(tl, MB_EXPORT_SPIN_L, tl->nstages - 1, nullptr, &n);
+      tmp.resize(n);
+      mb_term_list_export(tl, MB_EXPORT_SPIN_L, tl->nstages - 1, tmp.data(), &n);
+      break;
+    }
+    case MB_EXPORT_ALPHA_L:
+      for (size_t i = 0; i < tl->alphas.size(); i++) {
+        const uint32_t l = tl->nLam ? tl->alphaL[i] : 0u;
+        put(&l, 4);
+      }
       break;
     case MB_EXPORT_SIDE: {
       const Side &sd = tl->sides[size_t(stage)];
@@ -899,7 +1062,7 @@ const char *mb_last_error(void) { return g_err.c_str(); }
 namespace {
 
 constexpr uint64_t kFileMagic = 0x3153494c4d524554ull;   // "TERMLIS1"
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 2;
 
 struct Writer {
   FILE *f;
@@ -1000,6 +1163,7 @@ void fields(IO &io, TL &tl, std::vector<STAGE> &st, std::vector<SIDE> &sides) {
 // inside the table it points into.
 bool valid_loaded(const mb_term_list &t) {
   const mb_nucleus &n = t.nuc;
+  if (n.n_Lambda != 0 || t.nLam != 0) return false;   // not saved (mb_term_list_save)
   if (n.n_P < 0 || n.n_N < 0 || n.n_P + n.n_N < 1 || n.n_P + n.n_N > MB_MAX_STAGES) return false;
   if ((n.rel != 0 && n.rel != 1) || n.n_src < 1 || n.n_src > 3 || (n.n_src == 3 && n.rel)) return false;
   const int D = n.rel ? 4 : 2, A = n.n_P + n.n_N;
@@ -1083,6 +1247,7 @@ extern "C" {
 
 int mb_term_list_save(const mb_term_list *tl, const char *path) {
   if (!tl || !path) return fail(MB_EINVAL, "null argument");
+  if (tl->nLam) return fail(MB_EUNSUPPORTED, "saving a term list with a Lambda");
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(MB_EINVAL, std::string("cannot open ") + path + " for writing");
   Writer w{f};

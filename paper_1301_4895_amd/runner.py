@@ -11,18 +11,19 @@ class Runner:
 
     props_u / props_d: complex64 or complex128 device tensors
     [batch][V][n_src][12][12]; sink_w: complex128 [n_src][V] or None;
-    scale_exp: int32 [batch] or None.  Buffers are allocated once here;
-    ``run`` only launches."""
+    scale_exp: int32 [batch] or None; props_s: the strange propagator of a
+    system with a Lambda.  Buffers are allocated once here; ``run`` only
+    launches."""
 
     def __init__(self, tl: B.TermList, props_u, props_d, precision, sink_w=None, scale_exp=None,
-                 err_estimate=False):
+                 err_estimate=False, props_s=None):
         self.tl = tl
         if tl._dev is None:
             tl.upload(props_u.device)
         self.batch, self.V = props_u.shape[0], props_u.shape[1]
-        self.keep = (props_u, props_d, sink_w, scale_exp)
+        self.keep = (props_u, props_d, sink_w, scale_exp, props_s)
         self.p = B.problem(self.batch, self.V, props_u, props_d, precision,
-                           None if sink_w is None else torch.view_as_real(sink_w), scale_exp)
+                           None if sink_w is None else torch.view_as_real(sink_w), scale_exp, props_s)
         self.err_estimate = err_estimate
         nb, nbw, ncw = self._sizes()
         dev = props_u.device
@@ -66,7 +67,7 @@ class Runner:
     def set_props(self, props_u, props_d, scale_exp=None):
         """Points the problem at other propagators of the same shape."""
         sink_w = self.keep[2]
-        self.keep = (props_u, props_d, sink_w, scale_exp if scale_exp is not None else self.keep[3])
+        self.keep = (props_u, props_d, sink_w, scale_exp if scale_exp is not None else self.keep[3], self.keep[4])
         self.p.prop_u = props_u.data_ptr()
         self.p.prop_d = props_d.data_ptr()
         if scale_exp is not None:

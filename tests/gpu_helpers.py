@@ -108,8 +108,22 @@ def lib_blocks(r, tl):
     n = 2 * nyq * npsi * Bp * 16
     blk = (r.blocks[:n].view(torch.complex128).view(2, nyq, Bp // 16, npsi, 16).permute(0, 3, 1, 2, 4)
            .reshape(2, npsi, nyq, Bp))
-    e = r.blocks[n:n + 4 * Bp].view(torch.int32)
+    nl = nxi ** 3 * npsi * Bp * 16 if c.get("n_Lambda") else 0
+    e = r.blocks[n + nl:n + nl + 4 * Bp].view(torch.int32)
     return blk, e
+
+
+def lib_lambda_block(r, tl):
+    """The Lambda block of a Runner as [psi][block quark index][lane]."""
+    import torch
+    c = tl.counts()
+    nxi, npsi = c["n_xi"], c["n_psi"]
+    nyq = nxi * (nxi - 1) // 2 * nxi
+    Bp = (r.batch + 63) // 64 * 64
+    n = 2 * nyq * npsi * Bp * 16
+    nyl = nxi ** 3
+    return (r.blocks[n:n + nyl * npsi * Bp * 16].view(torch.complex128).view(nyl, Bp // 16, npsi, 16)
+            .permute(2, 0, 1, 3).reshape(npsi, nyl, Bp))
 
 
 def check_lane_exponent(blk_lane, e):

@@ -441,3 +441,95 @@ def test_rescale_exponent():
     for t in range(200):
         k = O.rescale_exponent(t, 0.5)
         assert 2**-0.5 <= math.exp(-0.5 * t) * 2.0**k <= 2**0.5
+
+
+# ---------------------------------------------------------------- one Lambda (third flavour)
+
+def _uca_corr_l(rel, nsrc, types, psis, chis, Su, Sd, Ss, sinkw=None, scale=1.0):
+    D = 4 if rel else 2
+    fP, fN = O.blocks(rel, nsrc, Su, Sd, sinkw, scale, D=D)
+    fL = O.blocks_lambda(rel, nsrc, Su, Sd, Ss, sinkw, scale, D=D) if O.LAMBDA in types else None
+    um, dm, sm, cf = O.L_uca(rel, nsrc, types, chis, with_s=True)
+    return O.corr_from_L(types, psis, fP, fN, um, dm, cf, fL=fL, sm=None if fL is None else sm)
+
+
+@pytest.mark.parametrize("rel", [False, True])
+def test_lambda_closed_form_and_literal_wick(rel):
+    """Single Lambda, (q1, q2, q3) = (s, u, d): all three flavours differ, so
+    the Wick contraction has one term (the direct one); the UCA with the
+    Lambda's G and block and the literal contraction give it too."""
+    V = 3
+    Su, Sd, Ss = rand_props(V), rand_props(V), rand_props(V)
+    w = RNG.normal(size=(1, V)) + 1j * RNG.normal(size=(1, V))
+    for delta, alpha in [(0, 0), (1, 0), (0, 1), (1, 1)] + ([(3, 2), (2, 3), (2, 2)] if rel else []):
+        c1 = O.lambda_closed(rel, Su, Sd, Ss, w, 0.5, delta, alpha)
+        c2 = _uca_corr_l(rel, 1, [O.LAMBDA], [delta], [alpha], Su, Sd, Ss, w, 0.5)
+        c3 = O.wick_literal(rel, 1, [O.LAMBDA], [delta], [alpha], Su, Sd, w, 0.5, Ss=Ss)
+        assert abs(c1) > 0
+        assert abs(c2 - c1) <= 1e-12 * abs(c1) and abs(c3 - c1) <= 1e-12 * abs(c1)
+
+
+def test_lambda_block_with_strange_equal_to_up_or_down():
+    """The three blocks share the baryon form of Sec. 1 and differ only in
+    the propagator of slot 1 (u for the proton, d for the neutron, s for the
+    Lambda): with S_s = S_u the Lambda block equals the proton's before
+    antisymmetrisation, with S_s = S_d the neutron's."""
+    V = 2
+    Su, Sd = rand_props(V), rand_props(V)
+    w = RNG.normal(size=(1, V)) + 1j * RNG.normal(size=(1, V))
+    fP, fN = O.blocks(True, 1, Su, Sd, w)
+    assert np.abs(fP).max() > 0
+    assert np.array_equal(O.blocks_lambda(True, 1, Su, Sd, Su, w), fP)
+    assert np.array_equal(O.blocks_lambda(True, 1, Su, Sd, Sd, w), fN)
+
+
+@pytest.mark.parametrize("rel,nsrc,types,psis,chis,V", [
+    (False, 1, [1, 2], [0, 1], [1, 0], 2),     # n + Lambda
+    (False, 1, [0, 2], [1, 1], [0, 1], 2),     # p + Lambda
+    (True, 1, [1, 2], [2, 0], [3, 1], 1),      # relativistic n + Lambda
+    (False, 2, [1, 2], [1, 2], [0, 3], 1),     # two sources
+])
+def test_lambda_uca_equals_literal_wick(rel, nsrc, types, psis, chis, V):
+    Su, Sd, Ss = rand_props(V, nsrc), rand_props(V, nsrc), rand_props(V, nsrc)
+    w = RNG.normal(size=(nsrc, V)) + 1j * RNG.normal(size=(nsrc, V))
+    a = _uca_corr_l(rel, nsrc, types, psis, chis, Su, Sd, Ss, w)
+    b = O.wick_literal(rel, nsrc, types, psis, chis, Su, Sd, w, Ss=Ss)
+    assert abs(b) > 0
+    assert abs(a - b) <= 1e-11 * abs(b)
+
+
+def test_lambda_isospin_mirror():
+    """Exchanging u and d maps the proton operator to minus the neutron's and
+    the Lambda's to minus itself ((C g5)^T = -C g5 with fermion exchange),
+    at the sink and the source alike: C_{n Lambda}(S_u, S_d, S_s) =
+    C_{p Lambda}(S_d, S_u, S_s), and for p n Lambda the proton and neutron
+    indices trade places."""
+    V = 2
+    Su, Sd, Ss = rand_props(V), rand_props(V), rand_props(V)
+    w = RNG.normal(size=(1, V)) + 1j * RNG.normal(size=(1, V))
+    for ps, ch in [([0, 1], [1, 0]), ([1, 1], [0, 1])]:
+        a = _uca_corr_l(False, 1, [1, 2], ps, ch, Su, Sd, Ss, w)
+        b = _uca_corr_l(False, 1, [0, 2], ps, ch, Sd, Su, Ss, w)
+        assert abs(a) > 0 and abs(a - b) <= 1e-12 * abs(a)
+    a = _uca_corr_l(False, 1, [0, 1, 2], [0, 1, 1], [1, 0, 0], Su, Sd, Ss, w)
+    b = _uca_corr_l(False, 1, [0, 1, 2], [1, 0, 1], [0, 1, 0], Sd, Su, Ss, w)
+    assert abs(a) > 0 and abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_lambda_two_source_factorisation():
+    """The neutron from source 1 and the Lambda from source 0, each with its
+    sink function on its own half of the sites (Sec. 6): the correlator is
+    the product of the one-source neutron and Lambda correlators."""
+    V = 4
+    S = [rand_props(V, 2) for _ in range(3)]
+    for X in S:
+        X[V // 2:, 0] = 0
+        X[:V // 2, 1] = 0
+    w = np.zeros((2, V), np.complex128)
+    w[0, :V // 2] = RNG.normal(size=V // 2) + 1j * RNG.normal(size=V // 2)
+    w[1, V // 2:] = RNG.normal(size=V // 2) + 1j * RNG.normal(size=V // 2)
+    # psi = chi = 2 alpha + s: neutron (alpha 1, s 1) = 3, Lambda (alpha 0, s 0) = 0
+    got = _uca_corr_l(False, 2, [1, 2], [3, 0], [3, 0], *S, w)
+    cn = _uca_corr_l(False, 1, [1], [1], [1], *[X[:, 1:] for X in S], w[1:])
+    cl = _uca_corr_l(False, 1, [2], [0], [0], *[X[:, :1] for X in S], w[:1])
+    assert abs(got) > 0 and abs(got - cn * cl) <= 1e-11 * abs(got)

@@ -888,3 +888,213 @@ def test_order_search_uses_the_projected_support():
     best = B.TermList(2, 1, False, 1, all_components=True, proj=W, path=B.MB_PATH_BEST, counts_only=True).counts()
     assert best["projected"] and best["n_lambda"] == min(counts.values())
     assert best["n_lambda"] <= c["n_lambda"]
+
+
+# ----------------------------------------------------------------- one Lambda (third flavour)
+
+LAMBDA_CASES = [
+    # rel, nsrc, nP, nN, spins (protons, neutrons, Lambda) or None for all components
+    (False, 1, 0, 0, None),            # a single Lambda
+    (True, 1, 0, 0, None),
+    (False, 1, 0, 1, None),            # Lambda + n
+    (False, 1, 1, 0, None),            # Lambda + p
+    (True, 1, 0, 1, (1, 2)),
+    (True, 1, 1, 0, None),
+    (False, 1, 1, 1, None),            # hypertriton (p n Lambda)
+    (False, 2, 0, 1, (1, 2)),          # two sources
+    (False, 2, 1, 1, None),
+    (False, 1, 1, 2, (0, 0, 1, 1)),    # Lambda + 3H
+    (False, 1, 2, 1, (0, 1, 0, 0)),    # Lambda + 3He
+]
+
+
+def lambda_termlist(rel, nsrc, nP, nN, spins):
+    if spins is None:
+        return B.TermList(nP, nN, rel, nsrc, all_components=True, n_Lambda=1)
+    return B.TermList.spin_state(nP, nN, rel, nsrc, spins, n_Lambda=1)
+
+
+def lambda_request(rel, nsrc, nP, nN, spins):
+    return (O.hyperon_request_all(nP, nN, 4 if rel else 2, nsrc) if spins is None
+            else O.hyperon_request_spin(nP, nN, spins))
+
+
+def _stage6(tl, s):
+    """Required components of stage s as rows (P, N, Lambda, u, d, s)."""
+    S = tl.export(B.MB_EXPORT_SPIN, s).reshape(-1, 2).astype(np.int64)
+    SL = tl.export(B.MB_EXPORT_SPIN_L, s).astype(np.int64)
+    Q = tl.export(B.MB_EXPORT_QUARK, s).reshape(-1, 2).astype(np.int64)
+    QS = tl.export(B.MB_EXPORT_QUARK_S, s).astype(np.int64)
+    sp = np.concatenate([S, SL[:, None]], 1)
+    q = np.concatenate([Q, QS[:, None]], 1)
+    return sp, q
+
+
+def _rows_sorted(r):
+    r = np.asarray(r, np.int64)
+    return r[np.lexsort(r.T[::-1])]
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins", LAMBDA_CASES)
+def test_lambda_term_list_bit_exact_against_oracle(rel, nsrc, nP, nN, spins):
+    """Systems with one Lambda (the baryon form of Sec. 1 with (s, u, d)
+    slots) against the oracle's direct enumeration: the path, L on sorted
+    (u, d, s) sets per source set, the required components of every stage
+    and every operation with its sign."""
+    tl = lambda_termlist(rel, nsrc, nP, nN, spins)
+    c = tl.counts()
+    ref = O.hyperon_term_list(rel, nsrc, nP, nN, lambda_request(rel, nsrc, nP, nN, spins), with_ops=True)
+    assert c["n_Lambda"] == 1 and c["path"] == ref["path"] and c["path"][-1] == B.MB_LAMBDA
+    alphas = np.concatenate([tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2),
+                             tl.export(B.MB_EXPORT_ALPHA_L)[:, None]], 1)
+    assert sorted(map(tuple, alphas.tolist())) == sorted(ref["L"].keys())
+    coef = tl.export(B.MB_EXPORT_COEF, dtype=np.int64)
+    na = len(alphas)
+    row, col, val = coef[:na + 1], coef[na + 1:na + 1 + coef[na]], coef[na + 1 + coef[na]:]
+    last = c["n_stages"] - 1
+    _, Qf = _stage6(tl, last)
+    for i, a in enumerate(map(tuple, alphas.tolist())):
+        got = {tuple(map(int, Qf[q])): int(v) for q, v in zip(col[row[i]:row[i + 1]], val[row[i]:row[i + 1]])}
+        assert got == ref["L"][a]
+    dl = np.concatenate([tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2), tl.export(B.MB_EXPORT_DELTA_L)[:, None]], 1)
+    assert sorted(map(tuple, dl.tolist())) == sorted(ref["dsets"])
+    # required components of every stage (the nucleon stages carry no Lambda)
+    for s in range(c["n_stages"]):
+        sp, q = _stage6(tl, s)
+        lib = _rows_sorted(np.concatenate([np.repeat(sp, len(q), 0), np.tile(q, (len(sp), 1))], 1))
+        r = ref["req"][s].astype(np.int64)
+        if r.shape[1] == 4:
+            r = np.stack([r[:, 0], r[:, 1], 0 * r[:, 0], r[:, 2], r[:, 3], 0 * r[:, 0]], 1)
+        else:
+            r = r[:, [0, 1, 2, 3, 4, 5]]
+        assert np.array_equal(lib, _rows_sorted(r)), s
+    # operations: nucleon steps as in the nucleon lists, the Lambda step here
+    for s in range(1, c["n_stages"]):
+        if c["path"][s] != B.MB_LAMBDA:
+            e = expand_ops(tl, s)
+            zk, xk = _key(*e["z"]), _key(*e["x"])
+            ysh = np.uint64(56 if c["path"][s] == 0 else 48)
+            yk = ((e["y"][0].astype(np.uint64) << ysh) | (e["y"][1].astype(np.uint64) << np.uint64(24)) |
+                  e["y"][2].astype(np.uint64))
+            lib_ops = np.stack([zk, xk, yk, e["sign"].astype(np.int64).astype(np.uint64)], 1)
+            ops = ref["ops"][s - 1]
+            zr, xr = ref["req"][s][ops[:, 0]], ref["req"][s - 1][ops[:, 1]]
+            yk2 = ((ops[:, 2].astype(np.uint64) << ysh) | (ops[:, 3].astype(np.uint64) << np.uint64(24)) |
+                   ops[:, 4].astype(np.uint64))
+            ora_ops = np.stack([_key(zr[:, :2], zr[:, 2:]), _key(xr[:, :2], xr[:, 2:]), yk2,
+                                ops[:, 5].astype(np.int64).astype(np.uint64)], 1)
+            assert np.array_equal(lib_ops[np.lexsort(lib_ops.T[::-1])], ora_ops[np.lexsort(ora_ops.T[::-1])]), s
+            continue
+        nxi = c["n_xi"]
+        sp, q = _stage6(tl, s)
+        Sp = tl.export(B.MB_EXPORT_SPIN, s - 1).reshape(-1, 2).astype(np.int64)
+        Qp = tl.export(B.MB_EXPORT_QUARK, s - 1).reshape(-1, 2).astype(np.int64)
+        qs = tl.export(B.MB_EXPORT_QSPLIT, s).reshape(len(q), -1, 2).astype(np.int64)
+        ss = tl.export(B.MB_EXPORT_SSPLIT, s, np.int32).reshape(len(sp), -1, 3)
+        assert ss.shape[1] == 1 and qs.shape[1] == c["n_lambda_step"][s] // c["n_req"][s]
+        y = qs[:, :, 1] & 0x7FFFFFFF
+        sgq = np.where(qs[:, :, 1] >> 31, -1, 1)
+        rows = []
+        for i in range(len(sp)):
+            xin, psi, sg = ss[i, 0]
+            for j in range(len(q)):
+                for k in range(qs.shape[1]):
+                    e_, c_, f_ = y[j, k] // (nxi * nxi), (y[j, k] // nxi) % nxi, y[j, k] % nxi
+                    xq = Qp[qs[j, k, 0]]
+                    rows.append(tuple(sp[i]) + tuple(q[j]) + (Sp[xin, 0], Sp[xin, 1], xq[0], xq[1], 1 << psi,
+                                                              1 << c_, 1 << f_, 1 << e_, sg * sgq[j, k]))
+        ops = ref["ops"][s - 1]
+        fin, xs = ref["req"][s], ref["req"][s - 1]
+        ora = [tuple(map(int, fin[o[0]])) + tuple(map(int, xs[o[1]])) + (int(o[2]), int(o[3]), int(o[4]),
+                                                                        int(o[5]), int(o[6])) for o in ops]
+        assert np.array_equal(_rows_sorted(rows), _rows_sorted(ora))
+    assert c["n_lambda"] == ref["n_lambda"]
+
+
+def test_lambda_errors():
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 1, False, 3, all_components=True, n_Lambda=1)   # 18 quark indices
+    assert e.value.code == B.MB_EUNSUPPORTED
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 1, False, 1, all_components=True, n_Lambda=2)
+    assert e.value.code == B.MB_EUNSUPPORTED
+    with pytest.raises(B.MBError) as e:
+        B.TermList(0, 1, False, 1, all_components=True, n_Lambda=1, path=B.MB_PATH_BEST)
+    assert e.value.code == B.MB_EUNSUPPORTED
+    with pytest.raises(B.MBError) as e:   # Lambda source set with two indices
+        B.TermList(0, 1, False, 1, sink_N=1, sink_L=3, alphas=[(0, 1, 3)], n_Lambda=1)
+    assert e.value.code == B.MB_EINVAL
+    with pytest.raises(B.MBError) as e:   # 2 protons + 2 neutrons + Lambda: 7 u quarks, 6 indices
+        B.TermList(2, 2, False, 1, all_components=True, n_Lambda=1)
+    assert e.value.code == B.MB_EPAULI
+    tl = lambda_termlist(False, 1, 0, 1, None)
+    import os
+    import tempfile
+    with pytest.raises(B.MBError) as e:
+        tl.save(os.path.join(tempfile.gettempdir(), "lambda_termlist.bin"))
+    assert e.value.code == B.MB_EUNSUPPORTED
+    # the blocks need the strange propagator (checked before any launch)
+    import ctypes as C
+    p = B.mb_problem(8, 64, B.MB_C64, B.MB_FP64, 1, 1, None, None, None)
+    assert B.lib().mb_make_blocks(tl.h, C.byref(p), C.c_void_p(1), 1 << 40, C.c_void_p(1), 1 << 40,
+                                  None) == B.MB_EINVAL
+    assert b"strange" in B.lib().mb_last_error()
+
+
+def _replay_lambda(tl, fb):
+    """The exported tables of a list with a Lambda replayed on blocks
+    fb[species][psi][block quark index] (numpy, one lane)."""
+    c = tl.counts()
+    nxi = c["n_xi"]
+    pr = {(a, b): i for i, (a, b) in enumerate(_pairs(nxi))}
+    npair = len(pr)
+    sp0, q0 = _stage6(tl, 0)
+    T0 = c["path"][0]
+    F = np.zeros((len(q0), len(sp0)), complex)
+    for qi, (u, d, s_) in enumerate(q0):
+        ub, db = O._bits(int(u)), O._bits(int(d))
+        if T0 == B.MB_LAMBDA:
+            y = (O._bits(int(s_))[0] * nxi + ub[0]) * nxi + db[0]
+        else:
+            y = pr[tuple(ub)] * nxi + db[0] if T0 == 0 else ub[0] * npair + pr[tuple(db)]
+        for si, (p, n, l) in enumerate(sp0):
+            psi = O._bits(int([p, n, l][T0]))[0]
+            F[qi, si] = fb[T0][psi, y]
+    for s in range(1, c["n_stages"]):
+        T = c["path"][s]
+        qs = tl.export(B.MB_EXPORT_QSPLIT, s).reshape(c["n_quark"][s], -1, 2)
+        ss = tl.export(B.MB_EXPORT_SSPLIT, s, np.int32).reshape(c["n_spin"][s], -1, 3)
+        xi = qs[:, :, 0].astype(np.int64)
+        yi = (qs[:, :, 1] & 0x7FFFFFFF).astype(np.int64)
+        sq = np.where(qs[:, :, 1] >> 31, -1.0, 1.0)
+        G = np.zeros((len(qs), len(ss)), complex)
+        for so in range(len(ss)):
+            for sin, psi, sg in ss[so]:
+                G[:, so] += (sg * sq * F[xi, sin] * fb[T][psi][yi]).sum(1)
+        F = G
+    return _final_sum(tl, F)
+
+
+@pytest.mark.parametrize("rel,nsrc,nP,nN,spins", [
+    (False, 1, 0, 0, None), (False, 1, 0, 1, None), (True, 1, 1, 0, (2, 1)), (False, 1, 1, 1, None),
+    (False, 2, 0, 1, (1, 2))])
+def test_lambda_tables_reproduce_oracle_correlators(rel, nsrc, nP, nN, spins):
+    """The library's tables of a list with a Lambda, replayed on oracle
+    blocks, give the oracle's correlators (eq. f_L_contr)."""
+    from tests.gpu_helpers import oracle_blocks_lib_layout
+    rng = np.random.default_rng(40 + nP * 10 + nN + 3 * nsrc)
+    V = 2
+    S = [rng.normal(size=(V, nsrc, 12, 12)) + 1j * rng.normal(size=(V, nsrc, 12, 12)) for _ in range(3)]
+    w = rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))
+    tl = lambda_termlist(rel, nsrc, nP, nN, spins)
+    fP, fN = O.blocks(rel, nsrc, S[0], S[1], w)
+    fL = O.blocks_lambda(rel, nsrc, S[0], S[1], S[2], w)
+    fb = list(oracle_blocks_lib_layout(fP, fN)) + [fL.reshape(fL.shape[0], -1)]
+    got = _replay_lambda(tl, fb)
+    dl = np.concatenate([tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2), tl.export(B.MB_EXPORT_DELTA_L)[:, None]], 1)
+    al = np.concatenate([tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2), tl.export(B.MB_EXPORT_ALPHA_L)[:, None]], 1)
+    req = lambda_request(rel, nsrc, nP, nN, spins)
+    ref = O.hyperon_correlators(rel, nsrc, nP, nN, req, S[0], S[1], S[2], w)
+    R = np.array([[ref[(tuple(map(int, d)), tuple(map(int, a)))] for a in al] for d in dl])
+    assert np.linalg.norm(R) > 0
+    assert np.linalg.norm(got - R) <= 1e-12 * np.linalg.norm(R)
