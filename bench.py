@@ -34,8 +34,17 @@ CONFIGS = {
     "c4": dict(workload="8Be NR, two sources, (0,1,2,3,0,1,2,3), L=32 T=64, 16 problems, complex64",
                nP=4, nN=4, rel=False, nsrc=2, spins=(0, 1, 2, 3, 0, 1, 2, 3), L=32, T=64, nprob=16,
                c128=False),
+    # beyond the paper's tables: a hypernucleus (third flavour, one Lambda
+    # after the nucleons) and five neutrons on three sources
+    "h5": dict(workload="Lambda + 4He relativistic, spins (0,1,0,1; 0), L=24 T=48, 16 problems, complex64, "
+                        "strange propagator with m = 0.6",
+               nP=2, nN=2, nLam=1, rel=True, nsrc=1, spins=(0, 1, 0, 1, 0), L=24, T=48, nprob=16, c128=False),
+    "n5": dict(workload="5 neutrons NR, three sources, (0,3,1,4,2), L=16 T=32, 2 problems, complex64",
+               nP=0, nN=5, rel=False, nsrc=3, spins=(0, 3, 1, 4, 2), L=16, T=32, nprob=2, c128=False),
 }
 M_DECAY = 0.5
+M_DECAY_S = 0.6   # strange propagators decay faster (heavier quark)
+NEXT = ["h5", "n5"]   # reported under next_workloads; tuned only when committed settings exist
 
 # The uneven batch: 64 problems drawn by seed from four nuclei, L in
 # {16, 24, 32}, T in {32, 64, 96}, complex64 propagators, 2^k(t) rescale.
@@ -156,12 +165,13 @@ def run_workload(name, args):
     cfg = CONFIGS[name]
     dev = torch.device("cuda:0")
     V, T, nprob, nsrc = cfg["L"] ** 3, cfg["T"], cfg["nprob"], cfg["nsrc"]
+    nlam = cfg.get("nLam", 0)
     lanes = nprob * T
     t0 = time.time()
     if cfg["spins"] is None:
-        tl = B.TermList(cfg["nP"], cfg["nN"], cfg["rel"], nsrc, all_components=True)
+        tl = B.TermList(cfg["nP"], cfg["nN"], cfg["rel"], nsrc, all_components=True, n_Lambda=nlam)
     else:
-        tl = B.TermList.spin_state(cfg["nP"], cfg["nN"], cfg["rel"], nsrc, cfg["spins"])
+        tl = B.TermList.spin_state(cfg["nP"], cfg["nN"], cfg["rel"], nsrc, cfg["spins"], n_Lambda=nlam)
     tl.upload(dev)
     counts = tl.counts()
     t_list = time.time() - t0
@@ -173,18 +183,26 @@ def run_workload(name, args):
     for b0 in range(0, lanes, chunk_gen):
         fill_props(props[b0:b0 + chunk_gen], seed=2013, stream_id=0, V=V, nsrc=nsrc, T=T, first_bt=b0,
                    m=M_DECAY)
+    props_s = None
+    if nlam:
+        props_s = torch.empty_like(props)
+        for b0 in range(0, lanes, chunk_gen):
+            fill_props(props_s[b0:b0 + chunk_gen], seed=2013, stream_id=1, V=V, nsrc=nsrc, T=T, first_bt=b0,
+                       m=M_DECAY_S)
     kexp = torch.tensor([int(math.floor(M_DECAY * (b % T) / math.log(2.0) + 0.5)) for b in range(lanes)],
                         dtype=torch.int32, device=dev)
     sink = None
-    if nsrc == 2:
-        w = np.stack([np.ones(V, np.complex128), momentum_phase(cfg["L"], 1)])
+    if nsrc >= 2:
+        # sink function s' of source s': zero momentum, then one and two units along x3
+        w = np.stack([np.ones(V, np.complex128)] + [momentum_phase(cfg["L"], p) for p in range(1, nsrc)])
         sink = torch.from_numpy(w).to(dev)
-    log(f"[bench] propagators {props.numel() * props.element_size() / 1e9:.1f} GB generated")
+    nbytes = props.numel() * props.element_size() * (2 if nlam else 1)
+    log(f"[bench] propagators {nbytes / 1e9:.1f} GB generated")
 
     chunk = lanes if args.chunk <= 0 else min(args.chunk, lanes)   # default: one launch for all lanes
     assert lanes % chunk == 0
     nchunk = lanes // chunk
-    A = cfg["nP"] + cfg["nN"]
+    A = cfg["nP"] + cfg["nN"] + nlam
     steps_idx = list(range(A + 1))
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
@@ -195,9 +213,13 @@ def run_workload(name, args):
     for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
-        r = Runner(tl, props[:chunk], props[:chunk], prec, sink, kexp[:chunk])
+        r = Runner(tl, props[:chunk], props[:chunk], prec, sink, kexp[:chunk],
+                   props_s=None if props_s is None else props_s[:chunk])
         tuning[prec_name] = None
-        if not args.no_autotune:
+        from paper_1301_4895_amd import autotune
+        if name in NEXT and autotune.committed(f"{name}|{prec_name}|{chunk}") is None and not args.retune:
+            tuning[prec_name] = {"source": "library defaults (not tuned)"}
+        elif not args.no_autotune:
             from paper_1301_4895_amd import autotune
             key = f"{name}|{prec_name}|{chunk}"
             best = None if args.retune else autotune.committed(key)
@@ -220,7 +242,7 @@ def run_workload(name, args):
         def one_pass(record):
             for c in range(nchunk):
                 sl = slice(c * chunk, (c + 1) * chunk)
-                r.set_props(props[sl], props[sl], kexp[sl])
+                r.set_props(props[sl], props[sl], kexp[sl], None if props_s is None else props_s[sl])
                 evs = [torch.cuda.Event(enable_timing=True) for _ in range(A + 3)] if record else None
                 if record:
                     evs[0].record(stream)
@@ -270,15 +292,16 @@ def run_workload(name, args):
         # in the timed launch settings; its correlators must be the timed ones
         sig = torch.empty((lanes,) + tuple(outs["mixed"].shape[1:]), dtype=torch.float64)
         same = True
-        if tuning.get("mixed") is not None:
+        if tuning.get("mixed") is not None and "steps" in tuning["mixed"]:
             from paper_1301_4895_amd import autotune
             autotune.apply(tl, {int(k): (0 if v["kernel"] == "direct" else 1, v["pass_group"], v["lds_bytes"],
                                          v["lane_tile"], v["unroll"], v["outputs_per_wave"], v["two_phase"], 0.0)
                                 for k, v in tuning["mixed"]["steps"].items()})
-        re = Runner(tl, props[:chunk], props[:chunk], B.MB_MIXED, sink, kexp[:chunk], err_estimate=True)
+        re = Runner(tl, props[:chunk], props[:chunk], B.MB_MIXED, sink, kexp[:chunk], err_estimate=True,
+                    props_s=None if props_s is None else props_s[:chunk])
         for c in range(nchunk):
             sl = slice(c * chunk, (c + 1) * chunk)
-            re.set_props(props[sl], props[sl], kexp[sl])
+            re.set_props(props[sl], props[sl], kexp[sl], None if props_s is None else props_s[sl])
             corr, _ = re.run()
             torch.cuda.synchronize()
             same = same and bool(np.array_equal(corr.cpu().numpy(), outs["mixed"][sl]))
@@ -313,7 +336,8 @@ def run_workload(name, args):
     # the launch time, against the HBM peak
     hbm_frac = None if traffic is None else traffic / (res["kernel_avg_ms"][dom] / 1e3) / 1e9 / HBM_PEAK_GBS
     bound = "hbm" if hbm_frac is not None and hbm_frac > alu_frac else "alu"
-    roofline = dict(bound=bound, kernel=f"recursion {dom} ({'proton' if counts['path'][s] == 0 else 'neutron'} added)",
+    species = ("proton", "neutron", "Lambda")[counts["path"][s]]
+    roofline = dict(bound=bound, kernel=f"recursion {dom} ({species} added)",
                     achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(alu_frac, 4), traffic=traffic,
                     hbm_frac=None if hbm_frac is None else round(hbm_frac, 4),
@@ -398,15 +422,23 @@ def blocks_roofline(cfg, counts, chunk, ms):
     8 064 for nonrelativistic one-source nuclei).  Bytes: the propagator
     entries the blocks need, (3 D)^2 per source and site (the rows and
     columns of the active spins), each read once.  The bound is the roof
-    with the longer ideal time; both fractions are reported."""
+    with the longer ideal time; both fractions are reported.  With a Lambda
+    its block adds the same contraction over all n_xi^2 ordered (u, d)
+    pairs and their diquarks, and the strange propagator's entries.  Three
+    sources run the site sums on the vector units (bound "alu", the same
+    FP64 peak)."""
     V = cfg["L"] ** 3
     npsi, nxi = counts["n_psi"], counts["n_xi"]
     D = 4 if cfg["rel"] else 2
     npair = nxi * (nxi + 1) // 2
     ncg5 = 4 if cfg["rel"] else 2
     per_site = 8.0 * 3 * npair * (npsi * nxi + 2 * ncg5)
+    nflav = 1
+    if cfg.get("nLam"):
+        per_site += 8.0 * 3 * nxi * nxi * (npsi * nxi + 2 * ncg5)
+        nflav = 2
     flops = chunk * V * per_site
-    nbytes = chunk * V * cfg["nsrc"] * (3 * D) ** 2 * (16 if cfg["c128"] else 8)
+    nbytes = chunk * V * cfg["nsrc"] * (3 * D) ** 2 * (16 if cfg["c128"] else 8) * nflav
     t_mfma, t_hbm = flops / (MFMA_F64_PEAK_TFLOPS * 1e12), nbytes / (HBM_PEAK_GBS * 1e9)
     tflops = flops / (ms / 1e3) / 1e12
     gbs = nbytes / (ms / 1e3) / 1e9
@@ -414,8 +446,8 @@ def blocks_roofline(cfg, counts, chunk, ms):
                mfma_frac=round(tflops / MFMA_F64_PEAK_TFLOPS, 4), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
                ideal_ms_mfma=round(t_mfma * 1e3, 4), ideal_ms_hbm=round(t_hbm * 1e3, 4))
     if t_mfma >= t_hbm:
-        out.update(bound="mfma", achieved=round(tflops, 3), peak=MFMA_F64_PEAK_TFLOPS, unit="TFLOP/s",
-                   frac=out["mfma_frac"])
+        out.update(bound="alu" if cfg["nsrc"] == 3 else "mfma", achieved=round(tflops, 3),
+                   peak=MFMA_F64_PEAK_TFLOPS, unit="TFLOP/s", frac=out["mfma_frac"])
     else:
         out.update(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=out["hbm_frac"])
     return out
@@ -483,7 +515,7 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    names = {"all": ["c3", "c4", "c5", "c2"], "c3+c4": ["c3", "c4"]}.get(args.config, [args.config])
+    names = {"all": ["c3", "c4", "c5", "c2"] + NEXT, "c3+c4": ["c3", "c4"]}.get(args.config, [args.config])
     ws = []
     for n in names:
         ws.append(run_mix(args) if n == "c5" else run_workload(n, args))
@@ -518,8 +550,12 @@ def main():
     line["cpu_baseline"] = cpu
     for k in ("term_list_build_s", "autotune"):
         line[k] = first[k]
-    for key, w in zip(("second_workload", "third_workload", "fourth_workload"), ws[1:]):
+    nxt = [w for n, w in zip(names[1:], ws[1:]) if n in NEXT]
+    for key, w in zip(("second_workload", "third_workload", "fourth_workload"),
+                      [w for n, w in zip(names[1:], ws[1:]) if n not in NEXT]):
         line[key] = summary(w)
+    if nxt:
+        line["next_workloads"] = {w["name"]: summary(w) for w in nxt}
     print(json.dumps(line), flush=True)
 
 

@@ -64,14 +64,17 @@ class Runner:
             torch.cuda.empty_cache()
             self.cws = torch.empty(ncw, dtype=torch.uint8, device=self.blocks.device)
 
-    def set_props(self, props_u, props_d, scale_exp=None):
+    def set_props(self, props_u, props_d, scale_exp=None, props_s=None):
         """Points the problem at other propagators of the same shape."""
         sink_w = self.keep[2]
-        self.keep = (props_u, props_d, sink_w, scale_exp if scale_exp is not None else self.keep[3], self.keep[4])
+        self.keep = (props_u, props_d, sink_w, scale_exp if scale_exp is not None else self.keep[3],
+                     props_s if props_s is not None else self.keep[4])
         self.p.prop_u = props_u.data_ptr()
         self.p.prop_d = props_d.data_ptr()
         if scale_exp is not None:
             self.p.scale_exp = scale_exp.data_ptr()
+        if props_s is not None:
+            self.p.prop_s = props_s.data_ptr()
 
     def run_blocks(self, stream=None):
         B.make_blocks(self.tl, self.p, self.blocks, self.bws, stream)

@@ -194,3 +194,107 @@ def test_8be_two_sources_full_size(oracle_threads):
         assert abs(ref) > 0
         assert abs(res[B.MB_FP64][lane] - ref) <= 1e-12 * abs(ref), lane
         assert abs(res[B.MB_MIXED][lane] - ref) <= 1e-6 * abs(ref), lane
+
+
+def test_5n_three_sources_full_size(oracle_threads):
+    """Five neutrons on three sources at the benchmark's size and launch
+    settings (64 lanes, V = 16^3): the blocks of one lane against the oracle,
+    then the correlator through the three-region factorisation (source s
+    and sink function s on the planes of region s): nn(source 0) x
+    nn(source 1) x n(source 2), each from the oracle, on sampled lanes."""
+    cfg = CONFIGS["n5"]
+    L = cfg["L"]
+    V = L ** 3
+    tl = B.TermList.spin_state(0, 5, False, 3, cfg["spins"])
+    lanes = all_lanes(cfg)
+    props = device_props(cfg, lanes)
+    k = torch.from_numpy(kexp(lanes, cfg["T"])).cuda()
+    w = np.stack([np.ones(V, np.complex128), SP.momentum_phase(L, 1), SP.momentum_phase(L, 2)])
+    r, _ = bench_runner("n5", tl, props, B.MB_FP64, torch.from_numpy(w).cuda(), k)
+    r.run_blocks()
+    torch.cuda.synchronize()
+    lane = 37
+    got_blocks, e = lane_blocks(r, tl, lane)
+    del r
+    S = host_lane(cfg, lane)
+    fP, fN = O.blocks(False, 3, S, S, w, 2.0 ** int(kexp(lanes, cfg["T"])[lane]))
+    ref_blocks = oracle_blocks_lib_layout(fP, fN) * 2.0 ** -e
+    for sp in range(2):
+        assert_close(got_blocks[sp], ref_blocks[sp], 1e-12, ("blocks", lane, sp), significant=BLOCKS_SIGNIFICANT)
+    region = np.minimum(np.arange(V) // (L * L) // 6, 2)
+    reg = torch.from_numpy(region).cuda()
+    wr = w.copy()
+    for s in range(3):
+        props[:, reg != s, s] = 0
+        wr[s, region != s] = 0
+    res, sig = {}, None
+    for prec in (B.MB_FP64, B.MB_MIXED):
+        rr, best = bench_runner("n5", tl, props, prec, torch.from_numpy(wr).cuda(), k)
+        print(f"n5 {'mixed' if prec else 'fp64'} launch settings {best}", flush=True)
+        corr, _ = rr.run()
+        torch.cuda.synchronize()
+        res[prec] = corr.cpu().numpy()[:, 0, 0]
+        if prec == B.MB_MIXED:
+            sig = rr.err[:, 0, 0, 0].cpu().numpy()
+        del rr, corr
+    del props, k, reg
+    torch.cuda.empty_cache()
+    nn, n1 = O.spin_state_request(0, 2, (0, 1)), O.spin_state_request(0, 1, (0,))
+    for lane in (0, 40, 63):
+        S = host_lane(cfg, lane)
+        for s in range(3):
+            S[region != s, s] = 0
+        sc = 2.0 ** int(kexp(lanes, cfg["T"])[lane])
+        c0 = O.correlators(False, 1, 0, 2, nn, S[:, :1], S[:, :1], wr[:1], sc)[((0, 3), (0, 3))]
+        c1 = O.correlators(False, 1, 0, 2, nn, S[:, 1:2], S[:, 1:2], wr[1:2], sc)[((0, 3), (0, 3))]
+        c2 = O.correlators(False, 1, 0, 1, n1, S[:, 2:], S[:, 2:], wr[2:], sc)[((0, 1), (0, 1))]
+        ref = c0 * c1 * c2
+        assert abs(ref) > 0
+        assert abs(res[B.MB_FP64][lane] - ref) <= 1e-12 * abs(ref), lane
+        assert abs(res[B.MB_MIXED][lane] - ref) <= max(1e-6 * abs(ref), 6 * sig[lane]), lane
+
+
+def test_lambda_4he_full_size():
+    """Lambda + 4He (relativistic, spins (0,1,0,1; 0)) at the benchmark's
+    size and launch settings (768 lanes, V = 24^3), with u != d: exchanging
+    the u and d propagators maps the proton operator to minus the
+    neutron's and the Lambda to minus itself at sink and source, so for this
+    spin state (the same indices for protons and neutrons) the correlator
+    is unchanged -- every lane of the timed FP64 path, 1e-12; the mixed path
+    against FP64 element by element (1e-6 or 6 estimated sigma)."""
+    from synth.gpu import fill_props
+
+    from bench import M_DECAY_S
+    cfg = CONFIGS["h5"]
+    V, T = cfg["L"] ** 3, cfg["T"]
+    lanes = all_lanes(cfg)
+    tl = B.TermList.spin_state(2, 2, True, 1, cfg["spins"], n_Lambda=1)
+    P = []
+    for stream, m in ((0, M_DECAY), (2, M_DECAY), (1, M_DECAY_S)):
+        x = torch.empty((lanes, V, 1, 12, 12), dtype=torch.complex64, device="cuda")
+        fill_props(x, seed=SEED, stream_id=stream, V=V, nsrc=1, T=T, first_bt=0, m=m)
+        P.append(x)
+    k = torch.from_numpy(kexp(lanes, T)).cuda()
+    out = {}
+    for prec in (B.MB_FP64, B.MB_MIXED):
+        key = f"h5|{'mixed' if prec == B.MB_MIXED else 'fp64'}|{lanes}"
+        best = autotune.committed(key)
+        got = []
+        for u, d in ((0, 1), (1, 0)):
+            r = Runner(tl, P[u], P[d], prec, None, k, err_estimate=prec == B.MB_MIXED, props_s=P[2])
+            if best is None:
+                best = autotune.tune(tl, r, key=None)
+            else:
+                autotune.apply(tl, best)
+            r.ensure_workspace()
+            corr, _ = r.run()
+            torch.cuda.synchronize()
+            got.append((corr.cpu().numpy(), None if prec == B.MB_FP64 else r.err[..., 0].cpu().numpy()))
+            del r, corr
+        out[prec] = got
+    del P, k
+    torch.cuda.empty_cache()
+    (a, _), (b, _) = out[B.MB_FP64]
+    assert_close(a, b, 1e-12, "h5 u <-> d mirror")
+    (m, sig), _ = out[B.MB_MIXED]
+    assert_close(m, a, 1e-6, "h5 mixed vs fp64", sigma=sig)
