@@ -210,6 +210,7 @@ def run_workload(name, args):
     results = {}
     outs = {}
     tuning = {}
+    applied = {}
     for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
@@ -231,11 +232,13 @@ def run_workload(name, args):
             else:
                 best = autotune.tune(tl, r, key=key, cache=args.tune_cache, log=log)
                 source = "autotuned in this run"
+            applied[prec_name] = best
             tuning[prec_name] = {"source": source, "steps": {
                 str(k): {"kernel": "lds-staged" if v[0] else "direct", "pass_group": v[1],
                          "lds_bytes": v[2], "lane_tile": v[3], "unroll": v[4],
                          "outputs_per_wave": v[5], "two_phase": v[6], "ms_when_tuned": round(v[7], 3)}
-                for k, v in best.items()}}
+                for k, v in best.items() if k > 0},
+                "blocks_kernel": "vector units" if best.get(0, (0,))[0] == 2 else "matrix cores (automatic)"}
         corr_all = torch.empty((lanes,) + tuple(r.corr.shape[1:]), dtype=torch.complex128, device=dev)
         ev = {}
 
@@ -292,11 +295,9 @@ def run_workload(name, args):
         # in the timed launch settings; its correlators must be the timed ones
         sig = torch.empty((lanes,) + tuple(outs["mixed"].shape[1:]), dtype=torch.float64)
         same = True
-        if tuning.get("mixed") is not None and "steps" in tuning["mixed"]:
+        if "mixed" in applied:
             from paper_1301_4895_amd import autotune
-            autotune.apply(tl, {int(k): (0 if v["kernel"] == "direct" else 1, v["pass_group"], v["lds_bytes"],
-                                         v["lane_tile"], v["unroll"], v["outputs_per_wave"], v["two_phase"], 0.0)
-                                for k, v in tuning["mixed"]["steps"].items()})
+            autotune.apply(tl, applied["mixed"])
         re = Runner(tl, props[:chunk], props[:chunk], B.MB_MIXED, sink, kexp[:chunk], err_estimate=True,
                     props_s=None if props_s is None else props_s[:chunk])
         for c in range(nchunk):

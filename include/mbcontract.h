@@ -327,7 +327,7 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
                         size_t *bytes);
 
 /* Launch tuning of recursion step `step` (1..A-1; -1 = every step), chosen by
- * an autotuner; results do not depend on it.
+ * an autotuner; results do not depend on it (up to the order of sums).
  *   MB_TUNE_PASS_GROUP  passthrough spin parts per thread: 0 = automatic
  *                       (3, 2 or 1, the largest that divides their count),
  *                       or 1, 2, 3, 6 (must divide the count; the LDS kernel
@@ -367,6 +367,12 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
  * the direct kernel with one passthrough part per thread and no output
  * grouping: other kernel, passthrough-group or grouping settings there make
  * the contraction return MB_EUNSUPPORTED before any launch.
+ * With step 0 (or -1):
+ *   MB_TUNE_BLOCKS      the site sums of mb_make_blocks: 0 (default) on the
+ *                       matrix cores where the shape has that kernel (every
+ *                       shape up to 12 quark indices), else on the vector
+ *                       units; 1 matrix cores (MB_EUNSUPPORTED beyond 12
+ *                       quark indices); 2 vector units, register-tiled
  * Returns MB_EINVAL for an unknown item, step or value.                      */
 #define MB_TUNE_PASS_GROUP 1
 #define MB_TUNE_LDS_BYTES 2
@@ -376,6 +382,7 @@ int mb_term_list_export(const mb_term_list *tl, int what, int stage, void *buf,
 #define MB_TUNE_GROUP 6
 #define MB_TUNE_PAIRED 7
 #define MB_TUNE_TWO_PHASE 8
+#define MB_TUNE_BLOCKS 9
 int mb_term_list_tune(mb_term_list *tl, int step, int what, int value);
 
 /* Copies the operation tables to device memory `dev` (caller-owned, at least

@@ -76,9 +76,37 @@ def committed(key):
 
 
 def apply(tl, best):
-    """Sets every step's launch settings from a {step: settings} table."""
+    """Sets every step's launch settings from a {step: settings} table
+    (step 0: the blocks kernel, (MB_TUNE_BLOCKS value, ms))."""
+    tl.tune(0, B.MB_TUNE_BLOCKS, int(best[0][0]) if 0 in best else 0)
     for s, v in best.items():
-        _apply(tl, s, *v[:7])
+        if s > 0:
+            _apply(tl, s, *v[:7])
+
+
+def _time_blocks(runner, reps):
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        runner.run_blocks()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return min(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+
+
+def _npass_nsingle(tl, c, s):
+    """Passthrough spin parts of step s (spin parts of the other species)
+    and the added baryon's single-flavour quark count (d of a proton, u of
+    a neutron; a Lambda step has no pair split: 1)."""
+    added = c["path"][s]
+    kP = sum(1 for t in c["path"][:s + 1] if t == 0)
+    kN = sum(1 for t in c["path"][:s + 1] if t == 1)
+    kL = s + 1 - kP - kN
+    k_added = (kP, kN, kL)[added]
+    npass = c["n_spin"][s] // math.comb(_base(tl, added), k_added)
+    nsingle = (kP + 2 * kN + kL) if added == 0 else (2 * kP + kN + kL) if added == 1 else 1
+    return npass, nsingle
 
 
 def _time_step(tl, runner, step, reps, stream):
@@ -115,33 +143,37 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
     free = torch.cuda.mem_get_info()[0] - (8 << 30)
     two_ok = {}
     for s in range(1, c["n_stages"]):
-        kP = sum(1 for t in c["path"][:s + 1] if t == 0)
-        kN = s + 1 - kP
-        nsingle = (kP + 2 * kN) if c["path"][s] == 0 else (2 * kP + kN)
+        nsingle = _npass_nsingle(tl, c, s)[1]
         two_ok[s] = nsingle > 1 and nsingle * c["n_req"][s] * lanes * elem <= free
     for s in range(1, c["n_stages"]):
         tl.tune(s, B.MB_TUNE_TWO_PHASE, int(two_ok[s]))
     runner.ensure_workspace()
     for s in range(1, c["n_stages"]):
         tl.tune(s, B.MB_TUNE_TWO_PHASE, 0)
+    best = {}
+    # the blocks: matrix cores (where the shape has that kernel) or the
+    # register-tiled vector-unit kernel
+    bres = []
+    for kern in ((0, 2) if c["n_xi"] <= 12 else (2,)):
+        tl.tune(0, B.MB_TUNE_BLOCKS, kern)
+        runner.run_blocks()
+        bres.append((_time_blocks(runner, reps), kern))
+    bms, bk = min(bres)
+    tl.tune(0, B.MB_TUNE_BLOCKS, bk)
+    best[0] = (bk, bms)
+    if log:
+        log("[autotune] blocks: " + ", ".join(f"{'vector' if k == 2 else 'matrix'}={m:.3f}ms" for m, k in bres))
     # bring every stage to a valid state once
     runner.run_blocks()
     for s in range(c["n_stages"] + 1):
         B.contract_step(tl, runner.p, runner.blocks, s, runner.corr, runner.exp, runner.cws,
                         stream.cuda_stream)
     torch.cuda.synchronize()
-    best = {}
     for s in range(1, c["n_stages"]):
         # the step reads stage s-1, written by the previous step: rerun it first
         B.contract_step(tl, runner.p, runner.blocks, s - 1, runner.corr, runner.exp, runner.cws,
                         stream.cuda_stream)
-        added = c["path"][s]
-        # passthrough parts of the step: spin parts of the other species
-        kP = sum(1 for t in c["path"][:s + 1] if t == 0)
-        kN = s + 1 - kP
-        other = 1 - added
-        npass = math.comb(_base(tl, other), kN if other == 1 else kP)
-        nsingle = (kP + 2 * kN) if added == 0 else (2 * kP + kN)
+        npass, nsingle = _npass_nsingle(tl, c, s)
         results = []
         for cand in _candidates(npass, nsingle if two_ok[s] else 1):
             _apply(tl, s, *cand)
@@ -168,9 +200,10 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
 
 
 def _base(tl, species):
-    """Size of the sink base set of a species."""
-    d = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+    """Size of the sink base set of a species (0 proton, 1 neutron, 2 Lambda)."""
+    d = (tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)[:, species] if species < 2
+         else tl.export(B.MB_EXPORT_DELTA_L))
     m = 0
-    for v in d[:, species]:
+    for v in d:
         m |= int(v)
     return bin(m).count("1")

@@ -24,6 +24,7 @@ MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUN
     1, 2, 3, 4, 5, 6
 MB_TUNE_PAIRED = 7
 MB_TUNE_TWO_PHASE = 8
+MB_TUNE_BLOCKS = 9
 (MB_EXPORT_QUARK, MB_EXPORT_SPIN, MB_EXPORT_QSPLIT, MB_EXPORT_SSPLIT, MB_EXPORT_COEF,
  MB_EXPORT_DELTA, MB_EXPORT_ALPHA, MB_EXPORT_PROJ, MB_EXPORT_SIDE, MB_EXPORT_QUARK_S, MB_EXPORT_SPIN_L,
  MB_EXPORT_DELTA_L, MB_EXPORT_ALPHA_L) = range(1, 14)

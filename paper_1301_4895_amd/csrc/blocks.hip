@@ -312,132 +312,218 @@ static hipError_t launch_bm(const BlocksArgs &a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// The same site sums on the vector units, for shapes without a matrix-core
-// instantiation (nonrelativistic operators with three sources: 18 quark
-// indices, 6 baryon indices).  A workgroup owns one lane, one chunk of sites
-// and a range of output entries (psi, xi1, pair) of the partial layout; for
-// every site it stages the propagator rows in LDS (in double), forms the
-// diquark of every pair and colour there, and every thread adds the three
-// colour products of its entries.
-constexpr int GEN_THREADS = 256, GEN_EPT = 8;   // entries per thread
-constexpr int GEN_MAXROW = 6, GEN_MAXXI = 18;
+// The same site sums on the vector units, register-tiled.  Per lane and
+// site chunk the blocks are f[r][p] += sum_{x, a} A_x[a][r] B_x[a][p] with
+// r = (psi, xi1) (R rows), p the (xi2, xi3) pairs (P columns, ordered as in
+// the matrix-core kernel), A_x = w S_q1 and B_x the diquark.  A thread owns
+// a tile of TR rows x TP pairs in registers; when the tiles of one lane are
+// fewer than the threads, G groups of threads take G different sites per
+// round and their tiles are added (in group order) at the end.  Per round
+// the workgroup stages the propagator rows of its sites in LDS (in double),
+// forms A and B there, and every thread adds the 3 x TR x TP complex
+// products of its tile: 3 (TR + TP) LDS operands for 3 TR TP fused
+// products.  Shapes: any D and N_s with 3 D N_s <= 18; the matrix-core
+// kernel is the default where it has an instantiation.
+constexpr int VT_THREADS = 256, VT_TR = 4, VT_TP = 4;
 
-template <typename TIN, bool SYM>
-__global__ __launch_bounds__(GEN_THREADS) void blocks_generic_kernel(BlocksArgs a) {
-  __shared__ double2 su[GEN_MAXROW * GEN_MAXXI], sd[GEN_MAXROW * GEN_MAXXI], s1[GEN_MAXROW * GEN_MAXXI];
-  __shared__ double2 dq[3 * GEN_MAXXI * GEN_MAXXI];
-  __shared__ double2 wsh[8];
-  const int tid = threadIdx.x;
-  const int nsrc = a.nsrc, D = a.D, nrow = 3 * D, nxi = 3 * D * nsrc, npsi = D * nsrc;
-  const int npair = SYM ? nxi * (nxi + 1) / 2 : nxi * nxi;
-  const int64_t nent = int64_t(npsi) * nxi * npair;
-  const int64_t ln = blockIdx.y;
-  const int chunk = blockIdx.x;
-  const int64_t e0 = int64_t(blockIdx.z) * GEN_THREADS * GEN_EPT;
-  const int64_t x0 = int64_t(chunk) * a.sites_per_chunk;
-  const int64_t x1 = min(a.V, x0 + a.sites_per_chunk);
-  const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[ln]) : 1.0;
-  const bool same1 = a.prop_q1 == a.prop_u;
-  const double2 *s1_f = (SYM || same1) ? su : s1;
-  const double2 *sd_f = SYM ? su : sd;
+struct VtShape {
+  int nrow, nxi, npsi, nsrc, R, P, Rp, Pp, ntile, tpw, nz, G, spg, nflav, lds_main, lds_red;
+};
 
-  // the entries of this thread: (psi, xi1, pair) and their A-operand rows
-  int e_xi1[GEN_EPT], e_pair[GEN_EPT], e_row0[GEN_EPT], e_sk[GEN_EPT];
-  bool e_ok[GEN_EPT];
-  double2 acc[GEN_EPT];
-#pragma unroll
-  for (int j = 0; j < GEN_EPT; j++) {
-    const int64_t e = e0 + tid + int64_t(j) * GEN_THREADS;
-    e_ok[j] = e < nent;
-    const int64_t ee = e_ok[j] ? e : 0;
-    const int pair = int(ee % npair);
-    const int rest = int(ee / npair);
-    const int xi1 = rest % nxi, psi = rest / nxi;
-    e_xi1[j] = xi1;
-    e_pair[j] = pair;
-    e_row0[j] = 3 * (psi / nsrc);   // row (alpha, colour 0) of the q1 propagator
-    e_sk[j] = psi % nsrc;           // sink function
-    acc[j] = make_double2(0.0, 0.0);
-  }
-  auto ld = [&](const void *base, int64_t x, int r, int xi) {
-    const int s = xi % nsrc, kap = xi / nsrc;
-    const int64_t off = (((ln * a.V + x) * nsrc + s) * 12 + r) * 12 + kap;
-    const TIN v = static_cast<const TIN *>(base)[off];
-    return make_double2(double(v.x) * scale, double(v.y) * scale);
-  };
-  for (int64_t x = x0; x < x1; x++) {
-    __syncthreads();   // the previous site's operands are no longer read
-    for (int i = tid; i < nrow * nxi; i += GEN_THREADS) {
-      const int r = i / nxi, xi = i % nxi;
-      su[i] = ld(a.prop_u, x, r, xi);
-      if (!SYM) {
-        sd[i] = ld(a.prop_d, x, r, xi);
-        if (!same1) s1[i] = ld(a.prop_q1, x, r, xi);
-      }
-    }
-    if (tid < nsrc)
-      wsh[tid] = a.sink_w ? reinterpret_cast<const double2 *>(a.sink_w)[int64_t(tid) * a.V + x] : make_double2(1.0, 0.0);
-    __syncthreads();
-    // diquark D_a[pair] = sum eps_abc (C g5)_{g d} S_u[(g, b), xi2] S_d[(d, c), xi3]
-    // ((C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1)
-    for (int i = tid; i < 3 * npair; i += GEN_THREADS) {
-      const int ac = i / npair, p = i % npair;
-      int x2, x3;
-      if (SYM) {
-        x3 = 0;
-        while ((x3 + 1) * (x3 + 2) / 2 <= p) x3++;
-        x2 = p - x3 * (x3 + 1) / 2;
-      } else {
-        x2 = p / nxi;
-        x3 = p % nxi;
-      }
-      const int bb = (ac + 1) % 3, cc = (ac + 2) % 3;
-      double re = 0.0, im = 0.0;
-      for (int gs = 0; gs < D; gs++) {
-        const double sg = (gs & 1) ? 1.0 : -1.0;
-        const int gd = gs ^ 1;
-        const double2 l0 = su[(3 * gs + bb) * nxi + x2], r0 = sd_f[(3 * gd + cc) * nxi + x3];
-        const double2 l1 = su[(3 * gs + cc) * nxi + x2], r1 = sd_f[(3 * gd + bb) * nxi + x3];
-        re += sg * ((l0.x * r0.x - l0.y * r0.y) - (l1.x * r1.x - l1.y * r1.y));
-        im += sg * ((l0.x * r0.y + l0.y * r0.x) - (l1.x * r1.y + l1.y * r1.x));
-      }
-      dq[i] = make_double2(re, im);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < GEN_EPT; j++) {
-      if (!e_ok[j]) continue;
-      const double2 w = wsh[e_sk[j]];
-#pragma unroll
-      for (int ac = 0; ac < 3; ac++) {
-        const double2 v = s1_f[(e_row0[j] + ac) * nxi + e_xi1[j]];
-        const double2 A = make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
-        const double2 B = dq[ac * npair + e_pair[j]];
-        acc[j].x = fma(A.x, B.x, fma(-A.y, B.y, acc[j].x));
-        acc[j].y = fma(A.x, B.y, fma(A.y, B.x, acc[j].y));
-      }
-    }
-  }
-  double2 *out = reinterpret_cast<double2 *>(a.partial) + (ln * a.nchunk + chunk) * nent;
-#pragma unroll
-  for (int j = 0; j < GEN_EPT; j++)
-    if (e_ok[j]) out[e0 + tid + int64_t(j) * GEN_THREADS] = acc[j];
+static VtShape vt_shape(const BlocksArgs &a, bool sym) {
+  VtShape v{};
+  v.nrow = 3 * a.D;
+  v.nsrc = a.nsrc;
+  v.nxi = 3 * a.D * a.nsrc;
+  v.npsi = a.D * a.nsrc;
+  v.R = v.npsi * v.nxi;
+  v.P = sym ? v.nxi * (v.nxi + 1) / 2 : v.nxi * v.nxi;
+  const int nRT = (v.R + VT_TR - 1) / VT_TR, nPT = (v.P + VT_TP - 1) / VT_TP;
+  v.Rp = nRT * VT_TR;
+  v.Pp = nPT * VT_TP;
+  v.ntile = nRT * nPT;
+  v.tpw = v.ntile < VT_THREADS ? v.ntile : VT_THREADS;
+  v.nz = (v.ntile + v.tpw - 1) / v.tpw;
+  v.G = VT_THREADS / v.tpw;
+  v.spg = 1;                  // sites per group and round
+  v.nflav = sym ? 1 : 3;      // u (= d = q1), or u, d and q1 (q1 staged even when it is u)
+  // per site of a round: propagator rows, sink weights, A, B (double2)
+  v.lds_main = v.G * v.spg * (v.nflav * v.nrow * v.nxi + v.nsrc + 3 * v.Rp + 3 * v.Pp) * 16 + 2 * v.Pp;
+  v.lds_red = v.G > 1 ? v.G * v.tpw * 4 * 16 : 0;
+  return v;
 }
 
 template <typename TIN, bool SYM>
-static hipError_t launch_generic(const BlocksArgs &a, hipStream_t s) {
-  const int nxi = 3 * a.D * a.nsrc, npsi = a.D * a.nsrc;
-  if (3 * a.D > GEN_MAXROW || nxi > GEN_MAXXI || a.nsrc > 8) return hipErrorInvalidValue;
-  const int npair = SYM ? nxi * (nxi + 1) / 2 : nxi * nxi;
-  const int64_t nent = int64_t(npsi) * nxi * npair;
-  const unsigned gz = unsigned((nent + GEN_THREADS * GEN_EPT - 1) / (GEN_THREADS * GEN_EPT));
-  hipLaunchKernelGGL((blocks_generic_kernel<TIN, SYM>), dim3(a.nchunk, unsigned(a.B), gz), dim3(GEN_THREADS), 0, s,
-                     a);
+__global__ __launch_bounds__(VT_THREADS) void blocks_vt_kernel(BlocksArgs a, VtShape v) {
+  extern __shared__ double2 lds[];
+  const int tid = threadIdx.x;
+  const int g = tid / v.tpw, tl = tid % v.tpw;
+  const int tile = int(blockIdx.z) * v.tpw + tl;
+  const bool active = g < v.G && tile < v.ntile;
+  const int nPT = v.Pp / VT_TP;
+  const int r0 = (tile / nPT) * VT_TR, p0 = (tile % nPT) * VT_TP;
+  const int64_t ln = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int64_t x0 = int64_t(chunk) * a.sites_per_chunk;
+  const int64_t x1 = min(a.V, x0 + a.sites_per_chunk);
+  const double scale = a.scale_exp ? ldexp(1.0, a.scale_exp[ln]) : 1.0;
+  const int nrx = v.nrow * v.nxi;
+  const int SR = v.G * v.spg;                                 // sites per round
+  // LDS areas (per site i of the round)
+  double2 *sprop = lds;                                       // [SR][nflav][nrow][nxi]
+  double2 *sw = sprop + SR * v.nflav * nrx;                   // [SR][nsrc]
+  double2 *sA = sw + SR * v.nsrc;                             // [SR][3][Rp]
+  double2 *sB = sA + SR * 3 * v.Rp;                           // [SR][3][Pp]
+  const void *src[3] = {a.prop_u, a.prop_d, a.prop_q1};       // staged flavours: u, d, q1
+  const int fq1 = SYM ? 0 : 2, fu = 0, fd = SYM ? 0 : 1;
+
+  // (x2, x3) of every pair, once per workgroup
+  unsigned char *px = reinterpret_cast<unsigned char *>(sB + SR * 3 * v.Pp);   // [2][Pp]
+  for (int p = tid; p < v.P; p += VT_THREADS) {
+    int x2, x3;
+    if (SYM) {
+      x3 = 0;
+      while ((x3 + 1) * (x3 + 2) / 2 <= p) x3++;
+      x2 = p - x3 * (x3 + 1) / 2;
+    } else {
+      x2 = p / v.nxi;
+      x3 = p % v.nxi;
+    }
+    px[p] = (unsigned char)x2;
+    px[v.Pp + p] = (unsigned char)x3;
+  }
+
+  double2 acc[VT_TR][VT_TP];
+#pragma unroll
+  for (int i = 0; i < VT_TR; i++)
+#pragma unroll
+    for (int j = 0; j < VT_TP; j++) acc[i][j] = make_double2(0.0, 0.0);
+
+  for (int64_t xb = x0; xb < x1; xb += SR) {
+    const int ns = int(min<int64_t>(SR, x1 - xb));   // sites of this round
+    __syncthreads();   // the previous round's operands are no longer read
+    for (int e = tid; e < ns * v.nflav * nrx; e += VT_THREADS) {
+      const int i = e / (v.nflav * nrx), f = (e / nrx) % v.nflav, rx = e % nrx;
+      const int r = rx / v.nxi, xi = rx % v.nxi;
+      const int s = xi % v.nsrc, kap = xi / v.nsrc;
+      const TIN val = static_cast<const TIN *>(src[f])[(((ln * a.V + xb + i) * v.nsrc + s) * 12 + r) * 12 + kap];
+      sprop[e] = make_double2(double(val.x) * scale, double(val.y) * scale);
+    }
+    if (tid < ns * v.nsrc)
+      sw[tid] = a.sink_w ? reinterpret_cast<const double2 *>(a.sink_w)[int64_t(tid % v.nsrc) * a.V + xb + tid / v.nsrc]
+                         : make_double2(1.0, 0.0);
+    __syncthreads();
+    // A[i][c][r] = w_{s'(psi)} S_q1[(alpha(psi), c), xi1]
+    for (int e = tid; e < ns * 3 * v.Rp; e += VT_THREADS) {
+      const int i = e / (3 * v.Rp), c = (e / v.Rp) % 3, r = e % v.Rp;
+      double2 out = make_double2(0.0, 0.0);
+      if (r < v.R) {
+        const int psi = r / v.nxi, xi1 = r % v.nxi;
+        const double2 w = sw[i * v.nsrc + psi % v.nsrc];
+        const double2 q = sprop[(i * v.nflav + fq1) * nrx + (3 * (psi / v.nsrc) + c) * v.nxi + xi1];
+        out = make_double2(w.x * q.x - w.y * q.y, w.x * q.y + w.y * q.x);
+      }
+      sA[e] = out;
+    }
+    // B[i][c][p]: the diquark sum eps_cbd (C g5)_{gamma delta} S_u[(gamma, b), x2]
+    // S_d[(delta, d), x3]  ((C g5): (0,1) -1, (1,0) +1, (2,3) -1, (3,2) +1)
+    for (int e = tid; e < ns * 3 * v.Pp; e += VT_THREADS) {
+      const int i = e / (3 * v.Pp), c = (e / v.Pp) % 3, p = e % v.Pp;
+      double re = 0.0, im = 0.0;
+      if (p < v.P) {
+        const int x2 = px[p], x3 = px[v.Pp + p];
+        const int bb = (c + 1) % 3, cc = (c + 2) % 3;
+        const double2 *su = sprop + (i * v.nflav + fu) * nrx, *sd = sprop + (i * v.nflav + fd) * nrx;
+        for (int gs = 0; gs < a.D; gs++) {
+          const double sg = (gs & 1) ? 1.0 : -1.0;
+          const int gd = gs ^ 1;
+          const double2 l0 = su[(3 * gs + bb) * v.nxi + x2], r0 = sd[(3 * gd + cc) * v.nxi + x3];
+          const double2 l1 = su[(3 * gs + cc) * v.nxi + x2], r1 = sd[(3 * gd + bb) * v.nxi + x3];
+          re += sg * ((l0.x * r0.x - l0.y * r0.y) - (l1.x * r1.x - l1.y * r1.y));
+          im += sg * ((l0.x * r0.y + l0.y * r0.x) - (l1.x * r1.y + l1.y * r1.x));
+        }
+      }
+      sB[e] = make_double2(re, im);
+    }
+    __syncthreads();
+    if (active) {
+      for (int ii = 0; ii < v.spg; ii++) {
+        const int i = g * v.spg + ii;   // this group's sites of the round
+        if (i >= ns) break;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          double2 av[VT_TR], bv[VT_TP];
+#pragma unroll
+          for (int t = 0; t < VT_TR; t++) av[t] = sA[(i * 3 + c) * v.Rp + r0 + t];
+#pragma unroll
+          for (int t = 0; t < VT_TP; t++) bv[t] = sB[(i * 3 + c) * v.Pp + p0 + t];
+#pragma unroll
+          for (int t = 0; t < VT_TR; t++)
+#pragma unroll
+            for (int u = 0; u < VT_TP; u++) {
+              acc[t][u].x = fma(av[t].x, bv[u].x, fma(-av[t].y, bv[u].y, acc[t][u].x));
+              acc[t][u].y = fma(av[t].x, bv[u].y, fma(av[t].y, bv[u].x, acc[t][u].y));
+            }
+        }
+      }
+    }
+  }
+  const int64_t nent = int64_t(v.R) * v.P;
+  double2 *out = reinterpret_cast<double2 *>(a.partial) + (ln * a.nchunk + chunk) * nent;
+  auto store = [&](int i, int j, double2 val) {
+    const int r = r0 + i, p = p0 + j;
+    if (r < v.R && p < v.P) out[int64_t(r) * v.P + p] = val;
+  };
+  if (v.G == 1) {
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < VT_TR; i++)
+#pragma unroll
+        for (int j = 0; j < VT_TP; j++) store(i, j, acc[i][j]);
+    }
+    return;
+  }
+  // add the groups' tiles in group order, four accumulators at a time
+  double2 *red = lds;   // [G][tpw][4]
+#pragma unroll
+  for (int q = 0; q < VT_TR * VT_TP / 4; q++) {
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) red[(g * v.tpw + tl) * 4 + k] = acc[(4 * q + k) / VT_TP][(4 * q + k) % VT_TP];
+    }
+    __syncthreads();
+    if (active && g == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        double2 t = red[tl * 4 + k];
+        for (int h = 1; h < v.G; h++) {
+          const double2 u = red[(h * v.tpw + tl) * 4 + k];
+          t.x += u.x;
+          t.y += u.y;
+        }
+        store((4 * q + k) / VT_TP, (4 * q + k) % VT_TP, t);
+      }
+    }
+  }
+}
+
+template <typename TIN, bool SYM>
+static hipError_t launch_vt(const BlocksArgs &a, hipStream_t s) {
+  const VtShape v = vt_shape(a, SYM);
+  if (v.nxi > 18) return hipErrorInvalidValue;
+  const int lds = v.lds_main > v.lds_red ? v.lds_main : v.lds_red;
+  // one sink weight per thread and round
+  if (lds > 65536 || v.G * v.spg * v.nsrc > VT_THREADS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((blocks_vt_kernel<TIN, SYM>), dim3(a.nchunk, unsigned(a.B), unsigned(v.nz)),
+                     dim3(VT_THREADS), lds, s, a, v);
   return hipGetLastError();
 }
 
 template <typename TIN>
 static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
+  if (a.kernel == 2 || (a.D == 2 && a.nsrc == 3))
+    return sym ? launch_vt<TIN, true>(a, s) : launch_vt<TIN, false>(a, s);
   if (a.D == 4 && a.nsrc == 1)
     return sym ? launch_bm<TIN, 12, 4, 12, true>(a, s) : launch_bm<TIN, 12, 4, 12, false>(a, s);
   // NR, one source: two output tiles (symmetric pairs) or three, so two
@@ -446,8 +532,6 @@ static hipError_t dispatch_bm(const BlocksArgs &a, bool sym, hipStream_t s) {
     return sym ? launch_bm<TIN, 6, 2, 6, true, 2>(a, s) : launch_bm<TIN, 6, 2, 6, false, 2>(a, s);
   if (a.D == 2 && a.nsrc == 2)
     return sym ? launch_bm<TIN, 12, 4, 6, true>(a, s) : launch_bm<TIN, 12, 4, 6, false>(a, s);
-  // nonrelativistic operators with three sources: the vector-unit sums
-  if (a.D == 2 && a.nsrc == 3) return sym ? launch_generic<TIN, true>(a, s) : launch_generic<TIN, false>(a, s);
   return hipErrorInvalidValue;
 }
 

@@ -162,6 +162,7 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   a.nchunk = nchunks_for(p->batch, p->V);
   a.sites_per_chunk = (p->V + a.nchunk - 1) / a.nchunk;
   a.in_c128 = p->in_dtype == MB_C128;
+  a.kernel = tl->blocks_kernel == 2 ? 2 : 0;
   const int npair_n = sym ? tl->nxi * (tl->nxi + 1) / 2 : tl->nxi * tl->nxi;
   const size_t half =
       al256(size_t(a.nchunk) * tl->npsi * tl->nxi * npair_n * 16 * size_t(p->batch));
@@ -327,6 +328,13 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
 
 int mb_term_list_tune(mb_term_list *tl, int step, int what, int value) {
   if (!tl) return fail(MB_EINVAL, "null argument");
+  if (what == MB_TUNE_BLOCKS) {
+    if (step != 0 && step != -1) return fail(MB_EINVAL, "the blocks kernel is set with step 0");
+    if (value < 0 || value > 2) return fail(MB_EINVAL, "blocks kernel must be 0, 1 or 2");
+    if (value == 1 && tl->nxi > 12) return fail(MB_EUNSUPPORTED, "no matrix-core blocks for 18 quark indices");
+    tl->blocks_kernel = value;
+    return MB_OK;
+  }
   if (step != -1 && (step < 1 || step >= tl->nstages)) return fail(MB_EINVAL, "step out of range");
   for (int s = 1; s < tl->nstages; s++) {
     if (step != -1 && s != step) continue;

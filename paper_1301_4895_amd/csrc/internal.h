@@ -75,6 +75,7 @@ struct mb_term_list {
   int path[MB_MAX_STAGES] = {};
   uint32_t SP = 0, SN = 0;                      // sink base sets
   std::vector<std::array<uint32_t, 2>> alphas;   // requested source sets
+  int blocks_kernel = 0;                         // MB_TUNE_BLOCKS: 0 automatic, 1 matrix cores, 2 vector units
   int nLam = 0;                                  // 1: one Lambda, added last
   uint32_t SL = 0;                               // the Lambda's sink base set
   std::vector<uint32_t> alphaL;                  // the Lambda's source set per column

@@ -20,6 +20,7 @@ struct BlocksArgs {
   int64_t B, V;
   int nsrc, D, nchunk, in_c128;
   int64_t sites_per_chunk;
+  int kernel;            // 0 automatic (matrix cores where instantiated), 2 vector units
 };
 hipError_t launch_blocks_partial(const BlocksArgs &a, bool mixed, bool sym, hipStream_t s);
 

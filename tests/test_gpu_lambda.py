@@ -71,13 +71,15 @@ def _oracle(tl, rel, nsrc, nP, nN, Su, Sd, Ss, w, k):
     return np.array([[c[(tuple(map(int, d)), tuple(map(int, a)))] for a in al] for d in dl])
 
 
+@pytest.mark.parametrize("kernel", [0, 2])
 @pytest.mark.parametrize("rel,nsrc", [(False, 1), (True, 1), (False, 2)])
 @pytest.mark.parametrize("same_ud,s_is_u", [(True, False), (False, False), (True, True)])
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
-def test_lambda_block_matches_oracle(rel, nsrc, same_ud, s_is_u, dtype):
+def test_lambda_block_matches_oracle(rel, nsrc, same_ud, s_is_u, dtype, kernel):
     V, nl = 27, 3
     Su, Sd, Ss, w, k = _inputs(61, nl, V, nsrc, dtype, same_ud, s_is_u)
     tl = _tl(rel, nsrc, 0, 1, None)
+    tl.tune(0, B.MB_TUNE_BLOCKS, kernel)
     for prec in (B.MB_FP64, B.MB_MIXED):
         r = _runner(tl, Su, Sd, Ss, w, k, prec)
         r.run_blocks()

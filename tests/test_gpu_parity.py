@@ -98,13 +98,18 @@ def test_device_generator_matches_host():
 
 # --------------------------------------------------------------------- blocks
 
+@pytest.mark.parametrize("kernel", [0, 2])
 @pytest.mark.parametrize("rel,nsrc", [(False, 1), (True, 1), (False, 2), (False, 3)])
 @pytest.mark.parametrize("same_ud", [True, False])
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
-def test_blocks_match_oracle(rel, nsrc, same_ud, dtype):
+def test_blocks_match_oracle(rel, nsrc, same_ud, dtype, kernel):
+    """Blocks of both site-sum kernels (MB_TUNE_BLOCKS 0: matrix cores where
+    the shape has them, 2: register-tiled vector units) against the
+    oracle's."""
     V, nl = 27, 3
     Su, Sd, w, k = _inputs(11, nl, V, nsrc, dtype, same_ud, with_sink=nsrc >= 2 or rel)
     tl = _tl(rel, nsrc, 1, 1, None)
+    tl.tune(0, B.MB_TUNE_BLOCKS, kernel)
     for prec, tol in [(B.MB_FP64, 1e-12), (B.MB_MIXED, 1e-12)]:
         (blocks, e), _, _ = _run(tl, Su, Sd, w, k, prec)
         for b in range(nl):

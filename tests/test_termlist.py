@@ -457,6 +457,22 @@ def test_split_order_single_index_then_pair_rank(nP, nN, rel, nsrc, spins):
             assert list(single[i].reshape(k[0], pp)[:, 0]) == bits
 
 
+def test_blocks_kernel_tuning_validation():
+    tl = B.TermList(1, 1, False, 1, all_components=True)
+    for v in (0, 1, 2):
+        tl.tune(0, B.MB_TUNE_BLOCKS, v)
+        tl.tune(-1, B.MB_TUNE_BLOCKS, v)
+    for step, v in ((1, 0), (0, 3), (0, -1)):
+        with pytest.raises(B.MBError) as e:
+            tl.tune(step, B.MB_TUNE_BLOCKS, v)
+        assert e.value.code == B.MB_EINVAL
+    t3 = B.TermList.spin_state(0, 3, False, 3, (0, 2, 4))
+    t3.tune(0, B.MB_TUNE_BLOCKS, 2)
+    with pytest.raises(B.MBError) as e:   # no matrix-core kernel for 18 quark indices
+        t3.tune(0, B.MB_TUNE_BLOCKS, 1)
+    assert e.value.code == B.MB_EUNSUPPORTED
+
+
 def test_launch_tuning_validation():
     """mb_term_list_tune accepts the documented values and rejects others
     (host only; launch settings never change results, which the GPU tests
