@@ -345,7 +345,7 @@ static VtShape vt_shape(const BlocksArgs &a, bool sym) {
   v.tpw = v.ntile < VT_THREADS ? v.ntile : VT_THREADS;
   v.nz = (v.ntile + v.tpw - 1) / v.tpw;
   v.G = VT_THREADS / v.tpw;
-  v.spg = 1;                  // sites per group and round
+  v.spg = v.G == 1 ? 2 : 1;   // sites per group and round (as VtC)
   v.nflav = sym ? 1 : 3;      // u (= d = q1), or u, d and q1 (q1 staged even when it is u)
   // per site of a round: propagator rows, sink weights, A, B (double2)
   v.lds_main = v.G * v.spg * (v.nflav * v.nrow * v.nxi + v.nsrc + 3 * v.Rp + 3 * v.Pp) * 16 + 2 * v.Pp;
@@ -353,8 +353,22 @@ static VtShape vt_shape(const BlocksArgs &a, bool sym) {
   return v;
 }
 
-template <typename TIN, bool SYM>
-__global__ __launch_bounds__(VT_THREADS) void blocks_vt_kernel(BlocksArgs a, VtShape v) {
+// The shape (D, N_s) is a template parameter, so that every index
+// division below is by a constant.
+template <int D, int NSRC, bool SYM>
+struct VtC {
+  static constexpr int nrow = 3 * D, nxi = 3 * D * NSRC, npsi = D * NSRC, R = npsi * nxi;
+  static constexpr int P = SYM ? nxi * (nxi + 1) / 2 : nxi * nxi;
+  static constexpr int nRT = (R + VT_TR - 1) / VT_TR, nPT = (P + VT_TP - 1) / VT_TP;
+  static constexpr int Rp = nRT * VT_TR, Pp = nPT * VT_TP, ntile = nRT * nPT;
+  static constexpr int tpw = ntile < VT_THREADS ? ntile : VT_THREADS, G = VT_THREADS / tpw;
+  static constexpr int spg = G == 1 ? 2 : 1;   // sites per group and round
+  static constexpr int nflav = SYM ? 1 : 3, nrx = nrow * nxi, SR = G * spg, nsrc = NSRC;
+};
+
+template <typename TIN, bool SYM, int D, int NSRC>
+__global__ __launch_bounds__(VT_THREADS) void blocks_vt_kernel(BlocksArgs a) {
+  constexpr VtC<D, NSRC, SYM> v{};
   extern __shared__ double2 lds[];
   const int tid = threadIdx.x;
   const int g = tid / v.tpw, tl = tid % v.tpw;
@@ -434,7 +448,7 @@ __global__ __launch_bounds__(VT_THREADS) void blocks_vt_kernel(BlocksArgs a, VtS
         const int x2 = px[p], x3 = px[v.Pp + p];
         const int bb = (c + 1) % 3, cc = (c + 2) % 3;
         const double2 *su = sprop + (i * v.nflav + fu) * nrx, *sd = sprop + (i * v.nflav + fd) * nrx;
-        for (int gs = 0; gs < a.D; gs++) {
+        for (int gs = 0; gs < D; gs++) {
           const double sg = (gs & 1) ? 1.0 : -1.0;
           const int gd = gs ^ 1;
           const double2 l0 = su[(3 * gs + bb) * v.nxi + x2], r0 = sd[(3 * gd + cc) * v.nxi + x3];
@@ -508,16 +522,24 @@ __global__ __launch_bounds__(VT_THREADS) void blocks_vt_kernel(BlocksArgs a, VtS
   }
 }
 
-template <typename TIN, bool SYM>
-static hipError_t launch_vt(const BlocksArgs &a, hipStream_t s) {
+template <typename TIN, bool SYM, int D, int NSRC>
+static hipError_t launch_vt_shape(const BlocksArgs &a, hipStream_t s) {
   const VtShape v = vt_shape(a, SYM);
-  if (v.nxi > 18) return hipErrorInvalidValue;
   const int lds = v.lds_main > v.lds_red ? v.lds_main : v.lds_red;
   // one sink weight per thread and round
-  if (lds > 65536 || v.G * v.spg * v.nsrc > VT_THREADS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((blocks_vt_kernel<TIN, SYM>), dim3(a.nchunk, unsigned(a.B), unsigned(v.nz)),
-                     dim3(VT_THREADS), lds, s, a, v);
+  if (lds > 65536 || v.G * v.spg * v.nsrc > VT_THREADS || v.G != VtC<D, NSRC, SYM>::G) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((blocks_vt_kernel<TIN, SYM, D, NSRC>), dim3(a.nchunk, unsigned(a.B), unsigned(v.nz)),
+                     dim3(VT_THREADS), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename TIN, bool SYM>
+static hipError_t launch_vt(const BlocksArgs &a, hipStream_t s) {
+  if (a.D == 2 && a.nsrc == 1) return launch_vt_shape<TIN, SYM, 2, 1>(a, s);
+  if (a.D == 4 && a.nsrc == 1) return launch_vt_shape<TIN, SYM, 4, 1>(a, s);
+  if (a.D == 2 && a.nsrc == 2) return launch_vt_shape<TIN, SYM, 2, 2>(a, s);
+  if (a.D == 2 && a.nsrc == 3) return launch_vt_shape<TIN, SYM, 2, 3>(a, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename TIN>
