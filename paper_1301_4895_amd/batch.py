@@ -21,6 +21,8 @@ class BatchRunner:
     """groups: list of dicts with keys
          tl        uploaded TermList (shared by groups of one nucleus)
          props     device tensor [lanes][V][n_src][12][12] (u = d)
+         props_s   the strange propagator, same layout (term lists with a
+                   Lambda only; optional otherwise)
          sink_w    complex128 [n_src][V] device tensor or None
          scale_exp int32 [lanes] device tensor or None
     After ``launch`` + synchronisation, ``corr[g]`` holds the correlators of
@@ -43,7 +45,8 @@ class BatchRunner:
             for b0 in range(0, lanes, chunk):
                 b1 = min(lanes, b0 + chunk)
                 p = B.problem(b1 - b0, g["props"].shape[1], g["props"][b0:b1], g["props"][b0:b1], precision,
-                              sink, None if g.get("scale_exp") is None else g["scale_exp"][b0:b1])
+                              sink, None if g.get("scale_exp") is None else g["scale_exp"][b0:b1],
+                              None if g.get("props_s") is None else g["props_s"][b0:b1])
                 self.items.append(dict(tl=g["tl"], prob=p, corr=self.corr[-1][b0:b1],
                                        exp=self.exp[-1][b0:b1]))
         self.batch = None

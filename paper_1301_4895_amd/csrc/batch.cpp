@@ -23,12 +23,15 @@ namespace {
 
 // Algorithmic flops of one item: the blocks as a dense contraction over
 // sites (rows psi x xi1, columns the diquark index pairs, 3 colour terms per
-// site) and 8 flops per complex multiply-add of the recursion.
+// site; with a Lambda also its block) and 8 flops per complex multiply-add
+// of the recursion.
 double item_cost(const mb_term_list *tl, const mb_problem *p) {
   const double rows = double(tl->npsi) * tl->nxi;
   const bool sym = p->prop_u == p->prop_d;
   const double pairs = sym ? tl->nxi * (tl->nxi + 1) / 2.0 : double(tl->nxi) * tl->nxi;
-  const double blocks = 8.0 * 3.0 * rows * pairs * double(p->V) * (sym ? 1 : 2);
+  double blocks = 8.0 * 3.0 * rows * pairs * double(p->V) * (sym ? 1 : 2);
+  // the Lambda's block runs over every ordered (u, d) pair
+  if (tl->nLam) blocks += 8.0 * 3.0 * rows * double(tl->nxi) * tl->nxi * double(p->V);
   int64_t nl = 0;
   for (const auto &s : tl->st) nl += s.n_lambda;
   return double(p->batch) * (blocks + 8.0 * double(nl));
@@ -98,6 +101,7 @@ int mb_batch_create(const mb_batch_item *items, int n_items, int n_branches, mb_
     if (rc) return rc;
     if (!it.blocks || !it.blocks_ws || !it.contract_ws || !it.corr_out)
       return fail(MB_EINVAL, "null device buffer in batch item");
+    if (it.tl->nLam && !it.prob.prop_s) return fail(MB_EINVAL, "batch item with a Lambda and no strange propagator");
     if (it.blocks_bytes < bb || it.blocks_ws_bytes < bw || it.contract_ws_bytes < cw)
       return fail(MB_ENOWORKSPACE, "batch item buffer too small");
     const size_t corr_bytes = size_t(it.prob.batch) * size_t(it.tl->st.back().nspin()) *

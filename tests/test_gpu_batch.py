@@ -221,3 +221,78 @@ def test_full_uneven_batch():
             ref = _oracle_lane(grp["tl"], m, S, None, k)
             assert_close(res[B.MB_FP64][g][lane], ref, 1e-12, (grp["name"], lane))
             assert_close(res[B.MB_MIXED][g][lane], ref, 1e-6, (grp["name"], lane), sigma=sig[g][lane])
+
+
+def test_batch_with_a_lambda_and_three_sources():
+    """One graph holding a hypernucleus (Lambda + n, all components), a
+    three-source nucleus (three neutrons, one per source) and p+n: the FP64
+    graph equals the single calls bit for bit and the oracle within 1e-12 on
+    every lane; the mixed graph equals its single calls and FP64 within
+    1e-6 or 6 estimated sigma."""
+    from paper_1301_4895_amd.runner import Runner
+    tl_l = B.TermList(0, 1, False, 1, all_components=True, n_Lambda=1)
+    tl_3 = B.TermList.spin_state(0, 3, False, 3, (0, 2, 4))
+    tl_pn = B.TermList(1, 1, False, 1, all_components=True)
+    specs = [("lambda", tl_l, 27, 1, 21), ("three", tl_3, 8, 3, 9), ("pn", tl_pn, 27, 1, 12)]
+    groups = []
+    rng = np.random.default_rng(3)
+    for gi, (name, tl, V, nsrc, lanes) in enumerate(specs):
+        tl.upload(DEV)
+        S = SP.props(91, 60 + gi, 1, lanes, V, nsrc, M_DECAY, np.complex128)[0]
+        Ss = SP.props(91, 70 + gi, 1, lanes, V, nsrc, 0.6, np.complex128)[0] if name == "lambda" else None
+        w = (rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))) if nsrc > 1 else None
+        k = np.array([int(math.floor(M_DECAY * t_ / math.log(2.0) + 0.5)) for t_ in range(lanes)], np.int32)
+        groups.append(dict(name=name, tl=tl, props=torch.from_numpy(S).to(DEV),
+                           props_s=None if Ss is None else torch.from_numpy(Ss).to(DEV),
+                           sink_w=None if w is None else torch.from_numpy(w).to(DEV),
+                           scale_exp=torch.from_numpy(k).to(DEV), host=S, host_s=Ss, w=w, k=k, nsrc=nsrc))
+    res = {}
+    for prec in (B.MB_FP64, B.MB_MIXED):
+        br = BatchRunner(groups, prec, n_branches=2, chunk=16)
+        br.launch()
+        torch.cuda.synchronize()
+        graph = [c.cpu().numpy() for c in br.corr]
+        for c in br.corr:
+            c.zero_()
+        br.run_eager()
+        torch.cuda.synchronize()
+        for g, c in enumerate(br.corr):
+            assert np.array_equal(c.cpu().numpy(), graph[g]), (prec, groups[g]["name"])
+        res[prec] = graph
+        br.batch.close()
+        del br
+        torch.cuda.empty_cache()
+    for gi, g in enumerate(groups):
+        sig = []
+        for b0 in range(0, g["props"].shape[0], 16):
+            b1 = min(g["props"].shape[0], b0 + 16)
+            r = Runner(g["tl"], g["props"][b0:b1], g["props"][b0:b1], B.MB_MIXED, g["sink_w"],
+                       g["scale_exp"][b0:b1], err_estimate=True,
+                       props_s=None if g["props_s"] is None else g["props_s"][b0:b1])
+            r.run()
+            torch.cuda.synchronize()
+            sig.append(r.err[..., 0].cpu().numpy())
+            del r
+        assert_close(res[B.MB_MIXED][gi], res[B.MB_FP64][gi], 1e-6, g["name"], sigma=np.concatenate(sig))
+    O.set_threads(8)
+    for gi, g in enumerate(groups):
+        tl = g["tl"]
+        d2 = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+        a2 = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
+        for lane in range(g["props"].shape[0]):
+            sc = 2.0 ** int(g["k"][lane])
+            if g["name"] == "lambda":
+                dl = np.concatenate([d2, tl.export(B.MB_EXPORT_DELTA_L)[:, None]], 1)
+                al = np.concatenate([a2, tl.export(B.MB_EXPORT_ALPHA_L)[:, None]], 1)
+                req = O.hyperon_request_all(0, 1, 2, 1)
+                Cd = O.hyperon_correlators(False, 1, 0, 1, req, g["host"][lane], g["host"][lane],
+                                           g["host_s"][lane], None, sc)
+            else:
+                dl, al = d2, a2
+                nP = 1 if g["name"] == "pn" else 0
+                nN = 1 if g["name"] == "pn" else 3
+                req = dict(sinkP=int(np.bitwise_or.reduce(d2[:, 0])), sinkN=int(np.bitwise_or.reduce(d2[:, 1])),
+                           alphas=[tuple(map(int, a)) for a in a2])
+                Cd = O.correlators(False, g["nsrc"], nP, nN, req, g["host"][lane], g["host"][lane], g["w"], sc)
+            ref = np.array([[Cd[(tuple(map(int, d)), tuple(map(int, a)))] for a in al] for d in dl])
+            assert_close(res[B.MB_FP64][gi][lane], ref, 1e-12, (g["name"], lane))
