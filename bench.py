@@ -56,6 +56,22 @@ MIX_TYPES = [
 ]
 MIX_SEED, MIX_N, MIX_STREAM0 = 2013, 64, 1000
 
+# library precision modes: tuning-table labels and the storage they stand for
+TUNE_LABEL = {0: "fp64", 1: "mixed", 2: "mixed-f32b"}
+STORAGE = {0: "f64", 1: "f32 stages, f64 blocks", 2: "f32 stages, f32 block copies for the steps, f64 blocks"}
+
+
+def mixed_precision(tl, args):
+    """MB_MIXED_F32B unless asked otherwise or a species has more than four
+    sink indices (no float-block step kernels there): then MB_MIXED."""
+    from paper_1301_4895_amd import autotune
+    from paper_1301_4895_amd import binding as B
+    if args.mixed_storage == "f32":
+        return B.MB_MIXED
+    c = tl.counts()
+    species = (0, 1, 2) if c.get("n_Lambda") else (0, 1)
+    return B.MB_MIXED if max(autotune._base(tl, sp) for sp in species) > 4 else B.MB_MIXED_F32B
+
 
 def mix_groups(dev, types=None, n=MIX_N, seed=MIX_SEED):
     """Groups (nucleus, L) of the uneven batch with device propagators; the
@@ -211,18 +227,18 @@ def run_workload(name, args):
     outs = {}
     tuning = {}
     applied = {}
-    for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
+    mixed = mixed_precision(tl, args)
+    for prec_name, prec in [("mixed", mixed), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
         r = Runner(tl, props[:chunk], props[:chunk], prec, sink, kexp[:chunk],
                    props_s=None if props_s is None else props_s[:chunk])
         tuning[prec_name] = None
         from paper_1301_4895_amd import autotune
-        if name in NEXT and autotune.committed(f"{name}|{prec_name}|{chunk}") is None and not args.retune:
+        key = f"{name}|{TUNE_LABEL[prec]}|{chunk}"
+        if name in NEXT and autotune.committed(key) is None and not args.retune:
             tuning[prec_name] = {"source": "library defaults (not tuned)"}
         elif not args.no_autotune:
-            from paper_1301_4895_amd import autotune
-            key = f"{name}|{prec_name}|{chunk}"
             best = None if args.retune else autotune.committed(key)
             source = "committed (paper_1301_4895_amd/tuned.json)"
             if best is not None:
@@ -298,7 +314,7 @@ def run_workload(name, args):
         if "mixed" in applied:
             from paper_1301_4895_amd import autotune
             autotune.apply(tl, applied["mixed"])
-        re = Runner(tl, props[:chunk], props[:chunk], B.MB_MIXED, sink, kexp[:chunk], err_estimate=True,
+        re = Runner(tl, props[:chunk], props[:chunk], mixed, sink, kexp[:chunk], err_estimate=True,
                     props_s=None if props_s is None else props_s[:chunk])
         for c in range(nchunk):
             sl = slice(c * chunk, (c + 1) * chunk)
@@ -350,7 +366,8 @@ def run_workload(name, args):
     roofline["blocks"] = blocks_roofline(cfg, counts, chunk, res["kernel_avg_ms"]["blocks"])
 
     return dict(name=name, cfg=cfg, lanes=lanes, V=V, counts=counts, chunk=chunk, results=results,
-                main=main_name, err=err, err_stats=err_stats, roofline=roofline, tuning=tuning, t_list=t_list)
+                main=main_name, err=err, err_stats=err_stats, roofline=roofline, tuning=tuning, t_list=t_list,
+                storage=STORAGE[mixed if main_name == "mixed" else B.MB_FP64])
 
 
 def run_mix(args):
@@ -368,7 +385,8 @@ def run_mix(args):
     log(f"[bench] mix: {len(probs)} problems, {len(groups)} groups, {lanes} lanes, "
         f"{sum(g['props'].numel() * 8 for g in groups) / 1e9:.1f} GB of propagators ({time.time() - t0:.1f}s)")
     results, outs, tuning = {}, {}, {}
-    for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
+    mixed = B.MB_MIXED_F32B if args.mixed_storage == "f32b" else B.MB_MIXED
+    for prec_name, prec in [("mixed", mixed), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
         sources = None
@@ -410,7 +428,7 @@ def run_mix(args):
                         f"complex64, one graph launch")
     return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=c5_chunk,
                 results=results, main=main_name, err=err, err_stats=err_stats, roofline=None, tuning=tuning,
-                t_list=0.0)
+                t_list=0.0, storage=STORAGE[mixed if main_name == "mixed" else B.MB_FP64])
 
 
 def blocks_roofline(cfg, counts, chunk, ms):
@@ -461,7 +479,8 @@ def summary(w):
         "value": round(res["value"], 2),
         "ms_per_step": round(res["ms_per_step"], 3),
         "config": {"workload": w["cfg"]["workload"], "lanes": w["lanes"], "V": w["V"],
-                   "n_lambda": w["counts"]["n_lambda"], "lanes_per_launch": w["chunk"], "precision": w["main"]},
+                   "n_lambda": w["counts"]["n_lambda"], "lanes_per_launch": w["chunk"], "precision": w["main"],
+                   "storage": w["storage"]},
         "fp64": ({"value": round(fp["value"], 2), "ms_per_step": round(fp["ms_per_step"], 3),
                   "speedup_mixed_over_fp64": round(res["value"] / fp["value"], 3)}
                  if fp is not None and w["main"] == "mixed" else None),
@@ -502,6 +521,10 @@ def main():
                     help="lanes per launch (default: every lane of the workload in one launch; batch items of at most 256 lanes for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--mixed-storage", choices=["f32b", "f32"], default="f32b",
+                    help="mixed path: float stages and float block copies for the steps (f32b, where the "
+                         "library has those kernels: at most four sink indices per species), or float "
+                         "stages and double blocks (f32)")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch settings")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every step in this run instead of using the committed settings")
@@ -539,11 +562,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         # both paths multiply and add in double; the mixed path stores the
-        # recursion stages in float
+        # recursion stages (and, by default, the blocks the steps read) in float
         "dtype": "f64",
         "data": "synthetic",
-        "config": dict(first["config"], storage=("f32 stages, f64 blocks" if ws[0]["main"] == "mixed"
-                                                 else "f64")),
+        "config": first["config"],
     }
     for k in ("fp64", "max_rel_err_mixed_vs_fp64", "rel_err_mixed_vs_fp64_per_lane", "kernel_avg_ms",
               "roofline"):

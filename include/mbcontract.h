@@ -76,6 +76,13 @@ extern "C" {
                                   memory traffic of the bandwidth-bound gathers);
                                   blocks stored in double, every product and sum
                                   formed in double                                */
+#define MB_MIXED_F32B 2        /* as MB_MIXED, and the recursion steps read float
+                                  copies of the block entries (rounded once from
+                                  the scaled double blocks); the first stage and
+                                  every product and sum as in MB_MIXED.  Steps
+                                  with more than four sink indices per species
+                                  (three sources) and the LDS-staged step kernel
+                                  are refused (MB_EUNSUPPORTED)                   */
 
 /* A nucleus of n_P protons and n_N neutrons (Sec. 7), and optionally one
  * Lambda hyperon.
@@ -398,7 +405,7 @@ int mb_term_list_upload(mb_term_list *tl, void *dev, size_t bytes, void *stream)
  *              larger sets of lanes are cut into several calls)
  *   V          sink sites per timeslice
  *   in_dtype   MB_C64 or MB_C128, element type of the propagators
- *   precision  MB_FP64 or MB_MIXED
+ *   precision  MB_FP64, MB_MIXED or MB_MIXED_F32B
  *   prop_u, prop_d  device, [B][V][n_src][12][12] complex of in_dtype:
  *              element [b][x][s][row][col] = S(x)[(spin,colour) row at the
  *              sink; source spin-colour col of source s]; prop_d may equal
@@ -441,18 +448,20 @@ int mb_workspace_query(const mb_term_list *tl, const mb_problem *p,
  * for the proton (u,u,d) and neutron (d,u,d), antisymmetrised without
  * normalisation in the two same-flavour slots (Sec. 4), for every lane.
  * The sum over sites runs in double precision and the blocks are stored in
- * double in both precision modes.
+ * double in every precision mode (MB_MIXED_F32B adds float copies).
  * With a Lambda also f_L of (q1, q2, q3) = (s, u, d), which has no two
  * slots of one flavour and is stored as it is.
- * Output layout (complex double in both precision modes): proton block
+ * Output layout (complex double in every precision mode): proton block
  * [block quark index][lane / 16][psi][lane % 16] followed by the neutron
  * block (and the Lambda block, n_xi^3 block quark indices), lanes padded to
- * a multiple of 64, then int32 e[lane] (padded
- * lanes included): the blocks of a lane are stored multiplied by 2^-e[lane]
- * (exact), e chosen so that their largest real or imaginary part lies in
- * [1/2, 1) (e = 0 for an all-zero lane).  Products of many blocks then stay
- * near 1 in float stage storage whatever the size of the propagators; the
- * final sum multiplies by 2^(A e).                                          */
+ * a multiple of 64, then int32 e[lane] (padded lanes included): the blocks
+ * of a lane are stored multiplied by 2^-e[lane] (exact), e chosen so that
+ * their largest real or imaginary part lies in [1/2, 1) (e = 0 for an
+ * all-zero lane).  Products of many blocks then stay near 1 in float stage
+ * storage whatever the size of the propagators; the final sum multiplies by
+ * 2^(A e).  With MB_MIXED_F32B the exponents are padded to a multiple of 256
+ * bytes and followed by the scaled block entries again as complex float,
+ * same layout and order, each rounded to nearest.                          */
 int mb_make_blocks(const mb_term_list *tl, const mb_problem *p, void *blocks,
                    size_t blocks_bytes, void *ws, size_t ws_bytes, void *stream);
 
@@ -487,10 +496,12 @@ int mb_make_blocks_noalloc(const mb_term_list *tl, const mb_problem *p, void *bl
  *             correlator of the unscaled propagators is corr_out * 2^-exp_out
  *   err_out   device, double [B][n_out][2] or NULL: for every output of
  *             corr_out (same order, main then side outputs), an a-posteriori
- *             estimate of how far the MB_MIXED result lies from the MB_FP64
- *             result for the same blocks, in the units of corr_out:
+ *             estimate of how far the MB_MIXED (or MB_MIXED_F32B) result
+ *             lies from the MB_FP64 result for the same blocks, in the units
+ *             of corr_out:
  *               [0]  sigma: standard deviation of that difference when the
- *                    rounding errors of the float stage storage are taken as
+ *                    rounding errors of the float stage storage (and of the
+ *                    float block copies with MB_MIXED_F32B) are taken as
  *                    independent (each stored real rounded to nearest, error
  *                    uniform on half an ulp each side), propagated through
  *                    every step of eq. recr_F and the sum of eq. C_final;

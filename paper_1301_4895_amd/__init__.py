@@ -6,9 +6,9 @@ term-list builder and HIP kernels for blocks and the recursion.  This package
 only marshals arguments (``binding``) and allocates device buffers with
 PyTorch (``runner``).
 """
-from .binding import (MB_C64, MB_C128, MB_FP64, MB_MIXED, MBError, TermList, contract_correlator,
+from .binding import (MB_C64, MB_C128, MB_FP64, MB_MIXED, MB_MIXED_F32B, MBError, TermList, contract_correlator,
                       make_blocks, problem, workspace_query)
 from .runner import Runner
 
 __all__ = ["TermList", "Runner", "MBError", "problem", "workspace_query", "make_blocks",
-           "contract_correlator", "MB_FP64", "MB_MIXED", "MB_C64", "MB_C128"]
+           "contract_correlator", "MB_FP64", "MB_MIXED", "MB_MIXED_F32B", "MB_C64", "MB_C128"]

@@ -139,7 +139,7 @@ def tune(tl: B.TermList, runner, key: str | None = None, cache: str | None = Non
     # memory (with a margin); the workspace for the largest of them is
     # allocated once (a reallocation would drop the stages the timed steps read)
     lanes = (runner.batch + 63) // 64 * 64
-    elem = 8 if runner.p.precision == B.MB_MIXED else 16
+    elem = 16 if runner.p.precision == B.MB_FP64 else 8
     free = torch.cuda.mem_get_info()[0] - (8 << 30)
     two_ok = {}
     for s in range(1, c["n_stages"]):

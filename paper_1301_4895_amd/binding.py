@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmbcontract.so")
 MB_OK, MB_EINVAL, MB_EPAULI, MB_EUNSUPPORTED, MB_ENOWORKSPACE, MB_EHIP, MB_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 MB_PATH_AUTO, MB_PATH_PROTONS_FIRST, MB_PATH_NEUTRONS_FIRST, MB_PATH_EXPLICIT, MB_PATH_BEST = 0, 1, 2, 3, 4
 MB_C64, MB_C128 = 0, 1
-MB_FP64, MB_MIXED = 0, 1
+MB_FP64, MB_MIXED, MB_MIXED_F32B = 0, 1, 2
 MB_MAX_STAGES = 16
 MB_TUNE_PASS_GROUP, MB_TUNE_LDS_BYTES, MB_TUNE_LANE_TILE, MB_TUNE_KERNEL, MB_TUNE_UNROLL, MB_TUNE_GROUP = \
     1, 2, 3, 4, 5, 6

@@ -691,6 +691,40 @@ __global__ __launch_bounds__(256) void blocks_scale_kernel(double2 *blk, int32_t
   }
 }
 
+// Float copies of one species' block for the recursion steps (float
+// stages, MB_MIXED_F32B): only the positions of the species' sink base set,
+// two neighbouring positions per lane side by side, so that one 16-byte load
+// of a lane fetches two block entries.  Entry (y, psi_of_pos[2j + h]) of lane
+// b goes to complex float h of float4 ((y * Bp/16 + b/16) * P + j) * 16 + b%16,
+// P = ceil(M / 2) position pairs (the odd tail padded with zeros).  One
+// thread per output float4.
+__global__ __launch_bounds__(256) void blocks_to_f32_kernel(const double2 *in, float4 *out, int64_t n, int64_t Bp,
+                                                            int npsi, int M, PsiPos pos) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int P = (M + 1) / 2;
+  const int l = int(i % 16);
+  const int j = int((i / 16) % P);
+  const int64_t yt = i / (16 * int64_t(P));   // y * Bp/16 + tile
+  const int64_t y = yt / (Bp / 16), t = yt % (Bp / 16);
+  const double2 *row = in + y * npsi * Bp + t * npsi * 16 + l;
+  const double2 a = row[pos.p[2 * j] * 16];
+  const double2 c = 2 * j + 1 < M ? row[pos.p[2 * j + 1] * 16] : make_double2(0.0, 0.0);
+  out[i] = make_float4(float(a.x), float(a.y), float(c.x), float(c.y));
+}
+
+hipError_t launch_blocks_to_f32(const void *blocks, void *out, int64_t rows, int64_t Bp, int npsi, int M,
+                                const int *psi_of_pos, hipStream_t s) {
+  if (M <= 0 || rows <= 0) return hipSuccess;
+  if (M > 8) return hipErrorInvalidValue;
+  PsiPos pos{};
+  for (int d = 0; d < M; d++) pos.p[d] = psi_of_pos[d];
+  const int64_t n = rows * (Bp / 16) * ((M + 1) / 2) * 16;
+  hipLaunchKernelGGL(blocks_to_f32_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const double2 *>(blocks), static_cast<float4 *>(out), n, Bp, npsi, M, pos);
+  return hipGetLastError();
+}
+
 hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s) {
   hipLaunchKernelGGL(blocks_scale_kernel, dim3(unsigned(Bp / 16)), dim3(256), 0, s, static_cast<double2 *>(blocks),
                      lane_exp, Bp, npsi, nyq2);

@@ -36,17 +36,19 @@ int check_problem(const mb_term_list *tl, const mb_problem *p) {
   if (p->batch < 1 || p->V < 1) return fail(MB_EINVAL, "batch and V must be positive");
   if (p->batch > MB_MAX_BATCH) return fail(MB_EUNSUPPORTED, "batch above MB_MAX_BATCH lanes");
   if (p->in_dtype != MB_C64 && p->in_dtype != MB_C128) return fail(MB_EINVAL, "bad in_dtype");
-  if (p->precision != MB_FP64 && p->precision != MB_MIXED) return fail(MB_EINVAL, "bad precision");
+  if (p->precision != MB_FP64 && p->precision != MB_MIXED && p->precision != MB_MIXED_F32B)
+    return fail(MB_EINVAL, "bad precision");
   if (tl->counts_only) return fail(MB_EINVAL, "counts-only term list");
   if (tl->nxi > 18) return fail(MB_EUNSUPPORTED, "blocks support at most 18 quark indices");
   return MB_OK;
 }
 
-size_t elem_bytes(const mb_problem *p) { return p->precision == MB_MIXED ? 8 : 16; }
+size_t elem_bytes(const mb_problem *p) { return p->precision == MB_FP64 ? 16 : 8; }
 
-// Blocks are stored in double in both precision modes (they are small and
-// every block entry enters every component).
-// followed by the per-lane block exponents (int32, padded lanes)
+// Blocks are stored in double in every precision mode (they are small and
+// every block entry enters every component), followed by the per-lane block
+// exponents (int32, padded lanes) and, with MB_MIXED_F32B, float copies of
+// the entries for the recursion steps.
 // Block quark indices of both nucleon blocks, then of the Lambda's (n_xi^3).
 int64_t block_rows(const mb_term_list *tl) {
   const int64_t nyq = int64_t(tl->nxi) * (tl->nxi - 1) / 2 * tl->nxi;
@@ -60,8 +62,25 @@ size_t blocks_entry_bytes(const mb_term_list *tl, const mb_problem *p) {
 uint32_t base_of(const mb_term_list *tl, int type) {
   return type == PROTON ? tl->SP : type == NEUTRON ? tl->SN : tl->SL;
 }
-size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+// Float block copies of MB_MIXED_F32B after the exponents: per species
+// (proton, neutron, Lambda) the positions of its sink base set, two per
+// lane side by side (16 bytes per lane and position pair).
+size_t blocks_f32_offset(const mb_term_list *tl, const mb_problem *p) {
   return blocks_entry_bytes(tl, p) + al256(size_t(lanes_padded(p->batch)) * 4);
+}
+int64_t species_rows(const mb_term_list *tl, int type) {
+  const int64_t nyq = int64_t(tl->nxi) * (tl->nxi - 1) / 2 * tl->nxi;
+  return type == LAMBDA ? (tl->nLam ? int64_t(tl->nxi) * tl->nxi * tl->nxi : 0) : nyq;
+}
+size_t f32_species_bytes(const mb_term_list *tl, const mb_problem *p, int type) {
+  const int npair = (__builtin_popcount(base_of(tl, type)) + 1) / 2;
+  return al256(size_t(species_rows(tl, type)) * size_t(lanes_padded(p->batch)) * size_t(npair) * 16);
+}
+size_t blocks_bytes_of(const mb_term_list *tl, const mb_problem *p) {
+  size_t f32 = 0;
+  if (p->precision == MB_MIXED_F32B)
+    for (int type = PROTON; type <= LAMBDA; type++) f32 += f32_species_bytes(tl, p, type);
+  return blocks_f32_offset(tl, p) + f32;
 }
 
 // Site-chunk partial sums: one set per nucleon block (one with u = d), then
@@ -149,7 +168,7 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   if (ws_bytes < blocks_ws_of(tl, p)) return fail(MB_ENOWORKSPACE, "blocks workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool sym = p->prop_u == p->prop_d;
-  const bool mixed = p->precision == MB_MIXED;
+  const bool mixed = p->precision != MB_FP64;
   BlocksArgs a{};
   a.prop_u = p->prop_u;
   a.prop_d = p->prop_d;
@@ -200,6 +219,19 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
                                                                      blocks_entry_bytes(tl, p)),
                                 f.Bp, tl->npsi, int(block_rows(tl)), s));
+  if (p->precision == MB_MIXED_F32B) {
+    // float copies of the base-set positions of every species, for the steps
+    const char *src = static_cast<const char *>(blocks);
+    char *dst = static_cast<char *>(blocks) + blocks_f32_offset(tl, p);
+    for (int type = PROTON; type <= LAMBDA; type++) {
+      int pos[8];
+      psi_positions(base_of(tl, type), pos);
+      HIP_CHECK(launch_blocks_to_f32(src, dst, species_rows(tl, type), f.Bp, tl->npsi,
+                                     __builtin_popcount(base_of(tl, type)), pos, s));
+      src += size_t(species_rows(tl, type)) * tl->npsi * f.Bp * 16;
+      dst += f32_species_bytes(tl, p, type);
+    }
+  }
   return MB_OK;
 }
 
@@ -409,7 +441,10 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   stage_buffer_sizes(tl, p, &ev, &od);
   const size_t main_ws = ev + od + proj_bytes_of(tl, p) + h_bytes_of(tl, p);
   if (ws_bytes < main_ws) return fail(MB_ENOWORKSPACE, "contraction workspace too small");
-  const bool mixed = p->precision == MB_MIXED;
+  const bool mixed = p->precision != MB_FP64;
+  // steps read float copies of the blocks (stage 0 and the error estimate
+  // read the double entries)
+  const bool fb32 = p->precision == MB_MIXED_F32B;
   // error estimates of the float stages (mixed path only; the FP64 path
   // reports 0): two error stages and the projected partials after the stages
   const bool err_stages = err_out && mixed;
@@ -424,6 +459,9 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
   const char *blk = static_cast<const char *>(blocks);
   // proton, neutron, Lambda
   const void *fblk[3] = {blk, blk + size_t(tl->npsi) * nyq * Bp * 16, blk + size_t(tl->npsi) * 2 * nyq * Bp * 16};
+  const char *blk32 = blk + blocks_f32_offset(tl, p);
+  const void *fblk32[3] = {blk32, blk32 + f32_species_bytes(tl, p, PROTON),
+                           blk32 + f32_species_bytes(tl, p, PROTON) + f32_species_bytes(tl, p, NEUTRON)};
   char *buf[2] = {static_cast<char *>(ws), static_cast<char *>(ws) + ev};
   char *hbuf = static_cast<char *>(ws) + ev + od + proj_bytes_of(tl, p);   // two-phase partials
   size_t eev = 0, eod = 0;
@@ -539,7 +577,8 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         StageArgs a{};
         a.Fin = buf[(step - 1) % 2];
         a.Fout = buf[step % 2];
-        a.fblk = fblk[S.type];
+        a.fblk = fb32 ? fblk32[S.type] : fblk[S.type];
+        a.fb32 = fb32;
         a.qsplit = reinterpret_cast<const uint32_t *>(img + tl->off_qsplit[step]);
         a.nq_out = int64_t(S.quark.size());
         a.Bp = Bp;
@@ -576,6 +615,9 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         }
         psi_positions(base_of(tl, S.type), a.psi_of_pos);
         if (a.M > 6) return fail(MB_EUNSUPPORTED, "more than 6 sink indices per species");
+        if (a.nq_out > 0 && fb32 && (S.tune_kernel == 1 || a.M > 4))
+          return fail(MB_EUNSUPPORTED,
+                      "float block copies: the direct or grouped step kernel with at most four sink indices");
         if (a.nq_out > 0 && S.tune_kernel == 1) {
           // the LDS-staged kernel holds one range of at most 36 pair rows:
           // n_xi <= 12 (one source relativistic, up to two nonrelativistic)
@@ -629,7 +671,12 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
             e.Ein = ebuf[(step - 1) % 2];
             e.Eout = ebuf[step % 2];
             e.F = a.Fout;
-            e.fblk = a.fblk;
+            e.fblk = fblk[S.type];
+            if (fb32) {
+              e.fb32 = 1;
+              e.Fprev = a.Fin;
+              e.paired_prev = a.paired_in != 0;
+            }
             e.qsplit = a.qsplit;
             e.nq_out = a.nq_out;
             e.Bp = Bp;
@@ -700,7 +747,7 @@ int mb_workspace_query_err(const mb_term_list *tl, const mb_problem *p, size_t *
   int rc = check_problem(tl, p);
   if (rc) return rc;
   if (!err_ws_bytes) return fail(MB_EINVAL, "null argument");
-  *err_ws_bytes = p->precision == MB_MIXED ? err_bytes_of(tl, p) : 0;
+  *err_ws_bytes = p->precision != MB_FP64 ? err_bytes_of(tl, p) : 0;
   return MB_OK;
 }
 

@@ -1,7 +1,8 @@
 // Recursion steps of eq. recr_F (first stage, final contraction with L of
 // eq. C_final, and the dispatch of the step kernels by storage type); the
 // step kernels themselves are in contract_impl.h, instantiated for float
-// stages in contract_f32.hip and for double stages in contract_f64.hip.
+// stages in contract_f32.hip (float blocks: contract_f32b.hip) and for double
+// stages in contract_f64.hip.
 #include <hip/hip_runtime.h>
 
 #include "contract_impl.h"
@@ -9,12 +10,14 @@
 namespace mb {
 
 hipError_t launch_stage_f32(const StageArgs &a, hipStream_t s);
+hipError_t launch_stage_f32b(const StageArgs &a, hipStream_t s);
 hipError_t launch_stage_f64(const StageArgs &a, hipStream_t s);
 hipError_t launch_stage_lds_f32(const StageLdsArgs &a, hipStream_t s);
 hipError_t launch_stage_lds_f64(const StageLdsArgs &a, hipStream_t s);
 
 hipError_t launch_stage(const StageArgs &a, bool mixed, hipStream_t s) {
-  return mixed ? launch_stage_f32(a, s) : launch_stage_f64(a, s);
+  if (!mixed) return launch_stage_f64(a, s);
+  return a.fb32 ? launch_stage_f32b(a, s) : launch_stage_f32(a, s);
 }
 
 hipError_t launch_stage_sum(const StageSumArgs &a, bool mixed, hipStream_t s) {

@@ -4,6 +4,6 @@
 
 namespace mb {
 
-hipError_t launch_stage_f32_m6(const StageArgs &a, hipStream_t s) { return launch_stage_t<float, 5, 6>(a, s); }
+hipError_t launch_stage_f32_m6(const StageArgs &a, hipStream_t s) { return launch_stage_t<float, double, 5, 6>(a, s); }
 
 }  // namespace mb

@@ -4,6 +4,6 @@
 
 namespace mb {
 
-hipError_t launch_stage_f64_m6(const StageArgs &a, hipStream_t s) { return launch_stage_t<double, 5, 6>(a, s); }
+hipError_t launch_stage_f64_m6(const StageArgs &a, hipStream_t s) { return launch_stage_t<double, double, 5, 6>(a, s); }
 
 }  // namespace mb

@@ -136,9 +136,10 @@ __device__ __forceinline__ TileOut xcd_map() {
 // stage order: a neutron step, or a proton step with one passthrough part).
 // PHA: part A of a two-phase step (work item = one output and one group of
 // pair splits sharing a single index; partial sums to H).
-template <typename TS, int M, int K, int PG, int TILE, int U, bool AP, int PKI, bool PHA>
+template <typename TS, typename TY, int M, int K, int PG, int TILE, int U, bool AP, int PKI, bool PHA>
 __device__ __forceinline__ void stage_body(const StageArgs &a) {
   using CS = typename c2<TS>::type;
+  using CY = typename c2<TY>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   constexpr int SUB = 64 / TILE;   // sub-waves splitting the quark splits
   // Part A with 16-lane tiles: the four sub-waves take four consecutive work
@@ -189,14 +190,19 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
   uint32_t roff[NIN], yoff[M];
 #pragma unroll
   for (int rr = 0; rr < NIN; rr++) roff[rr] = AP ? uint32_t(rr * a.npass + pass0) * ROW : uint32_t(pass0 * NIN + rr) * ROW;
+  // float block copies hold the base-set positions in pairs, 16 bytes per
+  // lane and pair: one load fetches two entries (a 16-lane row segment of a
+  // pair is 256 bytes, as one of a double entry)
+  constexpr bool YF = std::is_same<TY, float>::value;
+  constexpr int MP = (M + 1) / 2;
 #pragma unroll
-  for (int d = 0; d < M; d++) yoff[d] = uint32_t(a.psi_of_pos[d]) * 16 * uint32_t(sizeof(double2));
+  for (int d = 0; d < M; d++) yoff[d] = (YF ? uint32_t(d / 2) : uint32_t(a.psi_of_pos[d])) * 256u;
   const uint32_t x_lane = uint32_t(lane_off(b, ns_in)) * uint32_t(sizeof(CS));
   // paired input: the pair (2j, 2j+1) of spin parts of this lane, 16 bytes
   const uint32_t x_lane_pk = uint32_t((b >> 4) * ns_in * 16 + (b & 15) * 2) * uint32_t(sizeof(CS));
-  const uint32_t y_lane = uint32_t(lane_off(b, a.npsi)) * uint32_t(sizeof(double2));
+  const uint32_t y_lane = uint32_t(lane_off(b, YF ? MP : a.npsi)) * 16u;
   const int64_t xstride = int64_t(ns_in) * Bp * int64_t(sizeof(CS));
-  const int64_t ystride = int64_t(a.npsi) * Bp * int64_t(sizeof(double2));
+  const int64_t ystride = int64_t(YF ? MP : a.npsi) * Bp * 16;
 
   double2 acc[PG][NOUT];
 #pragma unroll
@@ -223,7 +229,7 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
   // loads in flight.
   constexpr bool SIGN_ON_X = NIN * PG < M;
   for (int s0 = 0; s0 < nspl; s0 += STEP * U) {
-    double2 fy[U][M];
+    CY fy[U][M];   // block entries as stored; widened to double at the products
     CS xin[U][PG][NIN];
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -231,8 +237,17 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
       const char *yrow = fb + int64_t(e[u].y & 0x7fffffffu) * ystride;
       if constexpr (SUB == 1) {
         // wave-uniform row bases: scalar base plus a 32-bit lane offset
+        if constexpr (YF) {
 #pragma unroll
-        for (int d = 0; d < M; d++) fy[u][d] = ld(reinterpret_cast<const double2 *>(yrow + yoff[d]), y_lane);
+          for (int j = 0; j < MP; j++) {
+            const float4 v = ld(reinterpret_cast<const float4 *>(yrow + yoff[2 * j]), y_lane);
+            fy[u][2 * j] = make_float2(v.x, v.y);
+            if (2 * j + 1 < M) fy[u][2 * j + 1] = make_float2(v.z, v.w);
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < M; d++) fy[u][d] = ld(reinterpret_cast<const CY *>(yrow + yoff[d]), y_lane);
+        }
 #pragma unroll
         for (int rr = 0; rr < NIN; rr++) {
           if constexpr (PKI == 1) {
@@ -263,8 +278,17 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
         // per-lane row bases: one 64-bit pointer per r (and per d), the
         // passthrough parts at immediate offsets from it
         const char *xl = xrow + x_lane, *yl = yrow + y_lane;
+        if constexpr (YF) {
 #pragma unroll
-        for (int d = 0; d < M; d++) fy[u][d] = *reinterpret_cast<const double2 *>(yl + yoff[d]);
+          for (int j = 0; j < MP; j++) {
+            const float4 v = *reinterpret_cast<const float4 *>(yl + yoff[2 * j]);
+            fy[u][2 * j] = make_float2(v.x, v.y);
+            if (2 * j + 1 < M) fy[u][2 * j + 1] = make_float2(v.z, v.w);
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < M; d++) fy[u][d] = *reinterpret_cast<const CY *>(yl + yoff[d]);
+        }
 #pragma unroll
         for (int rr = 0; rr < NIN; rr++) {
           const char *p = xl + roff[rr];
@@ -290,14 +314,17 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
     for (int u = 0; u < U; u++) {
       // the split sign multiplies the smaller operand set; a dropped split
       // adds zeros (its operands are finite values of the last split)
+      double2 fyd[M];
       if constexpr (SIGN_ON_X) {
 #pragma unroll
-        for (int g = 0; g < PG; g++) wedge_accumulate_x<M, K, true>(xin[u][g], fy[u], sgn[u], acc[g]);
+        for (int d = 0; d < M; d++) fyd[d] = make_double2(double(fy[u][d].x), double(fy[u][d].y));
+#pragma unroll
+        for (int g = 0; g < PG; g++) wedge_accumulate_x<M, K, true>(xin[u][g], fyd, sgn[u], acc[g]);
       } else {
 #pragma unroll
-        for (int d = 0; d < M; d++) fy[u][d] = make_double2(sgn[u] * fy[u][d].x, sgn[u] * fy[u][d].y);
+        for (int d = 0; d < M; d++) fyd[d] = make_double2(sgn[u] * double(fy[u][d].x), sgn[u] * double(fy[u][d].y));
 #pragma unroll
-        for (int g = 0; g < PG; g++) wedge_accumulate_x<M, K, false>(xin[u][g], fy[u], 1.0, acc[g]);
+        for (int g = 0; g < PG; g++) wedge_accumulate_x<M, K, false>(xin[u][g], fyd, 1.0, acc[g]);
       }
     }
     if constexpr (SUB == 1) {
@@ -337,10 +364,11 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
     }
 }
 
-// TS: storage type of F (float for MB_MIXED, double for MB_FP64); blocks are
-// stored in double.  Products and sums run in double in both cases: on CDNA4
-// double FMA issues at the rate of single FMA, so only the bandwidth-bound
-// storage is narrowed.  PG passthrough parts share each thread so that the
+// TS: storage type of F (float for the mixed modes, double for MB_FP64); TY:
+// storage type of the block entries the step reads (double, or float for
+// MB_MIXED_F32B, whose float stages read float copies of the blocks).
+// Products and sums run in double in every case: on CDNA4 double FMA issues
+// at the rate of single FMA, so only the bandwidth-bound storage is narrowed.  PG passthrough parts share each thread so that the
 // block entries of a split are loaded once for all of them.
 //
 // A wavefront owns TILE lanes (64 or 16) of one output quark part.  With
@@ -350,13 +378,13 @@ __device__ __forceinline__ void stage_body(const StageArgs &a) {
 // stage), which keeps four times more previous-stage rows in L2.  Which tile
 // is faster depends on the step; the autotuner decides.  The spin layout of
 // the step (added species proton or neutron) selects one of two bodies.
-template <typename TS, int M, int K, int PG, int TILE, int U, int PKI, bool PHA>
+template <typename TS, typename TY, int M, int K, int PG, int TILE, int U, int PKI, bool PHA>
 __global__ __launch_bounds__(64) void stage_kernel(StageArgs a) {
   if constexpr (PKI == 1) {
-    stage_body<TS, M, K, PG, TILE, U, true, 1, PHA>(a);   // launched only for a proton step
+    stage_body<TS, TY, M, K, PG, TILE, U, true, 1, PHA>(a);   // launched only for a proton step
   } else {
-    if (a.act_is_P) stage_body<TS, M, K, PG, TILE, U, true, PKI, PHA>(a);
-    else stage_body<TS, M, K, PG, TILE, U, false, PKI, PHA>(a);
+    if (a.act_is_P) stage_body<TS, TY, M, K, PG, TILE, U, true, PKI, PHA>(a);
+    else stage_body<TS, TY, M, K, PG, TILE, U, false, PKI, PHA>(a);
   }
 }
 
@@ -589,9 +617,10 @@ hipError_t launch_stage_lds_t(const StageLdsArgs &a, hipStream_t s) {
 // differs, and every other distinct row only when it occurs; each output
 // still loads its own previous-stage operands.  Comparisons are on
 // wave-uniform values, so every branch is uniform.
-template <typename TS, int M, int K, int PG, int G, bool PKI>
+template <typename TS, typename TY, int M, int K, int PG, int G, bool PKI>
 __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
   using CS = typename c2<TS>::type;
+  using CY = typename c2<TY>::type;
   constexpr int NIN = binom_c(M, K), NOUT = binom_c(M, K + 1);
   const int64_t ngrp = (a.nq_out + G - 1) / G;
   const int64_t n8 = (ngrp + 7) / 8 * 8;
@@ -606,7 +635,14 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
   auto sig_in = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NIN + r; };
   auto sig_out = [&](int r, int p) { return a.act_is_P ? r * a.npass + p : p * NOUT + r; };
   const CS *Fin = static_cast<const CS *>(a.Fin);
-  const double2 *fb = static_cast<const double2 *>(a.fblk);
+  const CY *fb = static_cast<const CY *>(a.fblk);
+  // float block copies: base-set positions in pairs, one 16-byte load per
+  // lane and pair
+  constexpr bool YF = std::is_same<TY, float>::value;
+  constexpr int MP = (M + 1) / 2;
+  const float4 *fb4 = static_cast<const float4 *>(a.fblk);
+  const uint32_t lane4 = uint32_t(lane_off(b, MP));
+  const int64_t ystride4 = int64_t(MP) * a.Bp;
   const uint2 *qs[G];
 #pragma unroll
   for (int g = 0; g < G; g++) qs[g] = reinterpret_cast<const uint2 *>(a.qsplit) + min(q0 + g, a.nq_out - 1) * a.Sq;
@@ -626,10 +662,25 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
 #pragma unroll
       for (int o = 0; o < NOUT; o++) acc[g][p][o] = make_double2(0.0, 0.0);
 
-  auto load_y = [&](uint32_t yi, double2 *y) {
-    const double2 *yrow = fb + int64_t(yi) * ystride;
+  auto load_y = [&](uint32_t yi, CY *y) {
+    if constexpr (YF) {
+      const float4 *yrow = fb4 + int64_t(yi) * ystride4;
 #pragma unroll
-    for (int d = 0; d < M; d++) y[d] = ld(yrow, f_off[d] * uint32_t(sizeof(double2)));
+      for (int j = 0; j < MP; j++) {
+        const float4 v = ld(yrow, (lane4 + uint32_t(j) * 16u) * 16u);
+        y[2 * j] = make_float2(v.x, v.y);
+        if (2 * j + 1 < M) y[2 * j + 1] = make_float2(v.z, v.w);
+      }
+    } else {
+      const CY *yrow = fb + int64_t(yi) * ystride;
+#pragma unroll
+      for (int d = 0; d < M; d++) y[d] = ld(yrow, f_off[d] * uint32_t(sizeof(CY)));
+    }
+  };
+  // block entries as stored, widened to double for the products
+  auto widen = [&](const CY *y, double2 *w) {
+#pragma unroll
+    for (int d = 0; d < M; d++) w[d] = make_double2(double(y[d].x), double(y[d].y));
   };
   for (int t = 0; t < a.Sq; t++) {
     uint2 e[G];
@@ -669,10 +720,13 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
           }
         }
     }
-    double2 fya[M], fyb[M];
-    load_y(ya, fya);
-    if (yb != ya) load_y(yb, fyb);
+    CY ra[M], rb[M];
+    load_y(ya, ra);
+    if (yb != ya) load_y(yb, rb);
     __builtin_amdgcn_sched_barrier(0);
+    double2 fya[M], fyb[M];
+    widen(ra, fya);
+    if (yb != ya) widen(rb, fyb);
 #pragma unroll
     for (int g = 0; g < G; g++) {
       const uint32_t yg = e[g].y & 0x7fffffffu;
@@ -684,8 +738,10 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
 #pragma unroll
         for (int p = 0; p < PG; p++) wedge_accumulate_x<M, K, true>(xin[g][p], fyb, sgn, acc[g][p]);
       } else {
+        CY rc[M];
         double2 fyc[M];
-        load_y(yg, fyc);
+        load_y(yg, rc);
+        widen(rc, fyc);
 #pragma unroll
         for (int p = 0; p < PG; p++) wedge_accumulate_x<M, K, true>(xin[g][p], fyc, sgn, acc[g][p]);
       }
@@ -707,7 +763,7 @@ __global__ __launch_bounds__(64) void stage_group_kernel(StageArgs a) {
   }
 }
 
-template <typename T, int M, int K, int PG, int G>
+template <typename T, typename TY, int M, int K, int PG, int G>
 static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
   const int64_t ngrp = (a.nq_out + G - 1) / G;
   const int64_t n8 = (ngrp + 7) / 8 * 8;
@@ -718,7 +774,7 @@ static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
     if constexpr (std::is_same<T, float>::value && binom_c(M, K) % 2 == 0) {
       if (a.act_is_P && a.npass != 1) return hipErrorInvalidValue;
       if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
-      hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G, true>), grid, dim3(64), a.lds_bytes, s, a);
+      hipLaunchKernelGGL((stage_group_kernel<T, TY, M, K, PG, G, true>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -726,11 +782,11 @@ static hipError_t launch_stage_group(const StageArgs &a, hipStream_t s) {
   }
   if (a.paired_in) return hipErrorInvalidValue;
   if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
-  hipLaunchKernelGGL((stage_group_kernel<T, M, K, PG, G, false>), grid, dim3(64), a.lds_bytes, s, a);
+  hipLaunchKernelGGL((stage_group_kernel<T, TY, M, K, PG, G, false>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int M, int K, int PG, int TILE, int U, bool PHA>
+template <typename T, typename TY, int M, int K, int PG, int TILE, int U, bool PHA>
 static hipError_t launch_stage_mkptuh(const StageArgs &a, hipStream_t s) {
   constexpr int SUB = 64 / TILE;
   const int64_t nwork = PHA ? (SUB > 1 ? (a.n_items + SUB - 1) / SUB : a.n_items) : a.nq_out;
@@ -744,7 +800,7 @@ static hipError_t launch_stage_mkptuh(const StageArgs &a, hipStream_t s) {
     if constexpr (F32 && TILE == 64 && PG % 2 == 0) {
       if (!a.act_is_P || a.npass % 2) return hipErrorInvalidValue;
       if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
-      hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 1, PHA>), grid, dim3(64), a.lds_bytes, s, a);
+      hipLaunchKernelGGL((stage_kernel<T, TY, M, K, PG, TILE, U, 1, PHA>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -756,74 +812,74 @@ static hipError_t launch_stage_mkptuh(const StageArgs &a, hipStream_t s) {
     if constexpr (F32 && TILE == 64 && binom_c(M, K) % 2 == 0) {
       if (a.act_is_P && a.npass != 1) return hipErrorInvalidValue;
       if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
-      hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 2, PHA>), grid, dim3(64), a.lds_bytes, s, a);
+      hipLaunchKernelGGL((stage_kernel<T, TY, M, K, PG, TILE, U, 2, PHA>), grid, dim3(64), a.lds_bytes, s, a);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
     }
   }
   if (a.dry) return hipSuccess;   // validation pass: this launch exists and fits
-  hipLaunchKernelGGL((stage_kernel<T, M, K, PG, TILE, U, 0, PHA>), grid, dim3(64), a.lds_bytes, s, a);
+  hipLaunchKernelGGL((stage_kernel<T, TY, M, K, PG, TILE, U, 0, PHA>), grid, dim3(64), a.lds_bytes, s, a);
   return hipGetLastError();
 }
 
 // part A of a two-phase step, or the whole step
-template <typename T, int M, int K, int PG, int TILE, int U>
+template <typename T, typename TY, int M, int K, int PG, int TILE, int U>
 static hipError_t launch_stage_mkptu(const StageArgs &a, hipStream_t s) {
-  return a.two_phase ? launch_stage_mkptuh<T, M, K, PG, TILE, U, true>(a, s)
-                     : launch_stage_mkptuh<T, M, K, PG, TILE, U, false>(a, s);
+  return a.two_phase ? launch_stage_mkptuh<T, TY, M, K, PG, TILE, U, true>(a, s)
+                     : launch_stage_mkptuh<T, TY, M, K, PG, TILE, U, false>(a, s);
 }
 
 // splits in flight per wavefront: as tuned, else 2 when the operands of two
 // splits fit in 32 registers
-template <typename T, int M, int K, int PG, int TILE>
+template <typename T, typename TY, int M, int K, int PG, int TILE>
 static hipError_t launch_stage_mkpt(const StageArgs &a, hipStream_t s) {
-  constexpr int VG_SPLIT = binom_c(M, K) * PG * int(sizeof(typename c2<T>::type)) / 4 + 4 * M;
+  constexpr int VG_SPLIT = (binom_c(M, K) * PG * int(sizeof(typename c2<T>::type)) + M * int(sizeof(typename c2<TY>::type))) / 4;
   const int u = a.unroll ? a.unroll : (VG_SPLIT <= 32 ? 2 : 1);
-  return u == 2 ? launch_stage_mkptu<T, M, K, PG, TILE, 2>(a, s) : launch_stage_mkptu<T, M, K, PG, TILE, 1>(a, s);
+  return u == 2 ? launch_stage_mkptu<T, TY, M, K, PG, TILE, 2>(a, s) : launch_stage_mkptu<T, TY, M, K, PG, TILE, 1>(a, s);
 }
 
 // outputs per wavefront (grouped kernel, 64 lanes, passthrough groups up to
 // 3), else lanes per wavefront
-template <typename T, int M, int K, int PG>
+template <typename T, typename TY, int M, int K, int PG>
 static hipError_t launch_stage_mkp(const StageArgs &a, hipStream_t s) {
   if constexpr (PG <= 3) {
     if (a.group == 2 || a.group == 4) {
       if (a.two_phase) return hipErrorInvalidValue;   // two-phase steps use the direct kernel
-      return a.group == 2 ? launch_stage_group<T, M, K, PG, 2>(a, s) : launch_stage_group<T, M, K, PG, 4>(a, s);
+      return a.group == 2 ? launch_stage_group<T, TY, M, K, PG, 2>(a, s) : launch_stage_group<T, TY, M, K, PG, 4>(a, s);
     }
   }
-  return a.tile == 16 ? launch_stage_mkpt<T, M, K, PG, 16>(a, s) : launch_stage_mkpt<T, M, K, PG, 64>(a, s);
+  return a.tile == 16 ? launch_stage_mkpt<T, TY, M, K, PG, 16>(a, s) : launch_stage_mkpt<T, TY, M, K, PG, 64>(a, s);
 }
 
 // passthrough group: as tuned (1, 2, 3 or 6), else 3 if it divides the
 // passthrough count, else 2, else 1
-template <typename T, int M, int K>
+template <typename T, typename TY, int M, int K>
 static hipError_t launch_stage_mk(const StageArgs &a, hipStream_t s) {
   if constexpr (M > 4) {
     // more than four sink indices per species (three sources): one
     // passthrough part per thread and the direct kernel (the wedge alone
     // holds up to C(6,3) = 20 outputs per thread)
     if (a.pg > 1 || a.group > 1) return hipErrorInvalidValue;
-    return a.tile == 16 ? launch_stage_mkpt<T, M, K, 1, 16>(a, s) : launch_stage_mkpt<T, M, K, 1, 64>(a, s);
+    return a.tile == 16 ? launch_stage_mkpt<T, TY, M, K, 1, 16>(a, s) : launch_stage_mkpt<T, TY, M, K, 1, 64>(a, s);
   } else {
-    if (a.pg == 1) return launch_stage_mkp<T, M, K, 1>(a, s);
-    if (a.pg == 2) return launch_stage_mkp<T, M, K, 2>(a, s);
-    if (a.pg == 3) return launch_stage_mkp<T, M, K, 3>(a, s);
-    if (a.pg == 6) return launch_stage_mkp<T, M, K, 6>(a, s);
-    if (a.npass % 3 == 0) return launch_stage_mkp<T, M, K, 3>(a, s);
-    if (a.npass % 2 == 0) return launch_stage_mkp<T, M, K, 2>(a, s);
-    return launch_stage_mkp<T, M, K, 1>(a, s);
+    if (a.pg == 1) return launch_stage_mkp<T, TY, M, K, 1>(a, s);
+    if (a.pg == 2) return launch_stage_mkp<T, TY, M, K, 2>(a, s);
+    if (a.pg == 3) return launch_stage_mkp<T, TY, M, K, 3>(a, s);
+    if (a.pg == 6) return launch_stage_mkp<T, TY, M, K, 6>(a, s);
+    if (a.npass % 3 == 0) return launch_stage_mkp<T, TY, M, K, 3>(a, s);
+    if (a.npass % 2 == 0) return launch_stage_mkp<T, TY, M, K, 2>(a, s);
+    return launch_stage_mkp<T, TY, M, K, 1>(a, s);
   }
 }
 
 // Instantiates the step kernels of the base-set sizes lo <= M <= hi only
 // (the translation units split the instantiations by M).
-template <typename T, int LO, int HI>
+template <typename T, typename TY, int LO, int HI>
 hipError_t launch_stage_t(const StageArgs &a, hipStream_t s) {
 #define MB_CASE(m, k) \
   if constexpr (LO <= m && m <= HI) { \
-    if (a.M == m && a.K == k) return launch_stage_mk<T, m, k>(a, s); \
+    if (a.M == m && a.K == k) return launch_stage_mk<T, TY, m, k>(a, s); \
   }
   MB_CASE(1, 0)
   MB_CASE(2, 0) MB_CASE(2, 1)

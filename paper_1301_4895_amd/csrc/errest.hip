@@ -14,6 +14,12 @@
 //   S  std-dev:  S_{s+1}(z)^2 = sum_splits S_s(x)^2 |f(y)|^2 + u^2 |F~_{s+1}(z)|^2 / 3
 // (the rounding error of one real value is uniform on half an ulp each side,
 // variance <= u^2 x^2 / 3; S treats the rounding errors as independent).
+// With MB_MIXED_F32B a step multiplies float copies f~ = f + d of the block
+// entries (|Re d| <= u |Re f|, |Im d| <= u |Im f|), which adds
+// sum_splits +-F~_s(x) d(y) to D_{s+1}(z): E gains sum_splits u |F~_s(x)| |f(y)|
+// and S^2 gains sum_splits u^2 |F~_s(x)|^2 |f(y)|^2 / 3 (a block entry enters
+// many splits, so S, which takes these errors as independent too, is only an
+// estimate; E stays a first-order bound).
 // The final sum gives, per correlator, E_C = sum |c| E(z) and
 // S_C^2 = sum c^2 S(z)^2, with the normalisation and the lane's block
 // exponent of the correlator itself.  Error stages use the plain stage
@@ -87,6 +93,16 @@ __global__ __launch_bounds__(64) void err_stage_kernel(ErrStageArgs a) {
     double fm[M];
 #pragma unroll
     for (int d = 0; d < M; d++) fm[d] = mag(fb[int64_t(y) * a.npsi * a.Bp + lane_off(b, a.npsi) + a.psi_of_pos[d] * 16]);
+    // float block copies: |F~_s(x)| of the stored previous stage
+    double xm[NIN];
+#pragma unroll
+    for (int r = 0; r < NIN; r++) xm[r] = 0.0;
+    if (a.fb32) {
+      const float2 *Fp = static_cast<const float2 *>(a.Fprev);
+#pragma unroll
+      for (int r = 0; r < NIN; r++)
+        xm[r] = mag(Fp[int64_t(en.x) * ns_in * a.Bp + spin_off(b, ns_in, sig_in(r), a.paired_prev)]);
+    }
 #pragma unroll
     for (int in = 0; in < (1 << M); in++) {
       if (popc_e(in) != K) continue;
@@ -98,6 +114,9 @@ __global__ __launch_bounds__(64) void err_stage_kernel(ErrStageArgs a) {
         e[ro] = fma(double(ein[ri].x), fm[d], e[ro]);
         const double s = double(ein[ri].y) * fm[d];
         v[ro] = fma(s, s, v[ro]);
+        const double t = U_F32 * xm[ri] * fm[d];   // zero unless a.fb32
+        e[ro] += t;
+        v[ro] = fma(t, t / 3.0, v[ro]);
       }
     }
   }

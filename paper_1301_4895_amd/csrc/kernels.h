@@ -41,6 +41,14 @@ hipError_t launch_blocks_finish_lambda(const FinishArgs &a, int nxi, int npsi, i
 // Per-lane block exponents (see blocks_scale_kernel): blocks scaled in place
 // by 2^-lane_exp[b]; nyq2 = block quark indices of all species together.
 hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s);
+// Float copies of one species' block (rows block quark indices, npsi spin
+// indices) for the steps of MB_MIXED_F32B: the M positions psi_of_pos of the
+// species' sink base set, two per lane side by side (blocks_to_f32_kernel).
+struct PsiPos {
+  int p[8];
+};
+hipError_t launch_blocks_to_f32(const void *blocks, void *out, int64_t rows, int64_t Bp, int npsi, int M,
+                                const int *psi_of_pos, hipStream_t s);
 
 // Lane-blocked layouts (lanes grouped in tiles of 16, Bp = padded lanes):
 //   stage   F[q][tile][sigma][16]     index q*ns*Bp + tile*ns*16 + sigma*16 + l
@@ -97,6 +105,7 @@ struct StageArgs {
                              // 2 pairs along the input sets (float stages, 64-lane waves)
   int paired_out;            // output stored in the paired layout (spin_off)
   int dry;                   // validate only: return what the launch would, launch nothing
+  int fb32;                  // fblk holds the paired float copies of the block entries (MB_MIXED_F32B)
   // Two-phase step, part A (two_phase = 1, direct kernel): work item
   // items[i] = q * nsingle + j takes the j-th group of pp pair splits of
   // output q (those with the j-th single index of q) and writes its partial
@@ -188,6 +197,12 @@ struct ErrStageArgs {
   const void *H;             // two-phase step: its float partials (or null)
   int nh;                    // number of partials
   int64_t hstride;           // elements between partials
+  // float block copies (MB_MIXED_F32B): the step multiplied the rounded
+  // entries, so every split adds |F~_{s-1}(x)| u |f(y)|; Fprev is stage s-1
+  // as stored (paired_prev: its layout)
+  int fb32;
+  const void *Fprev;
+  int paired_prev;
 };
 hipError_t launch_err_stage0(const ErrStageArgs &a, hipStream_t s);
 hipError_t launch_err_stage(const ErrStageArgs &a, hipStream_t s);

@@ -9,7 +9,9 @@ The oracle checks sampled lanes one by one:
     the full correlator through the two-source factorisation on disjoint
     regions (a property that holds at any size; the 8Be permutation sum
     itself is beyond the oracle).
-FP64 path: 1e-12 relative; mixed path: 1e-6 relative, element by element.
+FP64 path: 1e-12 relative; mixed paths (float stages with double blocks,
+MB_MIXED, and with float block copies, MB_MIXED_F32B, which the benchmark
+times where the library has its kernels): 1e-6 relative, element by element.
 
 Every run uses the launch settings the benchmark times: the committed table
 paper_1301_4895_amd/tuned.json (or, where it has no entry for the
@@ -23,7 +25,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from bench import CONFIGS, M_DECAY
+from bench import CONFIGS, M_DECAY, TUNE_LABEL
 from oracle import oracle as O
 from paper_1301_4895_amd import autotune
 from paper_1301_4895_amd import binding as B
@@ -78,8 +80,8 @@ def bench_runner(name, tl, props, prec, sink, k):
     (mixed: with the error estimates, which read the stages and leave the
     correlators unchanged)."""
     lanes = props.shape[0]
-    r = Runner(tl, props, props, prec, sink, k, err_estimate=prec == B.MB_MIXED)
-    key = f"{name}|{'mixed' if prec == B.MB_MIXED else 'fp64'}|{lanes}"
+    r = Runner(tl, props, props, prec, sink, k, err_estimate=prec != B.MB_FP64)
+    key = f"{name}|{TUNE_LABEL[prec]}|{lanes}"
     best = autotune.committed(key)
     if best is None:
         best = autotune.tune(tl, r, key=None)
@@ -103,22 +105,25 @@ def test_4he_relativistic_full_size(oracle_threads):
     lanes = all_lanes(cfg)
     props = device_props(cfg, lanes)
     k = torch.from_numpy(kexp(lanes, cfg["T"])).cuda()
-    out = {}
+    out, sig = {}, {}
     check_lanes = (3, 197, 700)
-    for prec in (B.MB_FP64, B.MB_MIXED):
+    mixed = (B.MB_MIXED, B.MB_MIXED_F32B)
+    for prec in (B.MB_FP64,) + mixed:
         r, best = bench_runner("c3", tl, props, prec, None, k)
-        print(f"c3 {'mixed' if prec else 'fp64'} launch settings {best}", flush=True)
+        print(f"c3 {TUNE_LABEL[prec]} launch settings {best}", flush=True)
         corr, _ = r.run()
         torch.cuda.synchronize()
         blocks = {lane: lane_blocks(r, tl, lane) for lane in check_lanes} if prec == B.MB_FP64 else None
-        sig = r.err[..., 0].cpu().numpy() if prec == B.MB_MIXED else None
+        if prec != B.MB_FP64:
+            sig[prec] = r.err[..., 0].cpu().numpy()
         out[prec] = (corr.cpu().numpy(), blocks)
         del r, corr
     # the device buffers go before any check (a failing check keeps this frame)
     del props, k
     torch.cuda.empty_cache()
     # mixed against FP64, every lane, element by element
-    assert_close(out[B.MB_MIXED][0], out[B.MB_FP64][0], 1e-6, "c3 mixed vs fp64", sigma=sig)
+    for prec in mixed:
+        assert_close(out[prec][0], out[B.MB_FP64][0], 1e-6, f"c3 {TUNE_LABEL[prec]} vs fp64", sigma=sig[prec])
     dsets = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
     asets = tl.export(B.MB_EXPORT_ALPHA).reshape(-1, 2)
     pairs = [(i, j) for i in (0, 14, 35) for j in (0, 21)] + [(7, 33), (28, 5)]
@@ -138,7 +143,9 @@ def test_4he_relativistic_full_size(oracle_threads):
             assert abs(ref) > 0
             # the timed instantiations of both paths against the oracle
             assert abs(out[B.MB_FP64][0][lane, i, j] - ref) <= 1e-12 * abs(ref), (lane, i, j)
-            assert abs(out[B.MB_MIXED][0][lane, i, j] - ref) <= max(1e-6 * abs(ref), 6 * sig[lane, i, j]), (lane, i, j)
+            for prec in mixed:
+                assert abs(out[prec][0][lane, i, j] - ref) <= max(1e-6 * abs(ref), 6 * sig[prec][lane, i, j]), \
+                    (prec, lane, i, j)
 
 
 def test_8be_two_sources_full_size(oracle_threads):
@@ -172,9 +179,10 @@ def test_8be_two_sources_full_size(oracle_threads):
     wr[0, x3 >= L // 2] = 0
     wr[1, x3 < L // 2] = 0
     res = {}
-    for prec in (B.MB_FP64, B.MB_MIXED):
+    mixed = (B.MB_MIXED, B.MB_MIXED_F32B)
+    for prec in (B.MB_FP64,) + mixed:
         rr, best = bench_runner("c4", tl, props, prec, torch.from_numpy(wr).cuda(), k)
-        print(f"c4 {'mixed' if prec else 'fp64'} launch settings {best}", flush=True)
+        print(f"c4 {TUNE_LABEL[prec]} launch settings {best}", flush=True)
         corr, _ = rr.run()
         torch.cuda.synchronize()
         res[prec] = corr.cpu().numpy()[:, 0, 0]
@@ -193,7 +201,8 @@ def test_8be_two_sources_full_size(oracle_threads):
         ref = c0 * c1
         assert abs(ref) > 0
         assert abs(res[B.MB_FP64][lane] - ref) <= 1e-12 * abs(ref), lane
-        assert abs(res[B.MB_MIXED][lane] - ref) <= 1e-6 * abs(ref), lane
+        for prec in mixed:
+            assert abs(res[prec][lane] - ref) <= 1e-6 * abs(ref), (prec, lane)
 
 
 def test_5n_three_sources_full_size(oracle_threads):
@@ -276,12 +285,14 @@ def test_lambda_4he_full_size():
         P.append(x)
     k = torch.from_numpy(kexp(lanes, T)).cuda()
     out = {}
-    for prec in (B.MB_FP64, B.MB_MIXED):
-        key = f"h5|{'mixed' if prec == B.MB_MIXED else 'fp64'}|{lanes}"
+    for prec in (B.MB_FP64, B.MB_MIXED, B.MB_MIXED_F32B):
+        key = f"h5|{TUNE_LABEL[prec]}|{lanes}"
         best = autotune.committed(key)
         got = []
         for u, d in ((0, 1), (1, 0)):
-            r = Runner(tl, P[u], P[d], prec, None, k, err_estimate=prec == B.MB_MIXED, props_s=P[2])
+            if prec != B.MB_FP64 and (u, d) == (1, 0):
+                continue   # the mirror is checked on the FP64 path
+            r = Runner(tl, P[u], P[d], prec, None, k, err_estimate=prec != B.MB_FP64, props_s=P[2])
             if best is None:
                 best = autotune.tune(tl, r, key=None)
             else:
@@ -296,5 +307,6 @@ def test_lambda_4he_full_size():
     torch.cuda.empty_cache()
     (a, _), (b, _) = out[B.MB_FP64]
     assert_close(a, b, 1e-12, "h5 u <-> d mirror")
-    (m, sig), _ = out[B.MB_MIXED]
-    assert_close(m, a, 1e-6, "h5 mixed vs fp64", sigma=sig)
+    for prec in (B.MB_MIXED, B.MB_MIXED_F32B):
+        (m, sig), = out[prec]
+        assert_close(m, a, 1e-6, f"h5 {TUNE_LABEL[prec]} vs fp64", sigma=sig)

@@ -324,6 +324,39 @@ def test_device_calls_validate_before_launch():
     assert L.mb_workspace_query(tc.h, C.byref(p), None, None, None) == B.MB_EINVAL
 
 
+def test_float_block_mode_workspace_sizes():
+    """MB_MIXED_F32B: the contraction and error-estimate workspaces of
+    MB_MIXED; the blocks buffer adds, after the exponents padded to 256
+    bytes, the float copies of every species' base-set positions in pairs.
+    Other precision values are refused."""
+    import ctypes as C
+    L = B.lib()
+    for tl, nl in ((lib_termlist(True, 1, 2, 2, None), 70), (lib_termlist(False, 2, 2, 2, None), 8)):
+        c = tl.counts()
+        nxi, npsi = c["n_xi"], c["n_psi"]
+        Bp = (nl + 63) // 64 * 64
+        entries = 2 * (nxi * (nxi - 1) // 2 * nxi) * npsi * Bp * 16
+        q = {prec: B.workspace_query(tl, B.mb_problem(nl, 64, B.MB_C64, prec, 1, 1, None, None))
+             for prec in (B.MB_FP64, B.MB_MIXED, B.MB_MIXED_F32B)}
+        assert q[B.MB_MIXED][0] == q[B.MB_FP64][0] == entries + 4 * Bp
+        dl = tl.export(B.MB_EXPORT_DELTA).reshape(-1, 2)
+        f32 = 0
+        for sp in (0, 1):   # species regions: rows x lanes x position pairs x 16 bytes, padded to 256
+            npair = (bin(int(np.bitwise_or.reduce(dl[:, sp]))).count("1") + 1) // 2
+            f32 += (nxi * (nxi - 1) // 2 * nxi * Bp * npair * 16 + 255) // 256 * 256
+        assert q[B.MB_MIXED_F32B][0] == entries + (4 * Bp + 255) // 256 * 256 + f32
+        assert q[B.MB_MIXED_F32B][1:] == q[B.MB_MIXED][1:]
+        errb = {}
+        for prec in (B.MB_FP64, B.MB_MIXED, B.MB_MIXED_F32B):
+            n = C.c_size_t()
+            p = B.mb_problem(nl, 64, B.MB_C64, prec, 1, 1, None, None)
+            assert L.mb_workspace_query_err(tl.h, C.byref(p), C.byref(n)) == B.MB_OK
+            errb[prec] = n.value
+        assert errb[B.MB_FP64] == 0 and errb[B.MB_MIXED_F32B] == errb[B.MB_MIXED] > 0
+    p = B.mb_problem(8, 64, B.MB_C64, 3, 1, 1, None, None)
+    assert L.mb_workspace_query(tl.h, C.byref(p), None, None, None) == B.MB_EINVAL
+
+
 def test_noalloc_blocks_refuse_problems_beyond_the_scratch():
     """mb_make_blocks_noalloc checks the partial-sum size against its fixed
     scratch before anything touches the device."""
