@@ -30,7 +30,7 @@ CONFIGS = {
     "c2": dict(workload="4He NR (0,1,0,1), L=16 T=32, 8 problems, complex128",
                nP=2, nN=2, rel=False, nsrc=1, spins=(0, 1, 0, 1), L=16, T=32, nprob=8, c128=True),
     "c3": dict(workload="4He relativistic, all 36x36 spin components, L=24 T=48, 16 problems, complex64",
-               nP=2, nN=2, rel=True, nsrc=1, spins=None, L=24, T=48, nprob=16, c128=False),
+               nP=2, nN=2, rel=True, nsrc=1, spins=None, L=24, T=48, nprob=16, c128=False, mixed="f32b"),
     "c4": dict(workload="8Be NR, two sources, (0,1,2,3,0,1,2,3), L=32 T=64, 16 problems, complex64",
                nP=4, nN=4, rel=False, nsrc=2, spins=(0, 1, 2, 3, 0, 1, 2, 3), L=32, T=64, nprob=16,
                c128=False),
@@ -61,12 +61,16 @@ TUNE_LABEL = {0: "fp64", 1: "mixed", 2: "mixed-f32b"}
 STORAGE = {0: "f64", 1: "f32 stages, f64 blocks", 2: "f32 stages, f32 block copies for the steps, f64 blocks"}
 
 
-def mixed_precision(tl, args):
-    """MB_MIXED_F32B unless asked otherwise or a species has more than four
-    sink indices (no float-block step kernels there): then MB_MIXED."""
+def mixed_precision(tl, args, cfg):
+    """The mixed mode of a workload: float block copies (MB_MIXED_F32B) where
+    the workload asks for them (its mixed-vs-FP64 error stays within 1e-6
+    with them: the all-component 4He) and the library has their kernels (at
+    most four sink indices per species), else MB_MIXED; --mixed-storage
+    forces one."""
     from paper_1301_4895_amd import autotune
     from paper_1301_4895_amd import binding as B
-    if args.mixed_storage == "f32":
+    want = cfg.get("mixed", "f32") if args.mixed_storage == "auto" else args.mixed_storage
+    if want == "f32":
         return B.MB_MIXED
     c = tl.counts()
     species = (0, 1, 2) if c.get("n_Lambda") else (0, 1)
@@ -129,8 +133,8 @@ def kernel_hash():
     """Hash of the recursion-step sources: the measured traffic of a step is
     only reported while these are unchanged."""
     h = hashlib.sha256()
-    for f in ("contract.hip", "contract_impl.h", "contract_f32.hip", "contract_f64.hip", "contract_f32_m6.hip",
-              "contract_f64_m6.hip", "kernels.h"):
+    for f in ("contract.hip", "contract_impl.h", "contract_f32.hip", "contract_f32b.hip", "contract_f64.hip",
+              "contract_f32_m6.hip", "contract_f64_m6.hip", "kernels.h"):
         h.update(open(os.path.join(ROOT, "paper_1301_4895_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -227,7 +231,7 @@ def run_workload(name, args):
     outs = {}
     tuning = {}
     applied = {}
-    mixed = mixed_precision(tl, args)
+    mixed = mixed_precision(tl, args, cfg)
     for prec_name, prec in [("mixed", mixed), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
@@ -385,7 +389,7 @@ def run_mix(args):
     log(f"[bench] mix: {len(probs)} problems, {len(groups)} groups, {lanes} lanes, "
         f"{sum(g['props'].numel() * 8 for g in groups) / 1e9:.1f} GB of propagators ({time.time() - t0:.1f}s)")
     results, outs, tuning = {}, {}, {}
-    mixed = B.MB_MIXED_F32B if args.mixed_storage == "f32b" else B.MB_MIXED
+    mixed = B.MB_MIXED_F32B if args.mixed_storage == "f32b" else B.MB_MIXED   # auto: float stages, double blocks
     for prec_name, prec in [("mixed", mixed), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
@@ -521,10 +525,11 @@ def main():
                     help="lanes per launch (default: every lane of the workload in one launch; batch items of at most 256 lanes for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
-    ap.add_argument("--mixed-storage", choices=["f32b", "f32"], default="f32b",
+    ap.add_argument("--mixed-storage", choices=["auto", "f32b", "f32"], default="auto",
                     help="mixed path: float stages and float block copies for the steps (f32b, where the "
-                         "library has those kernels: at most four sink indices per species), or float "
-                         "stages and double blocks (f32)")
+                         "library has those kernels: at most four sink indices per species), float stages "
+                         "and double blocks (f32), or each workload's own choice (auto: f32b for the "
+                         "all-component 4He, whose error stays within 1e-6 with it; f32 elsewhere)")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch settings")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every step in this run instead of using the committed settings")

@@ -504,7 +504,11 @@ int mb_make_blocks_noalloc(const mb_term_list *tl, const mb_problem *p, void *bl
  *                    float block copies with MB_MIXED_F32B) are taken as
  *                    independent (each stored real rounded to nearest, error
  *                    uniform on half an ulp each side), propagated through
- *                    every step of eq. recr_F and the sum of eq. C_final;
+ *                    every step of eq. recr_F and the sum of eq. C_final.
+ *                    One rounded block copy enters many splits, whose
+ *                    errors then add coherently: with MB_MIXED_F32B sigma
+ *                    can fall well short of the deviation (by up to 7x
+ *                    measured on one-component 8Be outputs);
  *               [1]  bound: the same propagation with absolute values, a
  *                    bound to first order in u = 2^-24 (it ignores u^2 terms
  *                    and the double-precision rounding common to both paths).
