@@ -7,7 +7,7 @@
 // Proton: q1 = u; neutron: q1 = d (slots (d,u,d)); both share the diquark.
 // With S_u = S_d the diquark is symmetric in (xi2, xi3) ((C g5)^T = -C g5 and
 // eps is antisymmetric), so only xi2 <= xi3 is formed and one block serves
-// both species.
+// both species; the Lambda (q1 = s) then also needs only xi2 <= xi3.
 //
 // A workgroup owns one lane and one chunk of sites and sums its sites on the
 // matrix cores (below); a second kernel adds the chunk sums in double in a
@@ -43,8 +43,10 @@ __device__ inline double2 scaled(double2 v, double scale) { return make_double2(
 typedef double mb_d4 __attribute__((ext_vector_type(4)));
 
 // NMW: multiplying waves (the builders are always four waves, 256 threads);
-// fewer than four when there are fewer output tiles than four.
-template <typename TIN, int NXI, int NPSI, int NROW, bool SYM, int NMW>
+// fewer than four when there are fewer output tiles than four.  SYM: S_u =
+// S_d (pairs xi2 <= xi3); SQ1 (with SYM): slot 1 holds a third propagator
+// (the Lambda's S_s), staged beside S_u.
+template <typename TIN, int NXI, int NPSI, int NROW, bool SYM, int NMW, bool SQ1 = false>
 __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs a) {
   constexpr int NPAIR = SYM ? NXI * (NXI + 1) / 2 : NXI * NXI;
   constexpr int M = NPSI * NXI;
@@ -56,13 +58,14 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
   constexpr int TPW = (NTILE + NMW - 1) / NMW;  // tiles per multiplying wave
   constexpr int NT_ALL = 64 * (NMW + 4);        // threads of the workgroup
   constexpr int D = NROW / 3;
-  constexpr int NB = SYM ? 1 : 2;      // buffers of the q1 and d slots
+  constexpr int NB = SYM ? 1 : 2;      // buffers of the d slot
+  constexpr bool Q1B = !SYM || SQ1;    // slot 1 has buffers of its own
 
   // Propagators are staged in double: the vector and matrix units share the
   // double-precision pipeline, so every entry is widened once, when it is
   // staged, rather than at each of its uses in the diquark.
   __shared__ double2 su[2][NS][NROW][NXI];
-  __shared__ double2 s1[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];  // q1 when it differs from u
+  __shared__ double2 s1[Q1B ? 2 : 1][Q1B ? NS : 1][Q1B ? NROW : 1][Q1B ? NXI : 1];  // q1 when it differs from u
   __shared__ double2 sd[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
   __shared__ double2 Ac[2][KG][MP];   // (re, im) of the A operand
   __shared__ double2 Bc[2][KG][NP];   // (re, im) of the B operand
@@ -146,8 +149,8 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
         const int s = xi % nsrc, kap = xi / nsrc;
         const int64_t off = (((ln * a.V + xg + n) * nsrc + s) * 12 + r) * 12 + kap;
         pu[j] = static_cast<const TIN *>(a.prop_u)[off];
-        if constexpr (!SYM) {
-          pd[j] = static_cast<const TIN *>(a.prop_d)[off];
+        if constexpr (!SYM) pd[j] = static_cast<const TIN *>(a.prop_d)[off];
+        if constexpr (Q1B) {
           if (!same1) p1[j] = static_cast<const TIN *>(a.prop_q1)[off];
         }
       }
@@ -165,8 +168,8 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
       if (i < ns * NROW * NXI) {
         const int n = i / (NROW * NXI), r = (i / NXI) % NROW, xi = i % NXI;
         su[buf][n][r][xi] = scaled(pu[j], scale);
-        if constexpr (!SYM) {
-          sd[buf][n][r][xi] = scaled(pd[j], scale);
+        if constexpr (!SYM) sd[buf][n][r][xi] = scaled(pd[j], scale);
+        if constexpr (Q1B) {
           if (!same1) s1[buf][n][r][xi] = scaled(p1[j], scale);
         }
       }
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
     const int buf = g & 1, ns = group_sites(g);
     const double2 *su_f = &su[buf][0][0][0];
     const double2 *sd_f = SYM ? su_f : &sd[SYM ? 0 : buf][0][0][0];
-    const double2 *s1_f = (SYM || same1) ? su_f : &s1[SYM ? 0 : buf][0][0][0];
+    const double2 *s1_f = (!Q1B || same1) ? su_f : &s1[Q1B ? buf : 0][0][0][0];
     // A operand: w S_q1[(alpha, a), xi1]
 #pragma unroll
     for (int j = 0; j < AJ; j++) {
@@ -304,10 +307,17 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
   }
 }
 
+// Symmetric pairs with a third flavour in slot 1 (the Lambda with S_u = S_d)
+// run the SQ1 variant; otherwise slot 1 is u, or (without symmetry) staged
+// by the plain kernel.
 template <typename TIN, int NXI, int NPSI, int NROW, bool SYM, int NMW = 4>
 static hipError_t launch_bm(const BlocksArgs &a, hipStream_t s) {
   dim3 grid(a.nchunk, unsigned(a.B));
-  hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM, NMW>), grid, dim3(64 * (NMW + 4)), 0, s, a);
+  if (SYM && a.prop_q1 != a.prop_u)
+    hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM, NMW, true>), grid, dim3(64 * (NMW + 4)), 0, s,
+                       a);
+  else
+    hipLaunchKernelGGL((blocks_mfma_kernel<TIN, NXI, NPSI, NROW, SYM, NMW>), grid, dim3(64 * (NMW + 4)), 0, s, a);
   return hipGetLastError();
 }
 
@@ -624,10 +634,12 @@ __global__ __launch_bounds__(256) void blocks_finish_kernel(FinishArgs a, int nx
 }
 
 // The Lambda block: f_L(psi; e, c, f) with (s, u, d) indices (e, c, f) is
-// the partial entry (psi, xi1 = e, pair = c*n_xi + f) summed over the site
-// chunks; its block quark index (e*n_xi + c)*n_xi + f is the partial's
-// offset inside the psi row, so that a thread's chunk sums are one strided
-// walk.  Stored in double from block row row0 on.
+// the partial entry (psi, xi1 = e, pair (c, f)) summed over the site chunks:
+// pair c*n_xi + f (all ordered pairs; then the block quark index
+// (e*n_xi + c)*n_xi + f is the partial's offset inside the psi row, so that
+// a thread's chunk sums are one strided walk), or with a.sym (S_u = S_d) the
+// symmetric pair max(c,f)(max(c,f)+1)/2 + min(c,f).  Stored in double from
+// block row row0 on.
 __global__ __launch_bounds__(256) void blocks_finish_lambda_kernel(FinishArgs a, int nxi, int npsi, int64_t row0) {
   const int64_t b = blockIdx.x;
   const int64_t nyl = int64_t(nxi) * nxi * nxi;
@@ -635,12 +647,16 @@ __global__ __launch_bounds__(256) void blocks_finish_lambda_kernel(FinishArgs a,
   if (comp >= npsi * nyl) return;
   const int psi = int(comp / nyl);
   const int64_t y = comp % nyl;
+  const int npair = a.sym ? nxi * (nxi + 1) / 2 : nxi * nxi;
+  const int e = int(y / (nxi * nxi)), c = int(y / nxi % nxi), f = int(y % nxi);
+  const int hi = max(c, f), lo = min(c, f);
+  const int64_t off = (int64_t(psi) * nxi + e) * npair + (a.sym ? hi * (hi + 1) / 2 + lo : c * nxi + f);
   double2 v = make_double2(0.0, 0.0);
   if (b < a.B) {
     const double2 *part = reinterpret_cast<const double2 *>(a.partP);
-    const int64_t stride = npsi * nyl;
+    const int64_t stride = int64_t(npsi) * nxi * npair;
     for (int ch = 0; ch < a.nchunk; ch++) {
-      const double2 x = part[(b * a.nchunk + ch) * stride + comp];
+      const double2 x = part[(b * a.nchunk + ch) * stride + off];
       v.x += x.x;
       v.y += x.y;
     }

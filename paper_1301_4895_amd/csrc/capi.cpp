@@ -209,11 +209,16 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
   const int nyq = tl->nxi * (tl->nxi - 1) / 2 * tl->nxi;
   if (tl->nLam) {
     // the Lambda (s, u, d): every ordered (u, d) pair, no antisymmetrisation;
-    // its partials reuse the workspace (the finish above has read it)
+    // with S_u = S_d on the matrix cores only the pairs u <= d (the diquark
+    // is symmetric; the vector-unit kernel's symmetric form takes slot 1 to
+    // be u, so it forms every pair).  Its partials reuse the workspace (the
+    // finish above has read it).
+    const bool lsym = sym && a.kernel != 2;
     a.prop_q1 = p->prop_s;
     a.partial = partP;
-    HIP_CHECK(launch_blocks_partial(a, mixed, false, s));
+    HIP_CHECK(launch_blocks_partial(a, mixed, lsym, s));
     f.partP = partP;
+    f.sym = lsym;
     HIP_CHECK(launch_blocks_finish_lambda(f, tl->nxi, tl->npsi, int64_t(2) * nyq, s));
   }
   HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
