@@ -30,7 +30,7 @@ CONFIGS = {
     "c2": dict(workload="4He NR (0,1,0,1), L=16 T=32, 8 problems, complex128",
                nP=2, nN=2, rel=False, nsrc=1, spins=(0, 1, 0, 1), L=16, T=32, nprob=8, c128=True),
     "c3": dict(workload="4He relativistic, all 36x36 spin components, L=24 T=48, 16 problems, complex64",
-               nP=2, nN=2, rel=True, nsrc=1, spins=None, L=24, T=48, nprob=16, c128=False, mixed="f32b"),
+               nP=2, nN=2, rel=True, nsrc=1, spins=None, L=24, T=48, nprob=16, c128=False),
     "c4": dict(workload="8Be NR, two sources, (0,1,2,3,0,1,2,3), L=32 T=64, 16 problems, complex64",
                nP=4, nN=4, rel=False, nsrc=2, spins=(0, 1, 2, 3, 0, 1, 2, 3), L=32, T=64, nprob=16,
                c128=False),
@@ -62,14 +62,15 @@ STORAGE = {0: "f64", 1: "f32 stages, f64 blocks", 2: "f32 stages, f32 block copi
 
 
 def mixed_precision(tl, args, cfg):
-    """The mixed mode of a workload: float block copies (MB_MIXED_F32B) where
-    the workload asks for them (its mixed-vs-FP64 error stays within 1e-6
-    with them: the all-component 4He) and the library has their kernels (at
-    most four sink indices per species), else MB_MIXED; --mixed-storage
-    forces one."""
+    """The mixed mode of a workload: float block copies (MB_MIXED_F32B) for a
+    list of all spin components (many outputs per lane, whose error stays
+    far below 1e-6 with them) where the library has their kernels (at most
+    four sink indices per species), else MB_MIXED (one spin component: the
+    cancellation in it lifts the coherent rounding of the block copies above
+    1e-6); --mixed-storage forces one."""
     from paper_1301_4895_amd import autotune
     from paper_1301_4895_amd import binding as B
-    want = cfg.get("mixed", "f32") if args.mixed_storage == "auto" else args.mixed_storage
+    want = ("f32b" if cfg["spins"] is None else "f32") if args.mixed_storage == "auto" else args.mixed_storage
     if want == "f32":
         return B.MB_MIXED
     c = tl.counts()
@@ -389,10 +390,13 @@ def run_mix(args):
     log(f"[bench] mix: {len(probs)} problems, {len(groups)} groups, {lanes} lanes, "
         f"{sum(g['props'].numel() * 8 for g in groups) / 1e9:.1f} GB of propagators ({time.time() - t0:.1f}s)")
     results, outs, tuning = {}, {}, {}
-    mixed = B.MB_MIXED_F32B if args.mixed_storage == "f32b" else B.MB_MIXED   # auto: float stages, double blocks
-    for prec_name, prec in [("mixed", mixed), ("fp64", B.MB_FP64)]:
+    for prec_name, prec in [("mixed", B.MB_MIXED), ("fp64", B.MB_FP64)]:
         if args.only and prec_name != args.only:
             continue
+        # every group in the leg's mode; the mixed leg picks per nucleus as
+        # the single workloads do
+        for g in groups:
+            g["precision"] = prec if prec == B.MB_FP64 else mixed_precision(g["tl"], args, MIX_TYPES[g["type"]])
         sources = None
         if not args.no_autotune:
             tuned = tune_nuclei(groups, prec, c5_chunk, cache=args.tune_cache, key="c5", log=log,
@@ -430,9 +434,13 @@ def run_mix(args):
     cfg = dict(workload=f"uneven batch: {len(probs)} problems drawn by seed {MIX_SEED} from "
                         f"{', '.join(m['name'] for m in MIX_TYPES)}; L in {{16,24,32}}, T in {{32,64,96}}; "
                         f"complex64, one graph launch")
+    storage = STORAGE[B.MB_FP64]
+    if main_name == "mixed":
+        storage = "; ".join(f"{m['name']}: {STORAGE[mixed_precision(tls[t], args, m)]}"
+                            for t, m in enumerate(MIX_TYPES) if t in tls)
     return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=c5_chunk,
                 results=results, main=main_name, err=err, err_stats=err_stats, roofline=None, tuning=tuning,
-                t_list=0.0, storage=STORAGE[mixed if main_name == "mixed" else B.MB_FP64])
+                t_list=0.0, storage=storage)
 
 
 def blocks_roofline(cfg, counts, chunk, ms):
@@ -528,8 +536,8 @@ def main():
     ap.add_argument("--mixed-storage", choices=["auto", "f32b", "f32"], default="auto",
                     help="mixed path: float stages and float block copies for the steps (f32b, where the "
                          "library has those kernels: at most four sink indices per species), float stages "
-                         "and double blocks (f32), or each workload's own choice (auto: f32b for the "
-                         "all-component 4He, whose error stays within 1e-6 with it; f32 elsewhere)")
+                         "and double blocks (f32), or per term list (auto: f32b for lists of all spin "
+                         "components, f32 for one spin state)")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch settings")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every step in this run instead of using the committed settings")

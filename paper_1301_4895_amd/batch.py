@@ -25,6 +25,8 @@ class BatchRunner:
                    Lambda only; optional otherwise)
          sink_w    complex128 [n_src][V] device tensor or None
          scale_exp int32 [lanes] device tensor or None
+         precision the group's precision mode (optional; default the
+                   runner's ``precision``)
     After ``launch`` + synchronisation, ``corr[g]`` holds the correlators of
     group g ([lanes][n_delta][n_alpha] complex128) and ``exp[g]`` their
     scale exponents."""
@@ -44,7 +46,8 @@ class BatchRunner:
             sink = None if g.get("sink_w") is None else torch.view_as_real(g["sink_w"])
             for b0 in range(0, lanes, chunk):
                 b1 = min(lanes, b0 + chunk)
-                p = B.problem(b1 - b0, g["props"].shape[1], g["props"][b0:b1], g["props"][b0:b1], precision,
+                p = B.problem(b1 - b0, g["props"].shape[1], g["props"][b0:b1], g["props"][b0:b1],
+                              g.get("precision", precision),
                               sink, None if g.get("scale_exp") is None else g["scale_exp"][b0:b1],
                               None if g.get("props_s") is None else g["props_s"][b0:b1])
                 self.items.append(dict(tl=g["tl"], prob=p, corr=self.corr[-1][b0:b1],
@@ -119,8 +122,9 @@ def tune_nuclei(groups, precision, chunk=256, cache=None, key=None, log=None, co
     """Launch settings of every distinct term list: the committed ones for
     this key (paper_1301_4895_amd/tuned.json) when present and
     committed_first, else the autotuner on the largest of its groups (the
-    settings do not depend on the volume).  Returns {id(tl): (settings,
-    source)}."""
+    settings do not depend on the volume), in the group's precision mode
+    (its "precision" entry, else ``precision``).  Returns {id(tl):
+    (settings, source)}."""
     from . import autotune
     from .runner import Runner
     best = {}
@@ -129,13 +133,14 @@ def tune_nuclei(groups, precision, chunk=256, cache=None, key=None, log=None, co
         if id(tl) in best:
             continue
         n = min(chunk, g["props"].shape[0])
-        k = None if key is None else f"{key}|{g['name']}|{precision}|{n}"
+        prec = g.get("precision", precision)
+        k = None if key is None else f"{key}|{g['name']}|{prec}|{n}"
         fixed = autotune.committed(k) if (committed_first and k) else None
         if fixed is not None:
             autotune.apply(tl, fixed)
             best[id(tl)] = (fixed, "committed")
             continue
-        r = Runner(tl, g["props"][:n], g["props"][:n], precision, g.get("sink_w"),
+        r = Runner(tl, g["props"][:n], g["props"][:n], prec, g.get("sink_w"),
                    None if g.get("scale_exp") is None else g["scale_exp"][:n])
         best[id(tl)] = (autotune.tune(tl, r, key=k, cache=cache, log=log), "autotuned")
         del r

@@ -30,8 +30,9 @@ double item_cost(const mb_term_list *tl, const mb_problem *p) {
   const bool sym = p->prop_u == p->prop_d;
   const double pairs = sym ? tl->nxi * (tl->nxi + 1) / 2.0 : double(tl->nxi) * tl->nxi;
   double blocks = 8.0 * 3.0 * rows * pairs * double(p->V) * (sym ? 1 : 2);
-  // the Lambda's block runs over every ordered (u, d) pair
-  if (tl->nLam) blocks += 8.0 * 3.0 * rows * double(tl->nxi) * tl->nxi * double(p->V);
+  // the Lambda's block runs over the same (u, d) pairs (every ordered pair
+  // when u != d)
+  if (tl->nLam) blocks += 8.0 * 3.0 * rows * pairs * double(p->V);
   int64_t nl = 0;
   for (const auto &s : tl->st) nl += s.n_lambda;
   return double(p->batch) * (blocks + 8.0 * double(nl));

@@ -60,8 +60,9 @@ def _oracle_pairs(tl, m, S, k, pairs):
 
 def _mixed_sigma(groups, chunk=256):
     """The library's estimated standard deviation of the rounding error of
-    every mixed correlator of every group (single calls with err_out; the
-    correlators are those of the graph)."""
+    every mixed correlator of every group (single calls with err_out, in the
+    group's mixed mode "mixed", default MB_MIXED; the correlators are those
+    of the graph)."""
     from paper_1301_4895_amd.runner import Runner
     out = []
     for g in groups:
@@ -69,7 +70,7 @@ def _mixed_sigma(groups, chunk=256):
         parts = []
         for b0 in range(0, lanes, chunk):
             b1 = min(lanes, b0 + chunk)
-            r = Runner(g["tl"], g["props"][b0:b1], g["props"][b0:b1], B.MB_MIXED, g.get("sink_w"),
+            r = Runner(g["tl"], g["props"][b0:b1], g["props"][b0:b1], g.get("mixed", B.MB_MIXED), g.get("sink_w"),
                        None if g.get("scale_exp") is None else g["scale_exp"][b0:b1], err_estimate=True)
             r.run()
             torch.cuda.synchronize()
@@ -169,13 +170,23 @@ def test_batch_rejects_shared_buffers_across_branches():
 
 
 def test_full_uneven_batch():
-    """In the launch settings the benchmark times (the committed table, keyed
-    like bench.py's C5 run)."""
+    """In the launch settings and precision modes the benchmark times (the
+    committed table, keyed like bench.py's C5 run; the mixed leg with float
+    block copies for the all-component nuclei)."""
+    import argparse
+
+    from bench import mixed_precision
     from paper_1301_4895_amd.batch import tune_nuclei
     groups, tls, probs = mix_groups(torch.device(DEV))
     assert sum(g["props"].shape[0] for g in groups) == sum(T for _, _, T in probs)
+    auto = argparse.Namespace(mixed_storage="auto")
+    for g in groups:
+        g["mixed"] = mixed_precision(g["tl"], auto, MIX_TYPES[g["type"]])
+    assert {g["mixed"] for g in groups} == {B.MB_MIXED, B.MB_MIXED_F32B}
     res = {}
     for prec in (B.MB_MIXED, B.MB_FP64):
+        for g in groups:
+            g["precision"] = g["mixed"] if prec == B.MB_MIXED else prec
         tuned = tune_nuclei(groups, prec, 256, key="c5")
         print(prec, {src for _, src in tuned.values()}, flush=True)
         br = BatchRunner(groups, prec, n_branches=4, chunk=256)
