@@ -46,7 +46,8 @@ def test_noalloc_blocks_match_workspace_blocks(rel, nsrc, same_ud, dtype, shapes
         Sd = Su if same_ud else host_props(81 + call, 1, nl, 1, V, nsrc, dtype)[:, 0]
         w = (rng.normal(size=(nsrc, V)) + 1j * rng.normal(size=(nsrc, V))) if nsrc == 2 else None
         k = rng.integers(-2, 3, size=nl).astype(np.int32)
-        for prec in (B.MB_FP64, B.MB_MIXED):
+        # MB_MIXED_F32B: the float block copies after the exponents too
+        for prec in (B.MB_FP64, B.MB_MIXED, B.MB_MIXED_F32B):
             got, ref = _blocks_both_ways(tl, Su, Sd, w, k, prec)
             assert np.array_equal(got, ref), (call, V, nl, prec)
 
