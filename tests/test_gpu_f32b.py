@@ -250,3 +250,31 @@ def test_three_sources():
     with pytest.raises(B.MBError) as ei:
         _run(tl, Su[:4], w, k[:4], B.MB_MIXED_F32B)
     assert ei.value.code == B.MB_EUNSUPPORTED
+
+
+def test_projected_and_side_outputs():
+    """Projected lists (one output per lane) and side nuclei (final sums of
+    earlier stages) read the float-block stages like the main output: every
+    output within its first-order bound of FP64, and element by element
+    within 1e-6 (or the bound)."""
+    from tests.spin_weights import sparse_weights
+    nl, V = 3, 27
+    Su, w, k = _inputs(91, nl, V, 1, np.complex64, False)
+    full = B.TermList(2, 1, False, 1, all_components=True)
+    cf = full.counts()
+    W = sparse_weights((cf["n_delta"], cf["n_alpha"]), 7, 0.3)
+    for tl in (B.TermList(2, 1, False, 1, all_components=True, proj=W),
+               B.TermList(2, 1, False, 1, all_components=True, sides=[(0, None), (1, None)])):
+        res = {}
+        for prec in (B.MB_FP64, B.MB_MIXED_F32B):
+            r = _runner(tl, Su, w, k, prec, err=True)
+            r.run()
+            torch.cuda.synchronize()
+            res[prec] = (r.out.cpu().numpy(), r.err_all.cpu().numpy())
+        got, ref = res[B.MB_MIXED_F32B][0], res[B.MB_FP64][0]
+        bound = res[B.MB_MIXED_F32B][1][:, 1]
+        d = np.abs(got - ref)
+        assert np.all(d <= bound), float((d / bound).max())
+        assert_close(got.reshape(nl, -1), ref.reshape(nl, -1), 1e-6, "float blocks vs fp64",
+                     sigma=(bound / 6).reshape(nl, -1))
+        assert np.all(res[B.MB_FP64][1] == 0)
