@@ -64,3 +64,44 @@ def test_mix_draw_is_seeded_and_spans_the_choices():
     assert {t for t, _, _ in a} == {0, 1, 2, 3}
     assert {L for _, L, _ in a} == {16, 24, 32}
     assert {T for _, _, T in a} == {32, 64, 96}
+
+
+def test_lambda_cost_counts_its_pairs():
+    """With a Lambda the blocks cost adds its site sums over the same (u, d)
+    pairs as the nucleons': the symmetric ones when u = d, every ordered one
+    otherwise."""
+    tl = B.TermList(1, 1, False, 1, all_components=True, n_Lambda=1)
+    cnt = tl.counts()
+    nxi, npsi = cnt["n_xi"], cnt["n_psi"]
+    for same in (True, False):
+        p = _prob(64, 4096, same)
+        _, cost = B.batch_plan([tl], [p], 1)
+        pairs = nxi * (nxi + 1) / 2 if same else nxi * nxi
+        nuc = 1 if same else 2
+        want = p.batch * (8.0 * 3 * npsi * nxi * pairs * p.V * (nuc + 1) + 8.0 * cnt["n_lambda"])
+        assert cost[0] == pytest.approx(want, rel=1e-12)
+
+
+def test_bench_mixed_mode_per_term_list():
+    """The benchmark's mixed leg: float block copies (MB_MIXED_F32B) for lists
+    of all spin components with at most four sink indices per species,
+    MB_MIXED for one spin state or more sink indices; --mixed-storage
+    overrides the choice."""
+    import argparse
+
+    import bench
+    auto = argparse.Namespace(mixed_storage="auto")
+    for m in bench.MIX_TYPES:
+        tl = (B.TermList(m["nP"], m["nN"], m["rel"], m["nsrc"], all_components=True) if m["spins"] is None
+              else B.TermList.spin_state(m["nP"], m["nN"], m["rel"], m["nsrc"], m["spins"]))
+        want = B.MB_MIXED_F32B if m["spins"] is None else B.MB_MIXED
+        assert bench.mixed_precision(tl, auto, m) == want, m["name"]
+        assert bench.mixed_precision(tl, argparse.Namespace(mixed_storage="f32"), m) == B.MB_MIXED
+        assert bench.mixed_precision(tl, argparse.Namespace(mixed_storage="f32b"), m) == B.MB_MIXED_F32B
+    # five sink indices per species (three sources): no float-block kernels
+    c = bench.CONFIGS["n5"]
+    tl = B.TermList(c["nP"], c["nN"], c["rel"], c["nsrc"], all_components=True)
+    assert bench.mixed_precision(tl, argparse.Namespace(mixed_storage="f32b"), dict(c, spins=None)) == B.MB_MIXED
+    c3 = bench.CONFIGS["c3"]
+    tl = B.TermList(c3["nP"], c3["nN"], c3["rel"], c3["nsrc"], all_components=True)
+    assert bench.mixed_precision(tl, auto, c3) == B.MB_MIXED_F32B
