@@ -15,6 +15,8 @@
 // scales every lane by its exponent.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace mb {
@@ -65,7 +67,11 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
   // double-precision pipeline, so every entry is widened once, when it is
   // staged, rather than at each of its uses in the diquark.
   __shared__ double2 su[2][NS][NROW][NXI];
-  __shared__ double2 s1[Q1B ? 2 : 1][Q1B ? NS : 1][Q1B ? NROW : 1][Q1B ? NXI : 1];  // q1 when it differs from u
+  // q1 when it differs from u: as read (complex float inputs stay float, half
+  // the bytes; widened and scaled, exactly, when the A operand is built), so
+  // that the Lambda's kernel with S_u = S_d fits two workgroups per CU
+  using S1T = typename std::conditional<std::is_same<TIN, float2>::value, float2, double2>::type;
+  __shared__ S1T s1[Q1B ? 2 : 1][Q1B ? NS : 1][Q1B ? NROW : 1][Q1B ? NXI : 1];
   __shared__ double2 sd[NB][SYM ? 1 : NS][SYM ? 1 : NROW][SYM ? 1 : NXI];
   __shared__ double2 Ac[2][KG][MP];   // (re, im) of the A operand
   __shared__ double2 Bc[2][KG][NP];   // (re, im) of the B operand
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
         su[buf][n][r][xi] = scaled(pu[j], scale);
         if constexpr (!SYM) sd[buf][n][r][xi] = scaled(pd[j], scale);
         if constexpr (Q1B) {
-          if (!same1) s1[buf][n][r][xi] = scaled(p1[j], scale);
+          if (!same1) s1[buf][n][r][xi] = p1[j];
         }
       }
     }
@@ -183,7 +189,8 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
     const int buf = g & 1, ns = group_sites(g);
     const double2 *su_f = &su[buf][0][0][0];
     const double2 *sd_f = SYM ? su_f : &sd[SYM ? 0 : buf][0][0][0];
-    const double2 *s1_f = (!Q1B || same1) ? su_f : &s1[Q1B ? buf : 0][0][0][0];
+    const bool q1_is_u = !Q1B || same1;
+    const S1T *s1_f = &s1[Q1B ? buf : 0][0][0][0];
     // A operand: w S_q1[(alpha, a), xi1]
 #pragma unroll
     for (int j = 0; j < AJ; j++) {
@@ -192,7 +199,7 @@ __global__ __launch_bounds__(64 * (NMW + 4)) void blocks_mfma_kernel(BlocksArgs 
         double re = 0.0, im = 0.0;
         if (a_src[j] >= 0 && a_n[j] < ns) {
           const double2 w = (&wsh[buf][0][0])[a_w[j]];
-          const double2 v = rd(s1_f, a_src[j]);
+          const double2 v = q1_is_u ? rd(su_f, a_src[j]) : scaled(s1_f[a_src[j]], scale);
           re = w.x * v.x - w.y * v.y;
           im = w.x * v.y + w.y * v.x;
         }
