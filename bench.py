@@ -64,18 +64,12 @@ STORAGE = {0: "f64", 1: "f32 stages, f64 blocks", 2: "f32 stages, f32 block copi
 def mixed_precision(tl, args, cfg):
     """The mixed mode of a workload: float block copies (MB_MIXED_F32B) for a
     list of all spin components (many outputs per lane, whose error stays
-    far below 1e-6 with them) where the library has their kernels (at most
-    four sink indices per species), else MB_MIXED (one spin component: the
+    far below 1e-6 with them), else MB_MIXED (one spin component: the
     cancellation in it lifts the coherent rounding of the block copies above
     1e-6); --mixed-storage forces one."""
-    from paper_1301_4895_amd import autotune
     from paper_1301_4895_amd import binding as B
     want = ("f32b" if cfg["spins"] is None else "f32") if args.mixed_storage == "auto" else args.mixed_storage
-    if want == "f32":
-        return B.MB_MIXED
-    c = tl.counts()
-    species = (0, 1, 2) if c.get("n_Lambda") else (0, 1)
-    return B.MB_MIXED if max(autotune._base(tl, sp) for sp in species) > 4 else B.MB_MIXED_F32B
+    return B.MB_MIXED if want == "f32" else B.MB_MIXED_F32B
 
 
 def mix_groups(dev, types=None, n=MIX_N, seed=MIX_SEED):
@@ -534,9 +528,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
     ap.add_argument("--mixed-storage", choices=["auto", "f32b", "f32"], default="auto",
-                    help="mixed path: float stages and float block copies for the steps (f32b, where the "
-                         "library has those kernels: at most four sink indices per species), float stages "
-                         "and double blocks (f32), or per term list (auto: f32b for lists of all spin "
+                    help="mixed path: float stages and float block copies for the steps (f32b), float "
+                         "stages and double blocks (f32), or per term list (auto: f32b for lists of all spin "
                          "components, f32 for one spin state)")
     ap.add_argument("--no-autotune", action="store_true", help="library default launch settings")
     ap.add_argument("--retune", action="store_true",

@@ -79,10 +79,9 @@ extern "C" {
 #define MB_MIXED_F32B 2        /* as MB_MIXED, and the recursion steps read float
                                   copies of the block entries (rounded once from
                                   the scaled double blocks); the first stage and
-                                  every product and sum as in MB_MIXED.  Steps
-                                  with more than four sink indices per species
-                                  (three sources) and the LDS-staged step kernel
-                                  are refused (MB_EUNSUPPORTED)                   */
+                                  every product and sum as in MB_MIXED.  The
+                                  LDS-staged step kernel (MB_TUNE_KERNEL = 1) is
+                                  refused with it (MB_EUNSUPPORTED)               */
 
 /* A nucleus of n_P protons and n_N neutrons (Sec. 7), and optionally one
  * Lambda hyperon.

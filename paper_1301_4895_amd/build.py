@@ -39,7 +39,7 @@ def _compile(src, obj, kind):
 def build_library(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     units = [("termlist.cpp", "host"), ("capi.cpp", "hipapi"), ("batch.cpp", "hipapi"), ("blocks.hip", "hip"),
-             ("contract.hip", "hip"), ("contract_f32.hip", "hip"), ("contract_f32b.hip", "hip"),
+             ("contract.hip", "hip"), ("contract_f32.hip", "hip"), ("contract_f32b.hip", "hip"), ("contract_f32b_m6.hip", "hip"),
              ("contract_f64.hip", "hip"), ("contract_f32_m6.hip", "hip"), ("contract_f64_m6.hip", "hip"),
              ("errest.hip", "hip"),
              ("noalloc.hip", "hip")]

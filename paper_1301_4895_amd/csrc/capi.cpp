@@ -620,9 +620,8 @@ static int contract_steps(const mb_term_list *tl, const mb_problem *p, const voi
         }
         psi_positions(base_of(tl, S.type), a.psi_of_pos);
         if (a.M > 6) return fail(MB_EUNSUPPORTED, "more than 6 sink indices per species");
-        if (a.nq_out > 0 && fb32 && (S.tune_kernel == 1 || a.M > 4))
-          return fail(MB_EUNSUPPORTED,
-                      "float block copies: the direct or grouped step kernel with at most four sink indices");
+        if (a.nq_out > 0 && fb32 && S.tune_kernel == 1)
+          return fail(MB_EUNSUPPORTED, "float block copies: the direct or grouped step kernel");
         if (a.nq_out > 0 && S.tune_kernel == 1) {
           // the LDS-staged kernel holds one range of at most 36 pair rows:
           // n_xi <= 12 (one source relativistic, up to two nonrelativistic)

@@ -84,8 +84,7 @@ def test_lambda_cost_counts_its_pairs():
 
 def test_bench_mixed_mode_per_term_list():
     """The benchmark's mixed leg: float block copies (MB_MIXED_F32B) for lists
-    of all spin components with at most four sink indices per species,
-    MB_MIXED for one spin state or more sink indices; --mixed-storage
+    of all spin components, MB_MIXED for one spin state; --mixed-storage
     overrides the choice."""
     import argparse
 
@@ -98,10 +97,9 @@ def test_bench_mixed_mode_per_term_list():
         assert bench.mixed_precision(tl, auto, m) == want, m["name"]
         assert bench.mixed_precision(tl, argparse.Namespace(mixed_storage="f32"), m) == B.MB_MIXED
         assert bench.mixed_precision(tl, argparse.Namespace(mixed_storage="f32b"), m) == B.MB_MIXED_F32B
-    # five sink indices per species (three sources): no float-block kernels
-    c = bench.CONFIGS["n5"]
-    tl = B.TermList(c["nP"], c["nN"], c["rel"], c["nsrc"], all_components=True)
-    assert bench.mixed_precision(tl, argparse.Namespace(mixed_storage="f32b"), dict(c, spins=None)) == B.MB_MIXED
+    c = bench.CONFIGS["n5"]   # one spin state on three sources
+    tl = B.TermList.spin_state(c["nP"], c["nN"], c["rel"], c["nsrc"], c["spins"])
+    assert bench.mixed_precision(tl, auto, c) == B.MB_MIXED
     c3 = bench.CONFIGS["c3"]
     tl = B.TermList(c3["nP"], c3["nN"], c3["rel"], c3["nsrc"], all_components=True)
     assert bench.mixed_precision(tl, auto, c3) == B.MB_MIXED_F32B

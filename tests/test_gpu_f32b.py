@@ -8,8 +8,9 @@ the FP64 path (element by element, or within 6 of the library's estimated
 standard deviations, or of the first-order bound where one component per
 lane is asked for) and of the oracle; the error estimate (err_out), which
 adds the rounding of the block copies, bounds the measured deviation; every
-launch setting the mode accepts gives the same correlators; and the shapes
-it has no kernels for are refused before any launch.
+launch setting the mode accepts gives the same correlators, and the
+LDS-staged kernel, which it has no form of, is refused before any launch;
+three sources with up to six sink indices per species.
 """
 import numpy as np
 import pytest
@@ -238,18 +239,21 @@ def test_float_block_launch_settings_keep_results(rel, nsrc, nP, nN, spins, V, n
         assert_close(got, ref, 1e-6, (kern, pg, tile, unroll, group, two), sigma=_accept(e, spins))
 
 
-def test_three_sources():
-    """Three sources run while no species has more than four sink indices;
-    five neutrons on three sources (five sink indices) are refused."""
-    Su, w, k = _inputs(3, 20, 8, 3, np.complex64, True)
-    tl = _tl(False, 3, 1, 2, (0, 1, 5))
+@pytest.mark.parametrize("nP,nN,spins,nl,V", [
+    (1, 2, (0, 1, 5), 20, 8),             # at most two sink indices per species
+    (0, 5, (0, 3, 1, 4, 2), 64, 64),      # five neutrons: five sink indices (odd: a padded pair)
+    (0, 3, None, 8, 8),                   # three neutrons, all components: six sink indices
+])
+def test_three_sources(nP, nN, spins, nl, V):
+    """Three sources, including the steps with five and six sink indices per
+    species, against FP64 (element by element within 1e-6, or the bound or
+    6 sigma) and within the first-order bound."""
+    Su, w, k = _inputs(3, nl, V, 3, np.complex64, True)
+    tl = _tl(False, 3, nP, nN, spins)
     c64, _ = _run(tl, Su, w, k, B.MB_FP64)
     cb, eb = _run(tl, Su, w, k, B.MB_MIXED_F32B)
-    assert_close(cb, c64, 1e-6, "float blocks vs fp64 (three sources)", sigma=_accept(eb, (0, 1, 5)))
-    tl = _tl(False, 3, 0, 5, (0, 3, 1, 4, 2))
-    with pytest.raises(B.MBError) as ei:
-        _run(tl, Su[:4], w, k[:4], B.MB_MIXED_F32B)
-    assert ei.value.code == B.MB_EUNSUPPORTED
+    assert_close(cb, c64, 1e-6, "float blocks vs fp64 (three sources)", sigma=_accept(eb, spins))
+    assert np.all(np.abs(cb - c64) <= eb[..., 1])
 
 
 def test_projected_and_side_outputs():
