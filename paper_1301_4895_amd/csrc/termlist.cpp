@@ -466,7 +466,8 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
                  bool counts_only, mb_term_list **out) {
   if (!nuc || !req || !out) return fail(MB_EINVAL, "null argument");
   if (n_side < 0 || (n_side > 0 && !side)) return fail(MB_EINVAL, "bad side requests");
-  if (nuc->n_Lambda < 0 || nuc->n_Lambda > 1) return fail(MB_EUNSUPPORTED, "at most one Lambda");
+  if (nuc->n_P < 0 || nuc->n_N < 0 || nuc->n_Lambda < 0) return fail(MB_EINVAL, "baryon counts must not be negative");
+  if (nuc->n_Lambda > 1) return fail(MB_EUNSUPPORTED, "at most one Lambda");
   if (nuc->n_Lambda && (nuc->path == MB_PATH_BEST || n_side > 0 || req->proj))
     return fail(MB_EUNSUPPORTED, "a Lambda with MB_PATH_BEST, side requests or a projection");
   if (nuc->path == MB_PATH_BEST) {
@@ -507,7 +508,7 @@ static int build(const mb_nucleus *nuc, const mb_spin_request *req, int n_side, 
   }
   *out = nullptr;
   const int nP = nuc->n_P, nN = nuc->n_N, nLam = nuc->n_Lambda, An = nP + nN;
-  if (nP < 0 || nN < 0 || An + nLam < 1) return fail(MB_EINVAL, "need at least one baryon");
+  if (An + nLam < 1) return fail(MB_EINVAL, "need at least one baryon");
   if (An + nLam > MB_MAX_STAGES) return fail(MB_EUNSUPPORTED, "more than 16 baryons");
   if (nuc->rel != 0 && nuc->rel != 1) return fail(MB_EINVAL, "rel must be 0 or 1");
   if (nuc->n_src < 1 || nuc->n_src > 3) return fail(MB_EUNSUPPORTED, "n_src must be 1, 2 or 3");

@@ -295,6 +295,10 @@ def test_error_codes():
     with pytest.raises(B.MBError) as e:
         B.TermList(0, 0, False, 1, all_components=True)
     assert e.value.code == B.MB_EINVAL
+    for counts in ((-1, 1, 0), (1, -2, 0), (1, 1, -1)):
+        with pytest.raises(B.MBError) as e:
+            B.TermList(counts[0], counts[1], False, 1, all_components=True, n_Lambda=counts[2])
+        assert e.value.code == B.MB_EINVAL and "negative" in str(e.value), counts
     L = B.lib()
     import ctypes as C
     h = C.c_void_p()
