@@ -346,22 +346,38 @@ def run_workload(name, args):
         key = f"{name}:{main_name}:{dom}"
         if t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {}):
             traffic = t["bytes_per_launch"][key]
+    sec = res["kernel_avg_ms"][dom] / 1e3
     alu_frac = achieved / VALU_PEAK_TFLOPS
-    # measured HBM traffic (FETCH_SIZE x calibration + WRITE_SIZE; FETCH_SIZE
-    # counts every L2 request to the memory fabric, MALL hits included) over
-    # the launch time, against the HBM peak
-    hbm_frac = None if traffic is None else traffic / (res["kernel_avg_ms"][dom] / 1e3) / 1e9 / HBM_PEAK_GBS
-    bound = "hbm" if hbm_frac is not None and hbm_frac > alu_frac else "alu"
-    species = ("proton", "neutron", "Lambda")[counts["path"][s]]
+    # algorithmic bytes of the step: the previous stage read once, the new
+    # stage written once, the added species' block entries read once
+    from paper_1301_4895_amd import autotune
+    prec = mixed if main_name == "mixed" else B.MB_FP64
+    elem = 16 if prec == B.MB_FP64 else 8
+    sp = counts["path"][s]
+    nxi = counts["n_xi"]
+    rows = nxi ** 3 if sp == 2 else nxi * (nxi - 1) // 2 * nxi
+    per_row = (autotune._base(tl, sp) + 1) // 2 * 16 if prec == B.MB_MIXED_F32B else counts["n_psi"] * 16
+    alg_bytes = ((counts["n_req"][s - 1] + counts["n_req"][s]) * elem + rows * per_row) * chunk
+    hbm_alg_frac = alg_bytes / sec / 1e9 / HBM_PEAK_GBS
+    # the bound is the roof with the larger algorithmic fraction
+    bound = "hbm" if hbm_alg_frac > alu_frac else "alu"
+    species = ("proton", "neutron", "Lambda")[sp]
     roofline = dict(bound=bound, kernel=f"recursion {dom} ({species} added)",
                     achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(alu_frac, 4), traffic=traffic,
-                    hbm_frac=None if hbm_frac is None else round(hbm_frac, 4),
-                    flops_per_launch=flops, launch_ms=round(res["kernel_avg_ms"][dom], 4))
+                    flops_per_launch=flops, algorithmic_bytes_per_launch=alg_bytes,
+                    hbm_frac_algorithmic=round(hbm_alg_frac, 4), launch_ms=round(res["kernel_avg_ms"][dom], 4))
     if bound == "hbm":
-        roofline.update(achieved=round(traffic / (res["kernel_avg_ms"][dom] / 1e3) / 1e9, 1), peak=HBM_PEAK_GBS,
-                        unit="GB/s", frac=round(hbm_frac, 4), alu_frac=round(alu_frac, 4),
-                        alu_achieved_tflops=round(achieved, 3))
+        roofline.update(achieved=round(alg_bytes / sec / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(hbm_alg_frac, 4), alu_frac=round(alu_frac, 4))
+    if traffic is not None:
+        # measured HBM traffic (FETCH_SIZE x calibration + WRITE_SIZE; FETCH_SIZE
+        # counts every L2 request to the memory fabric, MALL hits included):
+        # its rate against the HBM peak, and how many times the algorithmic
+        # bytes it moves (re-reads)
+        roofline.update(measured_traffic_gbps=round(traffic / sec / 1e9, 1),
+                        hbm_frac_measured_traffic=round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4),
+                        traffic_over_algorithmic=round(traffic / alg_bytes, 2))
     roofline["blocks"] = blocks_roofline(cfg, counts, chunk, res["kernel_avg_ms"]["blocks"])
 
     return dict(name=name, cfg=cfg, lanes=lanes, V=V, counts=counts, chunk=chunk, results=results,
