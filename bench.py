@@ -344,7 +344,10 @@ def run_workload(name, args):
     if os.path.exists(tf):
         t = json.load(open(tf))
         key = f"{name}:{main_name}:{dom}"
-        if t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {}):
+        # the counters were taken with each workload's own mixed mode (the
+        # default --mixed-storage auto) and the current step sources
+        if (t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {})
+                and (main_name != "mixed" or args.mixed_storage == "auto")):
             traffic = t["bytes_per_launch"][key]
     sec = res["kernel_avg_ms"][dom] / 1e3
     alu_frac = achieved / VALU_PEAK_TFLOPS
