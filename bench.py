@@ -338,7 +338,6 @@ def run_workload(name, args):
     dom = max(step_names, key=lambda n: res["kernel_avg_ms"][n])
     s = int(dom[4:])
     flops = counts["n_lambda_step"][s] * 8.0 * chunk
-    achieved = flops / (res["kernel_avg_ms"][dom] / 1e3) / 1e12
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
@@ -349,38 +348,15 @@ def run_workload(name, args):
         if (t.get("kernel_hash") == kernel_hash() and key in t.get("bytes_per_launch", {})
                 and (main_name != "mixed" or args.mixed_storage == "auto")):
             traffic = t["bytes_per_launch"][key]
-    sec = res["kernel_avg_ms"][dom] / 1e3
-    alu_frac = achieved / VALU_PEAK_TFLOPS
-    # algorithmic bytes of the step: the previous stage read once, the new
-    # stage written once, the added species' block entries read once
     from paper_1301_4895_amd import autotune
     prec = mixed if main_name == "mixed" else B.MB_FP64
-    elem = 16 if prec == B.MB_FP64 else 8
     sp = counts["path"][s]
     nxi = counts["n_xi"]
     rows = nxi ** 3 if sp == 2 else nxi * (nxi - 1) // 2 * nxi
     per_row = (autotune._base(tl, sp) + 1) // 2 * 16 if prec == B.MB_MIXED_F32B else counts["n_psi"] * 16
-    alg_bytes = ((counts["n_req"][s - 1] + counts["n_req"][s]) * elem + rows * per_row) * chunk
-    hbm_alg_frac = alg_bytes / sec / 1e9 / HBM_PEAK_GBS
-    # the bound is the roof with the larger algorithmic fraction
-    bound = "hbm" if hbm_alg_frac > alu_frac else "alu"
-    species = ("proton", "neutron", "Lambda")[sp]
-    roofline = dict(bound=bound, kernel=f"recursion {dom} ({species} added)",
-                    achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(alu_frac, 4), traffic=traffic,
-                    flops_per_launch=flops, algorithmic_bytes_per_launch=alg_bytes,
-                    hbm_frac_algorithmic=round(hbm_alg_frac, 4), launch_ms=round(res["kernel_avg_ms"][dom], 4))
-    if bound == "hbm":
-        roofline.update(achieved=round(alg_bytes / sec / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(hbm_alg_frac, 4), alu_frac=round(alu_frac, 4))
-    if traffic is not None:
-        # measured HBM traffic (FETCH_SIZE x calibration + WRITE_SIZE; FETCH_SIZE
-        # counts every L2 request to the memory fabric, MALL hits included):
-        # its rate against the HBM peak, and how many times the algorithmic
-        # bytes it moves (re-reads)
-        roofline.update(measured_traffic_gbps=round(traffic / sec / 1e9, 1),
-                        hbm_frac_measured_traffic=round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4),
-                        traffic_over_algorithmic=round(traffic / alg_bytes, 2))
+    roofline = step_roofline(flops, counts["n_req"][s - 1], counts["n_req"][s], 16 if prec == B.MB_FP64 else 8,
+                             rows * per_row, chunk, res["kernel_avg_ms"][dom], traffic)
+    roofline["kernel"] = f"recursion {dom} ({('proton', 'neutron', 'Lambda')[sp]} added)"
     roofline["blocks"] = blocks_roofline(cfg, counts, chunk, res["kernel_avg_ms"]["blocks"])
 
     return dict(name=name, cfg=cfg, lanes=lanes, V=V, counts=counts, chunk=chunk, results=results,
@@ -454,6 +430,36 @@ def run_mix(args):
     return dict(name="c5", cfg=cfg, lanes=lanes, V=None, counts=dict(n_lambda=None), chunk=c5_chunk,
                 results=results, main=main_name, err=err, err_stats=err_stats, roofline=None, tuning=tuning,
                 t_list=0.0, storage=storage)
+
+
+def step_roofline(flops, n_in, n_out, elem, block_bytes_per_lane, lanes, ms, traffic=None):
+    """The roofline object of a recursion step launch from its algorithmic
+    work: `flops` per launch against the vector peak, and the algorithmic
+    bytes (the previous stage's n_in components read once, the new stage's
+    n_out written once, elem bytes each, and the added species' block
+    entries read once, per lane) against HBM; the bound is the roof with the
+    larger fraction, whose achieved rate and fraction are reported.  The
+    measured HBM traffic (bytes per launch, or None) goes beside them: its
+    rate, HBM fraction and ratio to the algorithmic bytes."""
+    sec = ms / 1e3
+    alg_bytes = ((n_in + n_out) * elem + block_bytes_per_lane) * lanes
+    tflops = flops / sec / 1e12
+    alu_frac = tflops / VALU_PEAK_TFLOPS
+    hbm_frac = alg_bytes / sec / 1e9 / HBM_PEAK_GBS
+    out = dict(bound="alu", achieved=round(tflops, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+               frac=round(alu_frac, 4), traffic=traffic, flops_per_launch=flops,
+               algorithmic_bytes_per_launch=alg_bytes, hbm_frac_algorithmic=round(hbm_frac, 4),
+               launch_ms=round(ms, 4))
+    if hbm_frac > alu_frac:
+        out.update(bound="hbm", achieved=round(alg_bytes / sec / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(hbm_frac, 4), alu_frac=round(alu_frac, 4))
+    if traffic is not None:
+        # measured HBM traffic (FETCH_SIZE x calibration + WRITE_SIZE; FETCH_SIZE
+        # counts every L2 request to the memory fabric, MALL hits included)
+        out.update(measured_traffic_gbps=round(traffic / sec / 1e9, 1),
+                   hbm_frac_measured_traffic=round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4),
+                   traffic_over_algorithmic=round(traffic / alg_bytes, 2))
+    return out
 
 
 def blocks_roofline(cfg, counts, chunk, ms):
