@@ -15,6 +15,7 @@
 // scales every lane by its exponent.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
@@ -679,38 +680,60 @@ hipError_t launch_blocks_finish_lambda(const FinishArgs &a, int nxi, int npsi, i
 }
 
 // Per-lane exponent: e_b with 2^(e_b - 1) <= max |Re|, |Im| over the lane's
-// block entries (both species) < 2^e_b, and the entries multiplied by
+// block entries (every species) < 2^e_b, and the entries multiplied by
 // 2^-e_b (exact), so that products of many blocks stay near 1 whatever the
-// size of the propagators.  A workgroup takes one tile of 16 lanes; its 16
-// thread groups stride over the entries of their lane.
-__global__ __launch_bounds__(256) void blocks_scale_kernel(double2 *blk, int32_t *lane_exp, int64_t Bp, int npsi,
-                                                           int nyq2) {
+// size of the propagators.  Two passes over a grid of (lane tile of 16,
+// chunk of entries): the first writes every chunk's exponent per lane, the
+// second reduces them per lane (chunk 0 stores e_b) and scales its chunk.
+// In a workgroup the 16 thread groups stride over the chunk's entries of
+// their lane.
+struct ScaleGrid {
+  int64_t Bp, nent, per;   // padded lanes, entries per lane, entries per chunk
+  int npsi, nchunk;
+  __device__ int64_t addr(int64_t tile, int64_t e, int l) const {
+    return (e / npsi) * npsi * Bp + tile * npsi * 16 + (e % npsi) * 16 + l;
+  }
+};
+
+__global__ __launch_bounds__(256) void blocks_lane_max_kernel(const double2 *blk, int32_t *part, ScaleGrid g) {
   __shared__ int emax[16][16];
-  const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int64_t tile = blockIdx.x;
-  const int64_t nent = int64_t(nyq2) * npsi;   // (species, block quark index) x psi
-  auto addr = [&](int64_t e) { return (e / npsi) * npsi * Bp + tile * npsi * 16 + (e % npsi) * 16 + l; };
+  const int l = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t tile = blockIdx.x, c = blockIdx.y;
+  const int64_t e1 = min(g.nent, (c + 1) * g.per);
   int em = -100000;
-  for (int64_t e = g; e < nent; e += 16) {
-    const double2 v = blk[addr(e)];
+  for (int64_t e = c * g.per + grp; e < e1; e += 16) {
+    const double2 v = blk[g.addr(tile, e, l)];
     const double m = fmax(fabs(v.x), fabs(v.y));
     if (m > 0.0) em = max(em, ilogb(m) + 1);
   }
-  emax[g][l] = em;
+  emax[grp][l] = em;
   __syncthreads();
-  if (g == 0) {
-    int e = emax[0][l];
-    for (int i = 1; i < 16; i++) e = max(e, emax[i][l]);
-    emax[0][l] = e == -100000 ? 0 : e;   // an all-zero lane keeps its scale
-    lane_exp[tile * 16 + l] = emax[0][l];
+  if (grp == 0) {
+    for (int i = 1; i < 16; i++) em = max(em, emax[i][l]);
+    part[(tile * g.nchunk + c) * 16 + l] = em;
+  }
+}
+
+__global__ __launch_bounds__(256) void blocks_scale_kernel(double2 *blk, int32_t *lane_exp, const int32_t *part,
+                                                           ScaleGrid g) {
+  __shared__ int esh[16];
+  const int l = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t tile = blockIdx.x, c = blockIdx.y;
+  if (grp == 0) {
+    int e = -100000;
+    for (int i = 0; i < g.nchunk; i++) e = max(e, part[(tile * g.nchunk + i) * 16 + l]);
+    e = e == -100000 ? 0 : e;   // an all-zero lane keeps its scale
+    esh[l] = e;
+    if (c == 0) lane_exp[tile * 16 + l] = e;
   }
   __syncthreads();
-  const int sh = -emax[0][l];
-  for (int64_t e = g; e < nent; e += 16) {
-    double2 v = blk[addr(e)];
+  const int sh = -esh[l];
+  const int64_t e1 = min(g.nent, (c + 1) * g.per);
+  for (int64_t e = c * g.per + grp; e < e1; e += 16) {
+    double2 v = blk[g.addr(tile, e, l)];
     v.x = ldexp(v.x, sh);
     v.y = ldexp(v.y, sh);
-    blk[addr(e)] = v;
+    blk[g.addr(tile, e, l)] = v;
   }
 }
 
@@ -748,9 +771,29 @@ hipError_t launch_blocks_to_f32(const void *blocks, void *out, int64_t rows, int
   return hipGetLastError();
 }
 
-hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s) {
-  hipLaunchKernelGGL(blocks_scale_kernel, dim3(unsigned(Bp / 16)), dim3(256), 0, s, static_cast<double2 *>(blocks),
-                     lane_exp, Bp, npsi, nyq2);
+static int blocks_scale_chunks(int64_t Bp, int npsi, int nyq2, size_t scratch_bytes) {
+  const int64_t tiles = Bp / 16, nent = int64_t(nyq2) * npsi;
+  // about 2048 workgroups, at least 64 entries per chunk, within the scratch
+  int64_t c = (2048 + tiles - 1) / tiles;
+  c = std::min<int64_t>(c, std::max<int64_t>(1, nent / 64));
+  c = std::min<int64_t>(c, std::max<int64_t>(1, int64_t(scratch_bytes / (size_t(tiles) * 16 * 4))));
+  return int(std::max<int64_t>(1, c));
+}
+
+hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, void *scratch,
+                               size_t scratch_bytes, hipStream_t s) {
+  ScaleGrid g;
+  g.Bp = Bp;
+  g.npsi = npsi;
+  g.nent = int64_t(nyq2) * npsi;
+  g.nchunk = blocks_scale_chunks(Bp, npsi, nyq2, scratch_bytes);
+  g.per = (g.nent + g.nchunk - 1) / g.nchunk;
+  if (size_t(Bp / 16) * g.nchunk * 16 * 4 > scratch_bytes) return hipErrorInvalidValue;
+  int32_t *part = static_cast<int32_t *>(scratch);
+  dim3 grid(unsigned(Bp / 16), unsigned(g.nchunk));
+  hipLaunchKernelGGL(blocks_lane_max_kernel, grid, dim3(256), 0, s, static_cast<const double2 *>(blocks), part, g);
+  hipLaunchKernelGGL(blocks_scale_kernel, grid, dim3(256), 0, s, static_cast<double2 *>(blocks), lane_exp,
+                     static_cast<const int32_t *>(part), g);
   return hipGetLastError();
 }
 

@@ -221,9 +221,11 @@ int make_blocks_with(const mb_term_list *tl, const mb_problem *p, void *blocks, 
     f.sym = lsym;
     HIP_CHECK(launch_blocks_finish_lambda(f, tl->nxi, tl->npsi, int64_t(2) * nyq, s));
   }
+  // the per-chunk exponents go to the workspace (the finish kernels have read
+  // the partial sums)
   HIP_CHECK(launch_blocks_scale(blocks, reinterpret_cast<int32_t *>(static_cast<char *>(blocks) +
                                                                      blocks_entry_bytes(tl, p)),
-                                f.Bp, tl->npsi, int(block_rows(tl)), s));
+                                f.Bp, tl->npsi, int(block_rows(tl)), ws, ws_bytes, s));
   if (p->precision == MB_MIXED_F32B) {
     // float copies of the base-set positions of every species, for the steps
     const char *src = static_cast<const char *>(blocks);

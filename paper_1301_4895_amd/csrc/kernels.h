@@ -40,7 +40,11 @@ hipError_t launch_blocks_finish_lambda(const FinishArgs &a, int nxi, int npsi, i
 
 // Per-lane block exponents (see blocks_scale_kernel): blocks scaled in place
 // by 2^-lane_exp[b]; nyq2 = block quark indices of all species together.
-hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, hipStream_t s);
+// scratch: device memory for the per-chunk exponents (Bp/16 x chunks x 16
+// int32, the chunk count fitted to scratch_bytes; the blocks workspace,
+// free once the blocks are finished).
+hipError_t launch_blocks_scale(void *blocks, int32_t *lane_exp, int64_t Bp, int npsi, int nyq2, void *scratch,
+                               size_t scratch_bytes, hipStream_t s);
 // Float copies of one species' block (rows block quark indices, npsi spin
 // indices) for the steps of MB_MIXED_F32B: the M positions psi_of_pos of the
 // species' sink base set, two per lane side by side (blocks_to_f32_kernel).
